@@ -48,25 +48,30 @@ def _load():
         if not os.path.exists(_LIB):
             build()
         lib = ctypes.CDLL(_LIB)
-        i64, dbl, ptr = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
-        sig = {
-            "oracle_bicgk": [i64, i64, ptr, i64, ptr, ptr, ptr, ptr],
-            "oracle_gemver": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr, ptr,
-                              ptr, ptr, ptr, i64, ptr, ptr],
-            "oracle_atax": [i64, i64, ptr, i64, ptr, ptr],
-            "oracle_dgemvt": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr, ptr],
-            "oracle_axpydot": [i64, dbl, ptr, ptr, ptr, ptr, ptr],
-            "oracle_waxpby": [i64, dbl, ptr, dbl, ptr, ptr],
-            "oracle_vadd": [i64, ptr, ptr, ptr, ptr],
-            "oracle_set_threads": [ctypes.c_int],
-            "oracle_get_threads": [],
-        }
-        for name, args in sig.items():
-            fn = getattr(lib, name)
-            fn.argtypes = args
-            fn.restype = ctypes.c_int if name == "oracle_get_threads" else None
-        _lib = lib
+        _lib = bind(lib)
     return _lib
+
+
+def bind(lib):
+    """Declare the C signatures on a loaded copy of the oracle library."""
+    i64, dbl, ptr = ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "oracle_bicgk": [i64, i64, ptr, i64, ptr, ptr, ptr, ptr],
+        "oracle_gemver": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr, ptr,
+                          ptr, ptr, ptr, i64, ptr, ptr],
+        "oracle_atax": [i64, i64, ptr, i64, ptr, ptr],
+        "oracle_dgemvt": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr, ptr],
+        "oracle_axpydot": [i64, dbl, ptr, ptr, ptr, ptr, ptr],
+        "oracle_waxpby": [i64, dbl, ptr, dbl, ptr, ptr],
+        "oracle_vadd": [i64, ptr, ptr, ptr, ptr],
+        "oracle_set_threads": [ctypes.c_int],
+        "oracle_get_threads": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int if name == "oracle_get_threads" else None
+    return lib
 
 
 def _p(a: np.ndarray):

@@ -182,3 +182,22 @@ def test_threads_bitwise(orc):
     flat = lambda o: np.concatenate([np.ravel(a) for a in
                                      [o[0][0], o[0][1], *o[1], o[2], *o[3]]])
     assert np.array_equal(flat(outs[0]), flat(outs[1]))
+
+
+# ---- leading dimension ----------------------------------------------------
+
+@pytest.mark.parametrize("m,n,lda", [(5, 3, 4), (64, 65, 80), (130, 257, 300)])
+def test_lda_padding_is_ignored(orc, m, n, lda):
+    """A padded (m, lda) matrix whose padding is NaN gives bitwise the same
+    results as the compact (m, n) matrix with the same elements."""
+    Ap = synth.matrix(SEED, 70, m, n, lda=lda)
+    Ac = np.ascontiguousarray(Ap[:, :n])
+    p, r = U(71, n), U(72, m)
+    for a, b in zip(orc.bicgk(Ap, p, r, lda=lda), orc.bicgk(Ac, p, r)):
+        assert np.array_equal(a, b)
+    assert np.array_equal(orc.atax(Ap, p, lda=lda), orc.atax(Ac, p))
+    args = (U(73, m), U(74, n), U(75, m), U(76, n), U(77, m), U(78, n), 1.5, 0.7)
+    for a, b in zip(orc.gemver(Ap, *args, lda=lda), orc.gemver(Ac, *args)):
+        assert np.array_equal(a, b)
+    for a, b in zip(orc.dgemvt(Ap, r, p, 1.5, 0.7, lda=lda), orc.dgemvt(Ac, r, p, 1.5, 0.7)):
+        assert np.array_equal(a, b)
