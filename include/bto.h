@@ -1,0 +1,189 @@
+/*
+ * bto.h -- C interface of libbto.so: fused FP64 BLAS-1/2 sequences on AMD
+ * MI355X (gfx950).
+ *
+ * The seven kernels are those of Table I (Section V-A) of Belter, Jessup,
+ * Nelson, Norris and Siek, "Reliable Generation of High-Performance Matrix
+ * Algebra".  Each entry point computes exactly the statements of its table
+ * row, in the order listed there; the argument lists follow the paper's
+ * kernel specifications: named inputs, then named outputs (Section II,
+ * Fig. 1), row-major matrices (Section II) with the BLAS-style row count,
+ * column count and leading dimension of the dgemv listing of Section V-A.
+ *
+ * Every entry point offers two forms:
+ *   BTO_FUSED    -- loop fusion and array contraction applied as the
+ *                   paper's search would pick them (Sections III-IV): every
+ *                   statement sharing a matrix pass runs in one kernel, and
+ *                   temporaries never reach memory;
+ *   BTO_UNFUSED  -- one kernel per BLAS operation, each reading its inputs
+ *                   and writing its output once, out of place (the "BLAS
+ *                   calls translated to loops" baseline of Section V-B).
+ * Both forms give results within 1e-12 normwise relative error of the plain
+ * definition; with integer-valued data both are exact.
+ *
+ * Conventions shared by all entry points
+ *   - Matrices are m x n, row-major: element (i, j) at A[i*lda + j],
+ *     lda >= max(1, n).
+ *   - Every array pointer is a DEVICE pointer on the current HIP device,
+ *     allocated and owned by the caller.  The library never allocates,
+ *     frees or keeps device memory between calls.
+ *   - Work is enqueued on `stream` (NULL = the default stream) and the call
+ *     returns without synchronizing.  Inputs must stay valid, and outputs
+ *     untouched by others, until the stream reaches the end of the call.
+ *   - Outputs are overwritten (never accumulated into).  A zero extent is
+ *     valid: an empty sum is 0, so e.g. BiCGK with m = 0 writes s = 0.
+ *   - NaN and Inf propagate as IEEE arithmetic makes them; nothing checks.
+ *   - Reductions use fixed summation trees that depend only on the sizes,
+ *     so repeated calls give bitwise-identical results.
+ *   - `ws` is caller-provided device scratch of at least
+ *     bto_workspace_bytes(kernel, m, n, form) bytes, 256-byte aligned; its
+ *     contents on entry are ignored.  It may be NULL when that size is 0.
+ *   - Errors are returned synchronously before anything is enqueued:
+ *       BTO_ERR_INVALID_ARG  negative size, lda/ldb too small, NULL pointer
+ *                            with a nonzero extent, unknown form;
+ *       BTO_ERR_ALIAS        an output overlaps another operand other than
+ *                            in the exact aliases the entry point allows;
+ *       BTO_ERR_WORKSPACE    ws_bytes below the required size;
+ *       BTO_ERR_HIP          a launch failed (bto_last_error() tells why).
+ *   - The library is thread-safe; calls on one stream execute in order.
+ */
+#ifndef BTO_H
+#define BTO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { BTO_FUSED = 0, BTO_UNFUSED = 1 } bto_form;
+
+typedef enum {
+    BTO_SUCCESS = 0,
+    BTO_ERR_INVALID_ARG = 1,
+    BTO_ERR_ALIAS = 2,
+    BTO_ERR_WORKSPACE = 3,
+    BTO_ERR_HIP = 4,
+    BTO_ERR_UNSUPPORTED = 5
+} bto_status;
+
+typedef enum {
+    BTO_K_BICGK = 0,
+    BTO_K_GEMVER = 1,
+    BTO_K_ATAX = 2,
+    BTO_K_DGEMVT = 3,
+    BTO_K_AXPYDOT = 4,
+    BTO_K_WAXPBY = 5,
+    BTO_K_VADD = 6
+} bto_kernel;
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int bto_version(void);
+
+/* Bytes of scratch that `kernel` needs at size (m, n) in form `form`.
+ * Vector kernels take their length as n and ignore m.  Returns 0 on bad
+ * arguments.  The value only depends on the arguments. */
+size_t bto_workspace_bytes(bto_kernel kernel, int64_t m, int64_t n, bto_form form);
+
+/* Static text for a status code. */
+const char *bto_status_string(bto_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *bto_last_error(void);
+
+/* BICGK (Table I):  q <- A p ;  s <- A^T r.
+ * A: m x n (lda); p: n; r: m; outputs q: m, s: n.
+ * Fused: one pass over A computes both products (Section V-B notes this is
+ * the fusion the best tools found).  Unfused: dgemv 'N' then dgemv 'T'. */
+bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda,
+                     const double *p, const double *r, double *q, double *s,
+                     void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* GEMVER (Table I):
+ *   B <- A + u1 v1^T + u2 v2^T ;  x <- beta B^T y + z ;  w <- alpha B x
+ * in that order (w uses the new x).  A, B: m x n (lda, ldb); u1, u2, y, w:
+ * m; v1, v2, z, x: n.  B may be exactly A (B == A and ldb == lda): an
+ * in-place update.  Fused: pass 1 forms B and the x partial sums in one
+ * sweep of A; pass 2 computes w from B.  Unfused: ger, ger, dgemv 'T',
+ * dgemv 'N'. */
+bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta,
+                      const double *A, int64_t lda,
+                      const double *u1, const double *v1,
+                      const double *u2, const double *v2,
+                      const double *y, const double *z,
+                      double *B, int64_t ldb, double *x, double *w,
+                      void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* ATAX (Table I):  y <- A^T A x.  A: m x n (lda); x, y: n.
+ * Fused: each row of A is read once and kept on chip while its dot with x
+ * is reduced and then used to update y (the partitioning p(i) of
+ * Section III-D); the temporary A x never reaches memory.  For n above
+ * 16384 the fused form falls back to two passes.  Unfused: dgemv 'N' into
+ * a temporary, then dgemv 'T'. */
+bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda,
+                    const double *x, double *y,
+                    void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* DGEMVT (Table I):  x <- beta A^T y + z ;  w <- alpha A x  (new x).
+ * A: m x n (lda); y, w: m; z, x: n.  Two passes in both forms (w needs all
+ * of x); the fused form folds the scaling and the +z into the reduction
+ * epilogues and reads A in the order that reuses what the first pass left
+ * in cache. */
+bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta,
+                      const double *A, int64_t lda, const double *y, const double *z,
+                      double *x, double *w,
+                      void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* AXPYDOT (Table I, whose scalar result is named beta there):
+ *   z <- w - alpha v ;  r <- z^T u.
+ * Vectors of length n; r points to ONE double in device memory.  z may be
+ * exactly w.  Fused: one sweep writes z and the dot partial sums. */
+bto_status bto_axpydot(int64_t n, double alpha, const double *w, const double *v,
+                       const double *u, double *z, double *r,
+                       void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* WAXPBY (Table I):  w <- alpha x + beta y.  Length n; w may be exactly x
+ * or exactly y.  Unfused: scal into a temporary, then axpy. */
+bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta,
+                      const double *y, double *w,
+                      void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* VADD (Table I):  x <- w + y + z, evaluated as (w + y) + z.  Length n; x
+ * may be exactly w, y or z.  Unfused: two vector adds through a temporary. */
+bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z,
+                    double *x, void *ws, size_t ws_bytes, bto_form form,
+                    hipStream_t stream);
+
+/* ---- measurement support ------------------------------------------------
+ * Per-kernel timing with HIP events recorded on the stream each kernel is
+ * launched on.  While enabled, every kernel the library launches is
+ * bracketed by a pair of events.  bto_timing_collect() waits for the
+ * recorded events and folds them into per-kernel totals; bto_timing_get()
+ * reads total milliseconds and launch count of the idx-th kernel name
+ * (idx < bto_timing_count()).  Names stay valid until bto_timing_reset(). */
+bto_status bto_timing_enable(int enable);
+bto_status bto_timing_collect(void);
+int bto_timing_count(void);
+bto_status bto_timing_get(int idx, const char **name, int64_t *launches,
+                          double *total_ms);
+void bto_timing_reset(void);
+
+/* Bandwidth probes, used to calibrate hardware byte counters and to
+ * measure the achievable HBM ceiling: dst <- src (copy), *out <- sum(src)
+ * (read; out is one device double, the sum order is fixed), and
+ * a <- b + s*c (triad).  n doubles each. */
+bto_status bto_probe_copy(const double *src, double *dst, int64_t n, hipStream_t stream);
+bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
+bto_status bto_probe_triad(double *a, const double *b, const double *c, double s,
+                           int64_t n, hipStream_t stream);
+size_t bto_probe_read_workspace_bytes(int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTO_H */

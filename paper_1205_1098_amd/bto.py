@@ -1,0 +1,309 @@
+"""Python binding of libbto.so (the C entry points declared in include/bto.h).
+
+Argument marshalling only: every step of every kernel runs in the HIP
+library.  Tensors must be float64 on one ROCm device; vectors contiguous,
+matrices row-major with unit column stride (any row stride >= n is passed
+as the leading dimension).  Outputs and scratch are allocated with torch on
+the inputs' device; work is enqueued on the current torch stream of that
+device and nothing synchronizes.
+
+Importing this module loads the library and raises ImportError when it has
+not been built: there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbto.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1205_1098_amd.build_lib` "
+        "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FUSED, UNFUSED = 0, 1
+FORMS = {"fused": FUSED, "unfused": UNFUSED}
+KERNELS = {"bicgk": 0, "gemver": 1, "atax": 2, "dgemvt": 3, "axpydot": 4, "waxpby": 5, "vadd": 6}
+STATUS = {0: "success", 1: "invalid argument", 2: "illegal operand overlap",
+          3: "workspace too small", 4: "HIP error", 5: "unsupported"}
+
+_i64, _dbl, _ptr, _sz, _int = (ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_int)
+
+_SIGS = {
+    "bto_version": ([], _int),
+    "bto_workspace_bytes": ([_int, _i64, _i64, _int], _sz),
+    "bto_status_string": ([_int], ctypes.c_char_p),
+    "bto_last_error": ([], ctypes.c_char_p),
+    "bto_bicgk": ([_i64, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_gemver": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr,
+                    _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_atax": ([_i64, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_dgemvt": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz,
+                    _int, _ptr], _int),
+    "bto_axpydot": ([_i64, _dbl, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_waxpby": ([_i64, _dbl, _ptr, _dbl, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_vadd": ([_i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_timing_enable": ([_int], _int),
+    "bto_timing_collect": ([], _int),
+    "bto_timing_count": ([], _int),
+    "bto_timing_get": ([_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_i64),
+                        ctypes.POINTER(_dbl)], _int),
+    "bto_timing_reset": ([], None),
+    "bto_probe_copy": ([_ptr, _ptr, _i64, _ptr], _int),
+    "bto_probe_read": ([_ptr, _i64, _ptr, _ptr, _sz, _ptr], _int),
+    "bto_probe_triad": ([_ptr, _ptr, _ptr, _dbl, _i64, _ptr], _int),
+    "bto_probe_read_workspace_bytes": ([_i64], _sz),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+#: names of every function the header declares (the library must export all)
+EXPORTS = tuple(_SIGS)
+
+
+class BtoError(RuntimeError):
+    """A C entry point returned a status other than BTO_SUCCESS."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        raise BtoError(status, _lib.bto_last_error().decode())
+
+
+def version() -> int:
+    return int(_lib.bto_version())
+
+
+def _form(form) -> int:
+    if isinstance(form, int):
+        return form
+    try:
+        return FORMS[form]
+    except KeyError:
+        raise ValueError(f"form must be 'fused' or 'unfused', got {form!r}") from None
+
+
+def workspace_bytes(kernel: str, m: int, n: int, form="fused") -> int:
+    return int(_lib.bto_workspace_bytes(KERNELS[kernel], m, n, _form(form)))
+
+
+def _ptr_of(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(dev: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _check_vec(t: torch.Tensor, name: str, dev) -> None:
+    if t.dtype != torch.float64 or t.dim() != 1:
+        raise TypeError(f"{name}: expected a 1-D float64 tensor")
+    if t.device != dev:
+        raise ValueError(f"{name}: on {t.device}, expected {dev}")
+    if t.numel() > 1 and t.stride(0) != 1:
+        raise ValueError(f"{name}: must be contiguous")
+
+
+def _check_mat(t: torch.Tensor, name: str) -> int:
+    """Validate a row-major matrix view and return its leading dimension."""
+    if t.dtype != torch.float64 or t.dim() != 2:
+        raise TypeError(f"{name}: expected a 2-D float64 tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: must live on a ROCm device")
+    m, n = t.shape
+    if n > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name}: needs unit column stride (row-major)")
+    if m > 1 and t.stride(0) < max(n, 1):
+        raise ValueError(f"{name}: row stride {t.stride(0)} is below the column count {n}")
+    return t.stride(0) if m > 1 else max(n, 1)
+
+
+def _ws(kernel: str, m: int, n: int, form: int, dev, ws):
+    need = workspace_bytes(kernel, m, n, form)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if need else None
+    return ws, need if ws is None else ws.numel()
+
+
+def _empty(n: int, dev):
+    return torch.empty(n, dtype=torch.float64, device=dev)
+
+
+def bicgk(A, p, r, form="fused", q=None, s=None, ws=None):
+    """q = A p ; s = A^T r.  Returns (q, s)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    q = _empty(m, dev) if q is None else q
+    s = _empty(n, dev) if s is None else s
+    for t, nm in ((p, "p"), (r, "r"), (q, "q"), (s, "s")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("bicgk", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_bicgk(m, n, _ptr_of(A), lda, _ptr_of(p), _ptr_of(r), _ptr_of(q),
+                              _ptr_of(s), _ptr_of(ws), wsb, f, _stream(dev)))
+    return q, s
+
+
+def gemver(A, u1, v1, u2, v2, y, z, alpha, beta, form="fused", B=None, x=None, w=None,
+           ws=None):
+    """B = A + u1 v1^T + u2 v2^T ; x = beta B^T y + z ; w = alpha B x.
+
+    Pass ``B=A`` for the in-place update.  Returns (B, x, w)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    B = torch.empty((m, n), dtype=torch.float64, device=dev) if B is None else B
+    ldb = _check_mat(B, "B")
+    x = _empty(n, dev) if x is None else x
+    w = _empty(m, dev) if w is None else w
+    for t, nm in ((u1, "u1"), (v1, "v1"), (u2, "u2"), (v2, "v2"), (y, "y"), (z, "z"),
+                  (x, "x"), (w, "w")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("gemver", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_gemver(m, n, float(alpha), float(beta), _ptr_of(A), lda, _ptr_of(u1),
+                               _ptr_of(v1), _ptr_of(u2), _ptr_of(v2), _ptr_of(y), _ptr_of(z),
+                               _ptr_of(B), ldb, _ptr_of(x), _ptr_of(w), _ptr_of(ws), wsb, f,
+                               _stream(dev)))
+    return B, x, w
+
+
+def atax(A, x, form="fused", y=None, ws=None):
+    """y = A^T (A x)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    y = _empty(n, dev) if y is None else y
+    _check_vec(x, "x", dev)
+    _check_vec(y, "y", dev)
+    f = _form(form)
+    ws, wsb = _ws("atax", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_atax(m, n, _ptr_of(A), lda, _ptr_of(x), _ptr_of(y), _ptr_of(ws), wsb, f,
+                             _stream(dev)))
+    return y
+
+
+def dgemvt(A, y, z, alpha, beta, form="fused", x=None, w=None, ws=None):
+    """x = beta A^T y + z ; w = alpha A x.  Returns (x, w)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    x = _empty(n, dev) if x is None else x
+    w = _empty(m, dev) if w is None else w
+    for t, nm in ((y, "y"), (z, "z"), (x, "x"), (w, "w")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("dgemvt", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_dgemvt(m, n, float(alpha), float(beta), _ptr_of(A), lda, _ptr_of(y),
+                               _ptr_of(z), _ptr_of(x), _ptr_of(w), _ptr_of(ws), wsb, f,
+                               _stream(dev)))
+    return x, w
+
+
+def axpydot(w, v, u, alpha, form="fused", z=None, r=None, ws=None):
+    """z = w - alpha v ; r = z^T u.  Returns (z, r) with r a 1-element tensor."""
+    dev = w.device
+    n = w.numel()
+    z = _empty(n, dev) if z is None else z
+    r = _empty(1, dev) if r is None else r
+    for t, nm in ((w, "w"), (v, "v"), (u, "u"), (z, "z"), (r, "r")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("axpydot", 0, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_axpydot(n, float(alpha), _ptr_of(w), _ptr_of(v), _ptr_of(u), _ptr_of(z),
+                                _ptr_of(r), _ptr_of(ws), wsb, f, _stream(dev)))
+    return z, r
+
+
+def waxpby(x, y, alpha, beta, form="fused", w=None, ws=None):
+    """w = alpha x + beta y."""
+    dev = x.device
+    n = x.numel()
+    w = _empty(n, dev) if w is None else w
+    for t, nm in ((x, "x"), (y, "y"), (w, "w")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("waxpby", 0, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_waxpby(n, float(alpha), _ptr_of(x), float(beta), _ptr_of(y), _ptr_of(w),
+                               _ptr_of(ws), wsb, f, _stream(dev)))
+    return w
+
+
+def vadd(w, y, z, form="fused", x=None, ws=None):
+    """x = (w + y) + z."""
+    dev = w.device
+    n = w.numel()
+    x = _empty(n, dev) if x is None else x
+    for t, nm in ((w, "w"), (y, "y"), (z, "z"), (x, "x")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("vadd", 0, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_vadd(n, _ptr_of(w), _ptr_of(y), _ptr_of(z), _ptr_of(x), _ptr_of(ws),
+                             wsb, f, _stream(dev)))
+    return x
+
+
+# ---- measurement support ---------------------------------------------------
+
+def timing_enable(on: bool = True) -> None:
+    _check(_lib.bto_timing_enable(1 if on else 0))
+
+
+def timing_reset() -> None:
+    _lib.bto_timing_reset()
+
+
+def timing_read() -> dict:
+    """Wait for recorded events; return {kernel name: (launches, total ms)}."""
+    _check(_lib.bto_timing_collect())
+    out = {}
+    for i in range(_lib.bto_timing_count()):
+        name, cnt, ms = ctypes.c_char_p(), _i64(), _dbl()
+        _check(_lib.bto_timing_get(i, ctypes.byref(name), ctypes.byref(cnt), ctypes.byref(ms)))
+        out[name.value.decode()] = (int(cnt.value), float(ms.value))
+    return out
+
+
+def probe_copy(src, dst) -> None:
+    dev = src.device
+    with torch.cuda.device(dev):
+        _check(_lib.bto_probe_copy(_ptr_of(src), _ptr_of(dst), src.numel(), _stream(dev)))
+
+
+def probe_triad(a, b, c, s: float) -> None:
+    dev = a.device
+    with torch.cuda.device(dev):
+        _check(_lib.bto_probe_triad(_ptr_of(a), _ptr_of(b), _ptr_of(c), float(s), a.numel(),
+                                    _stream(dev)))
+
+
+def probe_read(src, out, ws=None) -> None:
+    dev = src.device
+    need = int(_lib.bto_probe_read_workspace_bytes(src.numel()))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if ws is None else ws
+    with torch.cuda.device(dev):
+        _check(_lib.bto_probe_read(_ptr_of(src), src.numel(), _ptr_of(out), _ptr_of(ws),
+                                   ws.numel(), _stream(dev)))

@@ -1,0 +1,752 @@
+// C entry points of libbto: argument checks, workspace layout, and the
+// fused / unfused kernel sequences for the seven Table I kernels.
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "bto.h"
+#include "bto_internal.hpp"
+
+using namespace bto;
+
+namespace {
+
+thread_local std::string t_error;
+
+bto_status fail(bto_status s, const std::string &msg)
+{
+    t_error = msg;
+    return s;
+}
+
+// ---- tile configurations ---------------------------------------------------
+//
+// Each matrix sweep has a slot whose tile shape can be changed at run time
+// (the autotuner does).  Workspace sizes are computed for the most demanding
+// shape any slot may take (kv >= 2, rb >= 32), so they depend on the
+// arguments alone.
+
+enum Slot {
+    SLOT_BICGK_FUSED = 0,
+    SLOT_GEMV_N,
+    SLOT_GEMV_T,
+    SLOT_GER,
+    SLOT_GEMVER_P1,
+    SLOT_GEMVER_P2,
+    SLOT_DGEMVT_P1,
+    SLOT_DGEMVT_P2,
+    SLOT_COUNT
+};
+
+const int kSlotOps[SLOT_COUNT] = {
+    OP_ROWDOT | OP_COLSUM,           // BICGK_FUSED
+    OP_ROWDOT,                       // GEMV_N
+    OP_COLSUM,                       // GEMV_T
+    OP_UPD1,                         // GER
+    OP_UPD1 | OP_UPD2 | OP_COLSUM,   // GEMVER_P1
+    OP_ROWDOT,                       // GEMVER_P2
+    OP_COLSUM,                       // DGEMVT_P1
+    OP_ROWDOT,                       // DGEMVT_P2
+};
+
+const char *const kSlotNames[SLOT_COUNT] = {
+    "bicgk_fused", "gemv_n", "gemv_t", "ger", "gemver_p1", "gemver_p2", "dgemvt_p1", "dgemvt_p2",
+};
+
+std::mutex g_cfg_mu;
+TileCfg g_cfg[SLOT_COUNT] = {
+    {4, 2, 128, 0},  // BICGK_FUSED
+    {4, 4, 128, 0},  // GEMV_N
+    {4, 4, 128, 0},  // GEMV_T
+    {4, 4, 128, 0},  // GER
+    {4, 2, 128, 0},  // GEMVER_P1
+    {4, 4, 128, 1},  // GEMVER_P2: walk B backwards, from what pass 1 left in cache
+    {4, 4, 128, 0},  // DGEMVT_P1
+    {4, 4, 128, 1},  // DGEMVT_P2
+};
+
+constexpr int kMinKv = 2;
+constexpr int kMinRb = 32;
+
+TileCfg cfg_of(Slot s)
+{
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    return g_cfg[s];
+}
+
+int64_t max_ncols(int64_t n) { return ceil_div(n, 128 * kMinKv); }
+int64_t max_nbands(int64_t m) { return ceil_div(m, kMinRb); }
+
+// ---- workspace carving -------------------------------------------------------
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *p) : base(static_cast<char *>(p)) {}
+    double *take(int64_t ndoubles)
+    {
+        double *p = base ? reinterpret_cast<double *>(base + off) : nullptr;
+        off += round256((size_t)(ndoubles > 0 ? ndoubles : 0) * sizeof(double));
+        return p;
+    }
+};
+
+size_t bytes_rowparts(int64_t m, int64_t n) { return round256((size_t)(max_ncols(n) * m) * 8); }
+size_t bytes_colparts(int64_t m, int64_t n) { return round256((size_t)(max_nbands(m) * n) * 8); }
+size_t bytes_vec(int64_t n) { return round256((size_t)n * 8); }
+
+size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
+{
+    switch (k) {
+    case BTO_K_BICGK:
+    case BTO_K_GEMVER:
+    case BTO_K_DGEMVT:
+        return bytes_rowparts(m, n) + bytes_colparts(m, n);
+    case BTO_K_ATAX: {
+        size_t split = bytes_vec(m) + bytes_rowparts(m, n) + bytes_colparts(m, n);
+        if (f == BTO_UNFUSED)
+            return split;
+        int64_t g = atax_rowres_parts(m, n);
+        size_t rowres = round256((size_t)(g * n) * 8);
+        return g > 0 ? rowres : split;
+    }
+    case BTO_K_AXPYDOT:
+        return round256((size_t)dot_parts(n) * 8);
+    case BTO_K_WAXPBY:
+    case BTO_K_VADD:
+        return f == BTO_UNFUSED ? bytes_vec(n) : 0;
+    }
+    return 0;
+}
+
+// ---- argument checks ---------------------------------------------------------
+
+struct Span {
+    const char *name;
+    uintptr_t lo, hi;  // [lo, hi), empty when lo == hi
+    bool out;
+};
+
+Span vspan(const char *name, const void *p, int64_t n, bool out)
+{
+    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return {name, lo, n > 0 ? lo + (uintptr_t)n * 8 : lo, out};
+}
+
+Span mspan(const char *name, const void *p, int64_t m, int64_t n, int64_t ld, bool out)
+{
+    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    if (m <= 0 || n <= 0)
+        return {name, lo, lo, out};
+    return {name, lo, lo + (uintptr_t)((m - 1) * ld + n) * 8, out};
+}
+
+Span wspan(const void *p, size_t bytes)
+{
+    uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+    return {"ws", lo, lo + bytes, true};
+}
+
+struct AllowedAlias {
+    const char *a, *b;
+};
+
+bool name_is(const char *x, const char *y) { return std::string(x) == y; }
+
+// An output may not overlap any other operand, except in an exact alias the
+// entry point allows (same start and same extent).
+bto_status check_aliases(const std::vector<Span> &sp, const std::vector<AllowedAlias> &ok)
+{
+    for (size_t i = 0; i < sp.size(); ++i) {
+        for (size_t j = i + 1; j < sp.size(); ++j) {
+            const Span &a = sp[i], &b = sp[j];
+            if (!a.out && !b.out)
+                continue;
+            if (a.lo == a.hi || b.lo == b.hi)
+                continue;
+            if (a.lo >= b.hi || b.lo >= a.hi)
+                continue;
+            bool exact = a.lo == b.lo && a.hi == b.hi;
+            bool allowed = false;
+            for (const AllowedAlias &al : ok)
+                if ((name_is(al.a, a.name) && name_is(al.b, b.name)) ||
+                    (name_is(al.a, b.name) && name_is(al.b, a.name)))
+                    allowed = true;
+            if (!(exact && allowed))
+                return fail(BTO_ERR_ALIAS, std::string("operand ") + a.name + " overlaps " + b.name);
+        }
+    }
+    return BTO_SUCCESS;
+}
+
+bto_status need(bool cond, const char *what)
+{
+    return cond ? BTO_SUCCESS : fail(BTO_ERR_INVALID_ARG, what);
+}
+
+#define BTO_TRY(expr)                         \
+    do {                                      \
+        bto_status _s = (expr);               \
+        if (_s != BTO_SUCCESS)                \
+            return _s;                        \
+    } while (0)
+
+bto_status check_form(bto_form f)
+{
+    return need(f == BTO_FUSED || f == BTO_UNFUSED, "form must be BTO_FUSED or BTO_UNFUSED");
+}
+
+bto_status check_matrix(int64_t m, int64_t n, const void *A, int64_t lda, const char *name)
+{
+    BTO_TRY(need(m >= 0 && n >= 0, "negative size"));
+    BTO_TRY(need(lda >= (n > 1 ? n : 1), "leading dimension smaller than max(1, n)"));
+    if (m > 0 && n > 0 && A == nullptr)
+        return fail(BTO_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    if (m > (int64_t)65535 * kMinRb)
+        return fail(BTO_ERR_UNSUPPORTED, "more rows than the tile grid can address");
+    return BTO_SUCCESS;
+}
+
+bto_status check_vec(const void *p, int64_t n, const char *name)
+{
+    if (n > 0 && p == nullptr)
+        return fail(BTO_ERR_INVALID_ARG, std::string(name) + " is NULL");
+    return BTO_SUCCESS;
+}
+
+bto_status check_ws(void *ws, size_t have, size_t needed)
+{
+    if (have < needed)
+        return fail(BTO_ERR_WORKSPACE, "workspace too small: need " + std::to_string(needed) +
+                                           " bytes, got " + std::to_string(have));
+    if (needed > 0 && ws == nullptr)
+        return fail(BTO_ERR_INVALID_ARG, "ws is NULL");
+    if (needed > 0 && (reinterpret_cast<uintptr_t>(ws) & 255u))
+        return fail(BTO_ERR_INVALID_ARG, "ws is not 256-byte aligned");
+    return BTO_SUCCESS;
+}
+
+bto_status check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("HIP: ") + hipGetErrorString(e));
+    return BTO_SUCCESS;
+}
+
+TileArgs targs(int64_t m, int64_t n, const double *A, int64_t lda)
+{
+    TileArgs a{};
+    a.m = m;
+    a.n = n;
+    a.A = A;
+    a.lda = lda;
+    a.ldb = lda;
+    return a;
+}
+
+FinishJob fjob(const double *P, int64_t nparts, int64_t len, double scale, const double *add,
+               double *out)
+{
+    return FinishJob{P, nparts, len, scale, add, out};
+}
+
+const FinishJob kNoJob{nullptr, 0, 0, 0.0, nullptr, nullptr};
+
+// out_rows = scale * A xr : tile sweep of A with row dots + finish
+void gemv_n(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *xr,
+            double scale, double *out, double *Prow, hipStream_t st)
+{
+    TileCfg c = cfg_of(s);
+    TileArgs a = targs(m, n, A, lda);
+    a.xr = xr;
+    a.Prow = Prow;
+    launch_tile(kSlotNames[s], OP_ROWDOT, c, a, st);
+    int64_t np = n > 0 ? tile_ncols(c, n) : 0;
+    launch_finish("finish", fjob(Prow, np, m, scale, nullptr, out), kNoJob, st);
+}
+
+// out_cols = scale * A^T yc + add
+void gemv_t(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *yc,
+            double scale, const double *add, double *out, double *Pcol, hipStream_t st)
+{
+    TileCfg c = cfg_of(s);
+    TileArgs a = targs(m, n, A, lda);
+    a.yc = yc;
+    a.Pcol = Pcol;
+    launch_tile(kSlotNames[s], OP_COLSUM, c, a, st);
+    int64_t np = m > 0 ? tile_nbands(c, m) : 0;
+    launch_finish("finish", fjob(Pcol, np, n, scale, add, out), kNoJob, st);
+}
+
+}  // namespace
+
+// ---- timing ------------------------------------------------------------------
+
+namespace {
+
+struct TimingRec {
+    int name;
+    hipEvent_t a, b;
+};
+
+std::mutex g_tmu;
+bool g_tenabled = false;
+std::vector<TimingRec> g_recs;
+std::vector<std::string> g_tnames;
+std::vector<double> g_tms;
+std::vector<int64_t> g_tcount;
+std::vector<hipEvent_t> g_pool;
+thread_local hipEvent_t t_start = nullptr;
+thread_local int t_name = -1;
+
+hipEvent_t take_event()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+int name_index(const char *name)
+{
+    for (size_t i = 0; i < g_tnames.size(); ++i)
+        if (g_tnames[i] == name)
+            return (int)i;
+    g_tnames.emplace_back(name);
+    g_tms.push_back(0.0);
+    g_tcount.push_back(0);
+    return (int)g_tnames.size() - 1;
+}
+
+}  // namespace
+
+namespace bto {
+
+void timing_begin(hipStream_t st, const char *name)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    t_start = nullptr;
+    if (!g_tenabled)
+        return;
+    hipEvent_t e = take_event();
+    if (!e)
+        return;
+    (void)hipEventRecord(e, st);
+    t_start = e;
+    t_name = name_index(name);
+}
+
+void timing_end(hipStream_t st)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (!t_start)
+        return;
+    hipEvent_t e = take_event();
+    if (!e) {
+        g_pool.push_back(t_start);
+        t_start = nullptr;
+        return;
+    }
+    (void)hipEventRecord(e, st);
+    g_recs.push_back({t_name, t_start, e});
+    t_start = nullptr;
+}
+
+}  // namespace bto
+
+extern "C" {
+
+int bto_version(void) { return 100; }
+
+size_t bto_workspace_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
+{
+    if (m < 0 || n < 0 || (f != BTO_FUSED && f != BTO_UNFUSED))
+        return 0;
+    return ws_bytes(k, m, n, f);
+}
+
+const char *bto_status_string(bto_status s)
+{
+    switch (s) {
+    case BTO_SUCCESS: return "success";
+    case BTO_ERR_INVALID_ARG: return "invalid argument";
+    case BTO_ERR_ALIAS: return "illegal operand overlap";
+    case BTO_ERR_WORKSPACE: return "workspace too small";
+    case BTO_ERR_HIP: return "HIP error";
+    case BTO_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char *bto_last_error(void) { return t_error.c_str(); }
+
+// ---- BICGK -------------------------------------------------------------------
+
+bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const double *p,
+                     const double *r, double *q, double *s, void *ws, size_t ws_bytes_,
+                     bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_vec(p, n, "p"));
+    BTO_TRY(check_vec(r, m, "r"));
+    BTO_TRY(check_vec(q, m, "q"));
+    BTO_TRY(check_vec(s, n, "s"));
+    const size_t need_ws = ws_bytes(BTO_K_BICGK, m, n, form);
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("p", p, n, false),
+                           vspan("r", r, m, false), vspan("q", q, m, true),
+                           vspan("s", s, n, true), wspan(ws, need_ws)},
+                          {}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+
+    Carve cv(ws);
+    double *Prow = cv.take(max_ncols(n) * m);
+    double *Pcol = cv.take(max_nbands(m) * n);
+    if (form == BTO_FUSED && m > 0 && n > 0) {
+        TileCfg c = cfg_of(SLOT_BICGK_FUSED);
+        TileArgs a = targs(m, n, A, lda);
+        a.xr = p;
+        a.yc = r;
+        a.Prow = Prow;
+        a.Pcol = Pcol;
+        launch_tile(kSlotNames[SLOT_BICGK_FUSED], OP_ROWDOT | OP_COLSUM, c, a, st);
+        launch_finish("finish", fjob(Prow, tile_ncols(c, n), m, 1.0, nullptr, q),
+                      fjob(Pcol, tile_nbands(c, m), n, 1.0, nullptr, s), st);
+    } else {
+        gemv_n(SLOT_GEMV_N, m, n, A, lda, p, 1.0, q, Prow, st);
+        gemv_t(SLOT_GEMV_T, m, n, A, lda, r, 1.0, nullptr, s, Pcol, st);
+    }
+    return check_launch();
+}
+
+// ---- GEMVER ------------------------------------------------------------------
+
+bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                      int64_t lda, const double *u1, const double *v1, const double *u2,
+                      const double *v2, const double *y, const double *z, double *B,
+                      int64_t ldb, double *x, double *w, void *ws, size_t ws_bytes_,
+                      bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_matrix(m, n, B, ldb, "B"));
+    BTO_TRY(check_vec(u1, m, "u1"));
+    BTO_TRY(check_vec(u2, m, "u2"));
+    BTO_TRY(check_vec(y, m, "y"));
+    BTO_TRY(check_vec(w, m, "w"));
+    BTO_TRY(check_vec(v1, n, "v1"));
+    BTO_TRY(check_vec(v2, n, "v2"));
+    BTO_TRY(check_vec(z, n, "z"));
+    BTO_TRY(check_vec(x, n, "x"));
+    if (B == A && ldb != lda && m > 1 && n > 0)
+        return fail(BTO_ERR_ALIAS, "B == A requires ldb == lda");
+    const size_t need_ws = ws_bytes(BTO_K_GEMVER, m, n, form);
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("u1", u1, m, false),
+                           vspan("v1", v1, n, false), vspan("u2", u2, m, false),
+                           vspan("v2", v2, n, false), vspan("y", y, m, false),
+                           vspan("z", z, n, false), mspan("B", B, m, n, ldb, true),
+                           vspan("x", x, n, true), vspan("w", w, m, true), wspan(ws, need_ws)},
+                          {{"A", "B"}}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+
+    Carve cv(ws);
+    double *Prow = cv.take(max_ncols(n) * m);
+    double *Pcol = cv.take(max_nbands(m) * n);
+    if (form == BTO_FUSED) {
+        // pass 1: B = A + u1 v1^T + u2 v2^T and the partial sums of B^T y
+        TileCfg c = cfg_of(SLOT_GEMVER_P1);
+        TileArgs a = targs(m, n, A, lda);
+        a.B = B;
+        a.ldb = ldb;
+        a.u1 = u1;
+        a.v1 = v1;
+        a.u2 = u2;
+        a.v2 = v2;
+        a.yc = y;
+        a.Pcol = Pcol;
+        launch_tile(kSlotNames[SLOT_GEMVER_P1], OP_UPD1 | OP_UPD2 | OP_COLSUM, c, a, st);
+        const int64_t np = (m > 0 && n > 0) ? tile_nbands(c, m) : 0;
+        launch_finish("finish", fjob(Pcol, np, n, beta, z, x), kNoJob, st);
+        // pass 2: w = alpha B x
+        gemv_n(SLOT_GEMVER_P2, m, n, B, ldb, x, alpha, w, Prow, st);
+    } else {
+        TileCfg c = cfg_of(SLOT_GER);
+        TileArgs a = targs(m, n, A, lda);
+        a.B = B;
+        a.ldb = ldb;
+        a.u1 = u1;
+        a.v1 = v1;
+        launch_tile("ger", OP_UPD1, c, a, st);     // B = A + u1 v1^T
+        a = targs(m, n, B, ldb);
+        a.B = B;
+        a.ldb = ldb;
+        a.u1 = u2;
+        a.v1 = v2;
+        launch_tile("ger", OP_UPD1, c, a, st);     // B = B + u2 v2^T
+        gemv_t(SLOT_GEMV_T, m, n, B, ldb, y, beta, z, x, Pcol, st);
+        gemv_n(SLOT_GEMV_N, m, n, B, ldb, x, alpha, w, Prow, st);
+    }
+    return check_launch();
+}
+
+// ---- ATAX --------------------------------------------------------------------
+
+bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                    double *y, void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(y, n, "y"));
+    const size_t need_ws = ws_bytes(BTO_K_ATAX, m, n, form);
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("x", x, n, false),
+                           vspan("y", y, n, true), wspan(ws, need_ws)},
+                          {}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+
+    const int64_t G = form == BTO_FUSED ? atax_rowres_parts(m, n) : 0;
+    Carve cv(ws);
+    if (G > 0) {
+        double *P = cv.take(G * n);
+        launch_atax_rowres(m, n, A, lda, x, P, st);
+        launch_finish("finish", fjob(P, G, n, 1.0, nullptr, y), kNoJob, st);
+    } else {
+        double *t = cv.take(m);
+        double *Prow = cv.take(max_ncols(n) * m);
+        double *Pcol = cv.take(max_nbands(m) * n);
+        gemv_n(SLOT_GEMV_N, m, n, A, lda, x, 1.0, t, Prow, st);
+        gemv_t(SLOT_GEMV_T, m, n, A, lda, t, 1.0, nullptr, y, Pcol, st);
+    }
+    return check_launch();
+}
+
+// ---- DGEMVT ------------------------------------------------------------------
+
+bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                      int64_t lda, const double *y, const double *z, double *x, double *w,
+                      void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_vec(y, m, "y"));
+    BTO_TRY(check_vec(w, m, "w"));
+    BTO_TRY(check_vec(z, n, "z"));
+    BTO_TRY(check_vec(x, n, "x"));
+    const size_t need_ws = ws_bytes(BTO_K_DGEMVT, m, n, form);
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("y", y, m, false),
+                           vspan("z", z, n, false), vspan("x", x, n, true),
+                           vspan("w", w, m, true), wspan(ws, need_ws)},
+                          {}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+
+    Carve cv(ws);
+    double *Prow = cv.take(max_ncols(n) * m);
+    double *Pcol = cv.take(max_nbands(m) * n);
+    if (form == BTO_FUSED) {
+        gemv_t(SLOT_DGEMVT_P1, m, n, A, lda, y, beta, z, x, Pcol, st);
+        gemv_n(SLOT_DGEMVT_P2, m, n, A, lda, x, alpha, w, Prow, st);
+    } else {
+        gemv_t(SLOT_GEMV_T, m, n, A, lda, y, beta, z, x, Pcol, st);
+        gemv_n(SLOT_GEMV_N, m, n, A, lda, x, alpha, w, Prow, st);
+    }
+    return check_launch();
+}
+
+// ---- AXPYDOT -----------------------------------------------------------------
+
+bto_status bto_axpydot(int64_t n, double alpha, const double *w, const double *v,
+                       const double *u, double *z, double *r, void *ws, size_t ws_bytes_,
+                       bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(w, n, "w"));
+    BTO_TRY(check_vec(v, n, "v"));
+    BTO_TRY(check_vec(u, n, "u"));
+    BTO_TRY(check_vec(z, n, "z"));
+    BTO_TRY(check_vec(r, 1, "r"));
+    const size_t need_ws = ws_bytes(BTO_K_AXPYDOT, 0, n, form);
+    BTO_TRY(check_aliases({vspan("w", w, n, false), vspan("v", v, n, false),
+                           vspan("u", u, n, false), vspan("z", z, n, true),
+                           vspan("r", r, 1, true), wspan(ws, need_ws)},
+                          {{"z", "w"}}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+
+    double *parts = Carve(ws).take(dot_parts(n));
+    if (form == BTO_FUSED) {
+        launch_dot(true, n, alpha, w, v, u, z, parts, r, st);
+    } else {
+        launch_ew(EW_AXMY, n, w, v, nullptr, alpha, 0.0, z, st);  // z = w - alpha v
+        launch_dot(false, n, 0.0, z, nullptr, u, nullptr, parts, r, st);
+    }
+    return check_launch();
+}
+
+// ---- WAXPBY ------------------------------------------------------------------
+
+bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta, const double *y,
+                      double *w, void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(y, n, "y"));
+    BTO_TRY(check_vec(w, n, "w"));
+    const size_t need_ws = ws_bytes(BTO_K_WAXPBY, 0, n, form);
+    BTO_TRY(check_aliases({vspan("x", x, n, false), vspan("y", y, n, false),
+                           vspan("w", w, n, true), wspan(ws, need_ws)},
+                          {{"w", "x"}, {"w", "y"}}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    if (form == BTO_FUSED) {
+        launch_ew(EW_WAXPBY, n, x, y, nullptr, alpha, beta, w, st);
+    } else {
+        double *t = Carve(ws).take(n);
+        launch_ew(EW_SCAL, n, x, nullptr, nullptr, alpha, 0.0, t, st);  // t = alpha x
+        launch_ew(EW_AXPY, n, t, y, nullptr, beta, 0.0, w, st);         // w = t + beta y
+    }
+    return check_launch();
+}
+
+// ---- VADD --------------------------------------------------------------------
+
+bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z, double *x,
+                    void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(w, n, "w"));
+    BTO_TRY(check_vec(y, n, "y"));
+    BTO_TRY(check_vec(z, n, "z"));
+    BTO_TRY(check_vec(x, n, "x"));
+    const size_t need_ws = ws_bytes(BTO_K_VADD, 0, n, form);
+    BTO_TRY(check_aliases({vspan("w", w, n, false), vspan("y", y, n, false),
+                           vspan("z", z, n, false), vspan("x", x, n, true), wspan(ws, need_ws)},
+                          {{"x", "w"}, {"x", "y"}, {"x", "z"}}));
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    if (form == BTO_FUSED) {
+        launch_ew(EW_VADD3, n, w, y, z, 0.0, 0.0, x, st);
+    } else {
+        double *t = Carve(ws).take(n);
+        launch_ew(EW_ADD2, n, w, y, nullptr, 0.0, 0.0, t, st);  // t = w + y
+        launch_ew(EW_ADD2, n, t, z, nullptr, 0.0, 0.0, x, st);  // x = t + z
+    }
+    return check_launch();
+}
+
+// ---- timing ------------------------------------------------------------------
+
+bto_status bto_timing_enable(int enable)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_tenabled = enable != 0;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_timing_collect(void)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    bto_status st = BTO_SUCCESS;
+    for (const TimingRec &r : g_recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            st = fail(BTO_ERR_HIP, "event timing failed");
+        } else {
+            g_tms[r.name] += ms;
+            g_tcount[r.name] += 1;
+        }
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    return st;
+}
+
+int bto_timing_count(void)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    return (int)g_tnames.size();
+}
+
+bto_status bto_timing_get(int idx, const char **name, int64_t *launches, double *total_ms)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    if (idx < 0 || idx >= (int)g_tnames.size())
+        return fail(BTO_ERR_INVALID_ARG, "timing index out of range");
+    if (name) *name = g_tnames[idx].c_str();
+    if (launches) *launches = g_tcount[idx];
+    if (total_ms) *total_ms = g_tms[idx];
+    return BTO_SUCCESS;
+}
+
+void bto_timing_reset(void)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    for (const TimingRec &r : g_recs) {
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+    g_tnames.clear();
+    g_tms.clear();
+    g_tcount.clear();
+}
+
+// ---- probes --------------------------------------------------------------------
+
+bto_status bto_probe_copy(const double *src, double *dst, int64_t n, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(src, n, "src"));
+    BTO_TRY(check_vec(dst, n, "dst"));
+    BTO_TRY(check_aliases({vspan("src", src, n, false), vspan("dst", dst, n, true)}, {}));
+    launch_copy(n, src, dst, st);
+    return check_launch();
+}
+
+size_t bto_probe_read_workspace_bytes(int64_t n)
+{
+    return n < 0 ? 0 : round256((size_t)dot_parts(n) * 8);
+}
+
+bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws, size_t ws_bytes_,
+                          hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(src, n, "src"));
+    BTO_TRY(check_vec(out, 1, "out"));
+    BTO_TRY(check_ws(ws, ws_bytes_, bto_probe_read_workspace_bytes(n)));
+    // sum of squares: both operands are the same stream, read once from HBM
+    launch_dot(false, n, 0.0, src, nullptr, src, nullptr, static_cast<double *>(ws), out, st);
+    return check_launch();
+}
+
+bto_status bto_probe_triad(double *a, const double *b, const double *c, double s, int64_t n,
+                           hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(a, n, "a"));
+    BTO_TRY(check_vec(b, n, "b"));
+    BTO_TRY(check_vec(c, n, "c"));
+    BTO_TRY(check_aliases({vspan("a", a, n, true), vspan("b", b, n, false), vspan("c", c, n, false)}, {}));
+    launch_triad(n, a, b, c, s, st);
+    return check_launch();
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Host-side declarations shared by the translation units of libbto.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace bto {
+
+// Per-kernel event timing (enabled through bto_timing_enable).
+void timing_begin(hipStream_t st, const char *name);
+void timing_end(hipStream_t st);
+
+// Launch `kernel` unless the grid is empty, bracketed by timing events.
+template <typename... KArgs, typename... Args>
+inline void launch(const char *name, void (*kernel)(KArgs...), dim3 grid, dim3 block,
+                   hipStream_t st, Args... args)
+{
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0)
+        return;
+    timing_begin(st, name);
+    kernel<<<grid, block, 0, st>>>(static_cast<KArgs>(args)...);
+    timing_end(st);
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+inline bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// Round a byte count up to the 256-byte granule used to carve workspaces.
+inline size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// ---- vector kernels (bto_vec.hip) ---------------------------------------
+
+enum EwOp {
+    EW_VADD3,    // out = (a + b) + c
+    EW_ADD2,     // out = a + b
+    EW_WAXPBY,   // out = s0*a + s1*b
+    EW_SCAL,     // out = s0*a
+    EW_AXPY,     // out = a + s0*b
+    EW_AXMY,     // out = a - s0*b
+};
+
+void launch_ew(EwOp op, int64_t n, const double *a, const double *b, const double *c,
+               double s0, double s1, double *out, hipStream_t st);
+
+// Number of partial sums the deterministic dot product of length n uses.
+int64_t dot_parts(int64_t n);
+
+// Dot partials: fused (z = w - alpha*v stored, partials of z.u) or plain
+// (partials of w.u; v, z unused), then the fixed-order finish into *r.
+void launch_dot(bool fused_axpy, int64_t n, double alpha, const double *w, const double *v,
+                const double *u, double *z, double *parts, double *r, hipStream_t st);
+
+void launch_copy(int64_t n, const double *src, double *dst, hipStream_t st);
+void launch_triad(int64_t n, double *a, const double *b, const double *c, double s,
+                  hipStream_t st);
+
+// ---- matrix kernels (bto_mat.hip) ---------------------------------------
+
+enum TileOps {
+    OP_ROWDOT = 1,  // partial row dots with xr, per column tile
+    OP_COLSUM = 2,  // partial column sums weighted by yc, per row band
+    OP_UPD1 = 4,    // B = A + u1 v1^T  (stored)
+    OP_UPD2 = 8,    // ... + u2 v2^T    (with OP_UPD1)
+};
+
+struct TileCfg {
+    int kv;    // 16-byte column pairs per lane: a column tile is 128*kv wide
+    int ru;    // rows loaded ahead per wave
+    int rb;    // rows per workgroup (4 waves); multiple of 4, at most 256
+    int rev;   // walk row bands in reverse order
+};
+
+struct TileArgs {
+    int64_t m, n, lda, ldb;
+    const double *A;
+    double *B;
+    const double *xr;  // length n, row-dot weights
+    const double *yc;  // length m, column-sum weights
+    const double *u1, *v1, *u2, *v2;
+    double *Prow;      // [ncol_tiles][m]
+    double *Pcol;      // [nrow_bands][n]
+};
+
+inline int64_t tile_ncols(const TileCfg &c, int64_t n) { return ceil_div(n, 128 * c.kv); }
+inline int64_t tile_nbands(const TileCfg &c, int64_t m) { return ceil_div(m, c.rb); }
+
+bool tile_cfg_supported(int ops, const TileCfg &c);
+void launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st);
+
+// out[i] = scale * sum_k P[k*len + i] (+ add[i]) for two independent jobs in
+// one launch (the second may have len 0).
+struct FinishJob {
+    const double *P;
+    int64_t nparts, len;
+    double scale;
+    const double *add;
+    double *out;
+};
+void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
+
+// Row-resident ATAX: each workgroup keeps one row of A on chip at a time.
+int64_t atax_rowres_parts(int64_t m, int64_t n);   // 0 when n is too wide
+void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                        double *P, hipStream_t st);
+
+}  // namespace bto

@@ -25,6 +25,9 @@ can be produced without the ones before it.
 
 from __future__ import annotations
 
+import concurrent.futures as cf
+import os
+
 import numpy as np
 
 GOLDEN = np.uint64(0x9E3779B97F4A7C15)
@@ -64,47 +67,80 @@ def stream_id(config: int, operand: int, instance: int = 0) -> int:
     return (instance << 16) | ((config & 0xFF) << 8) | (operand & 0xFF)
 
 
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _raw_into(state: np.uint64, out: np.ndarray, offset: int) -> None:
+    k = np.arange(offset + 1, offset + out.shape[0] + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        out[:] = _mix64(state + k * GOLDEN)
+
+
+def _convert(x: np.ndarray, kind: str, lo: int, hi: int) -> np.ndarray:
+    x = x >> np.uint64(11)
+    if kind == "uniform":
+        return x.astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
+    if kind == "int":
+        span = np.uint64(hi - lo + 1)
+        return ((x * span) >> np.uint64(53)).astype(np.int64).astype(np.float64) + lo
+    if kind == "unit":
+        return x.astype(np.float64) * (2.0 ** -53)
+    raise ValueError(f"unknown kind {kind!r}")
+
+
+def _fill(seed: int, stream: int, out: np.ndarray, offset: int, kind: str,
+          lo: int = -2, hi: int = 2) -> None:
+    """out[t] = element offset+t of the stream, converted to ``kind``; the
+    chunks are independent, so they are filled by a thread pool (numpy
+    releases the GIL inside its ufuncs)."""
+    state = np.uint64(stream_state(seed, stream))
+    count = out.shape[0]
+
+    def one(a: int) -> None:
+        b = min(count, a + _CHUNK)
+        tmp = np.empty(b - a, dtype=np.uint64)
+        _raw_into(state, tmp, offset + a)
+        out[a:b] = _convert(tmp, kind, lo, hi)
+
+    starts = range(0, count, _CHUNK)
+    if count <= 2 * _CHUNK:
+        for a in starts:
+            one(a)
+    else:
+        with cf.ThreadPoolExecutor(_workers()) as ex:
+            list(ex.map(one, starts))
+
+
 def raw(seed: int, stream: int, count: int, offset: int = 0) -> np.ndarray:
     """``count`` raw 64-bit outputs of a stream, starting at element ``offset``."""
-    state = np.uint64(stream_state(seed, stream))
     out = np.empty(count, dtype=np.uint64)
-    with np.errstate(over="ignore"):
-        for lo in range(0, count, _CHUNK):
-            hi = min(count, lo + _CHUNK)
-            k = np.arange(offset + lo + 1, offset + hi + 1, dtype=np.uint64)
-            out[lo:hi] = _mix64(state + k * GOLDEN)
+    _raw_into(np.uint64(stream_state(seed, stream)), out, offset)
     return out
 
 
 def uniform(seed: int, stream: int, count: int, offset: int = 0) -> np.ndarray:
     """Doubles uniform on [-1, 1), exact multiples of 2**-52."""
     out = np.empty(count, dtype=np.float64)
-    for lo in range(0, count, _CHUNK):
-        hi = min(count, lo + _CHUNK)
-        x = raw(seed, stream, hi - lo, offset + lo) >> np.uint64(11)
-        out[lo:hi] = x.astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
+    _fill(seed, stream, out, offset, "uniform")
     return out
 
 
 def small_ints(seed: int, stream: int, count: int, lo: int = -2, hi: int = 2,
                offset: int = 0) -> np.ndarray:
     """Integers uniform on [lo, hi], returned as doubles."""
-    span = np.uint64(hi - lo + 1)
     out = np.empty(count, dtype=np.float64)
-    for a in range(0, count, _CHUNK):
-        b = min(count, a + _CHUNK)
-        x = raw(seed, stream, b - a, offset + a) >> np.uint64(11)
-        out[a:b] = ((x * span) >> np.uint64(53)).astype(np.int64) + lo
+    _fill(seed, stream, out, offset, "int", lo, hi)
     return out
 
 
 def vector(seed: int, stream: int, n: int, kind: str = "uniform") -> np.ndarray:
     """A length-n vector of the given kind ("uniform" or "int")."""
-    if kind == "uniform":
-        return uniform(seed, stream, n)
-    if kind == "int":
-        return small_ints(seed, stream, n)
-    raise ValueError(f"unknown kind {kind!r}")
+    if kind not in ("uniform", "int"):
+        raise ValueError(f"unknown kind {kind!r}")
+    out = np.empty(n, dtype=np.float64)
+    _fill(seed, stream, out, 0, kind)
+    return out
 
 
 def matrix(seed: int, stream: int, m: int, n: int, lda: int | None = None,
@@ -118,30 +154,28 @@ def matrix(seed: int, stream: int, m: int, n: int, lda: int | None = None,
     lda = n if lda is None else lda
     if lda < n:
         raise ValueError("lda < n")
+    if kind not in ("uniform", "int"):
+        raise ValueError(f"unknown kind {kind!r}")
+    if lda == n:
+        a = np.empty((m, n), dtype=np.float64)
+        _fill(seed, stream, a.reshape(-1), 0, kind)
+        return a
     a = np.full((m, lda), pad_value, dtype=np.float64)
-    rows_per_chunk = max(1, _CHUNK // max(n, 1))
-    for i0 in range(0, m, rows_per_chunk):
-        i1 = min(m, i0 + rows_per_chunk)
-        cnt = (i1 - i0) * n
-        if cnt == 0:
-            continue
-        if kind == "uniform":
-            blk = uniform(seed, stream, cnt, offset=i0 * n)
-        elif kind == "int":
-            blk = small_ints(seed, stream, cnt, offset=i0 * n)
-        else:
-            raise ValueError(f"unknown kind {kind!r}")
-        a[i0:i1, :n] = blk.reshape(i1 - i0, n)
+    dense = np.empty(m * n, dtype=np.float64)
+    _fill(seed, stream, dense, 0, kind)
+    a[:, :n] = dense.reshape(m, n)
     return a
 
 
 def log_uniform_int(seed: int, stream: int, count: int, lo: int, hi: int) -> np.ndarray:
     """Integers n = min(hi, floor(lo * (hi/lo)**U)) with U uniform on [0, 1)."""
-    u = (raw(seed, stream, count) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    u = unit_uniform(seed, stream, count)
     n = np.floor(lo * np.power(hi / lo, u)).astype(np.int64)
     return np.minimum(n, hi)
 
 
 def unit_uniform(seed: int, stream: int, count: int) -> np.ndarray:
     """Doubles uniform on [0, 1)."""
-    return (raw(seed, stream, count) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+    out = np.empty(count, dtype=np.float64)
+    _fill(seed, stream, out, 0, "unit")
+    return out

@@ -1,0 +1,112 @@
+"""Host-side checks of the C boundary that need no GPU: the library loads,
+exports every function include/bto.h declares, sizes workspaces, and rejects
+bad arguments before it enqueues anything (no kernel is launched here)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bto.h")
+
+
+@pytest.fixture(scope="module")
+def bto():
+    from paper_1205_1098_amd import bto as b
+
+    return b
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bto_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(bto):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = ctypes.CDLL(bto.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), f"libbto.so does not export {name}"
+    assert set(names) == set(bto.EXPORTS)
+
+
+def test_version_and_status_strings(bto):
+    assert bto.version() >= 100
+    for s in range(6):
+        assert bto._lib.bto_status_string(s).decode()
+
+
+def test_workspace_sizes(bto):
+    n = 16384
+    for k in ("bicgk", "gemver", "dgemvt"):
+        b = bto.workspace_bytes(k, n, n, "fused")
+        # partial sums stay a few percent of the 2 GiB matrix
+        assert 0 < b < 0.05 * n * n * 8
+        assert b % 256 == 0
+    assert bto.workspace_bytes("atax", n, n, "fused") < 0.05 * n * n * 8
+    assert bto.workspace_bytes("waxpby", 0, 1 << 26, "fused") == 0
+    assert bto.workspace_bytes("vadd", 0, 1 << 26, "unfused") == (1 << 26) * 8
+    assert bto.workspace_bytes("axpydot", 0, 0, "fused") == 0
+    assert bto.workspace_bytes("bicgk", -1, 5, "fused") == 0
+
+
+FAKE = 1 << 40          # never dereferenced: every case below fails its checks
+
+
+def _call_bicgk(bto, m, n, A, lda, p, r, q, s, ws, wsb, form=0):
+    return bto._lib.bto_bicgk(m, n, A, lda, p, r, q, s, ws, wsb, form, None)
+
+
+def test_invalid_arguments(bto):
+    INV = 1
+    v = ctypes.c_void_p
+    assert _call_bicgk(bto, -1, 4, v(FAKE), 4, v(FAKE), v(FAKE), v(FAKE), v(FAKE), None, 0) == INV
+    assert _call_bicgk(bto, 4, 4, v(FAKE), 3, v(FAKE), v(FAKE), v(FAKE), v(FAKE), None, 0) == INV
+    assert _call_bicgk(bto, 4, 4, None, 4, v(FAKE), v(FAKE), v(FAKE), v(FAKE), None, 0) == INV
+    assert "NULL" in bto._lib.bto_last_error().decode()
+    assert _call_bicgk(bto, 4, 4, v(FAKE), 4, v(FAKE), v(FAKE), v(FAKE), v(FAKE), None, 0,
+                       form=7) == INV
+
+
+def test_alias_detection(bto):
+    ALIAS = 2
+    v = ctypes.c_void_p
+    m = n = 64
+    A = FAKE
+    p, r = FAKE + (1 << 20), FAKE + (2 << 20)
+    q, s = FAKE + (3 << 20), FAKE + (4 << 20)
+    ws = FAKE + (8 << 20)
+    wsb = bto.workspace_bytes("bicgk", m, n)
+    # q overlapping A
+    assert _call_bicgk(bto, m, n, v(A), n, v(p), v(r), v(A + 64), v(s), v(ws), wsb) == ALIAS
+    # q and s overlapping each other
+    assert _call_bicgk(bto, m, n, v(A), n, v(p), v(r), v(q), v(q + 8), v(ws), wsb) == ALIAS
+    # workspace overlapping an input
+    assert _call_bicgk(bto, m, n, v(A), n, v(p), v(r), v(q), v(s), v(A), wsb) == ALIAS
+    # GEMVER: B == A is allowed only with ldb == lda
+    lib = bto._lib
+    wsg = bto.workspace_bytes("gemver", m, n)
+    vec = [v(FAKE + (k << 20)) for k in range(1, 11)]
+    st = lib.bto_gemver(m, n, 1.5, 0.7, v(A), n + 2, *vec[:6], v(A), n, vec[6], vec[7],
+                        v(ws), wsg, 0, None)
+    assert st == ALIAS
+    # VADD: partial overlap of x with w is illegal
+    st = lib.bto_vadd(100, v(FAKE), v(FAKE + (1 << 20)), v(FAKE + (2 << 20)), v(FAKE + 8),
+                      None, 0, 0, None)
+    assert st == ALIAS
+
+
+def test_workspace_too_small(bto):
+    WS = 3
+    v = ctypes.c_void_p
+    m = n = 256
+    wsb = bto.workspace_bytes("bicgk", m, n)
+    base = FAKE
+    st = _call_bicgk(bto, m, n, v(base), n, v(base + (1 << 20)), v(base + (2 << 20)),
+                     v(base + (3 << 20)), v(base + (4 << 20)), v(base + (8 << 20)), wsb - 1)
+    assert st == WS
+    assert "workspace" in bto._lib.bto_last_error().decode()

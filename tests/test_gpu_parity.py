@@ -1,0 +1,387 @@
+"""GPU parity: every kernel, both forms, against the CPU oracle.
+
+Tolerance: normwise relative error max|gpu - oracle| / max|oracle| <= 1e-12
+per output array (absolute when the oracle output is all zero).  With
+integer-valued data every intermediate is an exact integer below 2**53, so
+both forms must then equal the oracle bit for bit, whatever the summation
+order.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_1098_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+SEED = synth.SEED
+FORMS = ("fused", "unfused")
+ALPHA, BETA = 1.5, 0.7
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1205_1098_amd import bto
+
+    return torch, bto, torch.device("cuda:0")
+
+
+def relerr(got, ref):
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    assert got.shape == ref.shape
+    if ref.size == 0:
+        return 0.0
+    num = float(np.max(np.abs(got - ref)))
+    den = float(np.max(np.abs(ref)))
+    return num / den if den > 0 else num
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def dmat(torch, dev, A, n):
+    """Device copy of an (m, lda) host array, returned as an (m, n) view."""
+    full = torch.from_numpy(np.ascontiguousarray(A)).to(dev)
+    return full[:, :n]
+
+
+def dvec(torch, dev, v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+
+
+def inputs(kind, m, n, lda, cfg, kern):
+    """Host inputs of one case: A (m, lda) and the vectors in ABI order."""
+    sid = lambda op: synth.stream_id(cfg, op, kern)
+    A = synth.matrix(SEED, sid(0), m, n, lda=lda, kind=kind)
+    vec = lambda op, k: synth.vector(SEED, sid(op), k, kind)
+    return A, vec
+
+
+MSHAPES = [(1, 1), (1, 7), (7, 1), (2, 3), (63, 64), (64, 63), (65, 127), (127, 65),
+           (256, 256), (512, 512), (513, 1000), (1000, 513), (300, 4097), (4097, 300),
+           (2047, 2049)]
+LDA_PAD = [0, 3, 8]
+
+
+def _lda(n, pad):
+    return max(n, 1) + pad
+
+
+# ---- matrix kernels at small and ragged sizes ------------------------------
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_bicgk(env, m, n, pad, form):
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 1, 0)
+    p, r = vec(1, n), vec(2, m)
+    q_ref, s_ref = oracle.bicgk(A, p, r, lda=lda)
+    q, s = bto.bicgk(dmat(torch, dev, A, n), dvec(torch, dev, p), dvec(torch, dev, r), form=form)
+    assert relerr(host(q), q_ref) <= TOL
+    assert relerr(host(s), s_ref) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_gemver(env, m, n, pad, form):
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 2, 0)
+    u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+    B_ref, x_ref, w_ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)
+    d = lambda a: dvec(torch, dev, a)
+    B, x, w = bto.gemver(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y), d(z),
+                         ALPHA, BETA, form=form)
+    assert relerr(host(B), B_ref) <= TOL
+    assert relerr(host(x), x_ref) <= TOL
+    assert relerr(host(w), w_ref) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 127), (513, 1000), (2047, 2049)])
+def test_gemver_in_place(env, m, n, form):
+    """B == A (same array, same leading dimension) gives the out-of-place result,
+    and leaves the row padding untouched."""
+    torch, bto, dev = env
+    lda = n + 5
+    A, vec = inputs("uniform", m, n, lda, 2, 1)
+    u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+    B_ref, x_ref, w_ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)
+    full = torch.from_numpy(A).to(dev)
+    Ad = full[:, :n]
+    d = lambda a: dvec(torch, dev, a)
+    B, x, w = bto.gemver(Ad, d(u1), d(v1), d(u2), d(v2), d(y), d(z), ALPHA, BETA, form=form,
+                         B=Ad)
+    assert B.data_ptr() == Ad.data_ptr()
+    assert relerr(host(Ad), B_ref) <= TOL
+    assert relerr(host(x), x_ref) <= TOL and relerr(host(w), w_ref) <= TOL
+    assert np.all(np.isnan(host(full)[:, n:]))
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES + [(3000, 8192), (700, 8193), (300, 16384)])
+def test_atax(env, m, n, pad, form):
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 3, 0)
+    x = vec(1, n)
+    y_ref = oracle.atax(A, x, lda=lda)
+    y = bto.atax(dmat(torch, dev, A, n), dvec(torch, dev, x), form=form)
+    assert relerr(host(y), y_ref) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_atax_wider_than_one_row_on_chip(env, form):
+    """n above 16384 backs off to the two-pass form."""
+    torch, bto, dev = env
+    m, n = 40, 16385
+    A, vec = inputs("uniform", m, n, n, 3, 1)
+    x = vec(1, n)
+    y = bto.atax(dmat(torch, dev, A, n), dvec(torch, dev, x), form=form)
+    assert relerr(host(y), oracle.atax(A, x)) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_dgemvt(env, m, n, pad, form):
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 4, 0)
+    y, z = vec(1, m), vec(2, n)
+    x_ref, w_ref = oracle.dgemvt(A, y, z, ALPHA, BETA, lda=lda)
+    x, w = bto.dgemvt(dmat(torch, dev, A, n), dvec(torch, dev, y), dvec(torch, dev, z),
+                      ALPHA, BETA, form=form)
+    assert relerr(host(x), x_ref) <= TOL
+    assert relerr(host(w), w_ref) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("m,n", [(0, 5), (5, 0), (0, 0)])
+def test_empty_matrix_extents(env, m, n, form):
+    torch, bto, dev = env
+    A = torch.zeros((m, n), dtype=torch.float64, device=dev)
+    rnd = lambda k, s: dvec(torch, dev, synth.uniform(SEED, s, k))
+    q, s = bto.bicgk(A, rnd(n, 1), rnd(m, 2), form=form)
+    assert np.all(host(q) == 0) and np.all(host(s) == 0)
+    z = rnd(n, 3)
+    B, x, w = bto.gemver(A, rnd(m, 4), rnd(n, 5), rnd(m, 6), rnd(n, 7), rnd(m, 8), z,
+                         ALPHA, BETA, form=form)
+    assert np.array_equal(host(x), host(z)) and np.all(host(w) == 0)
+    x2, w2 = bto.dgemvt(A, rnd(m, 9), z, ALPHA, BETA, form=form)
+    assert np.array_equal(host(x2), host(z)) and np.all(host(w2) == 0)
+    assert np.all(host(bto.atax(A, rnd(n, 10), form=form)) == 0)
+
+
+# ---- vector kernels ---------------------------------------------------------
+
+VSIZES = [0, 1, 2, 3, 127, 511, 512, 513, 4095, 4096, 4097, 100003, (1 << 20) + 1]
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n", VSIZES)
+def test_vector_kernels(env, n, form):
+    torch, bto, dev = env
+    v = lambda op: synth.uniform(SEED, synth.stream_id(5, op), n)
+    d = lambda a: dvec(torch, dev, a)
+    w, vv, u = v(0), v(1), v(2)
+    z_ref, r_ref = oracle.axpydot(w, vv, u, ALPHA)
+    z, r = bto.axpydot(d(w), d(vv), d(u), ALPHA, form=form)
+    assert relerr(host(z), z_ref) <= TOL
+    assert relerr(host(r), np.array([r_ref])) <= TOL
+    assert relerr(host(bto.waxpby(d(w), d(vv), ALPHA, BETA, form=form)),
+                  oracle.waxpby(w, vv, ALPHA, BETA)) <= TOL
+    assert relerr(host(bto.vadd(d(w), d(vv), d(u), form=form)), oracle.vadd(w, vv, u)) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("n", [1, 2, 4097, 100003])
+def test_vector_kernels_misaligned(env, n, form):
+    """Views starting one element into an allocation (8-byte, not 16-byte,
+    aligned) take the scalar path and give the same results."""
+    torch, bto, dev = env
+    v = lambda op: synth.uniform(SEED, synth.stream_id(5, op, 1), n + 1)
+    w, vv, u = v(0), v(1), v(2)
+    d = lambda a: dvec(torch, dev, a)[1:]
+    z_ref, r_ref = oracle.axpydot(w[1:], vv[1:], u[1:], ALPHA)
+    zbuf = torch.empty(n + 1, dtype=torch.float64, device=dev)
+    z, r = bto.axpydot(d(w), d(vv), d(u), ALPHA, form=form, z=zbuf[1:])
+    assert relerr(host(z), z_ref) <= TOL and relerr(host(r), np.array([r_ref])) <= TOL
+    wbuf = torch.empty(n + 1, dtype=torch.float64, device=dev)
+    out = bto.waxpby(d(w), d(vv), ALPHA, BETA, form=form, w=wbuf[1:])
+    assert relerr(host(out), oracle.waxpby(w[1:], vv[1:], ALPHA, BETA)) <= TOL
+    out = bto.vadd(d(w), d(vv), d(u), form=form, x=wbuf[1:])
+    assert relerr(host(out), oracle.vadd(w[1:], vv[1:], u[1:])) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_vector_exact_aliases(env, form):
+    torch, bto, dev = env
+    n = 100003
+    v = lambda op: synth.uniform(SEED, synth.stream_id(5, op, 2), n)
+    w, vv, u = v(0), v(1), v(2)
+    d = lambda a: dvec(torch, dev, a)
+    wd = d(w)
+    z, r = bto.axpydot(wd, d(vv), d(u), ALPHA, form=form, z=wd)          # z == w
+    z_ref, r_ref = oracle.axpydot(w, vv, u, ALPHA)
+    assert relerr(host(wd), z_ref) <= TOL and relerr(host(r), np.array([r_ref])) <= TOL
+    for which in ("x", "y"):
+        xd, yd = d(w), d(vv)
+        out = xd if which == "x" else yd
+        bto.waxpby(xd, yd, ALPHA, BETA, form=form, w=out)
+        assert relerr(host(out), oracle.waxpby(w, vv, ALPHA, BETA)) <= TOL
+    for which in range(3):
+        ins = [d(w), d(vv), d(u)]
+        bto.vadd(*ins, form=form, x=ins[which])
+        assert relerr(host(ins[which]), oracle.vadd(w, vv, u)) <= TOL
+
+
+# ---- closed forms, determinism, forms agree ---------------------------------
+
+@pytest.mark.parametrize("form", FORMS)
+def test_identity_closed_forms(env, form):
+    torch, bto, dev = env
+    n = 3001
+    I = torch.eye(n, dtype=torch.float64, device=dev)
+    x = dvec(torch, dev, synth.uniform(SEED, 77, n))
+    assert torch.equal(bto.atax(I, x, form=form), x)
+    q, s = bto.bicgk(I, x, x, form=form)
+    assert torch.equal(q, x) and torch.equal(s, x)
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_repeatable_bitwise(env, form):
+    torch, bto, dev = env
+    m, n = 4097, 3001
+    A, vec = inputs("uniform", m, n, n, 6, 0)
+    d = lambda a: dvec(torch, dev, a)
+    Ad = d(A)
+    args = [d(vec(1, m)), d(vec(2, n)), d(vec(3, m)), d(vec(4, n)), d(vec(5, m)), d(vec(6, n))]
+    first = [host(t) for t in bto.gemver(Ad, *args, ALPHA, BETA, form=form)]
+    again = [host(t) for t in bto.gemver(Ad, *args, ALPHA, BETA, form=form)]
+    for a, b in zip(first, again):
+        assert np.array_equal(a, b)
+    q1, s1 = bto.bicgk(Ad, args[1], args[0], form=form)
+    q2, s2 = bto.bicgk(Ad, args[1], args[0], form=form)
+    assert torch.equal(q1, q2) and torch.equal(s1, s2)
+    assert torch.equal(bto.atax(Ad, args[1], form=form), bto.atax(Ad, args[1], form=form))
+
+
+def test_errors_raise(env):
+    torch, bto, dev = env
+    A = torch.zeros((64, 64), dtype=torch.float64, device=dev)
+    p = torch.zeros(64, dtype=torch.float64, device=dev)
+    small = torch.empty(16, dtype=torch.uint8, device=dev)
+    with pytest.raises(bto.BtoError) as e:
+        bto.bicgk(A, p, p, ws=small)
+    assert e.value.status == 3
+    with pytest.raises(bto.BtoError) as e:
+        bto.bicgk(A, p, p, q=A[0], s=A[0, 1:].clone())
+    assert e.value.status == 2
+    with pytest.raises(bto.BtoError) as e:
+        buf = torch.zeros(200, dtype=torch.float64, device=dev)
+        bto.vadd(buf[:100], buf[100:], buf[100:], x=buf[50:150])
+    assert e.value.status == 2
+
+
+# ---- full-size workloads (the benchmark's launch configuration) -------------
+
+N = 16384
+NV = 1 << 26
+
+
+def _full_matrix_case(env, kind, kern):
+    torch, bto, dev = env
+    A, vec = inputs(kind, N, N, N, 3, kern)
+    return torch, bto, dev, A, vec
+
+
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+def test_full_bicgk_and_atax(env, kind):
+    torch, bto, dev, A, vec = _full_matrix_case(env, kind, 10)
+    p, r = vec(1, N), vec(2, N)
+    Ad, pd, rd = dvec(torch, dev, A), dvec(torch, dev, p), dvec(torch, dev, r)
+    q_ref, s_ref = oracle.bicgk(A, p, r)
+    y_ref = oracle.atax(A, p)
+    outs = {}
+    for form in FORMS:
+        q, s = bto.bicgk(Ad, pd, rd, form=form)
+        y = bto.atax(Ad, pd, form=form)
+        outs[form] = (host(q), host(s), host(y))
+        for got, ref in zip(outs[form], (q_ref, s_ref, y_ref)):
+            if kind == "int":
+                assert np.array_equal(got, ref)
+            else:
+                assert relerr(got, ref) <= TOL
+    q, s, _ = outs["fused"]
+    lhs, rhs = float(r @ q), float(s @ p)
+    assert abs(lhs - rhs) <= 1e-12 * float(np.abs(r) @ np.abs(q) + np.abs(s) @ np.abs(p))
+
+
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+def test_full_gemver(env, kind):
+    torch, bto, dev, A, vec = _full_matrix_case(env, kind, 11)
+    vs = [vec(k, N) for k in range(1, 7)]
+    al, be = (2.0, 3.0) if kind == "int" else (ALPHA, BETA)
+    B_ref, x_ref, w_ref = oracle.gemver(A, *vs, al, be)
+    Ad = dvec(torch, dev, A)
+    dv = [dvec(torch, dev, v) for v in vs]
+    Bd = torch.empty_like(Ad)
+    for form in FORMS:
+        B, x, w = bto.gemver(Ad, *dv, al, be, form=form, B=Bd)
+        for got, ref in zip((host(B), host(x), host(w)), (B_ref, x_ref, w_ref)):
+            if kind == "int":
+                assert np.array_equal(got, ref)
+            else:
+                assert relerr(got, ref) <= TOL
+        del B
+
+
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+def test_full_dgemvt(env, kind):
+    torch, bto, dev, A, vec = _full_matrix_case(env, kind, 12)
+    y, z = vec(1, N), vec(2, N)
+    al, be = (2.0, 3.0) if kind == "int" else (ALPHA, BETA)
+    x_ref, w_ref = oracle.dgemvt(A, y, z, al, be)
+    Ad, yd, zd = dvec(torch, dev, A), dvec(torch, dev, y), dvec(torch, dev, z)
+    for form in FORMS:
+        x, w = bto.dgemvt(Ad, yd, zd, al, be, form=form)
+        for got, ref in zip((host(x), host(w)), (x_ref, w_ref)):
+            if kind == "int":
+                assert np.array_equal(got, ref)
+            else:
+                assert relerr(got, ref) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+def test_full_vectors(env, kind):
+    torch, bto, dev = env
+    v = lambda op: synth.vector(SEED, synth.stream_id(3, op, 13), NV, kind)
+    w, vv, u = v(0), v(1), v(2)
+    al, be = (2.0, 3.0) if kind == "int" else (ALPHA, BETA)
+    z_ref, r_ref = oracle.axpydot(w, vv, u, al)
+    wx_ref = oracle.waxpby(w, vv, al, be)
+    va_ref = oracle.vadd(w, vv, u)
+    d = lambda a: dvec(torch, dev, a)
+    wd, vd, ud = d(w), d(vv), d(u)
+    for form in FORMS:
+        z, r = bto.axpydot(wd, vd, ud, al, form=form)
+        got = [host(z), host(r), host(bto.waxpby(wd, vd, al, be, form=form)),
+               host(bto.vadd(wd, vd, ud, form=form))]
+        ref = [z_ref, np.array([r_ref]), wx_ref, va_ref]
+        for g, rf in zip(got, ref):
+            if kind == "int":
+                assert np.array_equal(g, rf)
+            else:
+                assert relerr(g, rf) <= TOL
