@@ -1,0 +1,361 @@
+"""Benchmark: fused vs unfused FP64 BLAS-1/2 sequences on one MI355X.
+
+One step is one fused GEMVER at n = 16384 (B = A + u1 v1^T + u2 v2^T,
+x = beta B^T y + z, w = alpha B x; alpha = 1.5, beta = 0.7) on synthetic
+inputs already resident in HBM.  ``value`` is algorithmic HBM bytes per step
+(read A, write B, read B, plus every vector once) over the measured time per
+step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
+
+  unfused     the same step in the unfused form (one kernel per BLAS op)
+  roofline    the dominant kernel (pass 1 of GEMVER): algorithmic bytes per
+              launch over its average duration from HIP events recorded on
+              its stream during the timed region, against the 8 TB/s peak;
+              traffic = HBM bytes per launch from hardware counters when a
+              counter summary for the current kernel source is committed
+  suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26
+  stream      measured copy / read / triad ceilings at 2 GiB per array
+  cpu_baseline  the CPU oracle timed on the host cores on the same workload
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload gemver|bicgk|...]
+       [--no-suite] [--no-cpu] [--no-stream]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_GBS = 8000.0
+METRIC = "fused vs unfused HBM GB/s (% peak), GEMVER/BiCGK FP64; batch req/s, p99 latency"
+N = 16384
+NV = 1 << 26
+ALPHA, BETA = 1.5, 0.7
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_vec.hip",
+                  "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_api.hip"]
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="gemver",
+                    choices=["gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd"])
+    ap.add_argument("--no-suite", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target CPU time of the oracle baseline sample")
+    return ap.parse_args()
+
+
+# ---- algorithmic bytes (each matrix pass the dependencies force, each vector once)
+
+def alg_bytes(kernel: str, form: str, n: int = N, nv: int = NV) -> int:
+    M, v, V = n * n * 8, n * 8, nv * 8
+    fused = {
+        "gemver": 3 * M + 8 * v,     # read A, write B, read B; u1 v1 u2 v2 y z in, x w out
+        "bicgk": M + 4 * v,          # read A; p r in, q s out
+        "atax": M + 2 * v,           # read A; x in, y out
+        "dgemvt": 2 * M + 4 * v,     # two passes over A; y z in, x w out
+        "axpydot": 4 * V,            # w v u in, z out
+        "waxpby": 3 * V,             # x y in, w out
+        "vadd": 4 * V,               # w y z in, x out
+    }
+    unfused = {
+        "gemver": 6 * M + 12 * v,    # ger (2M), ger (2M), gemv_t (M), gemv_n (M)
+        "bicgk": 2 * M + 4 * v,
+        "atax": 2 * M + 4 * v,       # t written and read back
+        "dgemvt": 2 * M + 4 * v,
+        "axpydot": 5 * V,            # axpy (3V) + dot (2V)
+        "waxpby": 5 * V,             # scal (2V) + axpy (3V)
+        "vadd": 6 * V,               # add (3V) + add (3V)
+    }
+    return (fused if form == "fused" else unfused)[kernel]
+
+
+# dominant kernel of each workload's fused step and its algorithmic bytes per launch
+def dominant(kernel: str, n: int = N, nv: int = NV):
+    M, v, V = n * n * 8, n * 8, nv * 8
+    return {
+        "gemver": ("gemver_p1", 2 * M + 5 * v),
+        "bicgk": ("bicgk_fused", M + 2 * v),
+        "atax": ("atax_rowres", M + v),
+        "dgemvt": ("dgemvt_p1", M + v),
+        "axpydot": ("axpydot_fused", 4 * V),
+        "waxpby": ("ew_waxpby", 3 * V),
+        "vadd": ("ew_vadd3", 4 * V),
+    }[kernel]
+
+
+# ---- workloads ------------------------------------------------------------------
+
+class Workload:
+    """Device-resident inputs and outputs of one kernel at bench size."""
+
+    def __init__(self, torch, bto, synth, kernel, dev, shared=None):
+        self.kernel, self.bto, self.torch = kernel, bto, torch
+        seed = synth.SEED
+        sid = lambda op: synth.stream_id(2 if kernel == "gemver" else 3, op)
+        d = lambda a: torch.from_numpy(a).to(dev)
+        shared = {} if shared is None else shared
+        if kernel in ("gemver", "bicgk", "atax", "dgemvt"):
+            if "A" not in shared:
+                shared["A"] = d(synth.matrix(seed, sid(0), N, N))
+            self.A = shared["A"]
+            vec = lambda op: d(synth.uniform(seed, sid(op), N))
+            if kernel == "gemver":
+                self.vs = [vec(k) for k in range(1, 7)]
+                if "B" not in shared:
+                    shared["B"] = torch.empty_like(self.A)
+                self.B = shared["B"]
+                self.x, self.w = vec(7), vec(8)
+            elif kernel == "bicgk":
+                self.p, self.r, self.q, self.s = vec(1), vec(2), vec(3), vec(4)
+            elif kernel == "atax":
+                self.x, self.y = vec(1), vec(2)
+            else:
+                self.y, self.z, self.x, self.w = vec(1), vec(2), vec(3), vec(4)
+        else:
+            vec = lambda op: d(synth.uniform(seed, sid(16 + op), NV))
+            self.a, self.b, self.c, self.out = vec(0), vec(1), vec(2), vec(3)
+            self.r = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.ws = {f: torch.empty(max(1, bto.workspace_bytes(kernel, N, NV if kernel in
+                                                                   ("axpydot", "waxpby", "vadd")
+                                                                   else N, f)),
+                                  dtype=torch.uint8, device=dev) for f in ("fused", "unfused")}
+
+    def run(self, form: str) -> None:
+        b, k, ws = self.bto, self.kernel, self.ws[form]
+        if k == "gemver":
+            b.gemver(self.A, *self.vs, ALPHA, BETA, form=form, B=self.B, x=self.x, w=self.w, ws=ws)
+        elif k == "bicgk":
+            b.bicgk(self.A, self.p, self.r, form=form, q=self.q, s=self.s, ws=ws)
+        elif k == "atax":
+            b.atax(self.A, self.x, form=form, y=self.y, ws=ws)
+        elif k == "dgemvt":
+            b.dgemvt(self.A, self.y, self.z, ALPHA, BETA, form=form, x=self.x, w=self.w, ws=ws)
+        elif k == "axpydot":
+            b.axpydot(self.a, self.b, self.c, ALPHA, form=form, z=self.out, r=self.r, ws=ws)
+        elif k == "waxpby":
+            b.waxpby(self.a, self.b, ALPHA, BETA, form=form, w=self.out, ws=ws)
+        else:
+            b.vadd(self.a, self.b, self.c, form=form, x=self.out, ws=ws)
+
+
+def time_steps(torch, fn, steps: int, warmup: int) -> float:
+    """Seconds per step over `steps` calls after `warmup` untimed ones."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+# ---- hardware-counter traffic ------------------------------------------------------
+
+def source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel_name: str):
+    """HBM bytes per launch of `kernel_name` from a committed counter summary,
+    or None when there is none for the current kernel sources."""
+    path = os.path.join(PROFILES, f"{kernel_name}_n16384_counters.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("source_digest") != source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+# ---- CPU oracle baseline -------------------------------------------------------------
+
+def cpu_baseline(kernel: str, target_s: float):
+    import numpy as np
+
+    import oracle
+    from paper_1205_1098_amd import synth
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    seed = synth.SEED
+    sid = lambda op: synth.stream_id(2, op)
+    A = synth.matrix(seed, sid(0), N, N)
+    vs = [synth.uniform(seed, sid(k), N) for k in range(1, 7)]
+    reps, elapsed = 0, 0.0
+    while elapsed < target_s and reps < 20:
+        t0 = time.perf_counter()
+        if kernel == "gemver":
+            oracle.gemver(A, *vs, ALPHA, BETA)
+        elif kernel == "bicgk":
+            oracle.bicgk(A, vs[0], vs[1])
+        elif kernel == "atax":
+            oracle.atax(A, vs[0])
+        else:
+            oracle.dgemvt(A, vs[0], vs[1], ALPHA, BETA)
+        elapsed += time.perf_counter() - t0
+        reps += 1
+    per = elapsed / reps
+    del A
+    return {
+        "value": round(alg_bytes(kernel, "fused") / per / 1e9, 3),
+        "unit": "GB/s",
+        "cores": int(oracle.get_threads()),
+        "kind": "oracle",
+        "sample": f"{reps} full {kernel} n={N} call(s) on host data, {per * 1e3:.1f} ms each; "
+                  f"GB/s on the same algorithmic bytes as the GPU value",
+    }
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of these kernels is a design note, not a measured path.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1205_1098_amd import bto, synth
+
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(0)
+    shared = {}
+    main_wl = Workload(torch, bto, synth, args.workload, dev, shared)
+
+    # timed region: K fused steps, dominant-kernel events recorded on its stream
+    for _ in range(args.warmup):
+        main_wl.run("fused")
+    torch.cuda.synchronize()
+    bto.timing_reset()
+    bto.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        main_wl.run("fused")
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    bto.timing_enable(False)
+    times = bto.timing_read()
+    bto.timing_reset()
+
+    fused_bytes = alg_bytes(args.workload, "fused")
+    value = fused_bytes / sec / 1e9
+    dom_name, dom_bytes = dominant(args.workload)
+    launches, total_ms = times.get(dom_name, (0, 0.0))
+    dom_ms = total_ms / launches if launches else float("nan")
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = counter_traffic(dom_name)
+
+    sec_unf = time_steps(torch, lambda: main_wl.run("unfused"), max(3, args.steps // 2), 2)
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (SplitMix64 uniform[-1,1), seed 12051098), resident in HBM",
+        "config": {"workload": f"{args.workload} fused FP64 n={N}" if args.workload in
+                   ("gemver", "bicgk", "atax", "dgemvt") else f"{args.workload} fused FP64 N=2^26",
+                   "alpha": ALPHA, "beta": BETA, "form": "fused",
+                   "alg_bytes_per_step": fused_bytes},
+        "pct_peak": round(100 * value / PEAK_GBS, 2),
+        "unfused": {
+            "ms_per_step": round(sec_unf * 1e3, 4),
+            "gbs_same_bytes": round(fused_bytes / sec_unf / 1e9, 2),
+            "gbs_own_bytes": round(alg_bytes(args.workload, "unfused") / sec_unf / 1e9, 2),
+            "fused_speedup": round(sec_unf / sec, 3),
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom_name,
+            "achieved": round(achieved, 2),
+            "peak": PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / PEAK_GBS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": dom_bytes,
+            "avg_launch_ms": round(dom_ms, 5),
+            "launches_timed": launches,
+        },
+        "kernel_ms": {k: round(ms / c, 5) for k, (c, ms) in times.items() if c},
+        "device": {"name": props.name, "cus": props.multi_processor_count,
+                   "hbm_gib": round(props.total_memory / 2 ** 30, 1)},
+    }
+
+    if not args.no_suite:
+        suite = {}
+        for k in ("gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd"):
+            wl = main_wl if k == args.workload else Workload(torch, bto, synth, k, dev, shared)
+            ent = {}
+            for form in ("fused", "unfused"):
+                s = time_steps(torch, lambda: wl.run(form), 20, 3)
+                ent[form + "_ms"] = round(s * 1e3, 4)
+                ent[form + "_gbs"] = round(alg_bytes(k, form) / s / 1e9, 1)
+            ent["fused_pct_peak"] = round(100 * ent["fused_gbs"] / PEAK_GBS, 1)
+            ent["speedup"] = round(ent["unfused_ms"] / ent["fused_ms"], 3)
+            suite[k] = ent
+            if wl is not main_wl and k in ("axpydot", "waxpby", "vadd"):
+                del wl
+        result["suite"] = suite
+
+    if not args.no_stream:
+        n = 1 << 28   # 2 GiB per array
+        a = torch.empty(n, dtype=torch.float64, device=dev)
+        b = torch.ones(n, dtype=torch.float64, device=dev)
+        c = torch.ones(n, dtype=torch.float64, device=dev)
+        out = torch.zeros(1, dtype=torch.float64, device=dev)
+        st = {}
+        s = time_steps(torch, lambda: bto.probe_copy(b, a), 10, 2)
+        st["copy_gbs"] = round(2 * n * 8 / s / 1e9, 1)
+        s = time_steps(torch, lambda: bto.probe_read(b, out), 10, 2)
+        st["read_gbs"] = round(n * 8 / s / 1e9, 1)
+        s = time_steps(torch, lambda: bto.probe_triad(a, b, c, 0.5), 10, 2)
+        st["triad_gbs"] = round(3 * n * 8 / s / 1e9, 1)
+        result["stream"] = st
+        del a, b, c
+
+    shared.clear()
+    del main_wl
+    torch.cuda.empty_cache()
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(args.workload if args.workload in
+                                              ("gemver", "bicgk", "atax", "dgemvt") else "gemver",
+                                              args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

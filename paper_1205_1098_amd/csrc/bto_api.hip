@@ -401,11 +401,11 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
     BTO_TRY(check_vec(q, m, "q"));
     BTO_TRY(check_vec(s, n, "s"));
     const size_t need_ws = ws_bytes(BTO_K_BICGK, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("p", p, n, false),
                            vspan("r", r, m, false), vspan("q", q, m, true),
                            vspan("s", s, n, true), wspan(ws, need_ws)},
                           {}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
 
     Carve cv(ws);
     double *Prow = cv.take(max_ncols(n) * m);
@@ -450,13 +450,13 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
     if (B == A && ldb != lda && m > 1 && n > 0)
         return fail(BTO_ERR_ALIAS, "B == A requires ldb == lda");
     const size_t need_ws = ws_bytes(BTO_K_GEMVER, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("u1", u1, m, false),
                            vspan("v1", v1, n, false), vspan("u2", u2, m, false),
                            vspan("v2", v2, n, false), vspan("y", y, m, false),
                            vspan("z", z, n, false), mspan("B", B, m, n, ldb, true),
                            vspan("x", x, n, true), vspan("w", w, m, true), wspan(ws, need_ws)},
                           {{"A", "B"}}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
 
     Carve cv(ws);
     double *Prow = cv.take(max_ncols(n) * m);
@@ -509,10 +509,10 @@ bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const do
     BTO_TRY(check_vec(x, n, "x"));
     BTO_TRY(check_vec(y, n, "y"));
     const size_t need_ws = ws_bytes(BTO_K_ATAX, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("x", x, n, false),
                            vspan("y", y, n, true), wspan(ws, need_ws)},
                           {}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
 
     const int64_t G = form == BTO_FUSED ? atax_rowres_parts(m, n) : 0;
     Carve cv(ws);
@@ -544,11 +544,11 @@ bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta, const dou
     BTO_TRY(check_vec(z, n, "z"));
     BTO_TRY(check_vec(x, n, "x"));
     const size_t need_ws = ws_bytes(BTO_K_DGEMVT, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("y", y, m, false),
                            vspan("z", z, n, false), vspan("x", x, n, true),
                            vspan("w", w, m, true), wspan(ws, need_ws)},
                           {}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
 
     Carve cv(ws);
     double *Prow = cv.take(max_ncols(n) * m);
@@ -578,11 +578,11 @@ bto_status bto_axpydot(int64_t n, double alpha, const double *w, const double *v
     BTO_TRY(check_vec(z, n, "z"));
     BTO_TRY(check_vec(r, 1, "r"));
     const size_t need_ws = ws_bytes(BTO_K_AXPYDOT, 0, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({vspan("w", w, n, false), vspan("v", v, n, false),
                            vspan("u", u, n, false), vspan("z", z, n, true),
                            vspan("r", r, 1, true), wspan(ws, need_ws)},
                           {{"z", "w"}}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
 
     double *parts = Carve(ws).take(dot_parts(n));
     if (form == BTO_FUSED) {
@@ -606,10 +606,10 @@ bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta, con
     BTO_TRY(check_vec(y, n, "y"));
     BTO_TRY(check_vec(w, n, "w"));
     const size_t need_ws = ws_bytes(BTO_K_WAXPBY, 0, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({vspan("x", x, n, false), vspan("y", y, n, false),
                            vspan("w", w, n, true), wspan(ws, need_ws)},
                           {{"w", "x"}, {"w", "y"}}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     if (form == BTO_FUSED) {
         launch_ew(EW_WAXPBY, n, x, y, nullptr, alpha, beta, w, st);
     } else {
@@ -633,10 +633,10 @@ bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z
     BTO_TRY(check_vec(z, n, "z"));
     BTO_TRY(check_vec(x, n, "x"));
     const size_t need_ws = ws_bytes(BTO_K_VADD, 0, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({vspan("w", w, n, false), vspan("y", y, n, false),
                            vspan("z", z, n, false), vspan("x", x, n, true), wspan(ws, need_ws)},
                           {{"x", "w"}, {"x", "y"}, {"x", "z"}}));
-    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     if (form == BTO_FUSED) {
         launch_ew(EW_VADD3, n, w, y, z, 0.0, 0.0, x, st);
     } else {
@@ -730,7 +730,11 @@ bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws, s
     BTO_TRY(need(n >= 0, "negative size"));
     BTO_TRY(check_vec(src, n, "src"));
     BTO_TRY(check_vec(out, 1, "out"));
-    BTO_TRY(check_ws(ws, ws_bytes_, bto_probe_read_workspace_bytes(n)));
+    const size_t need_ws = bto_probe_read_workspace_bytes(n);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    BTO_TRY(check_aliases({vspan("src", src, n, false), vspan("out", out, 1, true),
+                           wspan(ws, need_ws)},
+                          {}));
     // sum of squares: both operands are the same stream, read once from HBM
     launch_dot(false, n, 0.0, src, nullptr, src, nullptr, static_cast<double *>(ws), out, st);
     return check_launch();

@@ -110,3 +110,17 @@ def test_workspace_too_small(bto):
                      v(base + (3 << 20)), v(base + (4 << 20)), v(base + (8 << 20)), wsb - 1)
     assert st == WS
     assert "workspace" in bto._lib.bto_last_error().decode()
+
+
+def test_workspace_checked_before_overlap(bto):
+    """A too-small workspace reports WORKSPACE even where the extent it would
+    need runs into another operand."""
+    v = ctypes.c_void_p
+    m = n = 256
+    wsb = bto.workspace_bytes("bicgk", m, n)
+    base = FAKE
+    ws = base + (16 << 20)
+    q = ws + 4096            # inside the required extent, past the provided one
+    st = _call_bicgk(bto, m, n, v(base), n, v(base + (1 << 20)), v(base + (2 << 20)),
+                     v(q), v(base + (4 << 20)), v(ws), 1024)
+    assert st == 3
