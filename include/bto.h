@@ -171,6 +171,26 @@ bto_status bto_timing_get(int idx, const char **name, int64_t *launches,
                           double *total_ms);
 void bto_timing_reset(void);
 
+/* ---- tuning --------------------------------------------------------------
+ * Every matrix sweep the entry points launch belongs to a slot (for example
+ * pass 1 of fused GEMVER, or the unfused dgemv 'N').  A slot's tile
+ * configuration is (shape, rb, rev): `shape` picks one of the compiled tile
+ * shapes (bto_tune_shape describes it: 16-byte column pairs per lane, rows
+ * of loads in flight per wave, waves across the columns and down the rows
+ * of a workgroup), `rb` is the number of rows per workgroup band and `rev`
+ * walks the bands in reverse.  These are the GPU counterparts of the
+ * partitioning and thread-count choices of Sections III-C and IV-D: they
+ * change speed, never results beyond summation order.  bto_tune_set
+ * returns BTO_ERR_INVALID_ARG for a configuration the slot cannot run; the
+ * table is process-wide and guarded by a lock. */
+int bto_tune_slot_count(void);
+const char *bto_tune_slot_name(int slot);
+int bto_tune_slot_ops(int slot);
+bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev);
+bto_status bto_tune_set(int slot, int shape, int rb, int rev);
+bto_status bto_tune_shape(int shape, int *kv, int *depth, int *waves_across,
+                          int *waves_down);
+
 /* Bandwidth probes, used to calibrate hardware byte counters and to
  * measure the achievable HBM ceiling: dst <- src (copy), *out <- sum(src)
  * (read; out is one device double, the sum order is fixed), and

@@ -61,6 +61,14 @@ _SIGS = {
     "bto_probe_read": ([_ptr, _i64, _ptr, _ptr, _sz, _ptr], _int),
     "bto_probe_triad": ([_ptr, _ptr, _ptr, _dbl, _i64, _ptr], _int),
     "bto_probe_read_workspace_bytes": ([_i64], _sz),
+    "bto_tune_slot_count": ([], _int),
+    "bto_tune_slot_name": ([_int], ctypes.c_char_p),
+    "bto_tune_slot_ops": ([_int], _int),
+    "bto_tune_get": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
+                     _int),
+    "bto_tune_set": ([_int, _int, _int, _int], _int),
+    "bto_tune_shape": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                        ctypes.POINTER(_int)], _int),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -307,3 +315,32 @@ def probe_read(src, out, ws=None) -> None:
     with torch.cuda.device(dev):
         _check(_lib.bto_probe_read(_ptr_of(src), src.numel(), _ptr_of(out), _ptr_of(ws),
                                    ws.numel(), _stream(dev)))
+
+
+# ---- tile configuration (the autotuner's knobs) ------------------------------
+
+def tune_slots() -> list:
+    """Names of the tunable matrix sweeps, in slot order."""
+    return [_lib.bto_tune_slot_name(i).decode() for i in range(_lib.bto_tune_slot_count())]
+
+
+def tune_slot_ops(slot: int) -> int:
+    return int(_lib.bto_tune_slot_ops(slot))
+
+
+def tune_get(slot: int) -> tuple:
+    """(shape, rb, rev) of a slot."""
+    a, b, c = _int(), _int(), _int()
+    _check(_lib.bto_tune_get(slot, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
+
+
+def tune_set(slot: int, shape: int, rb: int, rev: int = 0) -> None:
+    _check(_lib.bto_tune_set(slot, shape, rb, rev))
+
+
+def tune_shape(shape: int) -> dict:
+    """kv (16-byte pairs per lane), depth (rows in flight), waves across, waves down."""
+    v = [_int() for _ in range(4)]
+    _check(_lib.bto_tune_shape(shape, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("kv", "depth", "wc", "wr"), (int(x.value) for x in v)))

@@ -56,14 +56,14 @@ const char *const kSlotNames[SLOT_COUNT] = {
 
 std::mutex g_cfg_mu;
 TileCfg g_cfg[SLOT_COUNT] = {
-    {4, 2, 128, 0},  // BICGK_FUSED
-    {4, 4, 128, 0},  // GEMV_N
-    {4, 4, 128, 0},  // GEMV_T
-    {4, 4, 128, 0},  // GER
-    {4, 2, 128, 0},  // GEMVER_P1
-    {4, 4, 128, 1},  // GEMVER_P2: walk B backwards, from what pass 1 left in cache
-    {4, 4, 128, 0},  // DGEMVT_P1
-    {4, 4, 128, 1},  // DGEMVT_P2
+    {2, 128, 0},  // BICGK_FUSED: 8 waves across 4096 columns, 2 row groups
+    {0, 64, 0},   // GEMV_N: 4 waves across 4096 columns, 64 rows
+    {1, 256, 0},  // GEMV_T: 4 x 4 waves, 256-row bands
+    {6, 4, 0},    // GER: one row per wave, 256-column wave tiles
+    {6, 32, 0},   // GEMVER_P1: 256-column wave tiles, 32-row bands
+    {0, 64, 1},   // GEMVER_P2: walk B backwards, from what pass 1 left in cache
+    {1, 256, 0},  // DGEMVT_P1
+    {0, 64, 1},   // DGEMVT_P2
 };
 
 constexpr int kMinKv = 2;
@@ -255,29 +255,39 @@ FinishJob fjob(const double *P, int64_t nparts, int64_t len, double scale, const
 const FinishJob kNoJob{nullptr, 0, 0, 0.0, nullptr, nullptr};
 
 // out_rows = scale * A xr : tile sweep of A with row dots + finish
-void gemv_n(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *xr,
-            double scale, double *out, double *Prow, hipStream_t st)
+bto_status unsupported(Slot s)
+{
+    return fail(BTO_ERR_UNSUPPORTED, std::string("tile configuration of ") + kSlotNames[s] +
+                                         " is not supported");
+}
+
+bto_status gemv_n(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *xr,
+                  double scale, double *out, double *Prow, hipStream_t st)
 {
     TileCfg c = cfg_of(s);
     TileArgs a = targs(m, n, A, lda);
     a.xr = xr;
     a.Prow = Prow;
-    launch_tile(kSlotNames[s], OP_ROWDOT, c, a, st);
+    if (!launch_tile(kSlotNames[s], OP_ROWDOT, c, a, st))
+        return unsupported(s);
     int64_t np = n > 0 ? tile_ncols(c, n) : 0;
     launch_finish("finish", fjob(Prow, np, m, scale, nullptr, out), kNoJob, st);
+    return BTO_SUCCESS;
 }
 
 // out_cols = scale * A^T yc + add
-void gemv_t(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *yc,
-            double scale, const double *add, double *out, double *Pcol, hipStream_t st)
+bto_status gemv_t(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *yc,
+                  double scale, const double *add, double *out, double *Pcol, hipStream_t st)
 {
     TileCfg c = cfg_of(s);
     TileArgs a = targs(m, n, A, lda);
     a.yc = yc;
     a.Pcol = Pcol;
-    launch_tile(kSlotNames[s], OP_COLSUM, c, a, st);
+    if (!launch_tile(kSlotNames[s], OP_COLSUM, c, a, st))
+        return unsupported(s);
     int64_t np = m > 0 ? tile_nbands(c, m) : 0;
     launch_finish("finish", fjob(Pcol, np, n, scale, add, out), kNoJob, st);
+    return BTO_SUCCESS;
 }
 
 }  // namespace
@@ -417,12 +427,13 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
         a.yc = r;
         a.Prow = Prow;
         a.Pcol = Pcol;
-        launch_tile(kSlotNames[SLOT_BICGK_FUSED], OP_ROWDOT | OP_COLSUM, c, a, st);
+        if (!launch_tile(kSlotNames[SLOT_BICGK_FUSED], OP_ROWDOT | OP_COLSUM, c, a, st))
+            return unsupported(SLOT_BICGK_FUSED);
         launch_finish("finish", fjob(Prow, tile_ncols(c, n), m, 1.0, nullptr, q),
                       fjob(Pcol, tile_nbands(c, m), n, 1.0, nullptr, s), st);
     } else {
-        gemv_n(SLOT_GEMV_N, m, n, A, lda, p, 1.0, q, Prow, st);
-        gemv_t(SLOT_GEMV_T, m, n, A, lda, r, 1.0, nullptr, s, Pcol, st);
+        BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, A, lda, p, 1.0, q, Prow, st));
+        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, r, 1.0, nullptr, s, Pcol, st));
     }
     return check_launch();
 }
@@ -473,11 +484,12 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
         a.v2 = v2;
         a.yc = y;
         a.Pcol = Pcol;
-        launch_tile(kSlotNames[SLOT_GEMVER_P1], OP_UPD1 | OP_UPD2 | OP_COLSUM, c, a, st);
+        if (!launch_tile(kSlotNames[SLOT_GEMVER_P1], OP_UPD1 | OP_UPD2 | OP_COLSUM, c, a, st))
+            return unsupported(SLOT_GEMVER_P1);
         const int64_t np = (m > 0 && n > 0) ? tile_nbands(c, m) : 0;
         launch_finish("finish", fjob(Pcol, np, n, beta, z, x), kNoJob, st);
         // pass 2: w = alpha B x
-        gemv_n(SLOT_GEMVER_P2, m, n, B, ldb, x, alpha, w, Prow, st);
+        BTO_TRY(gemv_n(SLOT_GEMVER_P2, m, n, B, ldb, x, alpha, w, Prow, st));
     } else {
         TileCfg c = cfg_of(SLOT_GER);
         TileArgs a = targs(m, n, A, lda);
@@ -485,15 +497,16 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
         a.ldb = ldb;
         a.u1 = u1;
         a.v1 = v1;
-        launch_tile("ger", OP_UPD1, c, a, st);     // B = A + u1 v1^T
+        if (!launch_tile("ger", OP_UPD1, c, a, st))     // B = A + u1 v1^T
+            return unsupported(SLOT_GER);
         a = targs(m, n, B, ldb);
         a.B = B;
         a.ldb = ldb;
         a.u1 = u2;
         a.v1 = v2;
-        launch_tile("ger", OP_UPD1, c, a, st);     // B = B + u2 v2^T
-        gemv_t(SLOT_GEMV_T, m, n, B, ldb, y, beta, z, x, Pcol, st);
-        gemv_n(SLOT_GEMV_N, m, n, B, ldb, x, alpha, w, Prow, st);
+        launch_tile("ger", OP_UPD1, c, a, st);          // B = B + u2 v2^T
+        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, B, ldb, y, beta, z, x, Pcol, st));
+        BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, B, ldb, x, alpha, w, Prow, st));
     }
     return check_launch();
 }
@@ -524,8 +537,8 @@ bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const do
         double *t = cv.take(m);
         double *Prow = cv.take(max_ncols(n) * m);
         double *Pcol = cv.take(max_nbands(m) * n);
-        gemv_n(SLOT_GEMV_N, m, n, A, lda, x, 1.0, t, Prow, st);
-        gemv_t(SLOT_GEMV_T, m, n, A, lda, t, 1.0, nullptr, y, Pcol, st);
+        BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, A, lda, x, 1.0, t, Prow, st));
+        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, t, 1.0, nullptr, y, Pcol, st));
     }
     return check_launch();
 }
@@ -554,11 +567,11 @@ bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta, const dou
     double *Prow = cv.take(max_ncols(n) * m);
     double *Pcol = cv.take(max_nbands(m) * n);
     if (form == BTO_FUSED) {
-        gemv_t(SLOT_DGEMVT_P1, m, n, A, lda, y, beta, z, x, Pcol, st);
-        gemv_n(SLOT_DGEMVT_P2, m, n, A, lda, x, alpha, w, Prow, st);
+        BTO_TRY(gemv_t(SLOT_DGEMVT_P1, m, n, A, lda, y, beta, z, x, Pcol, st));
+        BTO_TRY(gemv_n(SLOT_DGEMVT_P2, m, n, A, lda, x, alpha, w, Prow, st));
     } else {
-        gemv_t(SLOT_GEMV_T, m, n, A, lda, y, beta, z, x, Pcol, st);
-        gemv_n(SLOT_GEMV_N, m, n, A, lda, x, alpha, w, Prow, st);
+        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, y, beta, z, x, Pcol, st));
+        BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, A, lda, x, alpha, w, Prow, st));
     }
     return check_launch();
 }
@@ -703,6 +716,59 @@ void bto_timing_reset(void)
     g_tnames.clear();
     g_tms.clear();
     g_tcount.clear();
+}
+
+// ---- tuning --------------------------------------------------------------------
+
+int bto_tune_slot_count(void) { return SLOT_COUNT; }
+
+const char *bto_tune_slot_name(int slot)
+{
+    return (slot >= 0 && slot < SLOT_COUNT) ? kSlotNames[slot] : "";
+}
+
+int bto_tune_slot_ops(int slot)
+{
+    return (slot >= 0 && slot < SLOT_COUNT) ? kSlotOps[slot] : 0;
+}
+
+bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
+{
+    t_error.clear();
+    if (slot < 0 || slot >= SLOT_COUNT)
+        return fail(BTO_ERR_INVALID_ARG, "slot out of range");
+    TileCfg c = cfg_of(static_cast<Slot>(slot));
+    if (shape) *shape = c.shape;
+    if (rb) *rb = c.rb;
+    if (rev) *rev = c.rev;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_tune_set(int slot, int shape, int rb, int rev)
+{
+    t_error.clear();
+    if (slot < 0 || slot >= SLOT_COUNT)
+        return fail(BTO_ERR_INVALID_ARG, "slot out of range");
+    TileCfg c{shape, rb, rev};
+    if (!tile_cfg_supported(kSlotOps[slot], c))
+        return fail(BTO_ERR_INVALID_ARG, "tile configuration not supported for this slot");
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    g_cfg[slot] = c;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_tune_shape(int shape, int *kv, int *depth, int *waves_across, int *waves_down)
+{
+    t_error.clear();
+    if (shape < 0 || shape >= kTileShapes)
+        return fail(BTO_ERR_INVALID_ARG, "shape out of range");
+    int info[4];
+    tile_shape_info(shape, info);
+    if (kv) *kv = info[0];
+    if (depth) *depth = info[1];
+    if (waves_across) *waves_across = info[2];
+    if (waves_down) *waves_down = info[3];
+    return BTO_SUCCESS;
 }
 
 // ---- probes --------------------------------------------------------------------

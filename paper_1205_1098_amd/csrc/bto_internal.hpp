@@ -66,10 +66,9 @@ enum TileOps {
 };
 
 struct TileCfg {
-    int kv;    // 16-byte column pairs per lane: a column tile is 128*kv wide
-    int ru;    // rows loaded ahead per wave
-    int rb;    // rows per workgroup (4 waves); multiple of 4, at most 256
-    int rev;   // walk row bands in reverse order
+    int shape;  // index into the instantiated tile shapes (KV, D, WC, WR)
+    int rb;     // rows per workgroup band
+    int rev;    // walk row bands in reverse order
 };
 
 struct TileArgs {
@@ -79,15 +78,19 @@ struct TileArgs {
     const double *xr;  // length n, row-dot weights
     const double *yc;  // length m, column-sum weights
     const double *u1, *v1, *u2, *v2;
-    double *Prow;      // [ncol_tiles][m]
-    double *Pcol;      // [nrow_bands][n]
+    double *Prow;      // [wave tiles][m]
+    double *Pcol;      // [row bands][n]
 };
 
-inline int64_t tile_ncols(const TileCfg &c, int64_t n) { return ceil_div(n, 128 * c.kv); }
-inline int64_t tile_nbands(const TileCfg &c, int64_t m) { return ceil_div(m, c.rb); }
-
+// Shapes 0..5 serve read-only sweeps, 6..10 sweeps that store B.
+constexpr int kTileShapes = 11;
 bool tile_cfg_supported(int ops, const TileCfg &c);
-void launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st);
+int tile_kv(const TileCfg &c);
+void tile_shape_info(int shape, int out[4]);   // kv, depth, waves across, waves down
+int64_t tile_ncols(const TileCfg &c, int64_t n);     // number of wave tiles across n
+inline int64_t tile_nbands(const TileCfg &c, int64_t m) { return ceil_div(m, c.rb); }
+// Returns false (launching nothing) when the configuration is not supported.
+bool launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st);
 
 // out[i] = scale * sum_k P[k*len + i] (+ add[i]) for two independent jobs in
 // one launch (the second may have len 0).

@@ -1,18 +1,26 @@
 // Matrix (BLAS-2) kernels over a row-major A.
 //
-// k_tile is one sweep of A in 2-D tiles (a column tile of 128*KV columns by
-// a band of rb rows per 4-wave workgroup).  Each lane owns KV 16-byte column
-// pairs of the tile for the whole band, so the per-column vectors it needs
-// (the row-dot weights, v1, v2, the column-sum accumulators) live in
-// registers and A streams through once.  Depending on OPS one sweep
+// k_tile is one sweep of A in 2-D tiles.  A workgroup is WC x WR waves: the
+// WC waves of a row group sit side by side across the columns (each owns a
+// wave tile of 128*KV columns, i.e. KV 16-byte pairs per lane), the WR row
+// groups split the workgroup's band of rb rows.  Each lane keeps the
+// per-column vectors of its columns in registers for the whole band (the
+// row-dot weights, v1, v2, the column-sum accumulators), so A streams
+// through exactly once, with D rows of loads kept in flight per wave.
+// Depending on OPS one sweep
 //   - forms B = A + u1 v1^T (+ u2 v2^T) and stores it          (OP_UPD1/2)
-//   - accumulates the row dots  sum_j B_ij xr_j  per column tile (OP_ROWDOT)
-//   - accumulates the column sums sum_i B_ij yc_i per row band   (OP_COLSUM)
+//   - accumulates the row dots  sum_j B_ij xr_j  per wave tile  (OP_ROWDOT)
+//   - accumulates the column sums sum_i B_ij yc_i per row band  (OP_COLSUM)
 // where B is A when no update is asked for.  This is the fused loop nest
-// {p(i){i{j ...}}} of Section III-C with the row-band partition p(i) across
-// workgroups and the column tile across lanes.  Row-dot partials land in
-// Prow[column tile][row], column-sum partials in Pcol[row band][column];
+// {p(i){i{j ...}}} of Section III-C: the row-band partition p(i) runs across
+// workgroups, the columns across lanes.  Row-dot partials land in
+// Prow[wave tile][row], column-sum partials in Pcol[row band][column];
 // k_finish reduces them in a fixed order.
+//
+// Read-only sweeps stream best with wide contiguous workgroup rows (WC*KV*2
+// KiB per row); sweeps that also write B stream best with narrow wave rows
+// and short bands.  Both families are instantiated below and the shape is a
+// run-time choice.
 
 #include "bto_dev.hpp"
 #include "bto_internal.hpp"
@@ -20,8 +28,6 @@
 namespace bto {
 
 namespace {
-
-constexpr int kTileThreads = 256;
 
 // Load the 16-byte pair of row `row` at column j (masked past n).
 template <bool VEC, bool FULL>
@@ -61,62 +67,66 @@ __device__ __forceinline__ d2 load_vec_pair(const double *v, int64_t j, int64_t 
     return r;
 }
 
-template <int KV, int RU, int OPS, bool VEC, bool FULL>
-__device__ __forceinline__ void tile_body(const TileArgs &a, int64_t ct, int64_t rb, int rbrows,
-                                          double *lds)
+// One wave's sweep over rows [r0, r1) of its wave tile starting at column c0.
+template <int KV, int D, int OPS, bool VEC, bool FULL>
+__device__ __forceinline__ void tile_rows(const TileArgs &a, int64_t c0, int64_t r0, int64_t r1,
+                                          int lane, d2 (&acc)[KV], double &mine)
 {
     constexpr bool ROWDOT = OPS & OP_ROWDOT;
     constexpr bool COLSUM = OPS & OP_COLSUM;
     constexpr bool UPD1 = OPS & OP_UPD1;
     constexpr bool UPD2 = OPS & OP_UPD2;
-    constexpr int CT = 128 * KV;
-
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int64_t c0 = ct * CT;
     const int64_t n = a.n;
 
-    d2 xr[KV], v1[KV], v2[KV], acc[KV];
+    d2 xr[KV], v1[KV], v2[KV];
 #pragma unroll
     for (int k = 0; k < KV; ++k) {
         const int64_t j = c0 + 2 * (lane + kWave * k);
-        acc[k] = d2{0.0, 0.0};
         if (ROWDOT) xr[k] = load_vec_pair(a.xr, j, n);
         if (UPD1) v1[k] = load_vec_pair(a.v1, j, n);
         if (UPD2) v2[k] = load_vec_pair(a.v2, j, n);
     }
 
-    const int rpw = rbrows >> 2;  // rows per wave
-    const int64_t r0 = rb * rbrows + (int64_t)wave * rpw;
-    const int64_t r1 = r0 + rpw < a.m ? r0 + rpw : a.m;
-    double mine = 0.0;
+    auto load_row = [&](int64_t i, d2 (&dst)[KV]) {
+        const double *row = a.A + i * a.lda;
+#pragma unroll
+        for (int k = 0; k < KV; ++k)
+            dst[k] = load_pair<VEC, FULL>(row, c0 + 2 * (lane + kWave * k), n);
+    };
 
-    for (int64_t i0 = r0; i0 < r1; i0 += RU) {
-        d2 v[RU][KV];
+    d2 ring[D][KV];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t i = i0 + u;
-            const double *row = a.A + i * a.lda;
+    for (int q = 0; q < D; ++q) {
+        if (r0 + q < r1) {
+            load_row(r0 + q, ring[q]);
+        } else {
 #pragma unroll
-            for (int k = 0; k < KV; ++k) {
-                const int64_t j = c0 + 2 * (lane + kWave * k);
-                v[u][k] = (i < r1) ? load_pair<VEC, FULL>(row, j, n) : d2{0.0, 0.0};
-            }
+            for (int k = 0; k < KV; ++k)
+                ring[q][k] = d2{0.0, 0.0};
         }
+    }
+
+    for (int64_t i0 = r0; i0 < r1; i0 += D) {
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-            const int64_t i = i0 + u;
+        for (int q = 0; q < D; ++q) {
+            const int64_t i = i0 + q;
             if (i >= r1)
                 break;
+            d2 v[KV];
+#pragma unroll
+            for (int k = 0; k < KV; ++k)
+                v[k] = ring[q][k];
+            if (i + D < r1)
+                load_row(i + D, ring[q]);
             if (UPD1) {
                 const double s1 = a.u1[i];
                 const double s2 = UPD2 ? a.u2[i] : 0.0;
                 double *brow = a.B + i * a.ldb;
 #pragma unroll
                 for (int k = 0; k < KV; ++k) {
-                    d2 b = v[u][k] + s1 * v1[k];
+                    d2 b = v[k] + s1 * v1[k];
                     if (UPD2) b = b + s2 * v2[k];
-                    v[u][k] = b;
+                    v[k] = b;
                     store_pair<VEC, FULL>(brow, c0 + 2 * (lane + kWave * k), n, b);
                 }
             }
@@ -124,14 +134,14 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int64_t ct, int64_t
                 const double yi = a.yc[i];
 #pragma unroll
                 for (int k = 0; k < KV; ++k)
-                    acc[k] += v[u][k] * yi;
+                    acc[k] += v[k] * yi;
             }
             if (ROWDOT) {
                 double p = 0.0;
 #pragma unroll
                 for (int k = 0; k < KV; ++k) {
-                    p += v[u][k].x * xr[k].x;
-                    p += v[u][k].y * xr[k].y;
+                    p += v[k].x * xr[k].x;
+                    p += v[k].y * xr[k].y;
                 }
                 p = wave_sum(p);
                 if (lane == (int)(i - r0))
@@ -139,85 +149,159 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int64_t ct, int64_t
             }
         }
     }
+}
 
-    if (ROWDOT) {
+template <int KV, int D, int WC, int WR, int OPS, bool VEC>
+__global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int rev)
+{
+    constexpr bool ROWDOT = OPS & OP_ROWDOT;
+    constexpr bool COLSUM = OPS & OP_COLSUM;
+    constexpr int CTW = 128 * KV;          // wave tile width (columns)
+    constexpr int CTB = WC * CTW;          // workgroup tile width
+    constexpr int NT = kWave * WC * WR;    // threads
+    __shared__ double lds[(COLSUM && WR > 1) ? WR * CTB : 1];
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wc = wave % WC, wr = wave / WC;
+    const int64_t band = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
+    const int64_t ctw = (int64_t)blockIdx.x * WC + wc;
+    const int64_t c0 = ctw * CTW;
+    const int rpw = rb / WR;
+    const int64_t r0 = band * rb + (int64_t)wr * rpw;
+    const int64_t r1 = r0 + rpw < a.m ? r0 + rpw : a.m;
+
+    d2 acc[KV];
+#pragma unroll
+    for (int k = 0; k < KV; ++k)
+        acc[k] = d2{0.0, 0.0};
+    double mine = 0.0;
+    if (c0 < a.n) {
+        if (c0 + CTW <= a.n)
+            tile_rows<KV, D, OPS, VEC, true>(a, c0, r0, r1, lane, acc, mine);
+        else
+            tile_rows<KV, D, OPS, VEC, false>(a, c0, r0, r1, lane, acc, mine);
+    }
+
+    if (ROWDOT && c0 < a.n) {
         if (lane < r1 - r0)
-            a.Prow[ct * a.m + r0 + lane] = mine;
+            a.Prow[ctw * a.m + r0 + lane] = mine;
     }
     if (COLSUM) {
-        // combine the four waves' column sums in wave order
+        if constexpr (WR == 1) {
 #pragma unroll
-        for (int k = 0; k < KV; ++k) {
-            const int c = 2 * (lane + kWave * k);
-            lds[wave * CT + c] = acc[k].x;
-            lds[wave * CT + c + 1] = acc[k].y;
-        }
-        lds_barrier();
-        for (int c = threadIdx.x; c < CT; c += kTileThreads) {
-            const int64_t j = c0 + c;
-            if (j < n) {
-                double s = ((lds[c] + lds[CT + c]) + lds[2 * CT + c]) + lds[3 * CT + c];
-                a.Pcol[rb * n + j] = s;
+            for (int k = 0; k < KV; ++k) {
+                const int64_t j = c0 + 2 * (lane + kWave * k);
+                if (j < a.n) a.Pcol[band * a.n + j] = acc[k].x;
+                if (j + 1 < a.n) a.Pcol[band * a.n + j + 1] = acc[k].y;
+            }
+        } else {
+            // combine the WR row groups' column sums in row-group order
+#pragma unroll
+            for (int k = 0; k < KV; ++k) {
+                const int c = wc * CTW + 2 * (lane + kWave * k);
+                lds[wr * CTB + c] = acc[k].x;
+                lds[wr * CTB + c + 1] = acc[k].y;
+            }
+            lds_barrier();
+            const int64_t cb = (int64_t)blockIdx.x * CTB;
+            for (int c = threadIdx.x; c < CTB; c += NT) {
+                const int64_t j = cb + c;
+                if (j < a.n) {
+                    double s = lds[c];
+#pragma unroll
+                    for (int r = 1; r < WR; ++r)
+                        s += lds[r * CTB + c];
+                    a.Pcol[band * a.n + j] = s;
+                }
             }
         }
     }
 }
 
-template <int KV, int RU, int OPS, bool VEC>
-__global__ __launch_bounds__(kTileThreads) void k_tile(TileArgs a, int rbrows, int rev)
+// The tile shapes instantiated for each family of sweeps.
+struct Shape {
+    int kv, d, wc, wr;
+};
+const Shape kShapes[] = {
+    // read-only sweeps (row dots, column sums, both)
+    {8, 2, 4, 1}, {8, 1, 4, 4}, {4, 2, 8, 2}, {4, 2, 4, 4}, {4, 4, 4, 1}, {8, 2, 4, 2},
+    // sweeps that store B
+    {2, 2, 1, 4}, {2, 4, 1, 4}, {4, 2, 1, 4}, {4, 4, 1, 4}, {2, 3, 1, 16},
+};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+constexpr int kFirstWriteShape = 6;
+
+bool shape_allowed(int ops, int shape)
 {
-    __shared__ double lds[(OPS & OP_COLSUM) ? 4 * 128 * KV : 1];
-    const int64_t ct = blockIdx.x;
-    const int64_t rb = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
-    const bool full = (ct + 1) * (128 * KV) <= a.n;
-    if (full)
-        tile_body<KV, RU, OPS, VEC, true>(a, ct, rb, rbrows, lds);
-    else
-        tile_body<KV, RU, OPS, VEC, false>(a, ct, rb, rbrows, lds);
+    if (shape < 0 || shape >= kNumShapes)
+        return false;
+    // 16 waves of 8-pair lanes cannot hold both row-dot weights and column
+    // accumulators in the 128 registers a 1024-thread workgroup allows
+    if (shape == 1 && (ops & OP_ROWDOT) && (ops & OP_COLSUM))
+        return false;
+    const bool writes = ops & OP_UPD1;
+    return writes ? shape >= kFirstWriteShape : shape < kFirstWriteShape;
 }
 
-template <int KV, int RU, int OPS>
+template <int KV, int D, int WC, int WR, int OPS>
 void launch_tile_t(const char *name, const TileCfg &c, const TileArgs &a, hipStream_t st)
 {
-    dim3 grid((unsigned)tile_ncols(c, a.n), (unsigned)tile_nbands(c, a.m));
+    dim3 grid((unsigned)ceil_div(a.n, WC * 128 * KV), (unsigned)ceil_div(a.m, c.rb));
     bool vec = aligned16(a.A) && (a.lda % 2 == 0);
     if (OPS & OP_UPD1)
         vec = vec && aligned16(a.B) && (a.ldb % 2 == 0);
+    dim3 block(kWave * WC * WR);
     if (vec)
-        launch(name, k_tile<KV, RU, OPS, true>, grid, dim3(kTileThreads), st, a, c.rb, c.rev);
+        launch(name, k_tile<KV, D, WC, WR, OPS, true>, grid, block, st, a, c.rb, c.rev);
     else
-        launch(name, k_tile<KV, RU, OPS, false>, grid, dim3(kTileThreads), st, a, c.rb, c.rev);
+        launch(name, k_tile<KV, D, WC, WR, OPS, false>, grid, block, st, a, c.rb, c.rev);
 }
 
 template <int OPS>
-bool launch_tile_ops(const char *name, const TileCfg &c, const TileArgs &a, hipStream_t st)
+void launch_tile_ops(const char *name, const TileCfg &c, const TileArgs &a, hipStream_t st)
 {
-#define BTO_TILE_CASE(KV_, RU_)                                       \
-    if (c.kv == KV_ && c.ru == RU_) {                                 \
-        if (st != (hipStream_t)-1)                                    \
-            launch_tile_t<KV_, RU_, OPS>(name, c, a, st);             \
-        return true;                                                  \
+    constexpr bool W = OPS & OP_UPD1;
+#define BTO_SHAPE(IDX, KV_, D_, WC_, WR_)                           \
+    case IDX:                                                       \
+        launch_tile_t<KV_, D_, WC_, WR_, OPS>(name, c, a, st);      \
+        return;
+    if constexpr (!W) {
+        switch (c.shape) {
+            BTO_SHAPE(0, 8, 2, 4, 1)
+        case 1:
+            if constexpr (!((OPS & OP_ROWDOT) && (OPS & OP_COLSUM)))
+                launch_tile_t<8, 1, 4, 4, OPS>(name, c, a, st);
+            return;
+            BTO_SHAPE(2, 4, 2, 8, 2)
+            BTO_SHAPE(3, 4, 2, 4, 4)
+            BTO_SHAPE(4, 4, 4, 4, 1)
+            BTO_SHAPE(5, 8, 2, 4, 2)
+        default: return;
+        }
+    } else {
+        switch (c.shape) {
+            BTO_SHAPE(6, 2, 2, 1, 4)
+            BTO_SHAPE(7, 2, 4, 1, 4)
+            BTO_SHAPE(8, 4, 2, 1, 4)
+            BTO_SHAPE(9, 4, 4, 1, 4)
+            BTO_SHAPE(10, 2, 3, 1, 16)
+        default: return;
+        }
     }
-    BTO_TILE_CASE(2, 2)
-    BTO_TILE_CASE(2, 4)
-    BTO_TILE_CASE(4, 2)
-    BTO_TILE_CASE(4, 4)
-    BTO_TILE_CASE(8, 1)
-    BTO_TILE_CASE(8, 2)
-#undef BTO_TILE_CASE
-    return false;
+#undef BTO_SHAPE
 }
 
-bool dispatch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st)
+void dispatch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st)
 {
     switch (ops) {
-    case OP_ROWDOT: return launch_tile_ops<OP_ROWDOT>(name, c, a, st);
-    case OP_COLSUM: return launch_tile_ops<OP_COLSUM>(name, c, a, st);
-    case OP_ROWDOT | OP_COLSUM: return launch_tile_ops<OP_ROWDOT | OP_COLSUM>(name, c, a, st);
-    case OP_UPD1: return launch_tile_ops<OP_UPD1>(name, c, a, st);
+    case OP_ROWDOT: launch_tile_ops<OP_ROWDOT>(name, c, a, st); break;
+    case OP_COLSUM: launch_tile_ops<OP_COLSUM>(name, c, a, st); break;
+    case OP_ROWDOT | OP_COLSUM: launch_tile_ops<OP_ROWDOT | OP_COLSUM>(name, c, a, st); break;
+    case OP_UPD1: launch_tile_ops<OP_UPD1>(name, c, a, st); break;
     case OP_UPD1 | OP_UPD2 | OP_COLSUM:
-        return launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_COLSUM>(name, c, a, st);
-    default: return false;
+        launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_COLSUM>(name, c, a, st);
+        break;
+    default: break;
     }
 }
 
@@ -372,18 +456,42 @@ constexpr int kCUs = 256;
 
 bool tile_cfg_supported(int ops, const TileCfg &c)
 {
+    if (!shape_allowed(ops, c.shape) || (c.rev != 0 && c.rev != 1))
+        return false;
+    const Shape &s = kShapes[c.shape];
+    if (c.rb < s.wr || c.rb % s.wr != 0 || c.rb > 4096)
+        return false;
+    // row-dot results are gathered one row per lane: at most 64 rows per wave
+    if ((ops & OP_ROWDOT) && c.rb / s.wr > kWave)
+        return false;
     // rb >= 32 keeps the column-sum partials within the workspace the C
     // entry points size for (at most ceil(m / 32) row bands)
-    if (c.rb < 32 || c.rb > 256 || c.rb % 4 != 0 || (c.rev != 0 && c.rev != 1))
+    if ((ops & OP_COLSUM) && c.rb < 32)
         return false;
-    return dispatch_tile("", ops, c, TileArgs{}, (hipStream_t)-1);
+    return true;
 }
 
-void launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st)
+int tile_kv(const TileCfg &c) { return kShapes[c.shape].kv; }
+
+void tile_shape_info(int shape, int out[4])
 {
+    const Shape &s = kShapes[shape];
+    out[0] = s.kv;
+    out[1] = s.d;
+    out[2] = s.wc;
+    out[3] = s.wr;
+}
+
+int64_t tile_ncols(const TileCfg &c, int64_t n) { return ceil_div(n, 128 * kShapes[c.shape].kv); }
+
+bool launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st)
+{
+    if (!tile_cfg_supported(ops, c))
+        return false;
     if (a.m <= 0 || a.n <= 0)
-        return;
+        return true;
     dispatch_tile(name, ops, c, a, st);
+    return true;
 }
 
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st)

@@ -11,8 +11,9 @@ namespace bto {
 
 namespace {
 
-constexpr int kBlock = 256;
-constexpr int kUnroll = 4;  // pairs per thread in the elementwise sweeps
+constexpr int kBlock = 256;       // threads per workgroup of the dot products
+constexpr int kEwBlock = 128;     // threads per workgroup of the elementwise sweeps
+constexpr int kUnroll = 4;        // pairs per thread in the dot products
 
 template <int OP>
 __device__ __forceinline__ d2 ew_apply(d2 a, d2 b, d2 c, double s0, double s1)
@@ -44,56 +45,35 @@ constexpr int ew_inputs()
     return OP == EW_VADD3 ? 3 : (OP == EW_SCAL ? 1 : 2);
 }
 
-// out = op(a, b, c) over n elements.  No __restrict__: `out` may be exactly
-// one of the inputs; each thread reads all of its elements before writing.
+// out = op(a, b, c) over n elements, one 16-byte pair per thread: short-lived
+// waves that load, compute, store and retire stream best when each element is
+// both read and written.  No __restrict__: `out` may be exactly one of the
+// inputs; each thread reads its elements before writing them.
 template <int OP, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_ew(int64_t n, const double *a, const double *b,
-                                               const double *c, double s0, double s1,
-                                               double *out)
+__global__ __launch_bounds__(kEwBlock) void k_ew(int64_t n, const double *a, const double *b,
+                                                 const double *c, double s0, double s1,
+                                                 double *out)
 {
     constexpr int NIN = ew_inputs<OP>();
     if constexpr (VEC) {
-        const int64_t npair = n >> 1;
-        const int64_t base = (int64_t)blockIdx.x * (kBlock * kUnroll) + threadIdx.x;
-        d2 va[kUnroll], vb[kUnroll], vc[kUnroll];
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t p = base + (int64_t)u * kBlock;
-            va[u] = vb[u] = vc[u] = d2{0.0, 0.0};
-            if (p < npair) {
-                va[u] = ld2_nt(a + 2 * p);
-                if (NIN > 1) vb[u] = ld2_nt(b + 2 * p);
-                if (NIN > 2) vc[u] = ld2_nt(c + 2 * p);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int64_t p = base + (int64_t)u * kBlock;
-            if (p < npair)
-                st2_nt(out + 2 * p, ew_apply<OP>(va[u], vb[u], vc[u], s0, s1));
+        const int64_t p = (int64_t)blockIdx.x * kEwBlock + threadIdx.x;
+        if (p < (n >> 1)) {
+            d2 va = ld2_nt(a + 2 * p), vb{0.0, 0.0}, vc{0.0, 0.0};
+            if (NIN > 1) vb = ld2_nt(b + 2 * p);
+            if (NIN > 2) vc = ld2_nt(c + 2 * p);
+            st2_nt(out + 2 * p, ew_apply<OP>(va, vb, vc, s0, s1));
         }
         if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
             const int64_t k = n - 1;
             out[k] = ew_apply1<OP>(a[k], NIN > 1 ? b[k] : 0.0, NIN > 2 ? c[k] : 0.0, s0, s1);
         }
     } else {
-        const int64_t base = (int64_t)blockIdx.x * (kBlock * kUnroll * 2) + threadIdx.x;
-        double va[2 * kUnroll], vb[2 * kUnroll], vc[2 * kUnroll];
+        const int64_t base = (int64_t)blockIdx.x * (2 * kEwBlock) + threadIdx.x;
 #pragma unroll
-        for (int u = 0; u < 2 * kUnroll; ++u) {
-            const int64_t k = base + (int64_t)u * kBlock;
-            va[u] = vb[u] = vc[u] = 0.0;
-            if (k < n) {
-                va[u] = a[k];
-                if (NIN > 1) vb[u] = b[k];
-                if (NIN > 2) vc[u] = c[k];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < 2 * kUnroll; ++u) {
-            const int64_t k = base + (int64_t)u * kBlock;
+        for (int u = 0; u < 2; ++u) {
+            const int64_t k = base + (int64_t)u * kEwBlock;
             if (k < n)
-                out[k] = ew_apply1<OP>(va[u], vb[u], vc[u], s0, s1);
+                out[k] = ew_apply1<OP>(a[k], NIN > 1 ? b[k] : 0.0, NIN > 2 ? c[k] : 0.0, s0, s1);
         }
     }
 }
@@ -107,135 +87,119 @@ void launch_ew_t(int64_t n, const double *a, const double *b, const double *c, d
                (NIN < 3 || aligned16(c));
     static const char *names[] = {"ew_vadd3", "ew_add2", "ew_waxpby", "ew_scal", "ew_axpy",
                                   "ew_axmy"};
-    const int64_t per_block = kBlock * kUnroll * 2;
-    dim3 grid((unsigned)ceil_div(n, per_block));
+    dim3 grid((unsigned)ceil_div(n, 2 * kEwBlock));
     if (vec)
-        launch(names[OP], k_ew<OP, true>, grid, dim3(kBlock), st, n, a, b, c, s0, s1, out);
+        launch(names[OP], k_ew<OP, true>, grid, dim3(kEwBlock), st, n, a, b, c, s0, s1, out);
     else
-        launch(names[OP], k_ew<OP, false>, grid, dim3(kBlock), st, n, a, b, c, s0, s1, out);
+        launch(names[OP], k_ew<OP, false>, grid, dim3(kEwBlock), st, n, a, b, c, s0, s1, out);
 }
 
 // ---- deterministic dot products ------------------------------------------
 //
-// The vector is cut into dot_parts(n) contiguous chunks of dot_chunk(n)
-// elements (a multiple of 512).  Each workgroup sums its chunk with four
-// rotating pair accumulators per thread, then lanes, then waves, always in
-// the same order, and writes one partial; a single workgroup then sums the
-// partials in a fixed tree.  The result depends on n only.
+// Workgroup b owns elements [2048 b, 2048 (b+1)): thread t takes pairs
+// 1024 b + t + 256 u (u = 0..3), sums its four products in u order, then
+// lanes, then waves, always in the same order, and writes one partial.  A
+// single 1024-thread workgroup then sums the partials in a fixed tree.  The
+// result depends on n only.
 
-int64_t dot_chunk(int64_t n)
-{
-    int64_t c = ceil_div(n, 2048);
-    c = ceil_div(c, 512) * 512;
-    return c < 4096 ? 4096 : c;
-}
+constexpr int64_t kDotTile = 2 * kBlock * kUnroll;   // elements per workgroup
 
-__device__ __forceinline__ double block_sum_256(double v, double *lds4)
+__device__ __forceinline__ double block_sum(double v, double *lds, int nwaves)
 {
     v = wave_sum(v);
     const int wave = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
-        lds4[wave] = v;
+        lds[wave] = v;
     lds_barrier();
-    return ((lds4[0] + lds4[1]) + lds4[2]) + lds4[3];
+    double s = lds[0];
+    for (int w = 1; w < nwaves; ++w)
+        s += lds[w];
+    return s;
 }
 
 // FUSED: z = w - alpha*v is stored and the partial of z.u is formed in the
 // same sweep.  Otherwise the partial of w.u (v and z are not touched).
 template <bool FUSED, bool VEC>
-__global__ __launch_bounds__(kBlock) void k_dot_part(int64_t n, int64_t chunk, double alpha,
-                                                     const double *w, const double *v,
-                                                     const double *u, double *z,
+__global__ __launch_bounds__(kBlock) void k_dot_part(int64_t n, double alpha, const double *w,
+                                                     const double *v, const double *u, double *z,
                                                      double *parts)
 {
-    __shared__ double lds4[4];
-    const int64_t lo = (int64_t)blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    d2 acc[4] = {d2{0.0, 0.0}, d2{0.0, 0.0}, d2{0.0, 0.0}, d2{0.0, 0.0}};
+    __shared__ double lds[kBlock / kWave];
+    d2 acc{0.0, 0.0};
     if constexpr (VEC) {
-        // chunk is even, so lo is even; pairs [lo/2, hi/2)
-        const int64_t p0 = lo / 2, p1 = hi / 2;
-        int64_t p = p0 + threadIdx.x;
-        for (; p + 3 * kBlock < p1; p += 4 * kBlock) {
-            d2 a[4], b[4], c[4];
+        const int64_t npair = n >> 1;
+        const int64_t base = (int64_t)blockIdx.x * (kBlock * kUnroll) + threadIdx.x;
+        d2 a[kUnroll], b[kUnroll], c[kUnroll];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                a[k] = ld2_nt(w + 2 * (p + k * kBlock));
-                b[k] = ld2_nt(u + 2 * (p + k * kBlock));
-                if (FUSED) c[k] = ld2_nt(v + 2 * (p + k * kBlock));
+        for (int k = 0; k < kUnroll; ++k) {
+            const int64_t p = base + (int64_t)k * kBlock;
+            a[k] = b[k] = c[k] = d2{0.0, 0.0};
+            if (p < npair) {
+                a[k] = ld2_nt(w + 2 * p);
+                b[k] = ld2_nt(u + 2 * p);
+                if (FUSED) c[k] = ld2_nt(v + 2 * p);
             }
+        }
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kUnroll; ++k) {
+            const int64_t p = base + (int64_t)k * kBlock;
+            if (p < npair) {
                 d2 zz = a[k];
                 if (FUSED) {
                     zz = a[k] - alpha * c[k];
-                    st2_nt(z + 2 * (p + k * kBlock), zz);
+                    st2_nt(z + 2 * p, zz);
                 }
-                acc[k] += zz * b[k];
+                acc += zz * b[k];
             }
         }
-        for (int k = 0; p < p1; p += kBlock, ++k) {
-            d2 a = ld2_nt(w + 2 * p), b = ld2_nt(u + 2 * p);
-            d2 zz = a;
-            if (FUSED) {
-                zz = a - alpha * ld2_nt(v + 2 * p);
-                st2_nt(z + 2 * p, zz);
-            }
-            acc[k & 3] += zz * b;
-        }
-        if ((hi & 1) && hi == n && threadIdx.x == 0) {
+        if ((n & 1) && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
             const int64_t k = n - 1;
             double zz = w[k];
             if (FUSED) {
                 zz = w[k] - alpha * v[k];
                 z[k] = zz;
             }
-            acc[0].x += zz * u[k];
+            acc.x += zz * u[k];
         }
     } else {
-        int k = 0;
-        for (int64_t e = lo + threadIdx.x; e < hi; e += kBlock, ++k) {
-            double zz = w[e];
-            if (FUSED) {
-                zz = w[e] - alpha * v[e];
-                z[e] = zz;
+        const int64_t base = (int64_t)blockIdx.x * kDotTile + threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < 2 * kUnroll; ++k) {
+            const int64_t e = base + (int64_t)k * kBlock;
+            if (e < n) {
+                double zz = w[e];
+                if (FUSED) {
+                    zz = w[e] - alpha * v[e];
+                    z[e] = zz;
+                }
+                if (k & 1) acc.y += zz * u[e]; else acc.x += zz * u[e];
             }
-            double t = zz * u[e];
-            if (k & 1) acc[(k >> 1) & 3].y += t; else acc[(k >> 1) & 3].x += t;
         }
     }
-    d2 s2 = (acc[0] + acc[1]) + (acc[2] + acc[3]);
-    double s = block_sum_256(s2.x + s2.y, lds4);
+    double s = block_sum(acc.x + acc.y, lds, kBlock / kWave);
     if (threadIdx.x == 0)
         parts[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_dot_finish(int64_t nparts, const double *parts,
-                                                       double *r)
+constexpr int kFinishBlock = 1024;
+
+__global__ __launch_bounds__(kFinishBlock) void k_dot_finish(int64_t nparts,
+                                                             const double *parts, double *r)
 {
-    __shared__ double lds4[4];
+    __shared__ double lds[kFinishBlock / kWave];
     double s = 0.0;
-    for (int64_t k = threadIdx.x; k < nparts; k += kBlock)
+    for (int64_t k = threadIdx.x; k < nparts; k += kFinishBlock)
         s += parts[k];
-    s = block_sum_256(s, lds4);
+    s = block_sum(s, lds, kFinishBlock / kWave);
     if (threadIdx.x == 0)
         *r = s;
 }
 
-__global__ __launch_bounds__(kBlock) void k_copy(int64_t npair, const double *src, double *dst)
+__global__ __launch_bounds__(kEwBlock) void k_copy(int64_t npair, const double *src, double *dst)
 {
-    const int64_t base = (int64_t)blockIdx.x * (kBlock * kUnroll) + threadIdx.x;
-    d2 v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const int64_t p = base + (int64_t)u * kBlock;
-        if (p < npair) v[u] = ld2_nt(src + 2 * p);
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        const int64_t p = base + (int64_t)u * kBlock;
-        if (p < npair) st2_nt(dst + 2 * p, v[u]);
-    }
+    const int64_t p = (int64_t)blockIdx.x * kEwBlock + threadIdx.x;
+    if (p < npair)
+        st2_nt(dst + 2 * p, ld2_nt(src + 2 * p));
 }
 
 }  // namespace
@@ -257,28 +221,28 @@ void launch_ew(EwOp op, int64_t n, const double *a, const double *b, const doubl
 
 int64_t dot_parts(int64_t n)
 {
-    return n <= 0 ? 0 : ceil_div(n, dot_chunk(n));
+    return n <= 0 ? 0 : ceil_div(n, kDotTile);
 }
 
 void launch_dot(bool fused_axpy, int64_t n, double alpha, const double *w, const double *v,
                 const double *u, double *z, double *parts, double *r, hipStream_t st)
 {
     const int64_t np = dot_parts(n);
-    const int64_t chunk = dot_chunk(n);
     bool vec = aligned16(w) && aligned16(u) && (!fused_axpy || (aligned16(v) && aligned16(z)));
     dim3 grid((unsigned)np), block(kBlock);
     if (fused_axpy) {
         if (vec)
-            launch("axpydot_fused", k_dot_part<true, true>, grid, block, st, n, chunk, alpha, w, v, u, z, parts);
+            launch("axpydot_fused", k_dot_part<true, true>, grid, block, st, n, alpha, w, v, u, z, parts);
         else
-            launch("axpydot_fused", k_dot_part<true, false>, grid, block, st, n, chunk, alpha, w, v, u, z, parts);
+            launch("axpydot_fused", k_dot_part<true, false>, grid, block, st, n, alpha, w, v, u, z, parts);
     } else {
         if (vec)
-            launch("dot_part", k_dot_part<false, true>, grid, block, st, n, chunk, alpha, w, v, u, z, parts);
+            launch("dot_part", k_dot_part<false, true>, grid, block, st, n, alpha, w, v, u, z, parts);
         else
-            launch("dot_part", k_dot_part<false, false>, grid, block, st, n, chunk, alpha, w, v, u, z, parts);
+            launch("dot_part", k_dot_part<false, false>, grid, block, st, n, alpha, w, v, u, z, parts);
     }
-    launch("dot_finish", k_dot_finish, dim3(1), block, st, np, (const double *)parts, r);
+    launch("dot_finish", k_dot_finish, dim3(1), dim3(kFinishBlock), st, np, (const double *)parts,
+           r);
 }
 
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t st)
@@ -290,8 +254,8 @@ void launch_copy(int64_t n, const double *src, double *dst, hipStream_t st)
         return;
     }
     const int64_t npair = n / 2;
-    launch("probe_copy", k_copy, dim3((unsigned)ceil_div(npair, kBlock * kUnroll)), dim3(kBlock),
-           st, npair, src, dst);
+    launch("probe_copy", k_copy, dim3((unsigned)ceil_div(npair, kEwBlock)), dim3(kEwBlock), st,
+           npair, src, dst);
 }
 
 void launch_triad(int64_t n, double *a, const double *b, const double *c, double s,
