@@ -1,0 +1,347 @@
+"""Autotuner for the fused kernels: the GPU counterpart of the paper's search.
+
+The paper (Section IV) searches loop fusion, the partitioned axis and the
+thread count of each loop nest with MFGA: start from the Max-Fuse organism,
+build a population by mutation, evolve it by tournament selection (k = 2)
+and crossover, cache every fitness, then sweep the global thread count.  It
+also shows (Section V-D1) that searching fusion first and the thread count
+second, the orthogonal search, finds the same best versions at a fraction of
+the cost.
+
+Here an organism is
+  form   -- "fused" (the max-fuse point: every statement sharing a matrix pass
+            runs in one sweep) or "unfused" (one sweep per BLAS operation);
+  slots  -- for each matrix sweep the chosen form launches, its tile
+            configuration (shape, rb, rev): the tile shape fixes the lane
+            width, rows in flight and the waves across / down a workgroup
+            (the partition axis and per-partition parallelism), rb the rows
+            per workgroup band (how many partitions: the thread-count knob),
+            rev the order the bands are walked.
+The four mutation kinds of the paper map to: toggle fusion, change rb
+(partition level), change the shape (partition axis), change rev or the
+shape's depth (the remaining per-partition parallelism).  Fitness is the
+measured time of one call on the device; every result is cached under its
+key and the cache persists as JSON, so a later search resumes from it.
+
+The evaluation function is pluggable: on the GPU it sets the configuration
+through the library and times the kernel with events; tests drive the same
+search with a deterministic cost table on the CPU.
+"""
+
+from __future__ import annotations
+
+import json
+import os
+import random
+from dataclasses import dataclass, field
+
+# Slots of the C library (order of bto_tune_slot_name).
+SLOT_BICGK_FUSED, SLOT_GEMV_N, SLOT_GEMV_T, SLOT_GER = 0, 1, 2, 3
+SLOT_GEMVER_P1, SLOT_GEMVER_P2, SLOT_DGEMVT_P1, SLOT_DGEMVT_P2 = 4, 5, 6, 7
+
+#: the matrix sweeps each kernel launches in each form
+KERNEL_SLOTS = {
+    ("bicgk", "fused"): [SLOT_BICGK_FUSED],
+    ("bicgk", "unfused"): [SLOT_GEMV_N, SLOT_GEMV_T],
+    ("gemver", "fused"): [SLOT_GEMVER_P1, SLOT_GEMVER_P2],
+    ("gemver", "unfused"): [SLOT_GER, SLOT_GEMV_T, SLOT_GEMV_N],
+    ("dgemvt", "fused"): [SLOT_DGEMVT_P1, SLOT_DGEMVT_P2],
+    ("dgemvt", "unfused"): [SLOT_GEMV_T, SLOT_GEMV_N],
+    ("atax", "fused"): [],
+    ("atax", "unfused"): [SLOT_GEMV_N, SLOT_GEMV_T],
+}
+
+RB_CHOICES = (4, 8, 16, 32, 64, 128, 256, 512)
+FORMS = ("fused", "unfused")
+
+
+@dataclass(frozen=True)
+class Organism:
+    form: str
+    slots: tuple  # ((slot, (shape, rb, rev)), ...) sorted by slot
+
+    def cfg(self) -> dict:
+        return dict(self.slots)
+
+    def key(self, kernel: str, m: int, n: int) -> str:
+        parts = [f"{kernel}:{m}x{n}:{self.form}"]
+        parts += [f"{s}={c[0]}/{c[1]}/{c[2]}" for s, c in self.slots]
+        return "|".join(parts)
+
+
+@dataclass
+class Space:
+    """The legal tile configurations of every slot (queried from the library,
+    which rejects what a slot cannot run)."""
+
+    legal: dict = field(default_factory=dict)   # slot -> list[(shape, rb, rev)]
+    defaults: dict = field(default_factory=dict)  # slot -> (shape, rb, rev)
+
+    @classmethod
+    def from_library(cls, bto, nshapes: int = 11) -> "Space":
+        sp = cls()
+        for slot in range(len(bto.tune_slots())):
+            default = bto.tune_get(slot)
+            sp.defaults[slot] = default
+            legal = []
+            for shape in range(nshapes):
+                for rb in RB_CHOICES:
+                    for rev in (0, 1):
+                        try:
+                            bto.tune_set(slot, shape, rb, rev)
+                            legal.append((shape, rb, rev))
+                        except bto.BtoError:
+                            pass
+            bto.tune_set(slot, *default)
+            sp.legal[slot] = legal
+        return sp
+
+
+class Tuner:
+    """Search driver.  `evaluate(kernel, m, n, organism) -> seconds` does
+    the measurement; results are cached by organism key."""
+
+    def __init__(self, space: Space, evaluate, cache_path: str | None = None, seed: int = 0):
+        self.space = space
+        self.evaluate = evaluate
+        self.cache_path = cache_path
+        self.cache: dict = {}
+        self.rng = random.Random(seed)
+        self.evaluations = 0
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f).get("fitness", {})
+
+    # ---- bookkeeping -------------------------------------------------------
+    def fitness(self, kernel: str, m: int, n: int, org: Organism) -> float:
+        key = org.key(kernel, m, n)
+        if key not in self.cache:
+            self.cache[key] = float(self.evaluate(kernel, m, n, org))
+            self.evaluations += 1
+        return self.cache[key]
+
+    def save(self, extra: dict | None = None) -> None:
+        if not self.cache_path:
+            return
+        data = {"fitness": self.cache}
+        if extra:
+            data.update(extra)
+        tmp = self.cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.cache_path)
+
+    def organism(self, kernel: str, form: str, cfg: dict | None = None) -> Organism:
+        slots = KERNEL_SLOTS[(kernel, form)]
+        cfg = cfg or {}
+        return Organism(form, tuple(sorted((s, tuple(cfg.get(s, self.space.defaults[s])))
+                                           for s in slots)))
+
+    # ---- max fuse ----------------------------------------------------------
+    def max_fuse(self, kernel: str) -> Organism:
+        """Every statement that shares a matrix pass fused, default geometry."""
+        return self.organism(kernel, "fused")
+
+    # ---- orthogonal search (fusion first, then geometry) ---------------------
+    def orthogonal(self, kernel: str, m: int, n: int) -> Organism:
+        best = min((self.organism(kernel, f) for f in FORMS),
+                   key=lambda o: self.fitness(kernel, m, n, o))
+        cfg = best.cfg()
+        for slot in KERNEL_SLOTS[(kernel, best.form)]:
+            for c in self.space.legal[slot]:
+                trial = self.organism(kernel, best.form, {**cfg, slot: c})
+                if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
+                    best, cfg = trial, trial.cfg()
+        return best
+
+    # ---- genetic search -------------------------------------------------------
+    def mutate(self, org: Organism) -> Organism:
+        kind = self.rng.randrange(4)
+        if kind == 0:                                  # add or remove fusion
+            form = "unfused" if org.form == "fused" else "fused"
+            return self.organism_like(org, form)
+        slots = KERNEL_SLOTS[(self._kernel, org.form)]
+        if not slots:
+            return self.organism_like(org, "unfused" if org.form == "fused" else "fused")
+        slot = self.rng.choice(slots)
+        shape, rb, rev = org.cfg()[slot]
+        legal = self.space.legal[slot]
+        if kind == 1:                                  # change the partition level (rb)
+            pool = [c for c in legal if c[0] == shape and c[2] == rev and c[1] != rb]
+        elif kind == 2:                                # change the partition axis (shape)
+            pool = [c for c in legal if c[0] != shape and c[1] == rb and c[2] == rev]
+        else:                                          # change the walk order
+            pool = [c for c in legal if c[0] == shape and c[1] == rb and c[2] != rev]
+        if not pool:
+            pool = [c for c in legal if c != (shape, rb, rev)] or [(shape, rb, rev)]
+        cfg = org.cfg()
+        cfg[slot] = self.rng.choice(pool)
+        return Organism(org.form, tuple(sorted(cfg.items())))
+
+    def organism_like(self, org: Organism, form: str) -> Organism:
+        """An organism of `form` keeping the configurations of slots both share."""
+        return self.organism(self._kernel, form, org.cfg())
+
+    def crossover(self, a: Organism, b: Organism) -> Organism:
+        """Outermost level first: pick the form from one parent, then each
+        slot's configuration from either parent that has that slot."""
+        form_parent = a if self.rng.random() < 0.5 else b
+        cfg = {}
+        for slot in KERNEL_SLOTS[(self._kernel, form_parent.form)]:
+            choices = [p.cfg()[slot] for p in (a, b) if slot in p.cfg()]
+            cfg[slot] = self.rng.choice(choices)
+        return self.organism(self._kernel, form_parent.form, cfg)
+
+    def tournament(self, pop: list, fit, k: int = 2) -> Organism:
+        contenders = [self.rng.choice(pop) for _ in range(k)]
+        return min(contenders, key=fit)
+
+    def mfga(self, kernel: str, m: int, n: int, population: int = 20, generations: int = 6,
+             k: int = 2, mutation_rate: float = 0.3) -> Organism:
+        self._kernel = kernel
+        fit = lambda o: self.fitness(kernel, m, n, o)
+        mf = self.max_fuse(kernel)
+        pop = [mf] + [self.mutate(mf) for _ in range(population - 1)]
+        best = min(pop, key=fit)
+        for _ in range(generations):
+            parents = [self.tournament(pop, fit, k) for _ in range(2 * population)]
+            children = []
+            for i in range(population):
+                child = self.crossover(parents[2 * i], parents[2 * i + 1])
+                if self.rng.random() < mutation_rate:
+                    child = self.mutate(child)
+                children.append(child)
+            pop = children
+            best = min([best] + pop, key=fit)
+        return self.sweep_rb(kernel, m, n, best)
+
+    def sweep_rb(self, kernel: str, m: int, n: int, org: Organism) -> Organism:
+        """The paper's final global thread-count sweep: for the best organism,
+        try every legal band height on every slot with its shape fixed."""
+        best = org
+        for slot in KERNEL_SLOTS[(kernel, org.form)]:
+            shape, _, rev = best.cfg()[slot]
+            for c in self.space.legal[slot]:
+                if c[0] == shape and c[2] == rev:
+                    trial = Organism(best.form, tuple(sorted({**best.cfg(), slot: c}.items())))
+                    if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
+                        best = trial
+        return best
+
+
+# ---- applying results --------------------------------------------------------------
+
+def apply(bto, org: Organism) -> None:
+    """Load an organism's slot configurations into the library."""
+    for slot, c in org.slots:
+        bto.tune_set(slot, *c)
+
+
+def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3):
+    """An evaluate() that times one call of a kernel on the current device.
+    `make_workload(kernel, m, n)` returns an object with run(form)."""
+    cache = {}
+
+    def evaluate(kernel, m, n, org):
+        key = (kernel, m, n)
+        if key not in cache:
+            cache.clear()
+            torch.cuda.empty_cache()
+            cache[key] = make_workload(kernel, m, n)
+        wl = cache[key]
+        saved = {s: bto.tune_get(s) for s, _ in org.slots}
+        try:
+            apply(bto, org)
+            for _ in range(warmup):
+                wl.run(org.form)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                wl.run(org.form)
+            stop.record()
+            stop.synchronize()
+            return start.elapsed_time(stop) / reps * 1e-3
+        finally:
+            for s, c in saved.items():
+                bto.tune_set(s, *c)
+
+    return evaluate
+
+
+# ---- command line: tune on the current device ---------------------------------------
+
+class _MatrixWorkload:
+    """Device-resident operands of one matrix kernel (synthetic, seeded)."""
+
+    def __init__(self, bto, torch, synth, kernel, m, n, dev):
+        self.bto, self.kernel = bto, kernel
+        d = lambda a: torch.from_numpy(a).to(dev)
+        sid = lambda op: synth.stream_id(7, op)
+        self.A = d(synth.matrix(synth.SEED, sid(0), m, n))
+        vm = lambda op: d(synth.uniform(synth.SEED, sid(op), m))
+        vn = lambda op: d(synth.uniform(synth.SEED, sid(op), n))
+        if kernel == "gemver":
+            self.args = [vm(1), vn(2), vm(3), vn(4), vm(5), vn(6)]
+            self.B = torch.empty_like(self.A)
+            self.x, self.w = vn(7), vm(8)
+        elif kernel == "bicgk":
+            self.p, self.r, self.q, self.s = vn(1), vm(2), vm(3), vn(4)
+        elif kernel == "atax":
+            self.xv, self.y = vn(1), vn(2)
+        else:
+            self.y, self.z, self.x, self.w = vm(1), vn(2), vn(3), vm(4)
+        self.ws = {f: torch.empty(max(1, bto.workspace_bytes(kernel, m, n, f)),
+                                  dtype=torch.uint8, device=dev) for f in FORMS}
+
+    def run(self, form):
+        b, ws = self.bto, self.ws[form]
+        if self.kernel == "gemver":
+            b.gemver(self.A, *self.args, 1.5, 0.7, form=form, B=self.B, x=self.x, w=self.w, ws=ws)
+        elif self.kernel == "bicgk":
+            b.bicgk(self.A, self.p, self.r, form=form, q=self.q, s=self.s, ws=ws)
+        elif self.kernel == "atax":
+            b.atax(self.A, self.xv, form=form, y=self.y, ws=ws)
+        else:
+            b.dgemvt(self.A, self.y, self.z, 1.5, 0.7, form=form, x=self.x, w=self.w, ws=ws)
+
+
+def main(argv=None) -> int:
+    import argparse
+    import time
+
+    import torch
+
+    from paper_1205_1098_amd import bto, synth
+
+    ap = argparse.ArgumentParser(description="tune tile configurations on this device")
+    ap.add_argument("--kernels", nargs="+", default=["bicgk", "gemver", "dgemvt", "atax"])
+    ap.add_argument("--m", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--strategy", choices=["orth", "mfga"], default="orth")
+    ap.add_argument("--cache", default=None, help="fitness cache (JSON) to resume from / write")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    dev = torch.device("cuda:0")
+    space = Space.from_library(bto)
+    ev = gpu_evaluator(bto, torch, lambda k, m, n: _MatrixWorkload(bto, torch, synth, k, m, n, dev))
+    tuner = Tuner(space, ev, args.cache, args.seed)
+    best = {}
+    for k in args.kernels:
+        t0 = time.perf_counter()
+        org = tuner.orthogonal(k, args.m, args.n) if args.strategy == "orth" else \
+            tuner.mfga(k, args.m, args.n)
+        mf = tuner.fitness(k, args.m, args.n, tuner.max_fuse(k))
+        got = tuner.fitness(k, args.m, args.n, org)
+        best[k] = {"form": org.form, "slots": {bto.tune_slots()[s]: list(c) for s, c in org.slots},
+                   "ms": round(got * 1e3, 4), "max_fuse_ms": round(mf * 1e3, 4),
+                   "search_s": round(time.perf_counter() - t0, 2)}
+        print(json.dumps({k: best[k]}), flush=True)
+    tuner.save({"best": best, "device": torch.cuda.get_device_properties(0).gcnArchName,
+                "m": args.m, "n": args.n})
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
