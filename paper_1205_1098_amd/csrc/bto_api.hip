@@ -107,7 +107,8 @@ size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
         size_t split = bytes_vec(m) + bytes_rowparts(m, n) + bytes_colparts(m, n);
         if (f == BTO_UNFUSED)
             return split;
-        int64_t g = atax_rowres_parts(m, n);
+        // sized for the largest grid any tunable workgroup size can give
+        int64_t g = atax_rowres_max_parts(m, n);
         size_t rowres = round256((size_t)(g * n) * 8);
         return g > 0 ? rowres : split;
     }
@@ -527,11 +528,12 @@ bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const do
                            vspan("y", y, n, true), wspan(ws, need_ws)},
                           {}));
 
-    const int64_t G = form == BTO_FUSED ? atax_rowres_parts(m, n) : 0;
+    const int threads = get_rowres_threads();
+    const int64_t G = form == BTO_FUSED ? atax_rowres_parts(m, n, threads) : 0;
     Carve cv(ws);
     if (G > 0) {
         double *P = cv.take(G * n);
-        launch_atax_rowres(m, n, A, lda, x, P, st);
+        launch_atax_rowres(m, n, A, lda, x, P, threads, st);
         launch_finish("finish", fjob(P, G, n, 1.0, nullptr, y), kNoJob, st);
     } else {
         double *t = cv.take(m);
@@ -720,10 +722,16 @@ void bto_timing_reset(void)
 
 // ---- tuning --------------------------------------------------------------------
 
-int bto_tune_slot_count(void) { return SLOT_COUNT; }
+// Slot SLOT_COUNT is the row-resident ATAX sweep: its "shape" is the
+// workgroup size (256, 512 or 1024 threads); rb and rev are 0.
+constexpr int kRowresSlot = SLOT_COUNT;
+
+int bto_tune_slot_count(void) { return SLOT_COUNT + 1; }
 
 const char *bto_tune_slot_name(int slot)
 {
+    if (slot == kRowresSlot)
+        return "atax_rowres";
     return (slot >= 0 && slot < SLOT_COUNT) ? kSlotNames[slot] : "";
 }
 
@@ -735,6 +743,13 @@ int bto_tune_slot_ops(int slot)
 bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
 {
     t_error.clear();
+    if (slot == kRowresSlot) {
+        std::lock_guard<std::mutex> g(g_cfg_mu);
+        if (shape) *shape = get_rowres_threads();
+        if (rb) *rb = 0;
+        if (rev) *rev = 0;
+        return BTO_SUCCESS;
+    }
     if (slot < 0 || slot >= SLOT_COUNT)
         return fail(BTO_ERR_INVALID_ARG, "slot out of range");
     TileCfg c = cfg_of(static_cast<Slot>(slot));
@@ -747,6 +762,12 @@ bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
 bto_status bto_tune_set(int slot, int shape, int rb, int rev)
 {
     t_error.clear();
+    if (slot == kRowresSlot) {
+        std::lock_guard<std::mutex> g(g_cfg_mu);
+        if (rb != 0 || rev != 0 || !set_rowres_threads(shape))
+            return fail(BTO_ERR_INVALID_ARG, "atax_rowres takes (256|512|1024, 0, 0)");
+        return BTO_SUCCESS;
+    }
     if (slot < 0 || slot >= SLOT_COUNT)
         return fail(BTO_ERR_INVALID_ARG, "slot out of range");
     TileCfg c{shape, rb, rev};

@@ -104,8 +104,11 @@ struct FinishJob {
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
 
 // Row-resident ATAX: each workgroup keeps one row of A on chip at a time.
-int64_t atax_rowres_parts(int64_t m, int64_t n);   // 0 when n is too wide
+int64_t atax_rowres_parts(int64_t m, int64_t n, int threads);   // 0 when n is too wide
+int64_t atax_rowres_max_parts(int64_t m, int64_t n);   // over every workgroup size
+bool set_rowres_threads(int t);                        // 256, 512 or 1024
+int get_rowres_threads();
 void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
-                        double *P, hipStream_t st);
+                        double *P, int threads, hipStream_t st);
 
 }  // namespace bto

@@ -22,6 +22,8 @@
 // and short bands.  Both families are instantiated below and the shape is a
 // run-time choice.
 
+#include <atomic>
+
 #include "bto_dev.hpp"
 #include "bto_internal.hpp"
 
@@ -119,8 +121,8 @@ __device__ __forceinline__ void tile_rows(const TileArgs &a, int64_t c0, int64_t
             if (i + D < r1)
                 load_row(i + D, ring[q]);
             if (UPD1) {
-                const double s1 = a.u1[i];
-                const double s2 = UPD2 ? a.u2[i] : 0.0;
+                const double s1 = ld_uniform(a.u1 + i);
+                const double s2 = UPD2 ? ld_uniform(a.u2 + i) : 0.0;
                 double *brow = a.B + i * a.ldb;
 #pragma unroll
                 for (int k = 0; k < KV; ++k) {
@@ -131,7 +133,7 @@ __device__ __forceinline__ void tile_rows(const TileArgs &a, int64_t c0, int64_t
                 }
             }
             if (COLSUM) {
-                const double yi = a.yc[i];
+                const double yi = ld_uniform(a.yc + i);
 #pragma unroll
                 for (int k = 0; k < KV; ++k)
                     acc[k] += v[k] * yi;
@@ -161,7 +163,11 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int 
     constexpr int NT = kWave * WC * WR;    // threads
     __shared__ double lds[(COLSUM && WR > 1) ? WR * CTB : 1];
 
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // The wave index is uniform across the wave; saying so keeps every row
+    // index scalar, so the per-row scalars (u1[i], y[i], ...) become scalar
+    // loads and never make a wave wait for its own prefetched rows.
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wc = wave % WC, wr = wave / WC;
     const int64_t band = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
     const int64_t ctw = (int64_t)blockIdx.x * WC + wc;
@@ -350,80 +356,143 @@ __global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int6
 //
 // y = A^T (A x) in one sweep of A: workgroup g owns rows [g*m/G, (g+1)*m/G).
 // For each row it loads the whole row into registers (NPT doubles per
-// thread), reduces t_i = A_i . x across the workgroup, and updates its
-// register copy of y with A_i^T t_i while the next row is already in
-// flight.  x sits in LDS.  This is the max-fuse organism of Section IV-A,
-// {p(i){i{j 1}{j 2}}}: the t_i reduction must finish before the update
-// (Section III-D), so the row stays on chip in between.
+// thread), reduces t_i = A_i . x across the workgroup, and then adds
+// A_i^T t_i to its copy of y while the next row is already in flight.  This
+// is the max-fuse organism of Section IV-A, {p(i){i{j 1}{j 2}}}: the t_i
+// reduction must finish before the update (Section III-D), so the row stays
+// on chip in between.
+//
+// Register budget: two whole rows (the one being applied and the next one)
+// plus x fill most of it, so each thread's slice of y lives in LDS instead
+// (only its owner ever touches it: no barrier).  Rows are read with buffer
+// loads: one lane offset in a vector register and the pair strides as
+// scalars.  The buffer's range (the even part of the row) returns zeros past
+// the row end; an odd last column is added by a scalar fix-up.
 
-template <int T, int NPT, bool VEC>
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferDword3 = 0x00020000;   // raw buffer descriptor word 3 on gfx9
+constexpr int kBufferNonTemporal = 2;
+
+template <int T, int NPT, bool VEC, bool ODD>
 __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const double *A,
                                                    int64_t lda, const double *x, double *P)
 {
     constexpr int NP = NPT / 2;     // pairs per thread
     constexpr int NW = T / kWave;   // waves per workgroup
-    __shared__ d2 xs[T * NP];
+    constexpr bool odd = VEC && ODD;   // n is odd: one column outside whole pairs
+    __shared__ d2 ys[T * NP];
     __shared__ double red[2][NW];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int p = tid; p < T * NP; p += T)
-        xs[p] = load_vec_pair(x, 2 * (int64_t)p, n);
-    lds_barrier();
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    d2 xv[NP], bufa[NP], bufb[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        xv[k] = load_vec_pair(x, 2 * (int64_t)(tid + T * k), n);
+        ys[tid + T * k] = d2{0.0, 0.0};
+        bufa[k] = d2{0.0, 0.0};
+        bufb[k] = d2{0.0, 0.0};
+    }
 
     const int64_t G = gridDim.x, g = blockIdx.x;
     const int64_t r0 = g * m / G, r1 = (g + 1) * m / G;
+    const int64_t nev = n & ~(int64_t)1;          // columns covered by whole pairs
+    const double xlast = odd ? x[n - 1] : 0.0;
+    // the thread and pair slot that own column n-1 when n is odd
+    const int64_t plast = (n - 1) / 2;
+    const bool own_last = odd && tid == (int)(plast % T);
+    const int klast = (int)(plast / T);
+    double lasta = 0.0, lastb = 0.0;
 
-    d2 yacc[NP], cur[NP], nxt[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        yacc[k] = d2{0.0, 0.0};
-        cur[k] = d2{0.0, 0.0};
-        nxt[k] = d2{0.0, 0.0};
-    }
-    auto load_row = [&](int64_t i, d2 *dst) {
+    auto load_row = [&](int64_t i, d2 (&dst)[NP], double &last) {
         const double *row = A + i * lda;
+        if constexpr (VEC) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<double *>(row), 0, (int)(nev * 8), kBufferDword3);
 #pragma unroll
-        for (int k = 0; k < NP; ++k) {
-            const int64_t j = 2 * (int64_t)(tid + T * k);
-            if (VEC && j + 1 < n)
-                dst[k] = ld2_nt(row + j);
-            else
-                dst[k] = load_pair<false, false>(row, j, n);
+            for (int k = 0; k < NP; ++k) {
+                const u4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, tid * 16, k * T * 16,
+                                                                   kBufferNonTemporal);
+                dst[k] = __builtin_bit_cast(d2, v);
+            }
+            if constexpr (odd)
+                last = ld_uniform(row + n - 1);
+        } else {
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                dst[k] = load_pair<false, false>(row, 2 * (int64_t)(tid + T * k), n);
         }
     };
-    if (r0 < r1)
-        load_row(r0, cur);
-    for (int64_t i = r0; i < r1; ++i) {
-        if (i + 1 < r1)
-            load_row(i + 1, nxt);
+    // t_i = A_i . x reduced over the workgroup, then y += A_i^T t_i
+    auto process = [&](int64_t i, const d2 (&cur)[NP], double last) {
         double part = 0.0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            const d2 xv = xs[tid + T * k];
-            part += cur[k].x * xv.x;
-            part += cur[k].y * xv.y;
+            part += cur[k].x * xv[k].x;
+            part += cur[k].y * xv[k].y;
         }
         part = wave_sum(part);
         const int buf = (int)(i & 1);
         if (lane == 0)
             red[buf][wave] = part;
         lds_barrier();
-        double t = 0.0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w)
-            t += red[buf][w];
+        // lane w < NW takes wave w's sum and a butterfly adds them: every
+        // wave gets the same t from the same fixed tree
+        double t = lane < NW ? red[buf][lane] : 0.0;
+        t = wave_sum(t);
+        if constexpr (odd)
+            t += last * xlast;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
-            yacc[k] += cur[k] * t;
-            cur[k] = nxt[k];
+            d2 yv = ys[tid + T * k];
+            yv += cur[k] * t;
+            if constexpr (odd) {
+                if (own_last && k == klast)
+                    yv.x += last * t;
+            }
+            ys[tid + T * k] = yv;
+            if (k % 2 == 1)
+                __builtin_amdgcn_sched_barrier(0);   // at most two y pairs in flight
         }
+    };
+    // two row buffers used in turn: the next row is always in flight while
+    // the current one is reduced and applied (the scheduling barriers stop
+    // the compiler from hoisting a buffer's reload above the update that
+    // still reads it, which would need a third row of registers)
+    // Inside the loop every load is unconditional, so the compiler can count
+    // exactly which loads a wait must cover; the last one or two rows are
+    // peeled off after it.
+    int64_t i = r0;
+    if (i < r1)
+        load_row(i, bufa, lasta);
+    for (; i + 2 < r1; i += 2) {
+        load_row(i + 1, bufb, lastb);
+        __builtin_amdgcn_sched_barrier(0);
+        process(i, bufa, lasta);
+        __builtin_amdgcn_sched_barrier(0);
+        load_row(i + 2, bufa, lasta);
+        __builtin_amdgcn_sched_barrier(0);
+        process(i + 1, bufb, lastb);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (i + 1 < r1) {
+        load_row(i + 1, bufb, lastb);
+        __builtin_amdgcn_sched_barrier(0);
+        process(i, bufa, lasta);
+        __builtin_amdgcn_sched_barrier(0);
+        process(i + 1, bufb, lastb);
+    } else if (i < r1) {
+        process(i, bufa, lasta);
+    }
+
     double *out = P + g * n;
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         const int64_t j = 2 * (int64_t)(tid + T * k);
-        if (j < n) out[j] = yacc[k].x;
-        if (j + 1 < n) out[j + 1] = yacc[k].y;
+        const d2 yv = ys[tid + T * k];
+        if (j < n) out[j] = yv.x;
+        if (j + 1 < n) out[j + 1] = yv.y;
     }
 }
 
@@ -431,19 +500,30 @@ struct RowresShape {
     int T, NPT;
 };
 
-// The narrowest (threads, doubles per thread) pair that covers n; T*NPT >= n.
-RowresShape rowres_shape(int64_t n)
+std::atomic<int> g_rowres_threads{1024};   // preferred workgroup size (tunable)
+
+// The workgroup size T (the preferred one first) and the fewest doubles per
+// thread NPT (even) with T*NPT >= n.
+RowresShape rowres_shape(int64_t n, int threads)
 {
-    static const RowresShape shapes[] = {{256, 2}, {256, 4}, {256, 8}, {512, 8}, {1024, 8}, {1024, 16}};
-    for (const RowresShape &s : shapes)
-        if ((int64_t)s.T * s.NPT >= n)
-            return s;
+    static const int npts[] = {2, 4, 8, 16, 32};
+    const int order[3][3] = {{1024, 512, 256}, {512, 1024, 256}, {256, 512, 1024}};
+    const int *pref = threads == 1024 ? order[0] : (threads == 512 ? order[1] : order[2]);
+    for (int o = 0; o < 3; ++o) {
+        const int T = pref[o];
+        for (int npt : npts) {
+            if (T == 1024 && npt > 16)
+                continue;   // two rows and y would not fit 128 registers
+            if ((int64_t)T * npt >= n)
+                return {T, npt};
+        }
+    }
     return {0, 0};
 }
 
 int rowres_blocks_per_cu(const RowresShape &s)
 {
-    // LDS holds x (T*NPT doubles); at most 160 KiB per CU.
+    // LDS holds the workgroup's y (T*NPT doubles); at most 160 KiB per CU.
     int by_lds = (int)(160 * 1024 / ((int64_t)s.T * s.NPT * 8 + 64));
     int by_threads = 2048 / s.T;
     int b = by_lds < by_threads ? by_lds : by_threads;
@@ -500,37 +580,77 @@ void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, h
     launch(name, k_finish, dim3((unsigned)(nb0 + nb1)), dim3(256), st, j0, j1, nb0);
 }
 
-int64_t atax_rowres_parts(int64_t m, int64_t n)
+bool set_rowres_threads(int t)
 {
-    RowresShape s = rowres_shape(n);
-    if (s.T == 0 || m <= 0 || n <= 0)
+    if (t != 256 && t != 512 && t != 1024)
+        return false;
+    g_rowres_threads = t;
+    return true;
+}
+
+int get_rowres_threads() { return g_rowres_threads.load(); }
+
+static int64_t rowres_parts_for(int64_t m, const RowresShape &s)
+{
+    if (s.T == 0 || m <= 0)
         return 0;
     int64_t g = (int64_t)kCUs * rowres_blocks_per_cu(s);
     return g < m ? g : m;
 }
 
-void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
-                        double *P, hipStream_t st)
+int64_t atax_rowres_parts(int64_t m, int64_t n, int threads)
 {
-    RowresShape s = rowres_shape(n);
-    const int64_t G = atax_rowres_parts(m, n);
+    if (n <= 0)
+        return 0;
+    return rowres_parts_for(m, rowres_shape(n, threads));
+}
+
+int64_t atax_rowres_max_parts(int64_t m, int64_t n)
+{
+    if (n <= 0)
+        return 0;
+    int64_t best = 0;
+    for (int t : {256, 512, 1024}) {
+        const int64_t p = rowres_parts_for(m, rowres_shape(n, t));
+        best = p > best ? p : best;
+    }
+    return best;
+}
+
+void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                        double *P, int threads, hipStream_t st)
+{
+    RowresShape s = rowres_shape(n, threads);
+    const int64_t G = atax_rowres_parts(m, n, threads);
     if (G == 0)
         return;
     const bool vec = aligned16(A) && lda % 2 == 0;
-#define BTO_ROWRES_CASE(T_, NPT_)                                                             \
-    if (s.T == T_ && s.NPT == NPT_) {                                                         \
-        if (vec)                                                                              \
-            launch("atax_rowres", k_atax_rowres<T_, NPT_, true>, dim3((unsigned)G), dim3(T_), \
-                   st, m, n, A, lda, x, P);                                                   \
-        else                                                                                  \
-            launch("atax_rowres", k_atax_rowres<T_, NPT_, false>, dim3((unsigned)G),          \
-                   dim3(T_), st, m, n, A, lda, x, P);                                         \
-        return;                                                                               \
+#define BTO_ROWRES_CASE(T_, NPT_)                                                              \
+    if (s.T == T_ && s.NPT == NPT_) {                                                          \
+        const dim3 g((unsigned)G), b(T_);                                                      \
+        if (vec && (n & 1))                                                                    \
+            launch("atax_rowres", k_atax_rowres<T_, NPT_, true, true>, g, b, st, m, n, A, lda, \
+                   x, P);                                                                      \
+        else if (vec)                                                                          \
+            launch("atax_rowres", k_atax_rowres<T_, NPT_, true, false>, g, b, st, m, n, A,     \
+                   lda, x, P);                                                                 \
+        else                                                                                   \
+            launch("atax_rowres", k_atax_rowres<T_, NPT_, false, false>, g, b, st, m, n, A,    \
+                   lda, x, P);                                                                 \
+        return;                                                                                \
     }
     BTO_ROWRES_CASE(256, 2)
     BTO_ROWRES_CASE(256, 4)
     BTO_ROWRES_CASE(256, 8)
+    BTO_ROWRES_CASE(256, 16)
+    BTO_ROWRES_CASE(256, 32)
+    BTO_ROWRES_CASE(512, 2)
+    BTO_ROWRES_CASE(512, 4)
     BTO_ROWRES_CASE(512, 8)
+    BTO_ROWRES_CASE(512, 16)
+    BTO_ROWRES_CASE(512, 32)
+    BTO_ROWRES_CASE(1024, 2)
+    BTO_ROWRES_CASE(1024, 4)
     BTO_ROWRES_CASE(1024, 8)
     BTO_ROWRES_CASE(1024, 16)
 #undef BTO_ROWRES_CASE

@@ -38,6 +38,7 @@ from dataclasses import dataclass, field
 # Slots of the C library (order of bto_tune_slot_name).
 SLOT_BICGK_FUSED, SLOT_GEMV_N, SLOT_GEMV_T, SLOT_GER = 0, 1, 2, 3
 SLOT_GEMVER_P1, SLOT_GEMVER_P2, SLOT_DGEMVT_P1, SLOT_DGEMVT_P2 = 4, 5, 6, 7
+SLOT_ATAX_ROWRES = 8   # its "shape" is the workgroup size of the row-resident sweep
 
 #: the matrix sweeps each kernel launches in each form
 KERNEL_SLOTS = {
@@ -47,7 +48,7 @@ KERNEL_SLOTS = {
     ("gemver", "unfused"): [SLOT_GER, SLOT_GEMV_T, SLOT_GEMV_N],
     ("dgemvt", "fused"): [SLOT_DGEMVT_P1, SLOT_DGEMVT_P2],
     ("dgemvt", "unfused"): [SLOT_GEMV_T, SLOT_GEMV_N],
-    ("atax", "fused"): [],
+    ("atax", "fused"): [SLOT_ATAX_ROWRES],
     ("atax", "unfused"): [SLOT_GEMV_N, SLOT_GEMV_T],
 }
 
@@ -84,8 +85,11 @@ class Space:
             default = bto.tune_get(slot)
             sp.defaults[slot] = default
             legal = []
-            for shape in range(nshapes):
-                for rb in RB_CHOICES:
+            shapes, rbs = range(nshapes), RB_CHOICES
+            if slot == SLOT_ATAX_ROWRES:
+                shapes, rbs = (256, 512, 1024), (0,)
+            for shape in shapes:
+                for rb in rbs:
                     for rev in (0, 1):
                         try:
                             bto.tune_set(slot, shape, rb, rev)
@@ -143,16 +147,25 @@ class Tuner:
         return self.organism(kernel, "fused")
 
     # ---- orthogonal search (fusion first, then geometry) ---------------------
-    def orthogonal(self, kernel: str, m: int, n: int) -> Organism:
-        best = min((self.organism(kernel, f) for f in FORMS),
-                   key=lambda o: self.fitness(kernel, m, n, o))
-        cfg = best.cfg()
-        for slot in KERNEL_SLOTS[(kernel, best.form)]:
-            for c in self.space.legal[slot]:
-                trial = self.organism(kernel, best.form, {**cfg, slot: c})
-                if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
-                    best, cfg = trial, trial.cfg()
-        return best
+    def orthogonal(self, kernel: str, m: int, n: int, forms=None) -> Organism:
+        """Fusion first (the better form at default geometry), then each of
+        its slots in turn over every legal configuration.  With `forms`
+        given, the geometry of each listed form is searched and the best
+        organism over them is returned (per-form bests in self.form_best)."""
+        if forms is None:
+            forms = [min(FORMS, key=lambda f: self.fitness(kernel, m, n,
+                                                           self.organism(kernel, f)))]
+        self.form_best = {}
+        for form in forms:
+            best = self.organism(kernel, form)
+            cfg = best.cfg()
+            for slot in KERNEL_SLOTS[(kernel, form)]:
+                for c in self.space.legal[slot]:
+                    trial = self.organism(kernel, form, {**cfg, slot: c})
+                    if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
+                        best, cfg = trial, trial.cfg()
+            self.form_best[form] = best
+        return min(self.form_best.values(), key=lambda o: self.fitness(kernel, m, n, o))
 
     # ---- genetic search -------------------------------------------------------
     def mutate(self, org: Organism) -> Organism:
@@ -321,6 +334,8 @@ def main(argv=None) -> int:
     ap.add_argument("--strategy", choices=["orth", "mfga"], default="orth")
     ap.add_argument("--cache", default=None, help="fitness cache (JSON) to resume from / write")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--forms", choices=["best", "both"], default="best",
+                    help="search the geometry of the better form only, or of both forms")
     args = ap.parse_args(argv)
 
     dev = torch.device("cuda:0")
@@ -330,13 +345,20 @@ def main(argv=None) -> int:
     best = {}
     for k in args.kernels:
         t0 = time.perf_counter()
-        org = tuner.orthogonal(k, args.m, args.n) if args.strategy == "orth" else \
+        forms = list(FORMS) if args.forms == "both" else None
+        org = tuner.orthogonal(k, args.m, args.n, forms) if args.strategy == "orth" else \
             tuner.mfga(k, args.m, args.n)
         mf = tuner.fitness(k, args.m, args.n, tuner.max_fuse(k))
         got = tuner.fitness(k, args.m, args.n, org)
-        best[k] = {"form": org.form, "slots": {bto.tune_slots()[s]: list(c) for s, c in org.slots},
+        names = bto.tune_slots()
+        best[k] = {"form": org.form, "slots": {names[s]: list(c) for s, c in org.slots},
                    "ms": round(got * 1e3, 4), "max_fuse_ms": round(mf * 1e3, 4),
                    "search_s": round(time.perf_counter() - t0, 2)}
+        if args.strategy == "orth" and forms:
+            best[k]["per_form"] = {
+                f: {"slots": {names[s]: list(c) for s, c in o.slots},
+                    "ms": round(tuner.fitness(k, args.m, args.n, o) * 1e3, 4)}
+                for f, o in tuner.form_best.items()}
         print(json.dumps({k: best[k]}), flush=True)
     tuner.save({"best": best, "device": torch.cuda.get_device_properties(0).gcnArchName,
                 "m": args.m, "n": args.n})
