@@ -55,7 +55,22 @@ def parse():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the 2 GiB copy probe (calibrates hardware byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(torch, bto, reps: int = 3) -> int:
+    """Copy 2 GiB `reps` times; prints the bytes each launch moves."""
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        bto.probe_copy(a, b)
+    torch.cuda.synchronize()
+    print(json.dumps({"probe": "copy", "doubles": n, "read_bytes": n * 8, "write_bytes": n * 8,
+                      "launches": reps}), flush=True)
+    return 0
 
 
 # ---- algorithmic bytes (each matrix pass the dependencies force, each vector once)
@@ -244,6 +259,8 @@ def main() -> int:
 
     from paper_1205_1098_amd import bto, synth
 
+    if args.copy_probe:
+        return copy_probe(torch, bto)
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(0)
     shared = {}

@@ -55,15 +55,18 @@ const char *const kSlotNames[SLOT_COUNT] = {
 };
 
 std::mutex g_cfg_mu;
+// Defaults: the best configurations the orthogonal search (fusion first,
+// then each sweep's tile shape, band height and walk order) found for
+// 16384 x 16384 on MI355X, each form searched separately.
 TileCfg g_cfg[SLOT_COUNT] = {
-    {2, 128, 0},  // BICGK_FUSED: 8 waves across 4096 columns, 2 row groups
-    {0, 64, 0},   // GEMV_N: 4 waves across 4096 columns, 64 rows
-    {1, 256, 0},  // GEMV_T: 4 x 4 waves, 256-row bands
-    {6, 4, 0},    // GER: one row per wave, 256-column wave tiles
-    {6, 32, 0},   // GEMVER_P1: 256-column wave tiles, 32-row bands
-    {0, 64, 1},   // GEMVER_P2: walk B backwards, from what pass 1 left in cache
-    {1, 256, 0},  // DGEMVT_P1
-    {0, 64, 1},   // DGEMVT_P2
+    {5, 128, 0},  // BICGK_FUSED: 4 x 2 waves, 8 pairs per lane (32 KiB per row), 2 rows in flight
+    {4, 4, 1},    // GEMV_N: 4 waves across 4096 columns, one row per wave
+    {3, 512, 0},  // GEMV_T: 4 x 4 waves, 512-row bands
+    {8, 4, 0},    // GER: one row per wave, 512-column wave tiles
+    {10, 32, 1},  // GEMVER_P1: 16 waves down 256 columns, 2 rows each, 3 rows in flight
+    {4, 4, 1},    // GEMVER_P2: one row per wave, bands walked backwards
+    {3, 512, 1},  // DGEMVT_P1
+    {4, 4, 0},    // DGEMVT_P2
 };
 
 constexpr int kMinKv = 2;

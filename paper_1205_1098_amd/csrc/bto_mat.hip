@@ -500,7 +500,7 @@ struct RowresShape {
     int T, NPT;
 };
 
-std::atomic<int> g_rowres_threads{1024};   // preferred workgroup size (tunable)
+std::atomic<int> g_rowres_threads{512};   // preferred workgroup size (tunable; best at n = 16384)
 
 // The workgroup size T (the preferred one first) and the fewest doubles per
 // thread NPT (even) with T*NPT >= n.
