@@ -23,7 +23,6 @@ Usage: python bench.py [--steps K] [--warmup W] [--workload gemver|bicgk|...]
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,8 +38,6 @@ N = 16384
 NV = 1 << 26
 ALPHA, BETA = 1.5, 0.7
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_vec.hip",
-                  "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_api.hip"]
 
 
 def parse():
@@ -55,6 +52,8 @@ def parse():
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 2 GiB copy probe (calibrates hardware byte counters)")
     return ap.parse_args()
@@ -181,14 +180,6 @@ def time_steps(torch, fn, steps: int, warmup: int) -> float:
 
 # ---- hardware-counter traffic ------------------------------------------------------
 
-def source_digest() -> str:
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def counter_traffic(kernel_name: str):
     """HBM bytes per launch of `kernel_name` from a committed counter summary,
     or None when there is none for the current kernel sources."""
@@ -201,6 +192,8 @@ def counter_traffic(kernel_name: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
+    from paper_1205_1098_amd.profsum import source_digest
+
     if fields.get("source_digest") != source_digest():
         return None
     try:
@@ -245,6 +238,40 @@ def cpu_baseline(kernel: str, target_s: float):
         "kind": "oracle",
         "sample": f"{reps} full {kernel} n={N} call(s) on host data, {per * 1e3:.1f} ms each; "
                   f"GB/s on the same algorithmic bytes as the GPU value",
+    }
+
+
+def bench_batched(torch, bto, count: int) -> dict:
+    """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
+    fair seeded coin) in one graph-captured persistent launch."""
+    from paper_1205_1098_amd import batch
+
+    insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
+                                        {"gemver": 0.5, "bicgk": 0.5}, config=4)
+    total = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in specs)
+    plan = bto.BatchPlan(insts, use_graph=True)
+    sec = time_steps(torch, plan.launch, 10, 2)
+    plan.close()
+    # the same instances launched one entry-point call at a time
+    def loop():
+        for inst in insts:
+            if inst["kind"] == "gemver":
+                bto.gemver(inst["A"], *inst["in"], inst["alpha"], inst["beta"], B=inst["B"],
+                           x=inst["out"][0], w=inst["out"][1])
+            else:
+                bto.bicgk(inst["A"], *inst["in"], q=inst["out"][0], s=inst["out"][1])
+    sec_loop = time_steps(torch, loop, 2, 1)
+    return {
+        "instances": count,
+        "gemver": sum(1 for s in specs if s.kind == "gemver"),
+        "n_range": [64, 2048],
+        "alg_gb": round(total / 1e9, 3),
+        "ms_per_batch": round(sec * 1e3, 3),
+        "inst_per_s": round(count / sec, 1),
+        "gbs": round(total / sec / 1e9, 1),
+        "pct_peak": round(100 * total / sec / 1e9 / PEAK_GBS, 1),
+        "per_instance_loop_ms": round(sec_loop * 1e3, 2),
+        "speedup_vs_loop": round(sec_loop / sec, 2),
     }
 
 
@@ -366,6 +393,9 @@ def main() -> int:
     shared.clear()
     del main_wl
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batched"] = bench_batched(torch, bto, args.batch_count)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(args.workload if args.workload in
                                               ("gemver", "bicgk", "atax", "dgemvt") else "gemver",

@@ -157,6 +157,55 @@ bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z
                     double *x, void *ws, size_t ws_bytes, bto_form form,
                     hipStream_t stream);
 
+/* ---- batched execution -----------------------------------------------------
+ * Many independent GEMVER, BICGK and ATAX instances (square or not, of
+ * uneven size, n <= 2048 columns each) run in one persistent launch.  Each
+ * instance has the operands and semantics of its entry point above; `in`
+ * and `out` list the vectors in the entry point's argument order:
+ *   GEMVER  in = {u1, v1, u2, v2, y, z}, out = {x, w}, B (may be A)
+ *   BICGK   in = {p, r},                 out = {q, s}
+ *   ATAX    in = {x},                    out = {y}
+ * Instances may share inputs (the same A for many requests); an output may
+ * not overlap any operand of any instance, other than B == A of its own.
+ * Matrices and vectors must be 16-byte aligned with even leading
+ * dimensions.  One workgroup computes a whole instance, in a fixed order, so
+ * results do not depend on how the instances are scheduled.
+ *
+ * bto_batch_plan_create validates every instance, orders them by decreasing
+ * work and copies the table to device memory (the plan owns that memory,
+ * and a scratch area for unfused ATAX temporaries, until it is destroyed).
+ * With use_graph set, the launch (a queue reset and the persistent kernel)
+ * is captured once in a HIP graph.  bto_batch_plan_launch enqueues the
+ * whole batch on `stream` and allocates nothing; successive launches of one
+ * plan must not overlap (they share the plan's queue counter).  This is the
+ * GPU counterpart of the paper's generated kernel partitioning its loops
+ * over threads (Sections III-C, IV-D), applied across instances. */
+typedef struct {
+    bto_kernel kind;          /* BTO_K_GEMVER, BTO_K_BICGK or BTO_K_ATAX */
+    bto_form form;
+    int64_t m, n, lda, ldb;   /* ldb: GEMVER only */
+    double alpha, beta;       /* GEMVER only */
+    const double *A;
+    double *B;                /* GEMVER only */
+    const double *in[6];
+    double *out[2];
+} bto_batch_desc;
+
+typedef struct {
+    int threads;       /* workgroup size: 256 or 512 (0 = default 256) */
+    int wgs_per_cu;    /* persistent workgroups per compute unit, 1..2 (0 = 2) */
+    int use_graph;     /* capture the launch in a HIP graph */
+} bto_batch_config;
+
+typedef struct bto_batch_plan bto_batch_plan;
+
+/* Largest column count a batched instance may have. */
+int64_t bto_batch_max_n(void);
+bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
+                                 const bto_batch_config *config, bto_batch_plan **plan);
+bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream);
+bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
+
 /* ---- measurement support ------------------------------------------------
  * Per-kernel timing with HIP events recorded on the stream each kernel is
  * launched on.  While enabled, every kernel the library launches is
@@ -201,6 +250,16 @@ bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws,
 bto_status bto_probe_triad(double *a, const double *b, const double *c, double s,
                            int64_t n, hipStream_t stream);
 size_t bto_probe_read_workspace_bytes(int64_t n);
+
+/* ---- synthetic inputs ------------------------------------------------------
+ * Fill a rows x cols block (leading dimension ld, device memory) with element
+ * (i, j) = element offset + i*cols + j of a SplitMix64 stream whose state
+ * starts at `state` (Steele, Lea and Flood 2014): kind 0 gives doubles
+ * uniform on [-1, 1), kind 1 integers uniform on [lo, hi].  Bit-identical to
+ * the package's host generator; used to build large benchmark workloads in
+ * place.  Returns BTO_ERR_INVALID_ARG for bad sizes or kinds. */
+bto_status bto_synth_fill(double *out, int64_t rows, int64_t cols, int64_t ld, uint64_t state,
+                          int64_t offset, int kind, int lo, int hi, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,12 @@ _SIGS = {
     "bto_tune_set": ([_int, _int, _int, _int], _int),
     "bto_tune_shape": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                         ctypes.POINTER(_int)], _int),
+    "bto_synth_fill": ([_ptr, _i64, _i64, _i64, ctypes.c_uint64, _i64, _int, _int, _int, _ptr],
+                       _int),
+    "bto_batch_max_n": ([], _i64),
+    "bto_batch_plan_create": ([_ptr, _int, _ptr, _ptr], _int),
+    "bto_batch_plan_launch": ([_ptr, _ptr], _int),
+    "bto_batch_plan_destroy": ([_ptr], _int),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -344,3 +350,111 @@ def tune_shape(shape: int) -> dict:
     v = [_int() for _ in range(4)]
     _check(_lib.bto_tune_shape(shape, *[ctypes.byref(x) for x in v]))
     return dict(zip(("kv", "depth", "wc", "wr"), (int(x.value) for x in v)))
+
+
+# ---- synthetic inputs in device memory ---------------------------------------------
+
+def synth_fill(out, state: int, offset: int = 0, kind: str = "uniform", lo: int = -2,
+               hi: int = 2) -> None:
+    """Fill a 1-D or row-major 2-D float64 tensor in place from a SplitMix64
+    stream state (see synth.stream_state); bit-identical to the host side."""
+    if out.dim() == 1:
+        rows, cols, ld = 1, out.numel(), max(out.numel(), 1)
+    else:
+        rows, cols = out.shape
+        ld = _check_mat(out, "out")
+    k = {"uniform": 0, "int": 1}[kind]
+    dev = out.device
+    with torch.cuda.device(dev):
+        _check(_lib.bto_synth_fill(_ptr_of(out), rows, cols, ld, ctypes.c_uint64(state), offset,
+                                   k, lo, hi, _stream(dev)))
+
+
+# ---- batched execution --------------------------------------------------------------
+
+class _Desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("form", ctypes.c_int),
+                ("m", _i64), ("n", _i64), ("lda", _i64), ("ldb", _i64),
+                ("alpha", _dbl), ("beta", _dbl),
+                ("A", _ptr), ("B", _ptr),
+                ("inp", _ptr * 6), ("out", _ptr * 2)]
+
+
+class _Config(ctypes.Structure):
+    _fields_ = [("threads", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
+                ("use_graph", ctypes.c_int)]
+
+
+def batch_max_n() -> int:
+    return int(_lib.bto_batch_max_n())
+
+
+class BatchPlan:
+    """Many GEMVER / BiCGK / ATAX instances in one persistent launch.
+
+    `instances` is a list of dicts with keys
+        kind ("gemver" | "bicgk" | "atax"), form ("fused" | "unfused"),
+        A (2-D tensor), in (list of 1-D tensors), out (list of 1-D tensors),
+        and for GEMVER: B (2-D tensor, may be A), alpha, beta
+    in the argument order of the single-instance entry points.  The plan keeps
+    references to every tensor; launch() enqueues the batch on the current
+    stream and allocates nothing."""
+
+    def __init__(self, instances, threads: int = 256, wgs_per_cu: int = 2,
+                 use_graph: bool = True):
+        self._keep = []
+        descs = (_Desc * max(len(instances), 1))()
+        dev = None
+        for i, inst in enumerate(instances):
+            d = descs[i]
+            A = inst["A"]
+            dev = A.device if dev is None else dev
+            lda = _check_mat(A, "A")
+            d.kind = KERNELS[inst["kind"]]
+            d.form = _form(inst.get("form", "fused"))
+            d.m, d.n = A.shape
+            d.lda = lda
+            d.A = A.data_ptr()
+            keep = [A]
+            if inst["kind"] == "gemver":
+                B = inst["B"]
+                d.ldb = _check_mat(B, "B")
+                d.B = B.data_ptr()
+                d.alpha, d.beta = float(inst["alpha"]), float(inst["beta"])
+                keep.append(B)
+            else:
+                d.ldb = lda
+            for k, t in enumerate(inst["in"]):
+                _check_vec(t, f"in[{k}]", A.device)
+                d.inp[k] = t.data_ptr()
+                keep.append(t)
+            for k, t in enumerate(inst["out"]):
+                _check_vec(t, f"out[{k}]", A.device)
+                d.out[k] = t.data_ptr()
+                keep.append(t)
+            self._keep.append(keep)
+        cfg = _Config(threads, wgs_per_cu, 1 if use_graph else 0)
+        self._plan = ctypes.c_void_p()
+        self.device = dev if dev is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_batch_plan_create(ctypes.byref(descs), len(instances), ctypes.byref(cfg),
+                                              ctypes.byref(self._plan)))
+        self.count = len(instances)
+
+    def launch(self) -> None:
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_batch_plan_launch(self._plan, _stream(self.device)))
+
+    def close(self) -> None:
+        if self._plan:
+            _lib.bto_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

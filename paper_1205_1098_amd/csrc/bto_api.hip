@@ -1,11 +1,14 @@
 // C entry points of libbto: argument checks, workspace layout, and the
 // fused / unfused kernel sequences for the seven Table I kernels.
 
+#include <algorithm>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
 #include "bto.h"
+#include "bto_batch.hpp"
 #include "bto_internal.hpp"
 
 using namespace bto;
@@ -314,6 +317,7 @@ std::vector<int64_t> g_tcount;
 std::vector<hipEvent_t> g_pool;
 thread_local hipEvent_t t_start = nullptr;
 thread_local int t_name = -1;
+thread_local bool t_capturing = false;   // no timing events inside a graph capture
 
 hipEvent_t take_event()
 {
@@ -322,8 +326,10 @@ hipEvent_t take_event()
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence (cache writeback and invalidate)
+    // at each record, which would slow the kernels being timed
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess)
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
         return nullptr;
     return e;
 }
@@ -347,7 +353,7 @@ void timing_begin(hipStream_t st, const char *name)
 {
     std::lock_guard<std::mutex> g(g_tmu);
     t_start = nullptr;
-    if (!g_tenabled)
+    if (!g_tenabled || t_capturing)
         return;
     hipEvent_t e = take_event();
     if (!e)
@@ -841,6 +847,284 @@ bto_status bto_probe_triad(double *a, const double *b, const double *c, double s
     BTO_TRY(check_aliases({vspan("a", a, n, true), vspan("b", b, n, false), vspan("c", c, n, false)}, {}));
     launch_triad(n, a, b, c, s, st);
     return check_launch();
+}
+
+}  // extern "C"
+
+// ---- batched execution ---------------------------------------------------------
+
+struct bto_batch_plan {
+    int count = 0;
+    BatchItem *d_items = nullptr;
+    int *d_order = nullptr;
+    int *d_next = nullptr;
+    double *d_scratch = nullptr;
+    int threads = 256;
+    int grid = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+namespace {
+
+struct BSpan {
+    uintptr_t lo, hi;
+    int inst;
+    bool out;
+    bool a_or_b;   // the instance's A or B (exact B == A alias allowed)
+};
+
+bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> &spans,
+                           BatchItem &it, int64_t &scratch)
+{
+    const std::string where = "instance " + std::to_string(idx) + ": ";
+    auto bad = [&](bto_status st, const std::string &msg) { return fail(st, where + msg); };
+    if (d.kind != BTO_K_GEMVER && d.kind != BTO_K_BICGK && d.kind != BTO_K_ATAX)
+        return bad(BTO_ERR_UNSUPPORTED, "kind must be GEMVER, BICGK or ATAX");
+    if (d.form != BTO_FUSED && d.form != BTO_UNFUSED)
+        return bad(BTO_ERR_INVALID_ARG, "unknown form");
+    const int64_t m = d.m, n = d.n;
+    if (m < 0 || n < 0)
+        return bad(BTO_ERR_INVALID_ARG, "negative size");
+    if (n > batch_max_n())
+        return bad(BTO_ERR_UNSUPPORTED, "more columns than a batched instance may have");
+    if (d.lda < (n > 1 ? n : 1) || (d.lda & 1))
+        return bad(BTO_ERR_INVALID_ARG, "lda must be even and at least max(1, n)");
+    const bool empty = m == 0 || n == 0;
+    if (!empty && (d.A == nullptr || !aligned16(d.A)))
+        return bad(BTO_ERR_INVALID_ARG, "A must be a 16-byte aligned device pointer");
+    int nin = 0, nout = 0;
+    int64_t in_len[6] = {0}, out_len[2] = {0};
+    if (d.kind == BTO_K_GEMVER) {
+        nin = 6; nout = 2;
+        const int64_t il[6] = {m, n, m, n, m, n};
+        std::copy(il, il + 6, in_len);
+        out_len[0] = n; out_len[1] = m;
+        if (d.ldb < (n > 1 ? n : 1) || (d.ldb & 1))
+            return bad(BTO_ERR_INVALID_ARG, "ldb must be even and at least max(1, n)");
+        if (!empty && (d.B == nullptr || !aligned16(d.B)))
+            return bad(BTO_ERR_INVALID_ARG, "B must be a 16-byte aligned device pointer");
+        if (d.B == d.A && d.ldb != d.lda && !empty)
+            return bad(BTO_ERR_ALIAS, "B == A requires ldb == lda");
+    } else if (d.kind == BTO_K_BICGK) {
+        nin = 2; nout = 2;
+        in_len[0] = n; in_len[1] = m;
+        out_len[0] = m; out_len[1] = n;
+    } else {
+        nin = 1; nout = 1;
+        in_len[0] = n;
+        out_len[0] = n;
+    }
+    for (int k = 0; k < nin; ++k)
+        if (in_len[k] > 0 && d.in[k] == nullptr)
+            return bad(BTO_ERR_INVALID_ARG, "input vector " + std::to_string(k) + " is NULL");
+    for (int k = 0; k < nout; ++k)
+        if (out_len[k] > 0 && d.out[k] == nullptr)
+            return bad(BTO_ERR_INVALID_ARG, "output vector " + std::to_string(k) + " is NULL");
+
+    auto add = [&](const void *p, int64_t bytes, bool out, bool ab) {
+        if (bytes > 0) {
+            uintptr_t lo = reinterpret_cast<uintptr_t>(p);
+            spans.push_back({lo, lo + (uintptr_t)bytes, idx, out, ab});
+        }
+    };
+    if (!empty) {
+        add(d.A, ((m - 1) * d.lda + n) * 8, false, true);
+        if (d.kind == BTO_K_GEMVER)
+            add(d.B, ((m - 1) * d.ldb + n) * 8, true, true);
+    }
+    for (int k = 0; k < nin; ++k)
+        add(d.in[k], in_len[k] * 8, false, false);
+    for (int k = 0; k < nout; ++k)
+        add(d.out[k], out_len[k] * 8, true, false);
+
+    it = BatchItem{};
+    it.kind = d.kind;
+    it.form = d.form;
+    it.m = m;
+    it.n = n;
+    it.lda = d.lda;
+    it.ldb = d.kind == BTO_K_GEMVER ? d.ldb : d.lda;
+    it.alpha = d.alpha;
+    it.beta = d.beta;
+    it.A = d.A;
+    it.B = d.B;
+    for (int k = 0; k < 6; ++k) it.vec[k] = k < nin ? d.in[k] : nullptr;
+    for (int k = 0; k < 2; ++k) it.out[k] = k < nout ? d.out[k] : nullptr;
+    it.scratch_off = 0;
+    if (d.kind == BTO_K_ATAX && d.form == BTO_UNFUSED) {
+        it.scratch_off = scratch;
+        scratch += (m + 31) / 32 * 32;   // 256-byte steps
+    }
+    return BTO_SUCCESS;
+}
+
+// No output of any instance may overlap another operand, except an
+// instance's B exactly equal to its own A.
+bto_status batch_check_overlaps(std::vector<BSpan> &spans)
+{
+    std::vector<BSpan> outs;
+    for (const BSpan &s : spans)
+        if (s.out) outs.push_back(s);
+    std::sort(outs.begin(), outs.end(), [](const BSpan &a, const BSpan &b) { return a.lo < b.lo; });
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].lo < outs[i - 1].hi)
+            return fail(BTO_ERR_ALIAS, "outputs of instances " + std::to_string(outs[i - 1].inst) +
+                                           " and " + std::to_string(outs[i].inst) + " overlap");
+    for (const BSpan &s : spans) {
+        if (s.out)
+            continue;
+        // the output with the largest start below s.hi is the only candidate
+        auto it = std::lower_bound(outs.begin(), outs.end(), s.hi,
+                                   [](const BSpan &o, uintptr_t v) { return o.lo < v; });
+        if (it == outs.begin())
+            continue;
+        const BSpan &o = *(it - 1);
+        if (o.hi <= s.lo)
+            continue;
+        const bool exact_ab = o.inst == s.inst && o.a_or_b && s.a_or_b && o.lo == s.lo &&
+                              o.hi == s.hi;
+        if (!exact_ab)
+            return fail(BTO_ERR_ALIAS, "an output of instance " + std::to_string(o.inst) +
+                                           " overlaps an input of instance " +
+                                           std::to_string(s.inst));
+    }
+    return BTO_SUCCESS;
+}
+
+double batch_cost(const bto_batch_desc &d)
+{
+    const double mn = (double)d.m * (double)d.n;
+    double passes = 1.0;
+    if (d.kind == BTO_K_GEMVER) passes = d.form == BTO_FUSED ? 3.0 : 6.0;
+    else passes = d.form == BTO_FUSED ? 1.0 : 2.0;
+    return passes * mn + (double)(d.m + d.n);
+}
+
+void plan_free(bto_batch_plan *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_next) (void)hipFree(p->d_next);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t bto_batch_max_n(void) { return batch_max_n(); }
+
+bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
+                                 const bto_batch_config *config, bto_batch_plan **plan)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (count < 0 || (count > 0 && !descs))
+        return fail(BTO_ERR_INVALID_ARG, "bad instance list");
+    bto_batch_config cfg{256, 2, 0};
+    if (config) {
+        cfg = *config;
+        if (cfg.threads == 0) cfg.threads = 256;
+        if (cfg.wgs_per_cu == 0) cfg.wgs_per_cu = 2;
+    }
+    if (!batch_threads_supported(cfg.threads))
+        return fail(BTO_ERR_INVALID_ARG, "threads must be 256 or 512");
+    if (cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 2)
+        return fail(BTO_ERR_INVALID_ARG, "wgs_per_cu must be 1 or 2");
+
+    std::vector<BSpan> spans;
+    std::vector<BatchItem> items((size_t)count);
+    int64_t scratch = 0;
+    for (int i = 0; i < count; ++i)
+        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], scratch));
+    BTO_TRY(batch_check_overlaps(spans));
+
+    // longest first (by memory traffic), ties by position
+    std::vector<int> order((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost((size_t)count);
+    for (int i = 0; i < count; ++i)
+        cost[i] = batch_cost(descs[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return check_launch() == BTO_SUCCESS ? fail(BTO_ERR_HIP, "no device") : BTO_ERR_HIP;
+
+    bto_batch_plan *p = new bto_batch_plan();
+    p->count = count;
+    p->threads = cfg.threads;
+    p->grid = cus * cfg.wgs_per_cu;
+    auto hip_fail = [&](const char *what) {
+        plan_free(p);
+        return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
+    };
+    if (hipMalloc(&p->d_next, 256) != hipSuccess)
+        return hip_fail("hipMalloc");
+    if (count > 0) {
+        if (hipMalloc(&p->d_items, sizeof(BatchItem) * (size_t)count) != hipSuccess ||
+            hipMalloc(&p->d_order, sizeof(int) * (size_t)count) != hipSuccess)
+            return hip_fail("hipMalloc");
+        if (hipMemcpy(p->d_items, items.data(), sizeof(BatchItem) * (size_t)count,
+                      hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(p->d_order, order.data(), sizeof(int) * (size_t)count,
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return hip_fail("hipMemcpy");
+    }
+    if (scratch > 0 && hipMalloc(&p->d_scratch, sizeof(double) * (size_t)scratch) != hipSuccess)
+        return hip_fail("hipMalloc");
+
+    if (cfg.use_graph) {
+        if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+            return hip_fail("hipStreamCreate");
+        if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return hip_fail("hipStreamBeginCapture");
+        t_capturing = true;
+        launch_batch(p->d_items, p->d_order, p->count, p->d_next, p->d_scratch, p->threads,
+                     p->grid, p->cap);
+        t_capturing = false;
+        if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
+            return hip_fail("hipStreamEndCapture");
+        if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+            return hip_fail("hipGraphInstantiate");
+    }
+    *plan = p;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->exec) {
+        timing_begin(stream, "batch_graph");
+        const hipError_t e = hipGraphLaunch(plan->exec, stream);
+        timing_end(stream);
+        if (e != hipSuccess)
+            return fail(BTO_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    } else {
+        launch_batch(plan->d_items, plan->d_order, plan->count, plan->d_next, plan->d_scratch,
+                     plan->threads, plan->grid, stream);
+    }
+    return check_launch();
+}
+
+bto_status bto_batch_plan_destroy(bto_batch_plan *plan)
+{
+    t_error.clear();
+    plan_free(plan);
+    return BTO_SUCCESS;
 }
 
 }  // extern "C"

@@ -1,0 +1,80 @@
+"""Batch plan validation on the host: bad instances are rejected before any
+device work (fake pointers, never dereferenced)."""
+
+import ctypes
+
+import pytest
+
+FAKE = 1 << 40
+MB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def bto():
+    from paper_1205_1098_amd import bto as b
+
+    return b
+
+
+def desc(bto, kind, m, n, lda, base):
+    d = bto._Desc()
+    d.kind = bto.KERNELS[kind]
+    d.form = 0
+    d.m, d.n, d.lda, d.ldb = m, n, lda, lda
+    d.alpha, d.beta = 1.5, 0.7
+    d.A = base
+    d.B = base + 64 * MB
+    for k in range(6):
+        d.inp[k] = base + (128 + k) * MB
+    for k in range(2):
+        d.out[k] = base + (160 + k) * MB
+    return d
+
+
+def create(bto, descs):
+    arr = (bto._Desc * len(descs))(*descs)
+    plan = ctypes.c_void_p()
+    cfg = bto._Config(256, 2, 0)
+    return bto._lib.bto_batch_plan_create(ctypes.byref(arr), len(descs), ctypes.byref(cfg),
+                                          ctypes.byref(plan))
+
+
+def test_max_n(bto):
+    assert bto.batch_max_n() == 2048
+
+
+def test_rejects_wide_instances(bto):
+    assert create(bto, [desc(bto, "gemver", 10, 2049, 2050, FAKE)]) == 5
+
+
+def test_rejects_odd_or_short_lda(bto):
+    assert create(bto, [desc(bto, "bicgk", 10, 100, 101, FAKE)]) == 1
+    assert create(bto, [desc(bto, "bicgk", 10, 100, 98, FAKE)]) == 1
+
+
+def test_rejects_unsupported_kind(bto):
+    d = desc(bto, "bicgk", 10, 100, 100, FAKE)
+    d.kind = bto.KERNELS["vadd"]
+    assert create(bto, [d]) == 5
+
+
+def test_rejects_misaligned_matrix(bto):
+    assert create(bto, [desc(bto, "atax", 10, 100, 100, FAKE + 8)]) == 1
+
+
+def test_rejects_cross_instance_output_overlap(bto):
+    a = desc(bto, "bicgk", 10, 100, 100, FAKE)
+    b = desc(bto, "bicgk", 10, 100, 100, FAKE + 1024 * MB)
+    b.out[0] = a.out[0] + 16          # instance 1 writes into instance 0's q
+    assert create(bto, [a, b]) == 2
+    c = desc(bto, "bicgk", 10, 100, 100, FAKE + 2048 * MB)
+    c.out[1] = a.A                    # instance 2 writes over instance 0's matrix
+    assert create(bto, [a, c]) == 2
+
+
+def test_rejects_bad_config(bto):
+    arr = (bto._Desc * 1)(desc(bto, "bicgk", 10, 100, 100, FAKE))
+    plan = ctypes.c_void_p()
+    cfg = bto._Config(384, 2, 0)
+    assert bto._lib.bto_batch_plan_create(ctypes.byref(arr), 1, ctypes.byref(cfg),
+                                          ctypes.byref(plan)) == 1

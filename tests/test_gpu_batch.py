@@ -1,0 +1,141 @@
+"""Batched execution on the GPU: every instance against the oracle, and the
+result independent of the schedule (workgroup size, grid, graph replay)."""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1205_1098_amd import batch, synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1205_1098_amd import bto
+
+    return torch, bto
+
+
+def relerr(got, ref):
+    ref = np.asarray(ref)
+    if ref.size == 0:
+        return 0.0
+    den = float(np.max(np.abs(ref)))
+    num = float(np.max(np.abs(np.asarray(got) - ref)))
+    return num / den if den > 0 else num
+
+
+def reference(spec, alpha, beta):
+    A, ins = batch.host_operands(spec)
+    if spec.kind == "gemver":
+        B, x, w = oracle.gemver(A, *ins, alpha, beta)
+        return [x, w], B
+    if spec.kind == "bicgk":
+        return list(oracle.bicgk(A, *ins)), None
+    return [oracle.atax(A, *ins)], None
+
+
+def check_all(torch, insts, specs, exact):
+    for inst, spec in zip(insts, specs):
+        outs, B = reference(spec, inst.get("alpha", 0.0), inst.get("beta", 0.0))
+        got = [t.cpu().numpy() for t in inst["out"]]
+        for g, r in zip(got, outs):
+            if exact:
+                assert np.array_equal(g, r), (spec.index, spec.kind, spec.n)
+            else:
+                assert relerr(g, r) <= TOL, (spec.index, spec.kind, spec.n)
+        if B is not None:
+            gb = inst["B"].cpu().numpy()
+            assert np.array_equal(gb, B) if exact else relerr(gb, B) <= TOL
+
+
+def test_device_fill_matches_host(env):
+    torch, bto = env
+    st = synth.stream_state(5, 77)
+    v = torch.empty(100003, dtype=torch.float64, device="cuda")
+    bto.synth_fill(v, st)
+    assert np.array_equal(v.cpu().numpy(), synth.uniform(5, 77, 100003))
+    full = torch.full((37, 48), float("nan"), dtype=torch.float64, device="cuda")
+    bto.synth_fill(full[:, :41], st, kind="int")
+    host = full.cpu().numpy()
+    assert np.array_equal(host[:, :41], synth.matrix(5, 77, 37, 41, kind="int"))
+    assert np.all(np.isnan(host[:, 41:]))
+    part = torch.empty(1000, dtype=torch.float64, device="cuda")
+    bto.synth_fill(part, st, offset=4096)
+    assert np.array_equal(part.cpu().numpy(), synth.uniform(5, 77, 1000, offset=4096))
+
+
+WEIGHTS = {"gemver": 0.4, "bicgk": 0.4, "atax": 0.2}
+
+
+@pytest.mark.parametrize("form", ["fused", "unfused"])
+@pytest.mark.parametrize("data", ["uniform", "int"])
+def test_batch_matches_oracle(env, form, data):
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 120, 64, 2048, WEIGHTS, seed=11, form=form,
+                                        data=data)
+    plan = bto.BatchPlan(insts)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=(data == "int"))
+    plan.close()
+
+
+def test_batch_edge_sizes(env):
+    torch, bto = env
+    insts, specs = [], []
+    for idx, n in enumerate([1, 2, 3, 63, 64, 65, 127, 129, 1023, 1025, 2047, 2048]):
+        for kind in batch.KINDS:
+            one, sp = batch.make_instances(torch, bto, 1, n, n, {kind: 1.0}, seed=100 + idx)
+            insts += one
+            specs += sp
+    plan = bto.BatchPlan(insts, use_graph=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=False)
+
+
+def test_schedule_independence_and_graph_replay(env):
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 200, 64, 2048, WEIGHTS, seed=12)
+    outs = lambda: [t.clone() for inst in insts for t in inst["out"]]
+    first = None
+    for threads, wgs, graph in [(256, 2, True), (512, 1, False), (256, 1, True), (512, 2, True)]:
+        for inst in insts:
+            for t in inst["out"]:
+                t.fill_(float("nan"))
+        plan = bto.BatchPlan(insts, threads=threads, wgs_per_cu=wgs, use_graph=graph)
+        for rep in range(3):
+            plan.launch()
+            torch.cuda.synchronize()
+            cur = outs()
+            if first is None:
+                first = cur
+            assert all(torch.equal(a, b) for a, b in zip(first, cur)), (threads, wgs, graph, rep)
+        plan.close()
+    check_all(torch, insts, specs, exact=False)
+
+
+def test_in_place_gemver_batch(env):
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 40, 64, 1500, {"gemver": 1.0}, seed=13,
+                                        in_place=True)
+    plan = bto.BatchPlan(insts)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=False)
+
+
+def test_batch_rejects_overlap(env):
+    torch, bto = env
+    insts, _ = batch.make_instances(torch, bto, 3, 64, 128, {"bicgk": 1.0}, seed=14)
+    insts[1]["out"][0] = insts[0]["out"][0]       # two instances write one vector
+    with pytest.raises(bto.BtoError) as e:
+        bto.BatchPlan(insts)
+    assert e.value.status == 2
