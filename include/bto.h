@@ -168,8 +168,11 @@ bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z
  * Instances may share inputs (the same A for many requests); an output may
  * not overlap any operand of any instance, other than B == A of its own.
  * Matrices and vectors must be 16-byte aligned with even leading
- * dimensions.  One workgroup computes a whole instance, in a fixed order, so
- * results do not depend on how the instances are scheduled.
+ * dimensions.  One workgroup computes a whole instance, in an order fixed by
+ * the instance and the workgroup size, so for a given workgroup size the
+ * results do not depend on the grid, the graph, the other instances or
+ * which workgroup takes the instance (another workgroup size adds the same
+ * terms in another fixed order).
  *
  * bto_batch_plan_create validates every instance, orders them by decreasing
  * work and copies the table to device memory (the plan owns that memory,

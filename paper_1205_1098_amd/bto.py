@@ -144,7 +144,8 @@ def _check_mat(t: torch.Tensor, name: str) -> int:
         raise ValueError(f"{name}: needs unit column stride (row-major)")
     if m > 1 and t.stride(0) < max(n, 1):
         raise ValueError(f"{name}: row stride {t.stride(0)} is below the column count {n}")
-    return t.stride(0) if m > 1 else max(n, 1)
+    # with one row the stride is not used; report it when it is a valid one
+    return t.stride(0) if m > 1 or t.stride(0) >= max(n, 1) else max(n, 1)
 
 
 def _ws(kernel: str, m: int, n: int, form: int, dev, ws):

@@ -889,7 +889,8 @@ bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> 
         return bad(BTO_ERR_INVALID_ARG, "negative size");
     if (n > batch_max_n())
         return bad(BTO_ERR_UNSUPPORTED, "more columns than a batched instance may have");
-    if (d.lda < (n > 1 ? n : 1) || (d.lda & 1))
+    // rows start 16-byte aligned: an even leading dimension (unused with one row)
+    if (d.lda < (n > 1 ? n : 1) || ((d.lda & 1) && m > 1))
         return bad(BTO_ERR_INVALID_ARG, "lda must be even and at least max(1, n)");
     const bool empty = m == 0 || n == 0;
     if (!empty && (d.A == nullptr || !aligned16(d.A)))
@@ -901,7 +902,7 @@ bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> 
         const int64_t il[6] = {m, n, m, n, m, n};
         std::copy(il, il + 6, in_len);
         out_len[0] = n; out_len[1] = m;
-        if (d.ldb < (n > 1 ? n : 1) || (d.ldb & 1))
+        if (d.ldb < (n > 1 ? n : 1) || ((d.ldb & 1) && m > 1))
             return bad(BTO_ERR_INVALID_ARG, "ldb must be even and at least max(1, n)");
         if (!empty && (d.B == nullptr || !aligned16(d.B)))
             return bad(BTO_ERR_INVALID_ARG, "B must be a 16-byte aligned device pointer");

@@ -102,11 +102,16 @@ def test_batch_edge_sizes(env):
 
 
 def test_schedule_independence_and_graph_replay(env):
+    """For a given workgroup size the results are bit-identical whatever the
+    grid, with or without the graph, and on every replay; a different
+    workgroup size adds the waves' column sums in another fixed order, so it
+    agrees to the tolerance (and both agree with the oracle)."""
     torch, bto = env
     insts, specs = batch.make_instances(torch, bto, 200, 64, 2048, WEIGHTS, seed=12)
     outs = lambda: [t.clone() for inst in insts for t in inst["out"]]
-    first = None
-    for threads, wgs, graph in [(256, 2, True), (512, 1, False), (256, 1, True), (512, 2, True)]:
+    by_threads = {}
+    for threads, wgs, graph in [(256, 2, True), (256, 1, False), (512, 1, False), (512, 2, True),
+                                (256, 1, True)]:
         for inst in insts:
             for t in inst["out"]:
                 t.fill_(float("nan"))
@@ -115,11 +120,12 @@ def test_schedule_independence_and_graph_replay(env):
             plan.launch()
             torch.cuda.synchronize()
             cur = outs()
-            if first is None:
-                first = cur
+            first = by_threads.setdefault(threads, cur)
             assert all(torch.equal(a, b) for a, b in zip(first, cur)), (threads, wgs, graph, rep)
         plan.close()
-    check_all(torch, insts, specs, exact=False)
+        check_all(torch, insts, specs, exact=False)
+    for a, b in zip(by_threads[256], by_threads[512]):
+        assert relerr(a.cpu().numpy(), b.cpu().numpy()) <= TOL
 
 
 def test_in_place_gemver_batch(env):
