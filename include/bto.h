@@ -16,8 +16,9 @@
  *                   statement sharing a matrix pass runs in one kernel, and
  *                   temporaries never reach memory;
  *   BTO_UNFUSED  -- one kernel per BLAS operation, each reading its inputs
- *                   and writing its output once, out of place (the "BLAS
- *                   calls translated to loops" baseline of Section V-B).
+ *                   and writing its output once, out of place (the plain
+ *                   per-BLAS-call loops the paper measures against,
+ *                   Section V-B).
  * Both forms give results within 1e-12 normwise relative error of the plain
  * definition; with integer-valued data both are exact.
  *
