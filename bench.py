@@ -28,6 +28,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -54,6 +56,9 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 2 GiB copy probe (calibrates hardware byte counters)")
     return ap.parse_args()
@@ -275,6 +280,66 @@ def bench_batched(torch, bto, count: int) -> dict:
     }
 
 
+def bench_serving(torch, bto, count: int, warmup: int) -> dict:
+    """Requests for BiCGK / GEMVER / ATAX (weights .4/.4/.2) over a pool of 64
+    device-resident matrices with n log-uniform on [256, 16384]: first all at
+    once (saturated throughput), then Poisson arrivals at 0.7 of it, served
+    with continuous batching and then by a one-at-a-time FIFO server."""
+    from paper_1205_1098_amd import serve
+
+    GiB = 1 << 30
+    sizes = serve.pool_sizes(64, 256, 16384)
+    pool = serve.MatrixPool(torch, bto, sizes)
+    total = warmup + count
+
+    def once(executor, reqs, slots, lanes):
+        executor.start()
+        srv = serve.Server(executor, budget_bytes=32 * GiB, slots=slots, lanes=lanes)
+        t0 = time.perf_counter()
+        srv.run(reqs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out = serve.summarize(reqs, warmup)
+        out["wall_s"] = round(wall, 3)
+        out["steps"] = srv.steps
+        out["mean_step_size"] = round(float(np.mean(srv.step_sizes)), 2) if srv.step_sizes else 0
+        out["peak_gib"] = round(srv.peak_bytes / GiB, 2)
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in out.items()}
+
+    # continuous batching over the single-instance entry points on two lanes
+    ex = serve.GpuExecutor(torch, bto, pool, batch_n=0)
+    print("serving: saturated run", file=sys.stderr, flush=True)
+    once(ex, serve.make_requests(min(total, 2000), sizes, rate=None, first_rid=900000), 64, 2)
+    sat = once(ex, serve.make_requests(total, sizes, rate=None), 64, 2)
+    lam = 0.7 * sat["req_per_s"]
+    print(f"serving: Poisson run at {lam:.0f} req/s", file=sys.stderr, flush=True)
+    poisson = once(ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
+    ex.close()
+    # the same, with requests of n <= 2048 through the batch plans
+    plan_ex = serve.GpuExecutor(torch, bto, pool)
+    print("serving: runs with batch plans", file=sys.stderr, flush=True)
+    plan_sat = once(plan_ex, serve.make_requests(total, sizes, rate=None), 64, 2)
+    plan_poisson = once(plan_ex, serve.make_requests(total, sizes, rate=lam, first_rid=total),
+                        64, 2)
+    plan_ex.close()
+    # the same arrivals served one at a time, first come first served
+    fifo_ex = serve.GpuExecutor(torch, bto, pool, lanes=1, batch_n=0)
+    print("serving: one-at-a-time FIFO run", file=sys.stderr, flush=True)
+    fifo = once(fifo_ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 1, 1)
+    fifo_ex.close()
+    res = {
+        "pool": len(sizes), "pool_gb": round(pool.bytes / 1e9, 2), "n_range": [256, 16384],
+        "weights": serve.WEIGHTS, "budget_gib": 32, "slots": 64, "lanes": 2,
+        "requests": count, "warmup": warmup, "seed": serve.synth.SEED,
+        "saturated": sat, "poisson_rate": round(lam, 1), "poisson": poisson,
+        "with_batch_plans": {"batch_n": int(bto.batch_max_n()), "saturated": plan_sat,
+                             "poisson": plan_poisson},
+        "fifo": fifo,
+    }
+    del pool
+    return res
+
+
 def main() -> int:
     args = parse()
     if args.gpus != 1:
@@ -395,6 +460,9 @@ def main() -> int:
     torch.cuda.empty_cache()
     if not args.no_batch:
         result["batched"] = bench_batched(torch, bto, args.batch_count)
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        result["serving"] = bench_serving(torch, bto, args.serve_requests, args.serve_warmup)
         torch.cuda.empty_cache()
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(args.workload if args.workload in

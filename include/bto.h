@@ -207,6 +207,27 @@ typedef struct bto_batch_plan bto_batch_plan;
 int64_t bto_batch_max_n(void);
 bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
                                  const bto_batch_config *config, bto_batch_plan **plan);
+
+/* A plan that is filled later, for loops that run a different set of
+ * instances each step (continuous batching in a server).  `capacity` is the
+ * most instances one refill may hold; `scratch_doubles` the scratch area for
+ * unfused ATAX instances (each needs its row count rounded up to a multiple
+ * of 32 doubles; 0 if there are none).  The plan starts with no instances. */
+bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
+                                       const bto_batch_config *config, bto_batch_plan **plan);
+
+/* Replace the plan's instances.  The instances are validated as in
+ * bto_batch_plan_create (BTO_ERR_INVALID_ARG / BTO_ERR_ALIAS, and
+ * BTO_ERR_INVALID_ARG for more than `capacity`, BTO_ERR_WORKSPACE for more
+ * scratch than the plan has); on error the plan keeps its previous
+ * instances.  The new table is copied to the device asynchronously on
+ * `stream` through pinned memory the plan owns, so it takes effect for
+ * launches enqueued on the same stream afterwards; the host call waits only
+ * until the previous refill's copy has been read.  Refills and launches of
+ * one plan must all be issued on one stream.  No device memory is
+ * allocated. */
+bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *descs, int count,
+                                hipStream_t stream);
 bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream);
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
 

@@ -73,6 +73,8 @@ _SIGS = {
                        _int),
     "bto_batch_max_n": ([], _i64),
     "bto_batch_plan_create": ([_ptr, _int, _ptr, _ptr], _int),
+    "bto_batch_plan_create_empty": ([_int, _i64, _ptr, _ptr], _int),
+    "bto_batch_plan_reset": ([_ptr, _ptr, _int, _ptr], _int),
     "bto_batch_plan_launch": ([_ptr, _ptr], _int),
     "bto_batch_plan_destroy": ([_ptr], _int),
 }
@@ -97,6 +99,39 @@ class BtoError(RuntimeError):
 def _check(status: int) -> None:
     if status != 0:
         raise BtoError(status, _lib.bto_last_error().decode())
+
+
+class Raw:
+    """The entry points on plain integers (device addresses, sizes, a HIP
+    stream handle), for callers that keep their own buffers and issue many
+    small calls, such as a request server.  The library validates every
+    argument as for the tensor wrappers; errors raise BtoError."""
+
+    @staticmethod
+    def bicgk(m, n, A, lda, p, r, q, s, ws, ws_bytes, form, stream):
+        _check(_lib.bto_bicgk(m, n, A, lda, p, r, q, s, ws, ws_bytes, form, stream))
+
+    @staticmethod
+    def gemver(m, n, alpha, beta, A, lda, u1, v1, u2, v2, y, z, B, ldb, x, w, ws, ws_bytes,
+               form, stream):
+        _check(_lib.bto_gemver(m, n, alpha, beta, A, lda, u1, v1, u2, v2, y, z, B, ldb, x, w,
+                               ws, ws_bytes, form, stream))
+
+    @staticmethod
+    def atax(m, n, A, lda, x, y, ws, ws_bytes, form, stream):
+        _check(_lib.bto_atax(m, n, A, lda, x, y, ws, ws_bytes, form, stream))
+
+    @staticmethod
+    def synth_fill(out, rows, cols, ld, state, stream, offset=0, kind=0, lo=-2, hi=2):
+        _check(_lib.bto_synth_fill(out, rows, cols, ld, state, offset, kind, lo, hi, stream))
+
+
+raw = Raw()
+
+
+def stream_handle(stream) -> int:
+    """The HIP stream handle of a torch stream."""
+    return int(stream.cuda_stream)
 
 
 def version() -> int:
@@ -373,7 +408,8 @@ def synth_fill(out, state: int, offset: int = 0, kind: str = "uniform", lo: int 
 
 # ---- batched execution --------------------------------------------------------------
 
-class _Desc(ctypes.Structure):
+class Desc(ctypes.Structure):
+    """bto_batch_desc."""
     _fields_ = [("kind", ctypes.c_int), ("form", ctypes.c_int),
                 ("m", _i64), ("n", _i64), ("lda", _i64), ("ldb", _i64),
                 ("alpha", _dbl), ("beta", _dbl),
@@ -390,6 +426,48 @@ def batch_max_n() -> int:
     return int(_lib.bto_batch_max_n())
 
 
+def _batch_descs(instances):
+    """Marshal instance dicts into a C array of bto_batch_desc."""
+    keep = []
+    descs = (Desc * max(len(instances), 1))()
+    dev = None
+    for i, inst in enumerate(instances):
+        d = descs[i]
+        A = inst["A"]
+        dev = A.device if dev is None else dev
+        lda = _check_mat(A, "A")
+        d.kind = KERNELS[inst["kind"]]
+        d.form = _form(inst.get("form", "fused"))
+        d.m, d.n = A.shape
+        d.lda = lda
+        d.A = A.data_ptr()
+        refs = [A]
+        if inst["kind"] == "gemver":
+            B = inst["B"]
+            d.ldb = _check_mat(B, "B")
+            d.B = B.data_ptr()
+            d.alpha, d.beta = float(inst["alpha"]), float(inst["beta"])
+            refs.append(B)
+        else:
+            d.ldb = lda
+        for k, t in enumerate(inst["in"]):
+            _check_vec(t, f"in[{k}]", A.device)
+            d.inp[k] = t.data_ptr()
+            refs.append(t)
+        for k, t in enumerate(inst["out"]):
+            _check_vec(t, f"out[{k}]", A.device)
+            d.out[k] = t.data_ptr()
+            refs.append(t)
+        keep.append(refs)
+    return descs, keep, dev
+
+
+def batch_scratch_doubles(instances) -> int:
+    """Scratch a plan needs for these instances (unfused ATAX temporaries)."""
+    return sum((inst["A"].shape[0] + 31) // 32 * 32 for inst in instances
+               if inst["kind"] == "atax" and inst.get("form", "fused") == "unfused")
+
+
 class BatchPlan:
     """Many GEMVER / BiCGK / ATAX instances in one persistent launch.
 
@@ -398,49 +476,59 @@ class BatchPlan:
         A (2-D tensor), in (list of 1-D tensors), out (list of 1-D tensors),
         and for GEMVER: B (2-D tensor, may be A), alpha, beta
     in the argument order of the single-instance entry points.  The plan keeps
-    references to every tensor; launch() enqueues the batch on the current
-    stream and allocates nothing."""
+    references to the tensors of its current instances; launch() enqueues the
+    batch on the current stream and allocates nothing.  A plan made with
+    `BatchPlan.empty` is refilled with `reset` before each launch."""
 
     def __init__(self, instances, threads: int = 256, wgs_per_cu: int = 2,
-                 use_graph: bool = True):
-        self._keep = []
-        descs = (_Desc * max(len(instances), 1))()
-        dev = None
-        for i, inst in enumerate(instances):
-            d = descs[i]
-            A = inst["A"]
-            dev = A.device if dev is None else dev
-            lda = _check_mat(A, "A")
-            d.kind = KERNELS[inst["kind"]]
-            d.form = _form(inst.get("form", "fused"))
-            d.m, d.n = A.shape
-            d.lda = lda
-            d.A = A.data_ptr()
-            keep = [A]
-            if inst["kind"] == "gemver":
-                B = inst["B"]
-                d.ldb = _check_mat(B, "B")
-                d.B = B.data_ptr()
-                d.alpha, d.beta = float(inst["alpha"]), float(inst["beta"])
-                keep.append(B)
-            else:
-                d.ldb = lda
-            for k, t in enumerate(inst["in"]):
-                _check_vec(t, f"in[{k}]", A.device)
-                d.inp[k] = t.data_ptr()
-                keep.append(t)
-            for k, t in enumerate(inst["out"]):
-                _check_vec(t, f"out[{k}]", A.device)
-                d.out[k] = t.data_ptr()
-                keep.append(t)
-            self._keep.append(keep)
+                 use_graph: bool = True, *, _capacity=None, _scratch=0, _device=None):
         cfg = _Config(threads, wgs_per_cu, 1 if use_graph else 0)
         self._plan = ctypes.c_void_p()
+        if _capacity is not None:
+            self.device = torch.device(_device if _device is not None else "cuda:0")
+            self._keep = []
+            with torch.cuda.device(self.device):
+                _check(_lib.bto_batch_plan_create_empty(int(_capacity), int(_scratch),
+                                                        ctypes.byref(cfg), ctypes.byref(self._plan)))
+            self.capacity, self.count = int(_capacity), 0
+            return
+        descs, self._keep, dev = _batch_descs(instances)
         self.device = dev if dev is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
             _check(_lib.bto_batch_plan_create(ctypes.byref(descs), len(instances), ctypes.byref(cfg),
                                               ctypes.byref(self._plan)))
-        self.count = len(instances)
+        self.capacity = self.count = len(instances)
+
+    @classmethod
+    def empty(cls, capacity: int, scratch_doubles: int = 0, threads: int = 256,
+              wgs_per_cu: int = 2, use_graph: bool = True, device="cuda:0") -> "BatchPlan":
+        return cls(None, threads, wgs_per_cu, use_graph, _capacity=capacity,
+                   _scratch=scratch_doubles, _device=device)
+
+    def reset(self, instances) -> None:
+        """Replace the instances (copied on the current stream; no allocation)."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        descs, keep, _ = _batch_descs(instances)
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_batch_plan_reset(self._plan, ctypes.byref(descs), len(instances),
+                                             _stream(self.device)))
+        self._keep, self.count = keep, len(instances)
+
+    def reset_descs(self, descs, count: int, stream: int, keep=None) -> None:
+        """Replace the instances from a filled `Desc` array (device addresses
+        as integers) with the copy enqueued on the raw `stream` handle; the
+        caller keeps the buffers alive."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        _check(_lib.bto_batch_plan_reset(self._plan, ctypes.byref(descs), count, stream))
+        self._keep, self.count = keep or [], count
+
+    def launch_on(self, stream: int) -> None:
+        """launch() on a raw HIP stream handle."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        _check(_lib.bto_batch_plan_launch(self._plan, stream))
 
     def launch(self) -> None:
         if not self._plan:

@@ -2,6 +2,7 @@
 // fused / unfused kernel sequences for the seven Table I kernels.
 
 #include <algorithm>
+#include <cstring>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -854,11 +855,18 @@ bto_status bto_probe_triad(double *a, const double *b, const double *c, double s
 // ---- batched execution ---------------------------------------------------------
 
 struct bto_batch_plan {
+    int capacity = 0;
     int count = 0;
     BatchItem *d_items = nullptr;
     int *d_order = nullptr;
-    int *d_next = nullptr;
+    int *d_meta = nullptr;          // {queue counter, instance count}
     double *d_scratch = nullptr;
+    int64_t scratch_cap = 0;        // doubles
+    // pinned staging of {items, order, count} for asynchronous refills, and
+    // the event that marks when the last refill has been read
+    char *h_stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t staged = nullptr;
     int threads = 256;
     int grid = 0;
     hipGraph_t graph = nullptr;
@@ -1006,14 +1014,45 @@ double batch_cost(const bto_batch_desc &d)
 void plan_free(bto_batch_plan *p)
 {
     if (!p) return;
+    if (p->staged) (void)hipEventSynchronize(p->staged);
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_order) (void)hipFree(p->d_order);
-    if (p->d_next) (void)hipFree(p->d_next);
+    if (p->d_meta) (void)hipFree(p->d_meta);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->staged) (void)hipEventDestroy(p->staged);
     delete p;
+}
+
+// Validate `descs`, order them largest first and build the device table
+// image: items, then the order, then the count.
+bto_status plan_image(const bto_batch_desc *descs, int count, std::vector<BatchItem> &items,
+                      std::vector<int> &order, int64_t &scratch)
+{
+    if (count < 0 || (count > 0 && !descs))
+        return fail(BTO_ERR_INVALID_ARG, "bad instance list");
+    std::vector<BSpan> spans;
+    items.assign((size_t)count, BatchItem{});
+    scratch = 0;
+    for (int i = 0; i < count; ++i)
+        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], scratch));
+    BTO_TRY(batch_check_overlaps(spans));
+    order.resize((size_t)count);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost((size_t)count);
+    for (int i = 0; i < count; ++i)
+        cost[i] = batch_cost(descs[i]);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    return BTO_SUCCESS;
+}
+
+size_t stage_size(int capacity)
+{
+    return round256(sizeof(BatchItem) * (size_t)capacity) + round256(sizeof(int) * (size_t)capacity) +
+           256;
 }
 
 }  // namespace
@@ -1022,15 +1061,11 @@ extern "C" {
 
 int64_t bto_batch_max_n(void) { return batch_max_n(); }
 
-bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
-                                 const bto_batch_config *config, bto_batch_plan **plan)
+}  // extern "C"
+
+static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_batch_config *config,
+                             bto_batch_plan **out)
 {
-    t_error.clear();
-    if (!plan)
-        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
-    *plan = nullptr;
-    if (count < 0 || (count > 0 && !descs))
-        return fail(BTO_ERR_INVALID_ARG, "bad instance list");
     bto_batch_config cfg{256, 2, 0};
     if (config) {
         cfg = *config;
@@ -1041,66 +1076,134 @@ bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
         return fail(BTO_ERR_INVALID_ARG, "threads must be 256 or 512");
     if (cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 2)
         return fail(BTO_ERR_INVALID_ARG, "wgs_per_cu must be 1 or 2");
-
-    std::vector<BSpan> spans;
-    std::vector<BatchItem> items((size_t)count);
-    int64_t scratch = 0;
-    for (int i = 0; i < count; ++i)
-        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], scratch));
-    BTO_TRY(batch_check_overlaps(spans));
-
-    // longest first (by memory traffic), ties by position
-    std::vector<int> order((size_t)count);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost((size_t)count);
-    for (int i = 0; i < count; ++i)
-        cost[i] = batch_cost(descs[i]);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-
+    if (capacity < 0 || scratch_doubles < 0)
+        return fail(BTO_ERR_INVALID_ARG, "negative capacity");
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        return check_launch() == BTO_SUCCESS ? fail(BTO_ERR_HIP, "no device") : BTO_ERR_HIP;
+        return fail(BTO_ERR_HIP, "no device");
 
     bto_batch_plan *p = new bto_batch_plan();
-    p->count = count;
+    p->capacity = capacity;
     p->threads = cfg.threads;
     p->grid = cus * cfg.wgs_per_cu;
+    p->scratch_cap = scratch_doubles;
+    p->stage_bytes = stage_size(capacity);
     auto hip_fail = [&](const char *what) {
         plan_free(p);
         return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
     };
-    if (hipMalloc(&p->d_next, 256) != hipSuccess)
+    if (hipMalloc(&p->d_meta, 256) != hipSuccess || hipMemset(p->d_meta, 0, 256) != hipSuccess)
         return hip_fail("hipMalloc");
-    if (count > 0) {
-        if (hipMalloc(&p->d_items, sizeof(BatchItem) * (size_t)count) != hipSuccess ||
-            hipMalloc(&p->d_order, sizeof(int) * (size_t)count) != hipSuccess)
-            return hip_fail("hipMalloc");
-        if (hipMemcpy(p->d_items, items.data(), sizeof(BatchItem) * (size_t)count,
-                      hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(p->d_order, order.data(), sizeof(int) * (size_t)count,
-                      hipMemcpyHostToDevice) != hipSuccess)
-            return hip_fail("hipMemcpy");
-    }
-    if (scratch > 0 && hipMalloc(&p->d_scratch, sizeof(double) * (size_t)scratch) != hipSuccess)
+    const size_t cap1 = capacity > 0 ? (size_t)capacity : 1;
+    if (hipMalloc(&p->d_items, sizeof(BatchItem) * cap1) != hipSuccess ||
+        hipMalloc(&p->d_order, sizeof(int) * cap1) != hipSuccess)
         return hip_fail("hipMalloc");
-
+    if (scratch_doubles > 0 &&
+        hipMalloc(&p->d_scratch, sizeof(double) * (size_t)scratch_doubles) != hipSuccess)
+        return hip_fail("hipMalloc");
+    if (hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault) != hipSuccess)
+        return hip_fail("hipHostMalloc");
+    if (hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
+        return hip_fail("hipEventCreate");
     if (cfg.use_graph) {
         if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
             return hip_fail("hipStreamCreate");
         if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return hip_fail("hipStreamBeginCapture");
         t_capturing = true;
-        launch_batch(p->d_items, p->d_order, p->count, p->d_next, p->d_scratch, p->threads,
-                     p->grid, p->cap);
+        launch_batch(p->d_items, p->d_order, p->d_meta, p->d_scratch, p->threads, p->grid, p->cap);
         t_capturing = false;
         if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
             return hip_fail("hipStreamEndCapture");
         if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
             return hip_fail("hipGraphInstantiate");
     }
+    *out = p;
+    return BTO_SUCCESS;
+}
+
+// Copy a validated table image into the plan on `stream` (asynchronously,
+// through the plan's pinned staging, after the previous refill was read).
+static bto_status plan_store(bto_batch_plan *p, const std::vector<BatchItem> &items,
+                             const std::vector<int> &order, hipStream_t stream)
+{
+    const int count = (int)items.size();
+    if (hipEventSynchronize(p->staged) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipEventSynchronize");
+    const size_t bi = round256(sizeof(BatchItem) * (size_t)p->capacity);
+    const size_t bo = round256(sizeof(int) * (size_t)p->capacity);
+    char *st = p->h_stage;
+    if (count > 0) {
+        std::memcpy(st, items.data(), sizeof(BatchItem) * (size_t)count);
+        std::memcpy(st + bi, order.data(), sizeof(int) * (size_t)count);
+    }
+    int meta[2] = {0, count};
+    std::memcpy(st + bi + bo, meta, sizeof(meta));
+    if ((count > 0 &&
+         (hipMemcpyAsync(p->d_items, st, sizeof(BatchItem) * (size_t)count, hipMemcpyHostToDevice,
+                         stream) != hipSuccess ||
+          hipMemcpyAsync(p->d_order, st + bi, sizeof(int) * (size_t)count, hipMemcpyHostToDevice,
+                         stream) != hipSuccess)) ||
+        hipMemcpyAsync(p->d_meta, st + bi + bo, sizeof(meta), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipEventRecord(p->staged, stream) != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("refill: ") + hipGetErrorString(hipGetLastError()));
+    p->count = count;
+    return BTO_SUCCESS;
+}
+
+extern "C" {
+
+bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
+                                 const bto_batch_config *config, bto_batch_plan **plan)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    std::vector<BatchItem> items;
+    std::vector<int> order;
+    int64_t scratch = 0;
+    BTO_TRY(plan_image(descs, count, items, order, scratch));
+    bto_batch_plan *p = nullptr;
+    BTO_TRY(plan_alloc(count, scratch, config, &p));
+    bto_status s = plan_store(p, items, order, p->cap ? p->cap : nullptr);
+    if (s == BTO_SUCCESS && hipEventSynchronize(p->staged) != hipSuccess)
+        s = fail(BTO_ERR_HIP, "hipEventSynchronize");
+    if (s != BTO_SUCCESS) {
+        plan_free(p);
+        return s;
+    }
     *plan = p;
     return BTO_SUCCESS;
+}
+
+bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
+                                       const bto_batch_config *config, bto_batch_plan **plan)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    return plan_alloc(capacity, scratch_doubles, config, plan);
+}
+
+bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *descs, int count,
+                                hipStream_t stream)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    if (count > plan->capacity)
+        return fail(BTO_ERR_INVALID_ARG, "more instances than the plan's capacity");
+    std::vector<BatchItem> items;
+    std::vector<int> order;
+    int64_t scratch = 0;
+    BTO_TRY(plan_image(descs, count, items, order, scratch));
+    if (scratch > plan->scratch_cap)
+        return fail(BTO_ERR_WORKSPACE, "unfused ATAX instances need more scratch than the plan has");
+    return plan_store(plan, items, order, stream);
 }
 
 bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
@@ -1115,8 +1218,8 @@ bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
         if (e != hipSuccess)
             return fail(BTO_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     } else {
-        launch_batch(plan->d_items, plan->d_order, plan->count, plan->d_next, plan->d_scratch,
-                     plan->threads, plan->grid, stream);
+        launch_batch(plan->d_items, plan->d_order, plan->d_meta, plan->d_scratch, plan->threads,
+                     plan->grid, stream);
     }
     return check_launch();
 }

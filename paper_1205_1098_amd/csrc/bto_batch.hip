@@ -307,10 +307,14 @@ __device__ __forceinline__ void dispatch_item(const BatchItem &it, double *tmp, 
 // two waves per SIMD, so the kernel must fit 256 registers per lane.
 template <int NW>
 __global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 2 : 2)))
-void k_batch(const BatchItem *items, const int *order, int count, int *next, double *scratch)
+void k_batch(const BatchItem *items, const int *order, int *meta, double *scratch)
 {
+    // meta[0]: queue counter (zeroed by k_batch_reset); meta[1]: instance
+    // count (written with the table, so a captured launch serves any refill)
     __shared__ Lds L;
     __shared__ int slot;
+    const int count = __builtin_nontemporal_load(meta + 1);
+    int *next = meta;
     for (;;) {
         if (threadIdx.x == 0)
             slot = atomicAdd(next, 1);
@@ -337,16 +341,14 @@ int64_t batch_max_n() { return kMaxN; }
 
 bool batch_threads_supported(int threads) { return threads == 256 || threads == 512; }
 
-void launch_batch(const BatchItem *items, const int *order, int count, int *next, double *scratch,
-                  int threads, int grid, hipStream_t st)
+void launch_batch(const BatchItem *items, const int *order, int *meta, double *scratch, int threads,
+                  int grid, hipStream_t st)
 {
-    launch("batch_reset", k_batch_reset, dim3(1), dim3(64), st, next);
-    if (count <= 0)
-        return;
+    launch("batch_reset", k_batch_reset, dim3(1), dim3(64), st, meta);
     if (threads == 512)
-        launch("batch", k_batch<8>, dim3(grid), dim3(512), st, items, order, count, next, scratch);
+        launch("batch", k_batch<8>, dim3(grid), dim3(512), st, items, order, meta, scratch);
     else
-        launch("batch", k_batch<4>, dim3(grid), dim3(256), st, items, order, count, next, scratch);
+        launch("batch", k_batch<4>, dim3(grid), dim3(256), st, items, order, meta, scratch);
 }
 
 }  // namespace bto

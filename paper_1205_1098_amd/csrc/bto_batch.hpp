@@ -22,7 +22,8 @@ struct BatchItem {
 
 int64_t batch_max_n();
 bool batch_threads_supported(int threads);
-void launch_batch(const BatchItem *items, const int *order, int count, int *next, double *scratch,
-                  int threads, int grid, hipStream_t st);
+// meta = {queue counter, instance count}
+void launch_batch(const BatchItem *items, const int *order, int *meta, double *scratch, int threads,
+                  int grid, hipStream_t st);
 
 }  // namespace bto

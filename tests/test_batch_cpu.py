@@ -17,7 +17,7 @@ def bto():
 
 
 def desc(bto, kind, m, n, lda, base):
-    d = bto._Desc()
+    d = bto.Desc()
     d.kind = bto.KERNELS[kind]
     d.form = 0
     d.m, d.n, d.lda, d.ldb = m, n, lda, lda
@@ -32,7 +32,7 @@ def desc(bto, kind, m, n, lda, base):
 
 
 def create(bto, descs):
-    arr = (bto._Desc * len(descs))(*descs)
+    arr = (bto.Desc * len(descs))(*descs)
     plan = ctypes.c_void_p()
     cfg = bto._Config(256, 2, 0)
     return bto._lib.bto_batch_plan_create(ctypes.byref(arr), len(descs), ctypes.byref(cfg),
@@ -73,7 +73,7 @@ def test_rejects_cross_instance_output_overlap(bto):
 
 
 def test_rejects_bad_config(bto):
-    arr = (bto._Desc * 1)(desc(bto, "bicgk", 10, 100, 100, FAKE))
+    arr = (bto.Desc * 1)(desc(bto, "bicgk", 10, 100, 100, FAKE))
     plan = ctypes.c_void_p()
     cfg = bto._Config(384, 2, 0)
     assert bto._lib.bto_batch_plan_create(ctypes.byref(arr), 1, ctypes.byref(cfg),

@@ -145,3 +145,46 @@ def test_batch_rejects_overlap(env):
     with pytest.raises(bto.BtoError) as e:
         bto.BatchPlan(insts)
     assert e.value.status == 2
+
+
+def test_refilled_plan_matches_fresh_plans(env):
+    """A plan made empty and refilled before each launch (its graph captured
+    once) computes every set of instances exactly as a plan built for that
+    set."""
+    torch, bto = env
+    sets = [batch.make_instances(torch, bto, c, 64, 2048, WEIGHTS, seed=20 + k, config=6 + k)
+            for k, c in enumerate([50, 7, 64, 1])]
+    sets.insert(2, ([], []))
+    outs = lambda insts: [t.clone() for inst in insts for t in inst["out"]]
+
+    def poison(insts):
+        for inst in insts:
+            for t in inst["out"]:
+                t.fill_(float("nan"))
+
+    for graph in (True, False):
+        plan = bto.BatchPlan.empty(64, 0, use_graph=graph)
+        for insts, specs in sets:
+            poison(insts)
+            plan.reset(insts)
+            plan.launch()
+            torch.cuda.synchronize()
+            got = outs(insts)
+            if insts:
+                check_all(torch, insts, specs, exact=False)
+                poison(insts)
+                fresh = bto.BatchPlan(insts, use_graph=graph)
+                fresh.launch()
+                torch.cuda.synchronize()
+                assert all(torch.equal(a, b) for a, b in zip(got, outs(insts))), graph
+                fresh.close()
+        many, _ = batch.make_instances(torch, bto, 65, 64, 128, WEIGHTS, seed=30, config=12)
+        with pytest.raises(bto.BtoError) as e:
+            plan.reset(many)
+        assert e.value.status == 1
+        unf, _ = batch.make_instances(torch, bto, 2, 64, 128, {"atax": 1.0}, seed=31,
+                                      config=13, form="unfused")
+        with pytest.raises(bto.BtoError) as e:
+            plan.reset(unf)
+        assert e.value.status == 3
+        plan.close()
