@@ -256,7 +256,11 @@ void bto_timing_reset(void);
  * partitioning and thread-count choices of Sections III-C and IV-D: they
  * change speed, never results beyond summation order.  bto_tune_set
  * returns BTO_ERR_INVALID_ARG for a configuration the slot cannot run; the
- * table is process-wide and guarded by a lock. */
+ * table is process-wide and guarded by a lock.  The last two slots are not
+ * tile sweeps: "atax_rowres" and "bicgk_rowres" pick the workgroup size
+ * (shape 256, 512 or 1024; rb = rev = 0) of the row-resident fused ATAX and
+ * BiCGK sweeps, which hold whole rows on chip; for "bicgk_rowres" shape 0
+ * selects the tile sweep of slot "bicgk_fused" instead. */
 int bto_tune_slot_count(void);
 const char *bto_tune_slot_name(int slot);
 int bto_tune_slot_ops(int slot);

@@ -106,7 +106,14 @@ size_t bytes_vec(int64_t n) { return round256((size_t)n * 8); }
 size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
 {
     switch (k) {
-    case BTO_K_BICGK:
+    case BTO_K_BICGK: {
+        const size_t tiles = bytes_rowparts(m, n) + bytes_colparts(m, n);
+        if (f == BTO_UNFUSED)
+            return tiles;
+        // either fused kernel may be selected by tuning: room for both
+        const size_t rowres = round256((size_t)(rowres_max_parts(m, n, true) * n) * 8);
+        return tiles > rowres ? tiles : rowres;
+    }
     case BTO_K_GEMVER:
     case BTO_K_DGEMVT:
         return bytes_rowparts(m, n) + bytes_colparts(m, n);
@@ -428,6 +435,16 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
                            vspan("s", s, n, true), wspan(ws, need_ws)},
                           {}));
 
+    const int bt = form == BTO_FUSED ? get_bicgk_rowres_threads() : 0;
+    const int64_t G = bt ? rowres_parts(m, n, bt, true) : 0;
+    if (G > 0) {
+        // row-resident sweep: q rows directly, s from G partial vectors
+        Carve cw(ws);
+        double *P = cw.take(G * n);
+        launch_bicgk_rowres(m, n, A, lda, p, r, q, P, bt, st);
+        launch_finish("finish", fjob(P, G, n, 1.0, nullptr, s), kNoJob, st);
+        return check_launch();
+    }
     Carve cv(ws);
     double *Prow = cv.take(max_ncols(n) * m);
     double *Pcol = cv.take(max_nbands(m) * n);
@@ -733,15 +750,20 @@ void bto_timing_reset(void)
 // ---- tuning --------------------------------------------------------------------
 
 // Slot SLOT_COUNT is the row-resident ATAX sweep: its "shape" is the
-// workgroup size (256, 512 or 1024 threads); rb and rev are 0.
+// workgroup size (256, 512 or 1024 threads); rb and rev are 0.  Slot
+// SLOT_COUNT + 1 is the row-resident BiCGK sweep, the same with shape 0
+// meaning "use the tile kernel of slot bicgk_fused instead".
 constexpr int kRowresSlot = SLOT_COUNT;
+constexpr int kBicgkRowresSlot = SLOT_COUNT + 1;
 
-int bto_tune_slot_count(void) { return SLOT_COUNT + 1; }
+int bto_tune_slot_count(void) { return SLOT_COUNT + 2; }
 
 const char *bto_tune_slot_name(int slot)
 {
     if (slot == kRowresSlot)
         return "atax_rowres";
+    if (slot == kBicgkRowresSlot)
+        return "bicgk_rowres";
     return (slot >= 0 && slot < SLOT_COUNT) ? kSlotNames[slot] : "";
 }
 
@@ -753,9 +775,10 @@ int bto_tune_slot_ops(int slot)
 bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
 {
     t_error.clear();
-    if (slot == kRowresSlot) {
+    if (slot == kRowresSlot || slot == kBicgkRowresSlot) {
         std::lock_guard<std::mutex> g(g_cfg_mu);
-        if (shape) *shape = get_rowres_threads();
+        if (shape)
+            *shape = slot == kRowresSlot ? get_rowres_threads() : get_bicgk_rowres_threads();
         if (rb) *rb = 0;
         if (rev) *rev = 0;
         return BTO_SUCCESS;
@@ -776,6 +799,12 @@ bto_status bto_tune_set(int slot, int shape, int rb, int rev)
         std::lock_guard<std::mutex> g(g_cfg_mu);
         if (rb != 0 || rev != 0 || !set_rowres_threads(shape))
             return fail(BTO_ERR_INVALID_ARG, "atax_rowres takes (256|512|1024, 0, 0)");
+        return BTO_SUCCESS;
+    }
+    if (slot == kBicgkRowresSlot) {
+        std::lock_guard<std::mutex> g(g_cfg_mu);
+        if (rb != 0 || rev != 0 || !set_bicgk_rowres_threads(shape))
+            return fail(BTO_ERR_INVALID_ARG, "bicgk_rowres takes (0|256|512|1024, 0, 0)");
         return BTO_SUCCESS;
     }
     if (slot < 0 || slot >= SLOT_COUNT)

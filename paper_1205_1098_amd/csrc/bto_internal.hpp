@@ -104,10 +104,21 @@ struct FinishJob {
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
 
 // Row-resident ATAX: each workgroup keeps one row of A on chip at a time.
-int64_t atax_rowres_parts(int64_t m, int64_t n, int threads);   // 0 when n is too wide
-int64_t atax_rowres_max_parts(int64_t m, int64_t n);   // over every workgroup size
+// Row-resident sweeps: the number of workgroups (partial column-sum
+// vectors) for a workgroup size, 0 when n is too wide or threads is 0.
+int64_t rowres_parts(int64_t m, int64_t n, int threads, bool bicgk);
+int64_t rowres_max_parts(int64_t m, int64_t n, bool bicgk);   // over every workgroup size
+inline int64_t atax_rowres_parts(int64_t m, int64_t n, int threads)
+{
+    return rowres_parts(m, n, threads, false);
+}
+inline int64_t atax_rowres_max_parts(int64_t m, int64_t n) { return rowres_max_parts(m, n, false); }
 bool set_rowres_threads(int t);                        // 256, 512 or 1024
 int get_rowres_threads();
+bool set_bicgk_rowres_threads(int t);                  // 0 (tile kernel), 256, 512 or 1024
+int get_bicgk_rowres_threads();
+void launch_bicgk_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *p,
+                         const double *r, double *q, double *P, int threads, hipStream_t st);
 void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
                         double *P, int threads, hipStream_t st);
 

@@ -352,36 +352,53 @@ __global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int6
     }
 }
 
-// ---- row-resident ATAX ----------------------------------------------------
+// ---- row-resident sweeps (ATAX, BiCGK) ------------------------------------
 //
-// y = A^T (A x) in one sweep of A: workgroup g owns rows [g*m/G, (g+1)*m/G).
-// For each row it loads the whole row into registers (NPT doubles per
-// thread), reduces t_i = A_i . x across the workgroup, and then adds
-// A_i^T t_i to its copy of y while the next row is already in flight.  This
-// is the max-fuse organism of Section IV-A, {p(i){i{j 1}{j 2}}}: the t_i
-// reduction must finish before the update (Section III-D), so the row stays
-// on chip in between.
+// Workgroup g owns rows [g*m/G, (g+1)*m/G) and reads each of them once,
+// whole: a thread holds NPT doubles of the row, and the same columns of the
+// row-dot vector, in registers.  The column sums of its columns accumulate
+// in its slice of LDS (only the owner touches a slice: no barrier), so the
+// workgroup ends with one partial column-sum vector, added over the
+// workgroups by the finish kernel.
+//
+// ATAX, y = A^T (A x): the max-fuse organism of Section IV-A,
+// {p(i){i{j 1}{j 2}}}.  The dot t_i = A_i . x must be complete before the
+// row's update y += A_i^T t_i (Section III-D), so it is reduced across the
+// workgroup for every row while the row stays on chip.
+//
+// BiCGK, q = A p and s = A^T r: the column weight r_i does not depend on the
+// row's dot, so the update never waits for it.  Each wave parks its partial
+// dot of the row in LDS, and the partials of up to kChunk rows are added in
+// wave order together (one barrier pair per chunk, not per row).
 //
 // Register budget: two whole rows (the one being applied and the next one)
-// plus x fill most of it, so each thread's slice of y lives in LDS instead
-// (only its owner ever touches it: no barrier).  Rows are read with buffer
-// loads: one lane offset in a vector register and the pair strides as
-// scalars.  The buffer's range (the even part of the row) returns zeros past
-// the row end; an odd last column is added by a scalar fix-up.
+// plus the dot vector fill most of it, hence the column sums in LDS.  Rows
+// are read with buffer loads: one lane offset in a vector register and the
+// pair strides as scalars.  The buffer's range (the even part of the row)
+// returns zeros past the row end; an odd last column is added by a scalar
+// fix-up.
 
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferDword3 = 0x00020000;   // raw buffer descriptor word 3 on gfx9
 constexpr int kBufferNonTemporal = 2;
+constexpr int kChunk = 64;                  // BiCGK rows per row-dot flush
 
-template <int T, int NPT, bool VEC, bool ODD>
-__global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const double *A,
-                                                   int64_t lda, const double *x, double *P)
+template <int T, bool BICGK>
+struct RowresLds {
+    static constexpr int NW = T / kWave;
+    static constexpr int kRed = BICGK ? kChunk * NW : 2 * NW;
+};
+
+template <int T, int NPT, bool VEC, bool ODD, bool BICGK>
+__global__ __launch_bounds__(T) void k_rowres(int64_t m, int64_t n, const double *A, int64_t lda,
+                                              const double *x, const double *r, double *q,
+                                              double *P)
 {
     constexpr int NP = NPT / 2;     // pairs per thread
     constexpr int NW = T / kWave;   // waves per workgroup
     constexpr bool odd = VEC && ODD;   // n is odd: one column outside whole pairs
     __shared__ d2 ys[T * NP];
-    __shared__ double red[2][NW];
+    __shared__ double red[RowresLds<T, BICGK>::kRed];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -403,10 +420,13 @@ __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const d
     const int64_t plast = (n - 1) / 2;
     const bool own_last = odd && tid == (int)(plast % T);
     const int klast = (int)(plast / T);
-    double lasta = 0.0, lastb = 0.0;
+    double lasta = 0.0, lastb = 0.0;   // A(i, n-1) when n is odd
+    double wa = 0.0, wb = 0.0;         // BiCGK: the row's column weight r_i
 
-    auto load_row = [&](int64_t i, d2 (&dst)[NP], double &last) {
+    auto load_row = [&](int64_t i, d2 (&dst)[NP], double &last, double &wgt) {
         const double *row = A + i * lda;
+        if constexpr (BICGK)
+            wgt = ld_uniform(r + i);
         if constexpr (VEC) {
             const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
                 const_cast<double *>(row), 0, (int)(nev * 8), kBufferDword3);
@@ -424,8 +444,25 @@ __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const d
                 dst[k] = load_pair<false, false>(row, 2 * (int64_t)(tid + T * k), n);
         }
     };
-    // t_i = A_i . x reduced over the workgroup, then y += A_i^T t_i
-    auto process = [&](int64_t i, const d2 (&cur)[NP], double last) {
+
+    // BiCGK row-dot bookkeeping: rows [rbase, rbase + cnt) have parked partials
+    int64_t rbase = r0;
+    int cnt = 0;
+    auto flush = [&]() {
+        lds_barrier();
+        if (tid < cnt) {
+            double sum = red[tid * NW];
+#pragma unroll
+            for (int w = 1; w < NW; ++w)
+                sum += red[tid * NW + w];
+            q[rbase + tid] = sum;
+        }
+        lds_barrier();
+        rbase += cnt;
+        cnt = 0;
+    };
+
+    auto process = [&](int64_t i, const d2 (&cur)[NP], double last, double w_row) {
         double part = 0.0;
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
@@ -433,16 +470,27 @@ __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const d
             part += cur[k].y * xv[k].y;
         }
         part = wave_sum(part);
-        const int buf = (int)(i & 1);
-        if (lane == 0)
-            red[buf][wave] = part;
-        lds_barrier();
-        // lane w < NW takes wave w's sum and a butterfly adds them: every
-        // wave gets the same t from the same fixed tree
-        double t = lane < NW ? red[buf][lane] : 0.0;
-        t = wave_sum(t);
-        if constexpr (odd)
-            t += last * xlast;
+        double t;
+        if constexpr (BICGK) {
+            if constexpr (odd) {
+                if (wave == 0)
+                    part += last * xlast;
+            }
+            if (lane == 0)
+                red[cnt * NW + wave] = part;
+            t = w_row;
+        } else {
+            const int buf = (int)(i & 1);
+            if (lane == 0)
+                red[buf * NW + wave] = part;
+            lds_barrier();
+            // lane w < NW takes wave w's sum and a butterfly adds them: every
+            // wave gets the same t from the same fixed tree
+            t = lane < NW ? red[buf * NW + lane] : 0.0;
+            t = wave_sum(t);
+            if constexpr (odd)
+                t += last * xlast;
+        }
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             d2 yv = ys[tid + T * k];
@@ -455,6 +503,10 @@ __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const d
             if (k % 2 == 1)
                 __builtin_amdgcn_sched_barrier(0);   // at most two y pairs in flight
         }
+        if constexpr (BICGK) {
+            if (++cnt == kChunk)
+                flush();
+        }
     };
     // two row buffers used in turn: the next row is always in flight while
     // the current one is reduced and applied (the scheduling barriers stop
@@ -465,25 +517,29 @@ __global__ __launch_bounds__(T) void k_atax_rowres(int64_t m, int64_t n, const d
     // peeled off after it.
     int64_t i = r0;
     if (i < r1)
-        load_row(i, bufa, lasta);
+        load_row(i, bufa, lasta, wa);
     for (; i + 2 < r1; i += 2) {
-        load_row(i + 1, bufb, lastb);
+        load_row(i + 1, bufb, lastb, wb);
         __builtin_amdgcn_sched_barrier(0);
-        process(i, bufa, lasta);
+        process(i, bufa, lasta, wa);
         __builtin_amdgcn_sched_barrier(0);
-        load_row(i + 2, bufa, lasta);
+        load_row(i + 2, bufa, lasta, wa);
         __builtin_amdgcn_sched_barrier(0);
-        process(i + 1, bufb, lastb);
+        process(i + 1, bufb, lastb, wb);
         __builtin_amdgcn_sched_barrier(0);
     }
     if (i + 1 < r1) {
-        load_row(i + 1, bufb, lastb);
+        load_row(i + 1, bufb, lastb, wb);
         __builtin_amdgcn_sched_barrier(0);
-        process(i, bufa, lasta);
+        process(i, bufa, lasta, wa);
         __builtin_amdgcn_sched_barrier(0);
-        process(i + 1, bufb, lastb);
+        process(i + 1, bufb, lastb, wb);
     } else if (i < r1) {
-        process(i, bufa, lasta);
+        process(i, bufa, lasta, wa);
+    }
+    if constexpr (BICGK) {
+        if (cnt > 0)
+            flush();
     }
 
     double *out = P + g * n;
@@ -501,6 +557,7 @@ struct RowresShape {
 };
 
 std::atomic<int> g_rowres_threads{512};   // preferred workgroup size (tunable; best at n = 16384)
+std::atomic<int> g_bicgk_rowres_threads{512};   // the same for BiCGK; 0 selects the tile kernel
 
 // The workgroup size T (the preferred one first) and the fewest doubles per
 // thread NPT (even) with T*NPT >= n.
@@ -521,10 +578,12 @@ RowresShape rowres_shape(int64_t n, int threads)
     return {0, 0};
 }
 
-int rowres_blocks_per_cu(const RowresShape &s)
+int rowres_blocks_per_cu(const RowresShape &s, bool bicgk)
 {
-    // LDS holds the workgroup's y (T*NPT doubles); at most 160 KiB per CU.
-    int by_lds = (int)(160 * 1024 / ((int64_t)s.T * s.NPT * 8 + 64));
+    // LDS holds the workgroup's column sums (T*NPT doubles) and the row-dot
+    // exchange; at most 160 KiB per CU.
+    const int64_t red = 8 * (int64_t)(s.T / kWave) * (bicgk ? kChunk : 2);
+    int by_lds = (int)(160 * 1024 / ((int64_t)s.T * s.NPT * 8 + red + 16));
     int by_threads = 2048 / s.T;
     int b = by_lds < by_threads ? by_lds : by_threads;
     return b < 1 ? 1 : b;
@@ -590,55 +649,71 @@ bool set_rowres_threads(int t)
 
 int get_rowres_threads() { return g_rowres_threads.load(); }
 
-static int64_t rowres_parts_for(int64_t m, const RowresShape &s)
+bool set_bicgk_rowres_threads(int t)
+{
+    if (t != 0 && t != 256 && t != 512 && t != 1024)
+        return false;
+    g_bicgk_rowres_threads = t;
+    return true;
+}
+
+int get_bicgk_rowres_threads() { return g_bicgk_rowres_threads.load(); }
+
+static int64_t rowres_parts_for(int64_t m, const RowresShape &s, bool bicgk)
 {
     if (s.T == 0 || m <= 0)
         return 0;
-    int64_t g = (int64_t)kCUs * rowres_blocks_per_cu(s);
+    int64_t g = (int64_t)kCUs * rowres_blocks_per_cu(s, bicgk);
     return g < m ? g : m;
 }
 
-int64_t atax_rowres_parts(int64_t m, int64_t n, int threads)
+int64_t rowres_parts(int64_t m, int64_t n, int threads, bool bicgk)
 {
-    if (n <= 0)
+    if (n <= 0 || threads == 0)
         return 0;
-    return rowres_parts_for(m, rowres_shape(n, threads));
+    return rowres_parts_for(m, rowres_shape(n, threads), bicgk);
 }
 
-int64_t atax_rowres_max_parts(int64_t m, int64_t n)
+int64_t rowres_max_parts(int64_t m, int64_t n, bool bicgk)
 {
     if (n <= 0)
         return 0;
     int64_t best = 0;
     for (int t : {256, 512, 1024}) {
-        const int64_t p = rowres_parts_for(m, rowres_shape(n, t));
+        const int64_t p = rowres_parts_for(m, rowres_shape(n, t), bicgk);
         best = p > best ? p : best;
     }
     return best;
 }
 
-void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
-                        double *P, int threads, hipStream_t st)
+template <int T_, int NPT_, bool BICGK>
+static void launch_rowres_shape(int64_t G, int64_t m, int64_t n, const double *A, int64_t lda,
+                                const double *x, const double *r, double *q, double *P,
+                                hipStream_t st)
 {
-    RowresShape s = rowres_shape(n, threads);
-    const int64_t G = atax_rowres_parts(m, n, threads);
+    const char *name = BICGK ? "bicgk_rowres" : "atax_rowres";
+    const dim3 g((unsigned)G), b(T_);
+    const bool vec = aligned16(A) && lda % 2 == 0;
+    if (vec && (n & 1))
+        launch(name, k_rowres<T_, NPT_, true, true, BICGK>, g, b, st, m, n, A, lda, x, r, q, P);
+    else if (vec)
+        launch(name, k_rowres<T_, NPT_, true, false, BICGK>, g, b, st, m, n, A, lda, x, r, q, P);
+    else
+        launch(name, k_rowres<T_, NPT_, false, false, BICGK>, g, b, st, m, n, A, lda, x, r, q,
+               P);
+}
+
+template <bool BICGK>
+static void launch_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                          const double *r, double *q, double *P, int threads, hipStream_t st)
+{
+    const RowresShape s = rowres_shape(n, threads);
+    const int64_t G = rowres_parts(m, n, threads, BICGK);
     if (G == 0)
         return;
-    const bool vec = aligned16(A) && lda % 2 == 0;
-#define BTO_ROWRES_CASE(T_, NPT_)                                                              \
-    if (s.T == T_ && s.NPT == NPT_) {                                                          \
-        const dim3 g((unsigned)G), b(T_);                                                      \
-        if (vec && (n & 1))                                                                    \
-            launch("atax_rowres", k_atax_rowres<T_, NPT_, true, true>, g, b, st, m, n, A, lda, \
-                   x, P);                                                                      \
-        else if (vec)                                                                          \
-            launch("atax_rowres", k_atax_rowres<T_, NPT_, true, false>, g, b, st, m, n, A,     \
-                   lda, x, P);                                                                 \
-        else                                                                                   \
-            launch("atax_rowres", k_atax_rowres<T_, NPT_, false, false>, g, b, st, m, n, A,    \
-                   lda, x, P);                                                                 \
-        return;                                                                                \
-    }
+#define BTO_ROWRES_CASE(T_, NPT_)                                                   \
+    if (s.T == T_ && s.NPT == NPT_)                                                 \
+        return launch_rowres_shape<T_, NPT_, BICGK>(G, m, n, A, lda, x, r, q, P, st);
     BTO_ROWRES_CASE(256, 2)
     BTO_ROWRES_CASE(256, 4)
     BTO_ROWRES_CASE(256, 8)
@@ -654,6 +729,18 @@ void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, cons
     BTO_ROWRES_CASE(1024, 8)
     BTO_ROWRES_CASE(1024, 16)
 #undef BTO_ROWRES_CASE
+}
+
+void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                        double *P, int threads, hipStream_t st)
+{
+    launch_rowres<false>(m, n, A, lda, x, nullptr, nullptr, P, threads, st);
+}
+
+void launch_bicgk_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *p,
+                         const double *r, double *q, double *P, int threads, hipStream_t st)
+{
+    launch_rowres<true>(m, n, A, lda, p, r, q, P, threads, st);
 }
 
 }  // namespace bto

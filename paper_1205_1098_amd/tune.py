@@ -39,10 +39,11 @@ from dataclasses import dataclass, field
 SLOT_BICGK_FUSED, SLOT_GEMV_N, SLOT_GEMV_T, SLOT_GER = 0, 1, 2, 3
 SLOT_GEMVER_P1, SLOT_GEMVER_P2, SLOT_DGEMVT_P1, SLOT_DGEMVT_P2 = 4, 5, 6, 7
 SLOT_ATAX_ROWRES = 8   # its "shape" is the workgroup size of the row-resident sweep
+SLOT_BICGK_ROWRES = 9  # likewise for BiCGK; shape 0 selects the tile sweep instead
 
 #: the matrix sweeps each kernel launches in each form
 KERNEL_SLOTS = {
-    ("bicgk", "fused"): [SLOT_BICGK_FUSED],
+    ("bicgk", "fused"): [SLOT_BICGK_ROWRES, SLOT_BICGK_FUSED],
     ("bicgk", "unfused"): [SLOT_GEMV_N, SLOT_GEMV_T],
     ("gemver", "fused"): [SLOT_GEMVER_P1, SLOT_GEMVER_P2],
     ("gemver", "unfused"): [SLOT_GER, SLOT_GEMV_T, SLOT_GEMV_N],
@@ -88,6 +89,8 @@ class Space:
             shapes, rbs = range(nshapes), RB_CHOICES
             if slot == SLOT_ATAX_ROWRES:
                 shapes, rbs = (256, 512, 1024), (0,)
+            elif slot == SLOT_BICGK_ROWRES:
+                shapes, rbs = (0, 256, 512, 1024), (0,)
             for shape in shapes:
                 for rb in rbs:
                     for rev in (0, 1):

@@ -90,6 +90,40 @@ def test_bicgk(env, m, n, pad, form):
     assert relerr(host(s), s_ref) <= TOL
 
 
+# the fused BiCGK sweeps: the tile kernel (slot value 0) and the row-resident
+# kernel at each workgroup size; (140000, 301) gives every workgroup more
+# than one 64-row batch of row dots, n = 16385 is too wide to hold a row on
+# chip and falls back to the tile kernel
+SLOT_BICGK_ROWRES = 9
+
+
+@pytest.mark.parametrize("threads", [0, 256, 512, 1024])
+@pytest.mark.parametrize("m,n,pad,kind", [
+    (1, 1, 0, "uniform"), (7, 1, 0, "uniform"), (2, 3, 3, "uniform"), (65, 127, 0, "uniform"),
+    (513, 1000, 8, "uniform"), (300, 4097, 3, "uniform"), (1000, 8193, 0, "uniform"),
+    (40, 16384, 0, "uniform"), (20, 16385, 0, "uniform"), (140000, 301, 0, "uniform"),
+    (999, 2049, 0, "int")])
+def test_bicgk_fused_paths(env, threads, m, n, pad, kind):
+    torch, bto, dev = env
+    assert bto.tune_slots()[SLOT_BICGK_ROWRES] == "bicgk_rowres"
+    lda = _lda(n, pad)
+    A, vec = inputs(kind, m, n, lda, 1, 7)
+    p, r = vec(1, n), vec(2, m)
+    q_ref, s_ref = oracle.bicgk(A, p, r, lda=lda)
+    saved = bto.tune_get(SLOT_BICGK_ROWRES)
+    bto.tune_set(SLOT_BICGK_ROWRES, threads, 0, 0)
+    try:
+        q, s = bto.bicgk(dmat(torch, dev, A, n), dvec(torch, dev, p), dvec(torch, dev, r))
+        torch.cuda.synchronize()
+    finally:
+        bto.tune_set(SLOT_BICGK_ROWRES, *saved)
+    if kind == "int":
+        assert np.array_equal(host(q), q_ref) and np.array_equal(host(s), s_ref)
+    else:
+        assert relerr(host(q), q_ref) <= TOL
+        assert relerr(host(s), s_ref) <= TOL
+
+
 @pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("pad", LDA_PAD)
 @pytest.mark.parametrize("m,n", MSHAPES)
