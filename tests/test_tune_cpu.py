@@ -1,0 +1,178 @@
+"""The autotuner's search logic on the CPU, driven by a deterministic cost
+table in place of device timings: the max-fuse start, the orthogonal search,
+the genetic search's reproducibility and legality, the fitness cache and its
+resumption, and the final band-height sweep."""
+
+import json
+import math
+
+import pytest
+
+from paper_1205_1098_amd import tune
+
+SHAPES = range(11)
+RBS = (8, 16, 32, 64, 128, 256)
+SLOTS = range(10)
+
+
+def fake_space():
+    sp = tune.Space()
+    for slot in SLOTS:
+        if slot in (tune.SLOT_ATAX_ROWRES, tune.SLOT_BICGK_ROWRES):
+            legal = [(t, 0, 0) for t in ((256, 512, 1024) if slot == tune.SLOT_ATAX_ROWRES
+                                         else (0, 256, 512, 1024))]
+        else:
+            # an uneven legal set, like the library's: some (shape, rb) pairs missing
+            legal = [(s, rb, rev) for s in SHAPES for rb in RBS for rev in (0, 1)
+                     if not (s % 3 == 1 and rb < 32)]
+        sp.legal[slot] = legal
+        sp.defaults[slot] = legal[len(legal) // 2]
+    return sp
+
+
+# Each slot has one best configuration; the cost of an organism is the
+# form's base cost plus, per slot, its distance from that slot's optimum.
+OPT = {slot: (slot % 11, RBS[slot % len(RBS)], slot % 2) for slot in SLOTS}
+OPT = {slot: (c[0], 64 if c[0] % 3 == 1 and c[1] < 32 else c[1], c[2]) for slot, c in OPT.items()}
+OPT[tune.SLOT_ATAX_ROWRES] = (512, 0, 0)
+OPT[tune.SLOT_BICGK_ROWRES] = (256, 0, 0)
+BASE = {"fused": 1.0, "unfused": 1.9}
+
+
+def slot_cost(slot, c):
+    o = OPT[slot]
+    if slot in (tune.SLOT_ATAX_ROWRES, tune.SLOT_BICGK_ROWRES):
+        return 0.0 if c == o else 0.05 + abs(c[0] - o[0]) / 1e4
+    return 0.02 * abs(c[0] - o[0]) + 0.01 * abs(math.log2(c[1] / o[1])) + 0.005 * (c[2] != o[2])
+
+
+class Counter:
+    def __init__(self, base=BASE):
+        self.calls = 0
+        self.base = base
+
+    def __call__(self, kernel, m, n, org):
+        self.calls += 1
+        return self.base[org.form] + sum(slot_cost(s, c) for s, c in org.slots)
+
+
+def legal_org(space, kernel, org):
+    slots = [s for s, _ in org.slots]
+    assert slots == sorted(tune.KERNEL_SLOTS[(kernel, org.form)])
+    return all(c in space.legal[s] for s, c in org.slots)
+
+
+def test_max_fuse_is_fused_with_defaults():
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter())
+    for kernel in ("bicgk", "gemver", "atax", "dgemvt"):
+        org = t.max_fuse(kernel)
+        assert org.form == "fused"
+        assert org.cfg() == {s: sp.defaults[s] for s in tune.KERNEL_SLOTS[(kernel, "fused")]}
+
+
+@pytest.mark.parametrize("kernel", ["bicgk", "gemver", "atax", "dgemvt"])
+def test_orthogonal_finds_separable_optimum(kernel):
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter())
+    best = t.orthogonal(kernel, 1000, 1000)
+    assert best.form == "fused"
+    assert best.cfg() == {s: OPT[s] for s in tune.KERNEL_SLOTS[(kernel, "fused")]}
+    # every legal configuration of every slot was visited once at most
+    budget = 2 + sum(len(sp.legal[s]) for s in tune.KERNEL_SLOTS[(kernel, "fused")])
+    assert t.evaluations <= budget
+
+
+def test_orthogonal_both_forms_and_fusion_choice():
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter({"fused": 2.5, "unfused": 1.0}))   # fusion loses here
+    best = t.orthogonal("gemver", 64, 64, forms=["fused", "unfused"])
+    assert set(t.form_best) == {"fused", "unfused"}
+    assert best.form == "unfused"
+    assert t.form_best["fused"].cfg() == {s: OPT[s] for s in
+                                          tune.KERNEL_SLOTS[("gemver", "fused")]}
+    t2 = tune.Tuner(sp, Counter({"fused": 2.5, "unfused": 1.0}))
+    assert t2.orthogonal("gemver", 64, 64).form == "unfused"
+
+
+def test_mfga_reproducible_and_legal():
+    sp = fake_space()
+    runs = []
+    for _ in range(2):
+        ev = Counter()
+        t = tune.Tuner(sp, ev, seed=7)
+        best = t.mfga("gemver", 512, 512, population=20, generations=6, k=2)
+        runs.append((best, ev.calls, dict(t.cache)))
+    assert runs[0][0] == runs[1][0] and runs[0][1] == runs[1][1] and runs[0][2] == runs[1][2]
+    best = runs[0][0]
+    assert legal_org(sp, "gemver", best)
+    t = tune.Tuner(sp, Counter(), seed=7)
+    mf = t.fitness("gemver", 512, 512, t.max_fuse("gemver"))
+    assert t.fitness("gemver", 512, 512, best) <= mf
+
+
+def test_mutation_and_crossover_stay_legal():
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter(), seed=3)
+    for kernel in ("bicgk", "gemver", "atax", "dgemvt"):
+        t._kernel = kernel
+        pop = [t.max_fuse(kernel)]
+        for i in range(300):
+            a, b = t.rng.choice(pop), t.rng.choice(pop)
+            child = t.mutate(t.crossover(a, b)) if i % 2 else t.mutate(a)
+            assert legal_org(sp, kernel, child), (kernel, child)
+            pop.append(child)
+        # the four mutation kinds reach both forms and change geometry
+        assert {o.form for o in pop} == {"fused", "unfused"}
+        assert len({o.slots for o in pop}) > 20
+
+
+def test_fitness_cache_counts_once_and_resumes(tmp_path):
+    sp = fake_space()
+    path = str(tmp_path / "cache.json")
+    ev = Counter()
+    t = tune.Tuner(sp, ev, cache_path=path, seed=1)
+    best = t.orthogonal("bicgk", 2048, 2048)
+    first = ev.calls
+    assert first == t.evaluations == len(t.cache)
+    again = t.orthogonal("bicgk", 2048, 2048)        # all cached
+    assert again == best and ev.calls == first
+    t.save({"note": "x"})
+    with open(path) as f:
+        data = json.load(f)
+    assert data["note"] == "x" and len(data["fitness"]) == first
+    ev2 = Counter()
+    t2 = tune.Tuner(sp, ev2, cache_path=path, seed=1)  # resume from disk
+    assert t2.orthogonal("bicgk", 2048, 2048) == best
+    assert ev2.calls == 0
+    # another size is another key
+    t2.fitness("bicgk", 4096, 4096, best)
+    assert ev2.calls == 1
+
+
+def test_sweep_rb_keeps_shape_and_improves():
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter())
+    slot = tune.SLOT_GEMVER_P1
+    o = OPT[slot]
+    start = t.organism("gemver", "fused", {slot: (o[0], 8 if (o[0], 8, o[2]) in sp.legal[slot]
+                                                  else 32, o[2])})
+    best = t.sweep_rb("gemver", 100, 100, start)
+    assert best.cfg()[slot][0] == o[0]
+    assert best.cfg()[slot][1] == o[1]
+    assert t.fitness("gemver", 100, 100, best) <= t.fitness("gemver", 100, 100, start)
+
+
+def test_apply_sets_every_slot():
+    calls = []
+
+    class FakeLib:
+        @staticmethod
+        def tune_set(slot, shape, rb, rev):
+            calls.append((slot, shape, rb, rev))
+
+    sp = fake_space()
+    t = tune.Tuner(sp, Counter())
+    org = t.orthogonal("gemver", 10, 10)
+    tune.apply(FakeLib, org)
+    assert calls == [(s, *c) for s, c in org.slots]
