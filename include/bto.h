@@ -172,12 +172,18 @@ bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z
  * dimensions.  One workgroup computes a whole instance, in an order fixed by
  * the instance and the workgroup size, so for a given workgroup size the
  * results do not depend on the grid, the graph, the other instances or
- * which workgroup takes the instance (another workgroup size adds the same
- * terms in another fixed order).
+ * which workgroup takes the instance (another workgroup size or tile size
+ * adds the same terms in another fixed order).  A fused instance larger
+ * than config.split_bytes is cut into row tiles taken by several
+ * workgroups: each tile writes its partial column sums to the plan's
+ * scratch, the last tile to finish adds them in tile order, and GEMVER's
+ * second-sweep tiles (queued after every first-sweep tile) start once that
+ * instance's x is complete.
  *
- * bto_batch_plan_create validates every instance, orders them by decreasing
- * work and copies the table to device memory (the plan owns that memory,
- * and a scratch area for unfused ATAX temporaries, until it is destroyed).
+ * bto_batch_plan_create validates every instance, orders the work by
+ * decreasing size and copies the table to device memory (the plan owns that
+ * memory, and a scratch area for unfused ATAX temporaries and tile
+ * partials, until it is destroyed).
  * With use_graph set, the launch (a queue reset and the persistent kernel)
  * is captured once in a HIP graph.  bto_batch_plan_launch enqueues the
  * whole batch on `stream` and allocates nothing; successive launches of one
@@ -197,22 +203,33 @@ typedef struct {
 
 typedef struct {
     int threads;       /* workgroup size: 256 or 512 (0 = default 256) */
-    int wgs_per_cu;    /* persistent workgroups per compute unit, 1..2 (0 = 2) */
+    int wgs_per_cu;    /* persistent workgroups per compute unit, 1..8 (0 = default 2;
+                          more than can be resident at once only queue) */
     int use_graph;     /* capture the launch in a HIP graph */
+    int64_t split_bytes;  /* fused instances whose matrix is larger are cut into
+                             row tiles of about this many bytes, run by several
+                             workgroups (0 = default 16 MiB; negative = never) */
 } bto_batch_config;
 
 typedef struct bto_batch_plan bto_batch_plan;
 
 /* Largest column count a batched instance may have. */
 int64_t bto_batch_max_n(void);
+
+/* Doubles of plan scratch the instances need (unfused ATAX temporaries and
+ * the column-sum partials of split instances) under `config` (may be NULL
+ * for the defaults); only kind, form, m and n are read.  -1 for a negative
+ * count or size. */
+int64_t bto_batch_scratch_doubles(const bto_batch_desc *descs, int count,
+                                  const bto_batch_config *config);
 bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
                                  const bto_batch_config *config, bto_batch_plan **plan);
 
 /* A plan that is filled later, for loops that run a different set of
  * instances each step (continuous batching in a server).  `capacity` is the
- * most instances one refill may hold; `scratch_doubles` the scratch area for
- * unfused ATAX instances (each needs its row count rounded up to a multiple
- * of 32 doubles; 0 if there are none).  The plan starts with no instances. */
+ * most instances one refill may hold; `scratch_doubles` the scratch area
+ * (bto_batch_scratch_doubles of the largest set of instances it will hold).
+ * The plan starts with no instances. */
 bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
                                        const bto_batch_config *config, bto_batch_plan **plan);
 
@@ -229,6 +246,12 @@ bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
 bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *descs, int count,
                                 hipStream_t stream);
 bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream);
+
+/* Wait for `stream` and report whether the plan's last launch completed
+ * its waits: a second-sweep tile waits a bounded time for its instance's
+ * first sweep, and BTO_ERR_HIP here means one gave up (the launch's results
+ * are then not valid).  Synchronizes; for tests and diagnostics. */
+bto_status bto_batch_plan_check(bto_batch_plan *plan, hipStream_t stream);
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
 
 /* ---- measurement support ------------------------------------------------

@@ -63,16 +63,19 @@ def _lda(n: int) -> int:
 
 def make_instances(torch, bto, count: int, lo: int, hi: int, weights: dict,
                    seed: int = synth.SEED, config: int = 4, form: str = "fused",
-                   data: str = "uniform", device="cuda:0", in_place: bool = False):
-    """Build `count` instances on `device`; returns (instances, specs)."""
+                   data: str = "uniform", device="cuda:0", in_place: bool = False,
+                   shapes: list | None = None):
+    """Build `count` instances on `device`; returns (instances, specs).
+    With `shapes` given, instance i is shapes[i] = (m, n) instead of square
+    with a drawn n (the kinds are still drawn)."""
     dev = torch.device(device)
     sizes, kinds = sizes_and_kinds(count, lo, hi, weights, seed, config)
+    dims = shapes if shapes is not None else [(n, n) for n in sizes]
     instances, specs = [], []
-    for idx, (n, kind) in enumerate(zip(sizes, kinds)):
-        m = n
+    for idx, ((m, n), kind) in enumerate(zip(dims, kinds)):
         state = lambda op: synth.stream_state(seed, synth.stream_id(config, op, idx))
         lda = _lda(n)
-        full = torch.empty((m, lda), dtype=torch.float64, device=dev)
+        full = torch.empty((max(m, 1), lda), dtype=torch.float64, device=dev)[:m]
         A = full[:, :n]
         bto.synth_fill(A, state(0), kind=data)
         inst = {"kind": kind, "form": form, "A": A, "in": [], "out": []}

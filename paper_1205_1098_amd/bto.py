@@ -74,6 +74,8 @@ _SIGS = {
     "bto_batch_max_n": ([], _i64),
     "bto_batch_plan_create": ([_ptr, _int, _ptr, _ptr], _int),
     "bto_batch_plan_create_empty": ([_int, _i64, _ptr, _ptr], _int),
+    "bto_batch_scratch_doubles": ([_ptr, _int, _ptr], _i64),
+    "bto_batch_plan_check": ([_ptr, _ptr], _int),
     "bto_batch_plan_reset": ([_ptr, _ptr, _int, _ptr], _int),
     "bto_batch_plan_launch": ([_ptr, _ptr], _int),
     "bto_batch_plan_destroy": ([_ptr], _int),
@@ -418,8 +420,9 @@ class Desc(ctypes.Structure):
 
 
 class _Config(ctypes.Structure):
+    """bto_batch_config."""
     _fields_ = [("threads", ctypes.c_int), ("wgs_per_cu", ctypes.c_int),
-                ("use_graph", ctypes.c_int)]
+                ("use_graph", ctypes.c_int), ("split_bytes", ctypes.c_int64)]
 
 
 def batch_max_n() -> int:
@@ -462,10 +465,20 @@ def _batch_descs(instances):
     return descs, keep, dev
 
 
-def batch_scratch_doubles(instances) -> int:
-    """Scratch a plan needs for these instances (unfused ATAX temporaries)."""
-    return sum((inst["A"].shape[0] + 31) // 32 * 32 for inst in instances
-               if inst["kind"] == "atax" and inst.get("form", "fused") == "unfused")
+def batch_scratch_doubles(instances, split_bytes: int = 0) -> int:
+    """Scratch a plan needs for these instances (unfused ATAX temporaries and
+    the column-sum partials of split instances)."""
+    descs = (Desc * max(len(instances), 1))()
+    for i, inst in enumerate(instances):
+        d = descs[i]
+        d.kind = KERNELS[inst["kind"]]
+        d.form = _form(inst.get("form", "fused"))
+        d.m, d.n = inst["A"].shape if "A" in inst else (inst["m"], inst["n"])
+    cfg = _Config(256, 0, 0, int(split_bytes))
+    need = _lib.bto_batch_scratch_doubles(ctypes.byref(descs), len(instances), ctypes.byref(cfg))
+    if need < 0:
+        raise ValueError("bad instance sizes")
+    return int(need)
 
 
 class BatchPlan:
@@ -480,9 +493,10 @@ class BatchPlan:
     batch on the current stream and allocates nothing.  A plan made with
     `BatchPlan.empty` is refilled with `reset` before each launch."""
 
-    def __init__(self, instances, threads: int = 256, wgs_per_cu: int = 2,
-                 use_graph: bool = True, *, _capacity=None, _scratch=0, _device=None):
-        cfg = _Config(threads, wgs_per_cu, 1 if use_graph else 0)
+    def __init__(self, instances, threads: int = 256, wgs_per_cu: int = 0,
+                 use_graph: bool = True, split_bytes: int = 0, *, _capacity=None, _scratch=0,
+                 _device=None):
+        cfg = _Config(threads, wgs_per_cu, 1 if use_graph else 0, int(split_bytes))
         self._plan = ctypes.c_void_p()
         if _capacity is not None:
             self.device = torch.device(_device if _device is not None else "cuda:0")
@@ -501,9 +515,18 @@ class BatchPlan:
 
     @classmethod
     def empty(cls, capacity: int, scratch_doubles: int = 0, threads: int = 256,
-              wgs_per_cu: int = 2, use_graph: bool = True, device="cuda:0") -> "BatchPlan":
-        return cls(None, threads, wgs_per_cu, use_graph, _capacity=capacity,
+              wgs_per_cu: int = 0, use_graph: bool = True, device="cuda:0",
+              split_bytes: int = 0) -> "BatchPlan":
+        return cls(None, threads, wgs_per_cu, use_graph, split_bytes, _capacity=capacity,
                    _scratch=scratch_doubles, _device=device)
+
+    def check(self) -> None:
+        """Wait for the current stream; raise if the last launch's tile waits
+        gave up (bto_batch_plan_check)."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_batch_plan_check(self._plan, _stream(self.device)))
 
     def reset(self, instances) -> None:
         """Replace the instances (copied on the current stream; no allocation)."""

@@ -884,14 +884,17 @@ bto_status bto_probe_triad(double *a, const double *b, const double *c, double s
 // ---- batched execution ---------------------------------------------------------
 
 struct bto_batch_plan {
-    int capacity = 0;
+    int capacity = 0;               // instances per refill
+    int unit_capacity = 0;
     int count = 0;
     BatchItem *d_items = nullptr;
-    int *d_order = nullptr;
-    int *d_meta = nullptr;          // {queue counter, instance count}
+    BatchUnit *d_units = nullptr;
+    int *d_meta = nullptr;          // kMetaInts control ints
+    int *d_sync = nullptr;          // two per instance: tiles done, x ready
     double *d_scratch = nullptr;
     int64_t scratch_cap = 0;        // doubles
-    // pinned staging of {items, order, count} for asynchronous refills, and
+    int64_t split_bytes = kBatchSplitBytes;   // <= 0: never split
+    // pinned staging of {items, units, meta} for asynchronous refills, and
     // the event that marks when the last refill has been read
     char *h_stage = nullptr;
     size_t stage_bytes = 0;
@@ -912,8 +915,28 @@ struct BSpan {
     bool a_or_b;   // the instance's A or B (exact B == A alias allowed)
 };
 
+// Rows per tile of an instance, or 0 when it runs whole: fused instances
+// whose matrix exceeds split_bytes are cut into row tiles of about that
+// size (at least 8 rows, at most kBatchMaxTiles tiles).
+int64_t tile_rows_for(int kind, int form, int64_t m, int64_t n, int64_t split_bytes)
+{
+    (void)kind;
+    if (form != BTO_FUSED || split_bytes <= 0 || m < 16 || n <= 0)
+        return 0;
+    if ((double)m * (double)n * 8.0 <= (double)split_bytes)
+        return 0;
+    int64_t r = ceil_div(split_bytes, 8 * n);
+    r = r < 8 ? 8 : r;
+    const int64_t rmin = ceil_div(m, (int64_t)kBatchMaxTiles);
+    r = r < rmin ? rmin : r;
+    r = ceil_div(r, (int64_t)8) * 8;
+    return ceil_div(m, r) > 1 ? r : 0;
+}
+
+int64_t part_stride(int64_t n) { return ceil_div(n, (int64_t)32) * 32; }
+
 bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> &spans,
-                           BatchItem &it, int64_t &scratch)
+                           BatchItem &it, int64_t &scratch, int64_t split_bytes)
 {
     const std::string where = "instance " + std::to_string(idx) + ": ";
     auto bad = [&](bto_status st, const std::string &msg) { return fail(st, where + msg); };
@@ -954,12 +977,20 @@ bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> 
         in_len[0] = n;
         out_len[0] = n;
     }
-    for (int k = 0; k < nin; ++k)
+    for (int k = 0; k < nin; ++k) {
         if (in_len[k] > 0 && d.in[k] == nullptr)
             return bad(BTO_ERR_INVALID_ARG, "input vector " + std::to_string(k) + " is NULL");
-    for (int k = 0; k < nout; ++k)
+        if (in_len[k] > 1 && !aligned16(d.in[k]))
+            return bad(BTO_ERR_INVALID_ARG, "input vector " + std::to_string(k) +
+                                                " must be 16-byte aligned");
+    }
+    for (int k = 0; k < nout; ++k) {
         if (out_len[k] > 0 && d.out[k] == nullptr)
             return bad(BTO_ERR_INVALID_ARG, "output vector " + std::to_string(k) + " is NULL");
+        if (out_len[k] > 1 && !aligned16(d.out[k]))
+            return bad(BTO_ERR_INVALID_ARG, "output vector " + std::to_string(k) +
+                                                " must be 16-byte aligned");
+    }
 
     auto add = [&](const void *p, int64_t bytes, bool out, bool ab) {
         if (bytes > 0) {
@@ -991,9 +1022,19 @@ bto_status batch_check_one(const bto_batch_desc &d, int idx, std::vector<BSpan> 
     for (int k = 0; k < 6; ++k) it.vec[k] = k < nin ? d.in[k] : nullptr;
     for (int k = 0; k < 2; ++k) it.out[k] = k < nout ? d.out[k] : nullptr;
     it.scratch_off = 0;
+    it.part_off = 0;
+    it.ntiles = 1;
+    it.tile_rows = m;
     if (d.kind == BTO_K_ATAX && d.form == BTO_UNFUSED) {
         it.scratch_off = scratch;
-        scratch += (m + 31) / 32 * 32;   // 256-byte steps
+        scratch += ceil_div(m, (int64_t)32) * 32;   // 256-byte steps
+    }
+    const int64_t r = tile_rows_for(d.kind, d.form, m, n, split_bytes);
+    if (r > 0) {
+        it.tile_rows = r;
+        it.ntiles = (int32_t)ceil_div(m, r);
+        it.part_off = scratch;
+        scratch += it.ntiles * part_stride(n);
     }
     return BTO_SUCCESS;
 }
@@ -1031,13 +1072,17 @@ bto_status batch_check_overlaps(std::vector<BSpan> &spans)
     return BTO_SUCCESS;
 }
 
-double batch_cost(const bto_batch_desc &d)
+// Matrix passes of a unit times its rows and columns: the work used to
+// order the queue (largest first).
+double unit_cost(const BatchItem &it, const BatchUnit &u)
 {
-    const double mn = (double)d.m * (double)d.n;
-    double passes = 1.0;
-    if (d.kind == BTO_K_GEMVER) passes = d.form == BTO_FUSED ? 3.0 : 6.0;
-    else passes = d.form == BTO_FUSED ? 1.0 : 2.0;
-    return passes * mn + (double)(d.m + d.n);
+    const double rows = (double)(u.r1 - u.r0), cols = (double)it.n;
+    double passes;
+    if (it.kind == BTO_K_GEMVER)
+        passes = u.phase == 0 ? (it.form == BTO_FUSED ? 3.0 : 6.0) : (u.phase == 1 ? 2.0 : 1.0);
+    else
+        passes = u.phase == 0 && it.form == BTO_UNFUSED ? 2.0 : 1.0;
+    return passes * rows * cols + rows + cols;
 }
 
 void plan_free(bto_batch_plan *p)
@@ -1048,18 +1093,23 @@ void plan_free(bto_batch_plan *p)
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->d_items) (void)hipFree(p->d_items);
-    if (p->d_order) (void)hipFree(p->d_order);
+    if (p->d_units) (void)hipFree(p->d_units);
     if (p->d_meta) (void)hipFree(p->d_meta);
+    if (p->d_sync) (void)hipFree(p->d_sync);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->staged) (void)hipEventDestroy(p->staged);
     delete p;
 }
 
-// Validate `descs`, order them largest first and build the device table
-// image: items, then the order, then the count.
-bto_status plan_image(const bto_batch_desc *descs, int count, std::vector<BatchItem> &items,
-                      std::vector<int> &order, int64_t &scratch)
+// Validate `descs` and build the device table image: the items and the
+// queue of units.  Whole instances and first-sweep tiles come first,
+// largest first; GEMVER's second-sweep tiles follow all of them, so a
+// workgroup that takes one only waits for tiles other running workgroups
+// already hold.
+bto_status plan_image(const bto_batch_desc *descs, int count, int64_t split_bytes,
+                      std::vector<BatchItem> &items, std::vector<BatchUnit> &units,
+                      int64_t &scratch)
 {
     if (count < 0 || (count > 0 && !descs))
         return fail(BTO_ERR_INVALID_ARG, "bad instance list");
@@ -1067,45 +1117,66 @@ bto_status plan_image(const bto_batch_desc *descs, int count, std::vector<BatchI
     items.assign((size_t)count, BatchItem{});
     scratch = 0;
     for (int i = 0; i < count; ++i)
-        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], scratch));
+        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], scratch, split_bytes));
     BTO_TRY(batch_check_overlaps(spans));
-    order.resize((size_t)count);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost((size_t)count);
-    for (int i = 0; i < count; ++i)
-        cost[i] = batch_cost(descs[i]);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<BatchUnit> first, second;
+    for (int i = 0; i < count; ++i) {
+        const BatchItem &it = items[i];
+        if (it.ntiles <= 1) {
+            first.push_back({i, 0, 0, it.m});
+            continue;
+        }
+        for (int t = 0; t < it.ntiles; ++t) {
+            const int64_t r0 = t * it.tile_rows;
+            const int64_t r1 = std::min(it.m, r0 + it.tile_rows);
+            first.push_back({i, 1, r0, r1});
+            if (it.kind == BTO_K_GEMVER)
+                second.push_back({i, 2, r0, r1});
+        }
+    }
+    auto by_cost = [&](std::vector<BatchUnit> &v) {
+        std::vector<double> cost(v.size());
+        std::vector<size_t> idx(v.size());
+        for (size_t k = 0; k < v.size(); ++k) {
+            cost[k] = unit_cost(items[v[k].item], v[k]);
+            idx[k] = k;
+        }
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        std::vector<BatchUnit> out(v.size());
+        for (size_t k = 0; k < v.size(); ++k) out[k] = v[idx[k]];
+        v.swap(out);
+    };
+    by_cost(first);
+    by_cost(second);
+    units = first;
+    units.insert(units.end(), second.begin(), second.end());
     return BTO_SUCCESS;
 }
 
-size_t stage_size(int capacity)
+// the most units one instance can make
+constexpr int kUnitsPerItem = 2 * kBatchMaxTiles;
+
+size_t stage_size(int capacity, int unit_capacity)
 {
-    return round256(sizeof(BatchItem) * (size_t)capacity) + round256(sizeof(int) * (size_t)capacity) +
-           256;
+    return round256(sizeof(BatchItem) * (size_t)capacity) +
+           round256(sizeof(BatchUnit) * (size_t)unit_capacity) + 256;
 }
 
 }  // namespace
 
-extern "C" {
-
-int64_t bto_batch_max_n(void) { return batch_max_n(); }
-
-}  // extern "C"
-
-static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_batch_config *config,
-                             bto_batch_plan **out)
+static bto_status plan_alloc(int capacity, int unit_capacity, int64_t scratch_doubles,
+                             const bto_batch_config *config, bto_batch_plan **out)
 {
-    bto_batch_config cfg{256, 2, 0};
+    bto_batch_config cfg{256, 0, 0, 0};
     if (config) {
         cfg = *config;
         if (cfg.threads == 0) cfg.threads = 256;
-        if (cfg.wgs_per_cu == 0) cfg.wgs_per_cu = 2;
     }
     if (!batch_threads_supported(cfg.threads))
         return fail(BTO_ERR_INVALID_ARG, "threads must be 256 or 512");
-    if (cfg.wgs_per_cu < 1 || cfg.wgs_per_cu > 2)
-        return fail(BTO_ERR_INVALID_ARG, "wgs_per_cu must be 1 or 2");
-    if (capacity < 0 || scratch_doubles < 0)
+    if (cfg.wgs_per_cu < 0 || cfg.wgs_per_cu > 8)
+        return fail(BTO_ERR_INVALID_ARG, "wgs_per_cu must be 0 (the default) to 8");
+    if (capacity < 0 || unit_capacity < 0 || scratch_doubles < 0)
         return fail(BTO_ERR_INVALID_ARG, "negative capacity");
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -1114,10 +1185,14 @@ static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_ba
 
     bto_batch_plan *p = new bto_batch_plan();
     p->capacity = capacity;
+    p->unit_capacity = unit_capacity;
     p->threads = cfg.threads;
-    p->grid = cus * cfg.wgs_per_cu;
+    p->split_bytes = cfg.split_bytes == 0 ? kBatchSplitBytes : cfg.split_bytes;
+    // 0: as many workgroups as can be resident at once
+    const int per_cu = cfg.wgs_per_cu ? cfg.wgs_per_cu : kBatchDefaultWgsPerCu;
+    p->grid = cus * per_cu;
     p->scratch_cap = scratch_doubles;
-    p->stage_bytes = stage_size(capacity);
+    p->stage_bytes = stage_size(capacity, unit_capacity);
     auto hip_fail = [&](const char *what) {
         plan_free(p);
         return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
@@ -1125,8 +1200,11 @@ static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_ba
     if (hipMalloc(&p->d_meta, 256) != hipSuccess || hipMemset(p->d_meta, 0, 256) != hipSuccess)
         return hip_fail("hipMalloc");
     const size_t cap1 = capacity > 0 ? (size_t)capacity : 1;
+    const size_t ucap1 = unit_capacity > 0 ? (size_t)unit_capacity : 1;
     if (hipMalloc(&p->d_items, sizeof(BatchItem) * cap1) != hipSuccess ||
-        hipMalloc(&p->d_order, sizeof(int) * cap1) != hipSuccess)
+        hipMalloc(&p->d_units, sizeof(BatchUnit) * ucap1) != hipSuccess ||
+        hipMalloc(&p->d_sync, 2 * sizeof(int) * cap1) != hipSuccess ||
+        hipMemset(p->d_sync, 0, 2 * sizeof(int) * cap1) != hipSuccess)
         return hip_fail("hipMalloc");
     if (scratch_doubles > 0 &&
         hipMalloc(&p->d_scratch, sizeof(double) * (size_t)scratch_doubles) != hipSuccess)
@@ -1141,7 +1219,8 @@ static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_ba
         if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return hip_fail("hipStreamBeginCapture");
         t_capturing = true;
-        launch_batch(p->d_items, p->d_order, p->d_meta, p->d_scratch, p->threads, p->grid, p->cap);
+        launch_batch(p->d_items, p->d_units, p->d_meta, p->d_sync, p->d_scratch, p->threads,
+                     p->grid, p->cap);
         t_capturing = false;
         if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
             return hip_fail("hipStreamEndCapture");
@@ -1155,26 +1234,28 @@ static bto_status plan_alloc(int capacity, int64_t scratch_doubles, const bto_ba
 // Copy a validated table image into the plan on `stream` (asynchronously,
 // through the plan's pinned staging, after the previous refill was read).
 static bto_status plan_store(bto_batch_plan *p, const std::vector<BatchItem> &items,
-                             const std::vector<int> &order, hipStream_t stream)
+                             const std::vector<BatchUnit> &units, hipStream_t stream)
 {
     const int count = (int)items.size();
+    const int nunits = (int)units.size();
     if (hipEventSynchronize(p->staged) != hipSuccess)
         return fail(BTO_ERR_HIP, "hipEventSynchronize");
     const size_t bi = round256(sizeof(BatchItem) * (size_t)p->capacity);
-    const size_t bo = round256(sizeof(int) * (size_t)p->capacity);
+    const size_t bu = round256(sizeof(BatchUnit) * (size_t)p->unit_capacity);
     char *st = p->h_stage;
-    if (count > 0) {
+    if (count > 0)
         std::memcpy(st, items.data(), sizeof(BatchItem) * (size_t)count);
-        std::memcpy(st + bi, order.data(), sizeof(int) * (size_t)count);
-    }
-    int meta[2] = {0, count};
-    std::memcpy(st + bi + bo, meta, sizeof(meta));
+    if (nunits > 0)
+        std::memcpy(st + bi, units.data(), sizeof(BatchUnit) * (size_t)nunits);
+    int meta[kMetaInts] = {0, nunits, 0, count};
+    std::memcpy(st + bi + bu, meta, sizeof(meta));
     if ((count > 0 &&
-         (hipMemcpyAsync(p->d_items, st, sizeof(BatchItem) * (size_t)count, hipMemcpyHostToDevice,
-                         stream) != hipSuccess ||
-          hipMemcpyAsync(p->d_order, st + bi, sizeof(int) * (size_t)count, hipMemcpyHostToDevice,
-                         stream) != hipSuccess)) ||
-        hipMemcpyAsync(p->d_meta, st + bi + bo, sizeof(meta), hipMemcpyHostToDevice, stream) !=
+         hipMemcpyAsync(p->d_items, st, sizeof(BatchItem) * (size_t)count, hipMemcpyHostToDevice,
+                        stream) != hipSuccess) ||
+        (nunits > 0 &&
+         hipMemcpyAsync(p->d_units, st + bi, sizeof(BatchUnit) * (size_t)nunits,
+                        hipMemcpyHostToDevice, stream) != hipSuccess) ||
+        hipMemcpyAsync(p->d_meta, st + bi + bu, sizeof(meta), hipMemcpyHostToDevice, stream) !=
             hipSuccess ||
         hipEventRecord(p->staged, stream) != hipSuccess)
         return fail(BTO_ERR_HIP, std::string("refill: ") + hipGetErrorString(hipGetLastError()));
@@ -1182,7 +1263,36 @@ static bto_status plan_store(bto_batch_plan *p, const std::vector<BatchItem> &it
     return BTO_SUCCESS;
 }
 
+static int64_t split_of(const bto_batch_config *config)
+{
+    if (!config || config->split_bytes == 0)
+        return kBatchSplitBytes;
+    return config->split_bytes;
+}
+
 extern "C" {
+
+int64_t bto_batch_max_n(void) { return batch_max_n(); }
+
+int64_t bto_batch_scratch_doubles(const bto_batch_desc *descs, int count,
+                                  const bto_batch_config *config)
+{
+    if (count < 0 || (count > 0 && !descs))
+        return -1;
+    const int64_t split = split_of(config);
+    int64_t need = 0;
+    for (int i = 0; i < count; ++i) {
+        const bto_batch_desc &d = descs[i];
+        if (d.m < 0 || d.n < 0)
+            return -1;
+        if (d.kind == BTO_K_ATAX && d.form == BTO_UNFUSED)
+            need += ceil_div(d.m, (int64_t)32) * 32;
+        const int64_t r = tile_rows_for(d.kind, d.form, d.m, d.n, split);
+        if (r > 0)
+            need += ceil_div(d.m, r) * part_stride(d.n);
+    }
+    return need;
+}
 
 bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
                                  const bto_batch_config *config, bto_batch_plan **plan)
@@ -1192,12 +1302,12 @@ bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
         return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
     *plan = nullptr;
     std::vector<BatchItem> items;
-    std::vector<int> order;
+    std::vector<BatchUnit> units;
     int64_t scratch = 0;
-    BTO_TRY(plan_image(descs, count, items, order, scratch));
+    BTO_TRY(plan_image(descs, count, split_of(config), items, units, scratch));
     bto_batch_plan *p = nullptr;
-    BTO_TRY(plan_alloc(count, scratch, config, &p));
-    bto_status s = plan_store(p, items, order, p->cap ? p->cap : nullptr);
+    BTO_TRY(plan_alloc(count, (int)units.size(), scratch, config, &p));
+    bto_status s = plan_store(p, items, units, p->cap ? p->cap : nullptr);
     if (s == BTO_SUCCESS && hipEventSynchronize(p->staged) != hipSuccess)
         s = fail(BTO_ERR_HIP, "hipEventSynchronize");
     if (s != BTO_SUCCESS) {
@@ -1215,7 +1325,9 @@ bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
     if (!plan)
         return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
     *plan = nullptr;
-    return plan_alloc(capacity, scratch_doubles, config, plan);
+    if (capacity < 0 || capacity > (1 << 24))
+        return fail(BTO_ERR_INVALID_ARG, "capacity out of range");
+    return plan_alloc(capacity, capacity * kUnitsPerItem, scratch_doubles, config, plan);
 }
 
 bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *descs, int count,
@@ -1227,12 +1339,16 @@ bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *desc
     if (count > plan->capacity)
         return fail(BTO_ERR_INVALID_ARG, "more instances than the plan's capacity");
     std::vector<BatchItem> items;
-    std::vector<int> order;
+    std::vector<BatchUnit> units;
     int64_t scratch = 0;
-    BTO_TRY(plan_image(descs, count, items, order, scratch));
+    BTO_TRY(plan_image(descs, count, plan->split_bytes, items, units, scratch));
     if (scratch > plan->scratch_cap)
-        return fail(BTO_ERR_WORKSPACE, "unfused ATAX instances need more scratch than the plan has");
-    return plan_store(plan, items, order, stream);
+        return fail(BTO_ERR_WORKSPACE, "the instances need " + std::to_string(scratch) +
+                                           " doubles of scratch, the plan has " +
+                                           std::to_string(plan->scratch_cap));
+    if ((int64_t)units.size() > plan->unit_capacity)
+        return fail(BTO_ERR_INVALID_ARG, "more work units than the plan can queue");
+    return plan_store(plan, items, units, stream);
 }
 
 bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
@@ -1247,10 +1363,25 @@ bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
         if (e != hipSuccess)
             return fail(BTO_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
     } else {
-        launch_batch(plan->d_items, plan->d_order, plan->d_meta, plan->d_scratch, plan->threads,
-                     plan->grid, stream);
+        launch_batch(plan->d_items, plan->d_units, plan->d_meta, plan->d_sync, plan->d_scratch,
+                     plan->threads, plan->grid, stream);
     }
     return check_launch();
+}
+
+bto_status bto_batch_plan_check(bto_batch_plan *plan, hipStream_t stream)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    int meta[kMetaInts] = {0, 0, 0, 0};
+    if (hipStreamSynchronize(stream) != hipSuccess ||
+        hipMemcpy(meta, plan->d_meta, sizeof(meta), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("check: ") + hipGetErrorString(hipGetLastError()));
+    if (meta[kMetaError] != 0)
+        return fail(BTO_ERR_HIP, "a tile of the last launch gave up waiting for its instance's "
+                                 "first sweep; its results are not valid");
+    return BTO_SUCCESS;
 }
 
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan)

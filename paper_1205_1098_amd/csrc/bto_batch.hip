@@ -1,21 +1,31 @@
 // Batched execution: thousands of independent GEMVER / BiCGK / ATAX
 // instances of uneven size in one persistent launch.
 //
-// One workgroup owns one instance at a time and runs all of its passes, so
-// no instance ever depends on another workgroup: no partial-sum buffers, no
-// cross-workgroup waits.  Inside the workgroup each wave takes whole rows
-// (rows i = wave, wave + NW, ...), so a row dot is a single wave reduction
-// and the column sums of the wave's rows accumulate in its lanes' registers;
-// the waves' column sums are then added in LDS in wave order.  Column-indexed
-// vectors (v1, v2, the row-dot weights) sit in LDS.  Instances are limited to
-// n <= 128 * kMaxPPL columns (2048): each lane covers up to kMaxPPL 16-byte
-// pairs of a row.
+// A workgroup takes one unit of work at a time: a whole instance, all of
+// whose passes it runs alone, or one row tile of a large fused instance,
+// which is cut into tiles so that several workgroups share it (the column
+// sums then go through per-tile partials, and GEMVER's second sweep waits
+// for its x; see run_tile).  Instances are limited to n <= 2048 columns.
 //
-// The host sorts the instances by decreasing work (longest first) and the
-// persistent workgroups pull them from one queue counter, so the largest
-// instances start first and the small ones fill in at the end.  Every
-// instance is computed the same way whichever workgroup takes it, so the
-// results do not depend on the schedule.
+// Inside the workgroup every thread owns fixed columns: a row is covered by
+// a group of `tpr` threads (a power of two), thread c of the group holding
+// 16-byte column pairs c, c + tpr, ... (NP of them), and the NT / tpr groups
+// ("row slots") take different rows side by side, so narrow instances still
+// use every lane.  A thread reads 8 pairs (4 in the sweeps that write B) per
+// batch of rows with every load issued before any is used, keeps the row-dot and
+// update vectors for its columns in registers and accumulates the column
+// sums of its columns in registers too.  A row dot is summed inside its
+// thread group with lane permutes; when a row spans several waves their
+// partial sums meet in LDS.  The row slots' column sums are added in LDS in
+// slot order at the end of the sweep.  The odd last column of an odd n is
+// handled by the first thread of each group.
+//
+// The host sorts the units by decreasing work (longest first; GEMVER's
+// second-sweep tiles after all others) and the persistent workgroups pull
+// them from one queue counter, so the largest work starts first and the
+// small units fill in at the end.  Every unit is computed the same way
+// whichever workgroup takes it, so the results depend only on the instance,
+// the workgroup size and the tile size, not on the schedule.
 
 #include "bto.h"
 #include "bto_batch.hpp"
@@ -26,313 +36,578 @@ namespace bto {
 
 namespace {
 
-constexpr int kMaxPPL = 16;                   // pairs per lane: n <= 2048
-constexpr int kMaxN = 128 * kMaxPPL;
+constexpr int kMaxN = 2048;
+constexpr int kMaxNT = 512;
 
 enum SweepOps { SW_ROWDOT = 1, SW_COLSUM = 2, SW_UPD1 = 4, SW_UPD2 = 8, SW_ATAX = 16 };
 
 struct Lds {
-    double v1[kMaxN];     // u-update column vectors / row-dot weights
-    double v2[kMaxN];
-    double xr[kMaxN];     // row-dot weights (p, x) or ATAX x
-    double red[kMaxN];    // column sums combined over the waves
+    double xs[kMaxN];            // GEMVER's x, handed from pass 1 to pass 2
+    double red[2 * kMaxNT];      // column sums of the row slots (one pair per thread)
+    double red_last[kMaxNT];     // the odd column's sums of the row slots
+    double park[2][64];          // row-dot partials of rows wider than a wave
+    int last;                    // this workgroup finished an instance's last tile
 };
 
-__device__ __forceinline__ d2 lds_pair(const double *v, int p) { return reinterpret_cast<const d2 *>(v)[p]; }
+// A second-sweep tile waits for its instance's x at most this many sleeps
+// (about a second); then it gives up, flags the launch as failed and
+// carries on, so every workgroup always reaches the end of the queue.
+constexpr int kSpinLimit = 1 << 22;
 
-// Load pair p (columns 2p, 2p+1) of a row; zero past n.  Rows are 16-byte
-// aligned (checked when the plan is built).
-__device__ __forceinline__ d2 row_pair(const double *row, int p, int64_t n)
+// Where a thread sits for one instance.
+struct Geo {
+    int64_t npf;   // whole column pairs, n / 2
+    int odd;       // n is odd: column n-1 belongs to the first thread of each group
+    int tpr;       // threads per row (a power of two)
+    int rs;        // row slots, NT / tpr
+    int c;         // pair column of this thread within its group
+    int slot;      // row slot of this thread
+};
+
+// Pairs per thread per row: the fewest that let NT threads cover a row.
+template <int NT>
+__device__ __forceinline__ int pairs_per_thread(int64_t n)
 {
-    const int64_t j = 2 * (int64_t)p;
-    if (j + 1 < n)
-        return ld2_nt(row + j);
-    d2 r{0.0, 0.0};
-    if (j < n)
-        r.x = row[j];
-    return r;
+    const int64_t npf = n >> 1;
+    return npf <= NT ? 1 : (npf <= 2 * NT ? 2 : 4);
 }
 
-// As row_pair, but a cached load: ATAX reads each row twice.
-__device__ __forceinline__ d2 row_pair_cached(const double *row, int p, int64_t n)
+template <int NT, int NP>
+__device__ __forceinline__ Geo geometry(int64_t n)
 {
-    const int64_t j = 2 * (int64_t)p;
-    if (j + 1 < n)
-        return ld2(row + j);
-    d2 r{0.0, 0.0};
-    if (j < n)
-        r.x = row[j];
-    return r;
+    Geo g;
+    g.npf = n >> 1;
+    g.odd = (int)(n & 1);
+    const int64_t per = (g.npf + NP - 1) / NP;
+    int t = 1;
+    while (t < per)
+        t <<= 1;
+    g.tpr = t;
+    g.rs = NT / t;
+    g.c = (int)threadIdx.x & (t - 1);
+    g.slot = (int)threadIdx.x / t;
+    return g;
 }
 
-__device__ __forceinline__ void row_store(double *row, int p, int64_t n, d2 v)
+// Sum over the aligned group of `tpr` lanes (tpr <= 64) holding one row.
+// Each step adds a lane's value to a partner's inside the group (the pairs
+// of the full-wave sum, see wave_sum); partners add the same two numbers, so
+// every lane of the group ends with the same, order-fixed sum.
+__device__ __forceinline__ double group_sum(double v, int tpr)
 {
-    const int64_t j = 2 * (int64_t)p;
-    if (j + 1 < n)
-        st2_nt(row + j, v);
-    else if (j < n)
-        row[j] = v.x;
+    if (tpr >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    if (tpr >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    if (tpr >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+    if (tpr >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+    if (tpr >= 32) v += swz16_f64(v);
+    if (tpr >= 64) v = readlane_f64(v, 0) + readlane_f64(v, 32);
+    return v;
 }
 
-// One sweep of the rows of an instance matrix by the waves of the workgroup.
-// OPS selects what each row contributes (see SweepOps).  Row results (dots)
-// are written to rowout[i] * rscale; column sums end up in lds.red.  A row is
-// handled in chunks of at most 8 pairs per lane, so a lane holds one chunk
-// plus its column accumulators; ATAX, whose update needs the whole row's dot
-// first, reads the row's chunks a second time (from cache) to apply it.
-template <int PPL, int OPS, int NW>
-__device__ __forceinline__ void sweep(int64_t m, int64_t n, const double *src, int64_t lds_,
-                                      double *dst, int64_t ldd, const double *u1, const double *u2,
-                                      const double *yc, double *rowout, double rscale, Lds &L)
+// Load the thread's pairs of a length-n vector (zeros where not owned).
+template <int NP>
+__device__ __forceinline__ void load_cols(const Geo &g, const double *v, int64_t n, d2 (&dst)[NP],
+                                          double &last)
+{
+    // unconditional loads (pair 0 stands in for a pair not owned), then
+    // zeroed; nothing at all when there is no whole pair (n <= 1)
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int64_t p = g.c + (int64_t)g.tpr * k;
+        const bool own = p < g.npf;
+        const d2 val = g.npf > 0 ? ld2(v + (own ? 2 * p : 0)) : d2{0.0, 0.0};
+        dst[k] = own ? val : d2{0.0, 0.0};
+    }
+    last = g.odd ? v[n - 1] : 0.0;
+}
+
+// The rows one thread holds for one batch: U rows of NP pairs, the odd
+// column and the per-row scalars.
+template <int U, int NP>
+struct RowBatch {
+    d2 a[U][NP];
+    double al[U], s1[U], s2[U], yw[U];
+};
+
+// One sweep of an instance's rows.  OPS selects what each row contributes:
+//   SW_UPD1 (+SW_UPD2): row <- row + s1_i v1 (+ s2_i v2), stored to dst
+//   SW_ROWDOT:          rowout[i] = rscale * (row . xr)
+//   SW_COLSUM:          acc += row * yc[i]
+//   SW_ATAX:            acc += row * (row . xr)
+// Rows i = base + u*rs + slot (u < U) form one batch (U*NP = 8 pairs per
+// thread, 4 when updating or for narrow BiCGK rows); all of a batch's loads
+// are issued before any is used.  Loads are never conditional: a row past
+// the end re-reads the last row and a pair past the end re-reads pair 0,
+// and the values are zeroed when used.
+template <int NT, int NP, int OPS>
+__device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const double *src,
+                                      int64_t lds_, double *dst, int64_t ldd, const double *u1,
+                                      const double *u2, const double *yc, double *rowout,
+                                      double rscale, const d2 (&xr)[NP], double xr_last,
+                                      const d2 (&v1)[NP], double v1_last, const d2 (&v2)[NP],
+                                      double v2_last, d2 (&acc)[NP], double &acc_last, Lds &L)
 {
     constexpr bool ROWDOT = OPS & SW_ROWDOT;
-    constexpr bool COLSUM = OPS & (SW_COLSUM | SW_ATAX);
+    constexpr bool COLSUM = OPS & SW_COLSUM;
     constexpr bool UPD1 = OPS & SW_UPD1;
     constexpr bool UPD2 = OPS & SW_UPD2;
     constexpr bool ATAX = OPS & SW_ATAX;
-    constexpr int CH = PPL < 8 ? PPL : 8;   // pairs per lane per chunk
-    constexpr int NCH = PPL / CH;
+    constexpr bool DOT = ROWDOT || ATAX;
+    // pairs per thread per batch: fewer for the sweeps that update (two row
+    // scalars and a store per row as well) or do two things with narrow rows
+    constexpr int PIF = (UPD1 || (ROWDOT && COLSUM && NP == 1)) ? 4 : 8;
+    constexpr int U = PIF / NP > 0 ? PIF / NP : 1;   // rows per slot per batch
+    typedef RowBatch<U, NP> Batch;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-
-    d2 acc[PPL];
+    const bool lead = g.c == 0;
+    const bool wide = g.tpr > kWave;        // a row spans several waves
+    const int nwr = wide ? g.tpr / kWave : 1;
+    const int wr = g.c / kWave;             // this wave's part of a wide row
+    const int64_t batch = (int64_t)U * g.rs;
+    int coff[NP];                           // column offset of each owned pair (0 if none)
+    bool pv[NP];
 #pragma unroll
-    for (int k = 0; k < PPL; ++k)
-        acc[k] = d2{0.0, 0.0};
+    for (int k = 0; k < NP; ++k) {
+        const int p = g.c + g.tpr * k;       // below n <= 2048
+        pv[k] = p < g.npf;
+        coff[k] = pv[k] ? 2 * p : 0;
+    }
+    const bool last_here = g.odd && lead;
+    int pb = 0;
 
-    for (int64_t i = wave; i < m; i += NW) {
-        const double *row = src + i * lds_;
-        // the LDS vectors do not change within a sweep; an index the
-        // optimiser cannot see through keeps it from hoisting them all into
-        // registers (a lane would then hold three more rows' worth)
-        int lo = lane;
-        asm volatile("" : "+v"(lo));
-        double s1 = 0.0, s2 = 0.0, yi = 0.0;
+    auto load = [&](int64_t base, Batch &b) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t ri = base + (int64_t)u * g.rs + g.slot;
+            const int64_t rc = ri < m ? ri : m - 1;
+            const double *row = src + rc * lds_;
+            // (a uniform test: with no whole pair, n <= 1, nothing is read
+            // beyond column n-1, and A may be empty)
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                b.a[u][k] = g.npf > 0 ? ld2_nt(row + coff[k]) : d2{0.0, 0.0};
+            b.al[u] = g.odd ? ld1_nt(row + n - 1) : 0.0;
+            if (UPD1) b.s1[u] = u1[rc];
+            if (UPD2) b.s2[u] = u2[rc];
+            // a vector load: the weights may have been written earlier in
+            // this launch (the unfused ATAX temporary)
+            if (COLSUM) b.yw[u] = __builtin_nontemporal_load(yc + rc);
+        }
+    };
+
+    auto process = [&](int64_t base, Batch &b) {
+        int64_t ri[U];
+        bool rv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ri[u] = base + (int64_t)u * g.rs + g.slot;
+            rv[u] = ri[u] < m;
+#pragma unroll
+            for (int k = 0; k < NP; ++k)
+                if (!(rv[u] && pv[k])) b.a[u][k] = d2{0.0, 0.0};
+            if (!rv[u]) b.al[u] = 0.0;
+        }
         if (UPD1) {
-            s1 = ld_uniform(u1 + i);
-            if (UPD2) s2 = ld_uniform(u2 + i);
-        }
-        if (OPS & SW_COLSUM) {
-            // a vector load: the weights may have been written earlier in this
-            // launch (the unfused ATAX temporary), which the scalar cache
-            // would not see
-            yi = __builtin_nontemporal_load(yc + i);
-        }
-        double part = 0.0;
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            d2 a[CH];
+            for (int u = 0; u < U; ++u) {
+                double *brow = dst + ri[u] * ldd;
 #pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                const int p = lane + kWave * (c * CH + k);
-                a[k] = ATAX ? row_pair_cached(row, p, n) : row_pair(row, p, n);
-            }
-            if (UPD1) {
-                double *brow = dst + i * ldd;
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    const int p = lane + kWave * (c * CH + k);
-                    const int q = lo + kWave * (c * CH + k);
-                    d2 b = a[k] + s1 * lds_pair(L.v1, q);
-                    if (UPD2) b = b + s2 * lds_pair(L.v2, q);
-                    a[k] = b;
-                    row_store(brow, p, n, b);
+                for (int k = 0; k < NP; ++k) {
+                    d2 v = b.a[u][k] + b.s1[u] * v1[k];
+                    if (UPD2) v = v + b.s2[u] * v2[k];
+                    b.a[u][k] = v;
+                    if (rv[u] && pv[k]) st2_nt(brow + coff[k], v);
                 }
-            }
-            if (ROWDOT || ATAX) {
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    const d2 w = lds_pair(L.xr, lo + kWave * (c * CH + k));
-                    part += a[k].x * w.x;
-                    part += a[k].y * w.y;
+                if (g.odd) {
+                    double bl = b.al[u] + b.s1[u] * v1_last;
+                    if (UPD2) bl = bl + b.s2[u] * v2_last;
+                    b.al[u] = bl;
+                    if (rv[u] && lead) st1_nt(brow + n - 1, bl);
                 }
-            }
-            if (OPS & SW_COLSUM) {
+                if (!rv[u]) {
+                    // keep the masked row zero for the sums below
 #pragma unroll
-                for (int k = 0; k < CH; ++k)
-                    acc[c * CH + k] += a[k] * yi;
-            }
-            if (ATAX && NCH == 1) {
-                // the whole row is in registers: apply once the dot is known
-                const double dot = wave_sum(part);
-#pragma unroll
-                for (int k = 0; k < CH; ++k)
-                    acc[k] += a[k] * dot;
-            }
-        }
-        if (ROWDOT) {
-            const double dot = wave_sum(part);
-            if (lane == 0)
-                rowout[i] = rscale * dot;
-        }
-        if (ATAX && NCH > 1) {
-            const double dot = wave_sum(part);
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    const int p = lane + kWave * (c * CH + k);
-                    acc[c * CH + k] += row_pair_cached(row, p, n) * dot;
+                    for (int k = 0; k < NP; ++k) b.a[u][k] = d2{0.0, 0.0};
+                    b.al[u] = 0.0;
                 }
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    if (!pv[k]) b.a[u][k] = d2{0.0, 0.0};
             }
         }
-    }
-
-    if (COLSUM) {
-        // red = ((acc_0 + acc_1) + acc_2) + ...: the waves add in turn
-        for (int w = 0; w < NW; ++w) {
-            if (wave == w) {
+        double dot[U];
+        if (DOT) {
 #pragma unroll
-                for (int k = 0; k < PPL; ++k) {
-                    const int p = lane + kWave * k;
-                    if (2 * p < n) {
-                        d2 *r = reinterpret_cast<d2 *>(L.red) + p;
-                        *r = w == 0 ? acc[k] : *r + acc[k];
+            for (int u = 0; u < U; ++u) {
+                double part = 0.0;
+#pragma unroll
+                for (int k = 0; k < NP; ++k) {
+                    part += b.a[u][k].x * xr[k].x;
+                    part += b.a[u][k].y * xr[k].y;
+                }
+                if (last_here) part += b.al[u] * xr_last;
+                dot[u] = wide ? wave_sum(part) : group_sum(part, g.tpr);
+            }
+            if (wide) {
+                // partials of each row's waves meet in LDS, added in wave order
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (lane == 0) L.park[pb][(u * g.rs + g.slot) * nwr + wr] = dot[u];
+                lds_barrier();
+                if (ATAX) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const double *pp = &L.park[pb][(u * g.rs + g.slot) * nwr];
+                        double t = pp[0];
+                        for (int w = 1; w < nwr; ++w) t += pp[w];
+                        dot[u] = t;
                     }
+                } else if (threadIdx.x < batch && base + (int64_t)threadIdx.x < m) {
+                    const double *pp = &L.park[pb][threadIdx.x * nwr];
+                    double t = pp[0];
+                    for (int w = 1; w < nwr; ++w) t += pp[w];
+                    rowout[base + threadIdx.x] = rscale * t;
                 }
+                pb ^= 1;
+            } else if (ROWDOT) {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (lead && rv[u]) rowout[ri[u]] = rscale * dot[u];
             }
-            __syncthreads();
         }
+        if (COLSUM || ATAX) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double w = ATAX ? dot[u] : (rv[u] ? b.yw[u] : 0.0);
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    acc[k] += b.a[u][k] * w;
+                if (last_here) acc_last += b.al[u] * w;
+            }
+        }
+    };
+
+    // all of a batch's loads are issued before any of its values is used;
+    // the other workgroups on the compute unit cover the wait
+    for (int64_t base = 0; base < m; base += batch) {
+        Batch b;
+        load(base, b);
+        process(base, b);
     }
 }
 
-// Load a length-n vector into LDS, zero-filled up to npad (the columns the
-// lanes cover), so that masked columns multiply zeros by zeros whatever an
-// earlier instance left there.
-__device__ __forceinline__ void stage(double *dst, const double *src, int64_t n, int64_t npad)
+// out[j] = scale * (column sum j) + add[j] (add may be null); optionally
+// also into keep (LDS).  The row slots' sums are added in slot order.
+template <int NT, int NP>
+__device__ __forceinline__ void finish_cols(const Geo &g, int64_t n, const d2 (&acc)[NP],
+                                            double acc_last, double scale, const double *add,
+                                            double *out, double *keep, Lds &L)
 {
-    for (int64_t j = threadIdx.x; j < npad; j += blockDim.x)
-        dst[j] = j < n ? src[j] : 0.0;
-}
-
-// out[j] = scale * red[j] + add[j] (add may be null); optionally keep it in
-// LDS, zero-filled up to npad.  (Columns j < n are read and written by the
-// same thread, so `keep` may be the buffer `add` was staged in.)
-__device__ __forceinline__ void finish_cols(const Lds &L, int64_t n, int64_t npad, double scale, const double *add,
-                            double *out, double *keep)
-{
-    for (int64_t j = threadIdx.x; j < npad; j += blockDim.x) {
-        if (j < n) {
-            const double v = add ? scale * L.red[j] + add[j] : scale * L.red[j];
-            out[j] = v;
-            if (keep) keep[j] = v;
-        } else if (keep) {
-            keep[j] = 0.0;
+    if (g.rs == 1) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) {
+            const int64_t p = g.c + (int64_t)g.tpr * k;
+            if (p < g.npf) {
+                d2 v = acc[k] * scale;
+                if (add) v += ld2(add + 2 * p);
+                *reinterpret_cast<d2 *>(out + 2 * p) = v;
+                if (keep) *reinterpret_cast<d2 *>(keep + 2 * p) = v;
+            }
         }
-    }
-}
-
-template <int PPL, int NW>
-__device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &L)
-{
-    const int64_t m = it.m, n = it.n;
-    const int64_t npad = 128 * PPL;
-    if (it.kind == BTO_K_BICGK) {
-        // q = A p ; s = A^T r
-        const double *p = it.vec[0], *r = it.vec[1];
-        double *q = it.out[0], *s = it.out[1];
-        stage(L.xr, p, n, npad);
-        __syncthreads();
-        if (it.form == BTO_FUSED) {
-            sweep<PPL, SW_ROWDOT | SW_COLSUM, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr,
-                                                 r, q, 1.0, L);
-        } else {
-            sweep<PPL, SW_ROWDOT, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
-                                      q, 1.0, L);
-            sweep<PPL, SW_COLSUM, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, r,
-                                      nullptr, 1.0, L);
+        if (g.odd && g.c == 0) {
+            double v = acc_last * scale;
+            if (add) v += add[n - 1];
+            out[n - 1] = v;
+            if (keep) keep[n - 1] = v;
         }
-        finish_cols(L, n, npad, 1.0, nullptr, s, nullptr);
-    } else if (it.kind == BTO_K_GEMVER) {
-        // B = A + u1 v1^T + u2 v2^T ; x = beta B^T y + z ; w = alpha B x
-        const double *u1 = it.vec[0], *v1 = it.vec[1], *u2 = it.vec[2], *v2 = it.vec[3];
-        const double *y = it.vec[4], *z = it.vec[5];
-        double *x = it.out[0], *w = it.out[1];
-        stage(L.v1, v1, n, npad);
-        stage(L.v2, v2, n, npad);
-        __syncthreads();
-        if (it.form == BTO_FUSED) {
-            sweep<PPL, SW_UPD1 | SW_UPD2 | SW_COLSUM, NW>(m, n, it.A, it.lda, it.B, it.ldb, u1,
-                                                         u2, y, nullptr, 1.0, L);
-        } else {
-            sweep<PPL, SW_UPD1, NW>(m, n, it.A, it.lda, it.B, it.ldb, u1, nullptr, nullptr,
-                                    nullptr, 1.0, L);
-            __syncthreads();
-            stage(L.v1, v2, n, npad);
-            __syncthreads();
-            sweep<PPL, SW_UPD1, NW>(m, n, it.B, it.ldb, it.B, it.ldb, u2, nullptr, nullptr,
-                                    nullptr, 1.0, L);
-            __syncthreads();
-            sweep<PPL, SW_COLSUM, NW>(m, n, it.B, it.ldb, nullptr, 0, nullptr, nullptr, y,
-                                      nullptr, 1.0, L);
-        }
-        finish_cols(L, n, npad, it.beta, z, x, L.xr);
-        __syncthreads();
-        sweep<PPL, SW_ROWDOT, NW>(m, n, it.B, it.ldb, nullptr, 0, nullptr, nullptr, nullptr, w,
-                                  it.alpha, L);
     } else {
-        // ATAX: y = A^T (A x)
-        const double *xv = it.vec[0];
-        double *y = it.out[0];
-        stage(L.xr, xv, n, npad);
+        // here NP == 1 and npf <= tpr: thread (slot, c) holds pair c of slot
+        reinterpret_cast<d2 *>(L.red)[g.slot * g.tpr + g.c] = acc[0];
+        if (g.c == 0) L.red_last[g.slot] = acc_last;
         __syncthreads();
-        if (it.form == BTO_FUSED) {
-            sweep<PPL, SW_ATAX, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
-                                    nullptr, 1.0, L);
-        } else {
-            // t = A x into the instance's scratch, then y = A^T t
-            sweep<PPL, SW_ROWDOT, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
-                                      tmp, 1.0, L);
-            __syncthreads();
-            sweep<PPL, SW_COLSUM, NW>(m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, tmp,
-                                      nullptr, 1.0, L);
+        for (int64_t p = threadIdx.x; p < g.npf; p += NT) {
+            const d2 *r = reinterpret_cast<const d2 *>(L.red);
+            d2 v = r[p];
+            for (int s = 1; s < g.rs; ++s) v += r[s * g.tpr + p];
+            v = v * scale;
+            if (add) v += ld2(add + 2 * p);
+            *reinterpret_cast<d2 *>(out + 2 * p) = v;
+            if (keep) *reinterpret_cast<d2 *>(keep + 2 * p) = v;
         }
-        finish_cols(L, n, npad, 1.0, nullptr, y, nullptr);
+        if (g.odd && threadIdx.x == 0) {
+            double v = L.red_last[0];
+            for (int s = 1; s < g.rs; ++s) v += L.red_last[s];
+            v = v * scale;
+            if (add) v += add[n - 1];
+            out[n - 1] = v;
+            if (keep) keep[n - 1] = v;
+        }
     }
     __syncthreads();
 }
 
-template <int NW>
-__device__ __forceinline__ void dispatch_item(const BatchItem &it, double *tmp, Lds &L)
+template <int NP>
+__device__ __forceinline__ void zero(d2 (&v)[NP], double &last)
 {
-    // the fewest 16-byte pairs per lane that cover the row
-    if (it.n <= 128) run_item<1, NW>(it, tmp, L);
-    else if (it.n <= 256) run_item<2, NW>(it, tmp, L);
-    else if (it.n <= 512) run_item<4, NW>(it, tmp, L);
-    else if (it.n <= 1024) run_item<8, NW>(it, tmp, L);
-    else run_item<16, NW>(it, tmp, L);
+#pragma unroll
+    for (int k = 0; k < NP; ++k) v[k] = d2{0.0, 0.0};
+    last = 0.0;
 }
 
-// LDS (64 KiB per workgroup) allows two 4-wave workgroups per compute unit:
-// two waves per SIMD, so the kernel must fit 256 registers per lane.
-template <int NW>
-__global__ __launch_bounds__(kWave *NW) __attribute__((amdgpu_waves_per_eu(NW == 4 ? 2 : 2)))
-void k_batch(const BatchItem *items, const int *order, int *meta, double *scratch)
+template <int NT, int NP>
+__device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &L)
 {
-    // meta[0]: queue counter (zeroed by k_batch_reset); meta[1]: instance
-    // count (written with the table, so a captured launch serves any refill)
-    __shared__ Lds L;
-    __shared__ int slot;
-    const int count = __builtin_nontemporal_load(meta + 1);
-    int *next = meta;
-    for (;;) {
+    const int64_t m = it.m, n = it.n;
+    const Geo g = geometry<NT, NP>(n);
+    d2 xr[NP], v1[NP], v2[NP], acc[NP];
+    double xr_l, v1_l, v2_l, acc_l;
+    zero(xr, xr_l);
+    zero(v1, v1_l);
+    zero(v2, v2_l);
+    zero(acc, acc_l);
+    if (it.kind == BTO_K_BICGK) {
+        // q = A p ; s = A^T r
+        const double *p = it.vec[0], *r = it.vec[1];
+        double *q = it.out[0], *s = it.out[1];
+        load_cols(g, p, n, xr, xr_l);
+        if (it.form == BTO_FUSED) {
+            sweep<NT, NP, SW_ROWDOT | SW_COLSUM>(g, m, n, it.A, it.lda, nullptr, 0, nullptr,
+                                                 nullptr, r, q, 1.0, xr, xr_l, v1, v1_l, v2,
+                                                 v2_l, acc, acc_l, L);
+        } else {
+            sweep<NT, NP, SW_ROWDOT>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
+                                     q, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+            sweep<NT, NP, SW_COLSUM>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, r,
+                                     nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        }
+        finish_cols<NT, NP>(g, n, acc, acc_l, 1.0, nullptr, s, nullptr, L);
+    } else if (it.kind == BTO_K_GEMVER) {
+        // B = A + u1 v1^T + u2 v2^T ; x = beta B^T y + z ; w = alpha B x
+        const double *u1 = it.vec[0], *vv1 = it.vec[1], *u2 = it.vec[2], *vv2 = it.vec[3];
+        const double *y = it.vec[4], *z = it.vec[5];
+        double *x = it.out[0], *w = it.out[1];
+        load_cols(g, vv1, n, v1, v1_l);
+        if (it.form == BTO_FUSED) {
+            load_cols(g, vv2, n, v2, v2_l);
+            sweep<NT, NP, SW_UPD1 | SW_UPD2 | SW_COLSUM>(g, m, n, it.A, it.lda, it.B, it.ldb, u1,
+                                                         u2, y, nullptr, 1.0, xr, xr_l, v1, v1_l,
+                                                         v2, v2_l, acc, acc_l, L);
+        } else {
+            sweep<NT, NP, SW_UPD1>(g, m, n, it.A, it.lda, it.B, it.ldb, u1, nullptr, nullptr,
+                                   nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+            __syncthreads();
+            load_cols(g, vv2, n, v1, v1_l);
+            sweep<NT, NP, SW_UPD1>(g, m, n, it.B, it.ldb, it.B, it.ldb, u2, nullptr, nullptr,
+                                   nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+            __syncthreads();
+            sweep<NT, NP, SW_COLSUM>(g, m, n, it.B, it.ldb, nullptr, 0, nullptr, nullptr, y,
+                                     nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        }
+        finish_cols<NT, NP>(g, n, acc, acc_l, it.beta, z, x, L.xs, L);
+        load_cols(g, L.xs, n, xr, xr_l);
+        sweep<NT, NP, SW_ROWDOT>(g, m, n, it.B, it.ldb, nullptr, 0, nullptr, nullptr, nullptr, w,
+                                 it.alpha, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+    } else {
+        // ATAX: y = A^T (A x)
+        const double *xv = it.vec[0];
+        double *y = it.out[0];
+        load_cols(g, xv, n, xr, xr_l);
+        if (it.form == BTO_FUSED) {
+            sweep<NT, NP, SW_ATAX>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
+                                   nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        } else {
+            // t = A x into the instance's scratch, then y = A^T t
+            sweep<NT, NP, SW_ROWDOT>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
+                                     tmp, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+            __syncthreads();
+            sweep<NT, NP, SW_COLSUM>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, tmp,
+                                     nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        }
+        finish_cols<NT, NP>(g, n, acc, acc_l, 1.0, nullptr, y, nullptr, L);
+    }
+    __syncthreads();
+}
+
+// One row tile [r0, r1) of a split fused instance.
+//   phase 1: the instance's first sweep over the tile's rows (row results
+//            written directly), the tile's column sums into its partial
+//            vector; the workgroup that completes the instance's last tile
+//            adds the partials in tile order (s, y, or GEMVER's x, after
+//            which it raises the instance's x-ready flag);
+//   phase 2: GEMVER's w = alpha B x over the tile's rows, once x is ready.
+// Partials and flags cross workgroups (and the XCDs' separate L2 caches):
+// writers make their stores visible with a device-scope release before
+// counting, readers acquire at device scope before reading.
+template <int NT, int NP>
+__device__ __forceinline__ void run_tile(const BatchItem &it, const BatchUnit &un,
+                                         double *scratch, int *sync, int *err, Lds &L)
+{
+    const int64_t n = it.n, r0 = un.r0, mt = un.r1 - un.r0;
+    const Geo g = geometry<NT, NP>(n);
+    d2 xr[NP], v1[NP], v2[NP], acc[NP];
+    double xr_l, v1_l, v2_l, acc_l;
+    zero(xr, xr_l);
+    zero(v1, v1_l);
+    zero(v2, v2_l);
+    zero(acc, acc_l);
+    const int64_t ldp = (n + 31) / 32 * 32;
+    double *part = scratch + it.part_off;
+    const int T = it.ntiles;
+    const double *A = it.A + r0 * it.lda;
+    if (un.phase == 1) {
+        const int t = (int)(r0 / it.tile_rows);
+        if (it.kind == BTO_K_BICGK) {
+            load_cols(g, it.vec[0], n, xr, xr_l);
+            sweep<NT, NP, SW_ROWDOT | SW_COLSUM>(g, mt, n, A, it.lda, nullptr, 0, nullptr, nullptr,
+                                                 it.vec[1] + r0, it.out[0] + r0, 1.0, xr, xr_l,
+                                                 v1, v1_l, v2, v2_l, acc, acc_l, L);
+        } else if (it.kind == BTO_K_GEMVER) {
+            load_cols(g, it.vec[1], n, v1, v1_l);
+            load_cols(g, it.vec[3], n, v2, v2_l);
+            sweep<NT, NP, SW_UPD1 | SW_UPD2 | SW_COLSUM>(
+                g, mt, n, A, it.lda, it.B + r0 * it.ldb, it.ldb, it.vec[0] + r0, it.vec[2] + r0,
+                it.vec[4] + r0, nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        } else {
+            load_cols(g, it.vec[0], n, xr, xr_l);
+            sweep<NT, NP, SW_ATAX>(g, mt, n, A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
+                                   nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
+        }
+        finish_cols<NT, NP>(g, n, acc, acc_l, 1.0, nullptr, part + t * ldp, nullptr, L);
+        __threadfence();   // this thread's partial (and B rows) visible device-wide
+        __syncthreads();
         if (threadIdx.x == 0)
-            slot = atomicAdd(next, 1);
+            L.last = __hip_atomic_fetch_add(sync, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+                     T - 1;
         __syncthreads();
-        const int idx = slot;
+        if (L.last) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            double scale = 1.0;
+            const double *add = nullptr;
+            double *out = it.out[it.kind == BTO_K_BICGK ? 1 : 0];
+            if (it.kind == BTO_K_GEMVER) {
+                scale = it.beta;
+                add = it.vec[5];
+            }
+            for (int64_t j = threadIdx.x; j < n; j += NT) {
+                double v = part[j];
+                for (int k = 1; k < T; ++k)
+                    v += part[k * ldp + j];
+                v = v * scale;
+                if (add) v += add[j];
+                out[j] = v;
+            }
+            if (it.kind == BTO_K_GEMVER) {
+                __threadfence();
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    __hip_atomic_store(sync + 1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
         __syncthreads();
-        if (idx >= count)
-            break;   // every workgroup reaches this once the queue is drained
-        const int item = order[idx];
-        const BatchItem it = items[item];
-        dispatch_item<NW>(it, scratch + it.scratch_off, L);
+    } else {
+        if (threadIdx.x == 0) {
+            int spins = 0;
+            while (__hip_atomic_load(sync + 1, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                if (++spins > kSpinLimit) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        load_cols(g, it.out[0], n, xr, xr_l);
+        sweep<NT, NP, SW_ROWDOT>(g, mt, n, it.B + r0 * it.ldb, it.ldb, nullptr, 0, nullptr, nullptr,
+                                 nullptr, it.out[1] + r0, it.alpha, xr, xr_l, v1, v1_l, v2, v2_l,
+                                 acc, acc_l, L);
+        __syncthreads();
     }
 }
 
-__global__ void k_batch_reset(int *next)
+template <int NT>
+__device__ __forceinline__ void dispatch_tile(const BatchItem &it, const BatchUnit &un,
+                                              double *scratch, int *sync, int *err, Lds &L)
 {
-    if (threadIdx.x == 0)
-        *next = 0;
+    const int np = pairs_per_thread<NT>(it.n);
+    if (np == 1) run_tile<NT, 1>(it, un, scratch, sync, err, L);
+    else if (np == 2) run_tile<NT, 2>(it, un, scratch, sync, err, L);
+    else if constexpr (NT < 512) run_tile<NT, 4>(it, un, scratch, sync, err, L);
+}
+
+template <int NT>
+__device__ __forceinline__ void dispatch_item(const BatchItem &it, double *tmp, Lds &L)
+{
+    const int np = pairs_per_thread<NT>(it.n);
+    if (np == 1) run_item<NT, 1>(it, tmp, L);
+    else if (np == 2) run_item<NT, 2>(it, tmp, L);
+    else if constexpr (NT < 512) run_item<NT, 4>(it, tmp, L);
+}
+
+// Read-only table entries at a uniform index, through scalar loads.
+__device__ __forceinline__ uint32_t load_uniform_word(const void *base, int idx)
+{
+    typedef const uint32_t __attribute__((address_space(4))) *cw;
+    return reinterpret_cast<cw>(reinterpret_cast<uintptr_t>(base))[idx];
+}
+
+template <typename R>
+__device__ __forceinline__ R load_uniform_record(const R *table, int idx)
+{
+    static_assert(sizeof(R) % 4 == 0, "records are read as 32-bit words");
+    struct Words {
+        uint32_t w[sizeof(R) / 4];
+    } words;
+    const int first = idx * (int)(sizeof(R) / 4);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(R) / 4); ++k)
+        words.w[k] = load_uniform_word(table, first + k);
+    return __builtin_bit_cast(R, words);
+}
+
+// Registers (at most 128 per lane) and LDS (under 32 KiB) let four 256-thread
+// workgroups, or two of 512, share a compute unit: four waves per SIMD.
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_batch(const BatchItem *items, const BatchUnit *units, int *meta, int *sync,
+             double *scratch)
+{
+    // the unit count is written with the table, so a captured launch
+    // serves any refill
+    __shared__ Lds L;
+    __shared__ int slot;
+    const int count = __builtin_nontemporal_load(meta + kMetaUnits);
+    for (;;) {
+        if (threadIdx.x == 0)
+            slot = atomicAdd(meta + kMetaNext, 1);
+        __syncthreads();
+        // a uniform index, so the unit and the instance come through scalar
+        // loads into scalar registers (reads only: the table is written by
+        // the host before the launch and never while the kernel runs)
+        const int idx = __builtin_amdgcn_readfirstlane(slot);
+        __syncthreads();
+        if (idx >= count)
+            break;   // every workgroup reaches this once the queue is drained
+        const BatchUnit un = load_uniform_record(units, idx);
+        const BatchItem it = load_uniform_record(items, un.item);
+        if (un.phase == 0)
+            dispatch_item<NT>(it, scratch + it.scratch_off, L);
+        else
+            dispatch_tile<NT>(it, un, scratch, sync + 2 * un.item, meta + kMetaError, L);
+    }
+}
+
+// Clear the queue counter, the error flag and the instances' sync counters.
+__global__ __launch_bounds__(256) void k_batch_reset(int *meta, int *sync)
+{
+    const int64_t nsync = 2 * (int64_t)__builtin_nontemporal_load(meta + kMetaItems);
+    const int64_t tid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (tid == 0) {
+        meta[kMetaNext] = 0;
+        meta[kMetaError] = 0;
+    }
+    for (int64_t k = tid; k < nsync; k += (int64_t)gridDim.x * 256)
+        sync[k] = 0;
 }
 
 }  // namespace
@@ -341,14 +616,14 @@ int64_t batch_max_n() { return kMaxN; }
 
 bool batch_threads_supported(int threads) { return threads == 256 || threads == 512; }
 
-void launch_batch(const BatchItem *items, const int *order, int *meta, double *scratch, int threads,
-                  int grid, hipStream_t st)
+void launch_batch(const BatchItem *items, const BatchUnit *units, int *meta, int *sync,
+                  double *scratch, int threads, int grid, hipStream_t st)
 {
-    launch("batch_reset", k_batch_reset, dim3(1), dim3(64), st, meta);
+    launch("batch_reset", k_batch_reset, dim3(16), dim3(256), st, meta, sync);
     if (threads == 512)
-        launch("batch", k_batch<8>, dim3(grid), dim3(512), st, items, order, meta, scratch);
+        launch("batch", k_batch<512>, dim3(grid), dim3(512), st, items, units, meta, sync, scratch);
     else
-        launch("batch", k_batch<4>, dim3(grid), dim3(256), st, items, order, meta, scratch);
+        launch("batch", k_batch<256>, dim3(grid), dim3(256), st, items, units, meta, sync, scratch);
 }
 
 }  // namespace bto

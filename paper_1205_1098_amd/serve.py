@@ -382,7 +382,7 @@ class GpuExecutor:
 
     def __init__(self, torch, bto, pool: MatrixPool, lanes: int = 2, capacity: int = 64,
                  plans_per_lane: int = 4, batch_n: int | None = None, threads: int = 256,
-                 wgs_per_cu: int = 2, seed: int = synth.SEED, keep_outputs: bool = False,
+                 wgs_per_cu: int = 0, seed: int = synth.SEED, keep_outputs: bool = False,
                  device="cuda:0"):
         """`batch_n`: requests with at most this many columns go through the
         batch plans (None: the library's limit; 0: none)."""
@@ -403,7 +403,13 @@ class GpuExecutor:
         if batch:
             self.bstreams = [torch.cuda.Stream(self.dev) for _ in range(lanes)]
             self.hbatch = [bto.stream_handle(st) for st in self.bstreams]
-            self.plans = [[bto.BatchPlan.empty(capacity, 0, threads, wgs_per_cu, True, self.dev)
+            # scratch for the tile partials of a full plan of the largest
+            # batched requests
+            small = [n for n in set(pool.sizes) if n <= self.batch_max]
+            per = max((bto.batch_scratch_doubles([{"kind": k, "m": n, "n": n}])
+                       for k in KINDS for n in small), default=0)
+            self.plans = [[bto.BatchPlan.empty(capacity, capacity * per, threads, wgs_per_cu,
+                                               True, self.dev)
                            for _ in range(plans_per_lane)] for _ in range(lanes)]
             self.descs = [[(bto.Desc * capacity)() for _ in range(plans_per_lane)]
                           for _ in range(lanes)]

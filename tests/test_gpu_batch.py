@@ -101,6 +101,30 @@ def test_batch_edge_sizes(env):
     check_all(torch, insts, specs, exact=False)
 
 
+# around every change of thread geometry (pairs per thread, threads per row,
+# rows spanning several waves), odd and even n, tall and one-row matrices
+RECT = [(1, 2048), (3, 2047), (2, 129), (300, 130), (7, 257), (64, 258), (65, 259),
+        (9, 513), (33, 515), (5, 1025), (17, 1026), (129, 1027), (5000, 3), (4097, 1),
+        (1, 1), (2, 2), (3000, 64), (700, 2000)]
+
+
+@pytest.mark.parametrize("form", ["fused", "unfused"])
+@pytest.mark.parametrize("threads", [256, 512])
+def test_batch_rectangular_geometries(env, form, threads):
+    torch, bto = env
+    insts, specs = [], []
+    for k, kind in enumerate(batch.KINDS):
+        i, sp = batch.make_instances(torch, bto, len(RECT), 1, 2, {kind: 1.0}, seed=15,
+                                     config=20 + k, form=form, shapes=RECT)
+        insts += i
+        specs += sp
+    plan = bto.BatchPlan(insts, threads=threads, use_graph=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=False)
+    plan.close()
+
+
 def test_schedule_independence_and_graph_replay(env):
     """For a given workgroup size the results are bit-identical whatever the
     grid, with or without the graph, and on every replay; a different
@@ -110,8 +134,8 @@ def test_schedule_independence_and_graph_replay(env):
     insts, specs = batch.make_instances(torch, bto, 200, 64, 2048, WEIGHTS, seed=12)
     outs = lambda: [t.clone() for inst in insts for t in inst["out"]]
     by_threads = {}
-    for threads, wgs, graph in [(256, 2, True), (256, 1, False), (512, 1, False), (512, 2, True),
-                                (256, 1, True)]:
+    for threads, wgs, graph in [(256, 0, True), (256, 1, False), (512, 1, False), (512, 0, True),
+                                (256, 3, True)]:
         for inst in insts:
             for t in inst["out"]:
                 t.fill_(float("nan"))
@@ -162,8 +186,10 @@ def test_refilled_plan_matches_fresh_plans(env):
             for t in inst["out"]:
                 t.fill_(float("nan"))
 
+    scratch = max(bto.batch_scratch_doubles(insts) for insts, _ in sets)
+    assert scratch > 0     # some instances are split into tiles
     for graph in (True, False):
-        plan = bto.BatchPlan.empty(64, 0, use_graph=graph)
+        plan = bto.BatchPlan.empty(64, scratch, use_graph=graph)
         for insts, specs in sets:
             poison(insts)
             plan.reset(insts)
@@ -182,9 +208,45 @@ def test_refilled_plan_matches_fresh_plans(env):
         with pytest.raises(bto.BtoError) as e:
             plan.reset(many)
         assert e.value.status == 1
-        unf, _ = batch.make_instances(torch, bto, 2, 64, 128, {"atax": 1.0}, seed=31,
-                                      config=13, form="unfused")
+        plan.close()
+    # a plan without scratch refuses instances that need some
+    small = bto.BatchPlan.empty(8, 0)
+    for form, lo in (("unfused", 64), ("fused", 1500)):
+        need, _ = batch.make_instances(torch, bto, 2, lo, lo + 10, {"atax": 1.0}, seed=31,
+                                       config=13, form=form)
+        assert bto.batch_scratch_doubles(need) > 0
         with pytest.raises(bto.BtoError) as e:
-            plan.reset(unf)
+            small.reset(need)
         assert e.value.status == 3
+    small.close()
+
+
+@pytest.mark.parametrize("split", [-1, 0, 64 << 10])
+def test_tiled_instances(env, split):
+    """Fused instances cut into row tiles (default 2 MiB, or 64 KiB: the most
+    tiles) or never cut: every result matches the oracle, is identical on
+    replays and other grids, and no tile gave up waiting."""
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 150, 64, 2048, WEIGHTS, seed=16, config=17)
+    tall, tspecs = batch.make_instances(torch, bto, 6, 1, 2, {"gemver": 1, "bicgk": 1,
+                                                               "atax": 1}, seed=17, config=18,
+                                        shapes=[(20000, 33), (9000, 2048), (3001, 1999),
+                                                (20000, 1), (17, 2048), (16, 2047)])
+    insts += tall
+    specs += tspecs
+    first = None
+    for threads, wgs, graph in [(256, 0, True), (256, 1, False), (512, 0, True)]:
+        plan = bto.BatchPlan(insts, threads=threads, wgs_per_cu=wgs, use_graph=graph,
+                             split_bytes=split)
+        for rep in range(2):
+            for inst in insts:
+                for t in inst["out"]:
+                    t.fill_(float("nan"))
+            plan.launch()
+            plan.check()
+            cur = [t.clone() for inst in insts for t in inst["out"]]
+            if threads == 256:
+                first = first or cur
+                assert all(torch.equal(a, b) for a, b in zip(first, cur)), (threads, wgs, rep)
+        check_all(torch, insts, specs, exact=False)
         plan.close()
