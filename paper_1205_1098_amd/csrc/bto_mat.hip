@@ -659,11 +659,21 @@ bool set_bicgk_rowres_threads(int t)
 
 int get_bicgk_rowres_threads() { return g_bicgk_rowres_threads.load(); }
 
+// Workgroups of a row-resident sweep: as many as fit at once, but no more
+// than give each at least kMinRowsPerGroup rows (each writes an n-long
+// partial that the finish reads back: with one row apiece the partials
+// would weigh as much as the matrix) unless that leaves a compute unit
+// idle, and never more than m.
+constexpr int64_t kMinRowsPerGroup = 16;
+
 static int64_t rowres_parts_for(int64_t m, const RowresShape &s, bool bicgk)
 {
     if (s.T == 0 || m <= 0)
         return 0;
     int64_t g = (int64_t)kCUs * rowres_blocks_per_cu(s, bicgk);
+    int64_t want = ceil_div(m, kMinRowsPerGroup);
+    want = want < kCUs ? kCUs : want;
+    g = g < want ? g : want;
     return g < m ? g : m;
 }
 
