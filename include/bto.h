@@ -262,6 +262,9 @@ bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
  * reads total milliseconds and launch count of the idx-th kernel name
  * (idx < bto_timing_count()).  Names stay valid until bto_timing_reset(). */
 bto_status bto_timing_enable(int enable);
+/* Time only the launches named `name` (NULL or "" = all): fewer events in
+ * the stream when one kernel is the subject. */
+bto_status bto_timing_only(const char *name);
 bto_status bto_timing_collect(void);
 int bto_timing_count(void);
 bto_status bto_timing_get(int idx, const char **name, int64_t *launches,

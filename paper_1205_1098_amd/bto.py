@@ -53,6 +53,7 @@ _SIGS = {
     "bto_vadd": ([_i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_timing_enable": ([_int], _int),
     "bto_timing_collect": ([], _int),
+    "bto_timing_only": ([ctypes.c_char_p], _int),
     "bto_timing_count": ([], _int),
     "bto_timing_get": ([_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_i64),
                         ctypes.POINTER(_dbl)], _int),
@@ -322,6 +323,11 @@ def vadd(w, y, z, form="fused", x=None, ws=None):
 
 def timing_enable(on: bool = True) -> None:
     _check(_lib.bto_timing_enable(1 if on else 0))
+
+
+def timing_only(name: str | None) -> None:
+    """Restrict timing to launches of one kernel name (None: all)."""
+    _check(_lib.bto_timing_only(name.encode() if name else None))
 
 
 def timing_reset() -> None:

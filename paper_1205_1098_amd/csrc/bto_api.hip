@@ -11,6 +11,7 @@
 #include "bto.h"
 #include "bto_batch.hpp"
 #include "bto_internal.hpp"
+#include "bto_tuned.hpp"
 
 using namespace bto;
 
@@ -31,47 +32,8 @@ bto_status fail(bto_status s, const std::string &msg)
 // shape any slot may take (kv >= 2, rb >= 32), so they depend on the
 // arguments alone.
 
-enum Slot {
-    SLOT_BICGK_FUSED = 0,
-    SLOT_GEMV_N,
-    SLOT_GEMV_T,
-    SLOT_GER,
-    SLOT_GEMVER_P1,
-    SLOT_GEMVER_P2,
-    SLOT_DGEMVT_P1,
-    SLOT_DGEMVT_P2,
-    SLOT_COUNT
-};
-
-const int kSlotOps[SLOT_COUNT] = {
-    OP_ROWDOT | OP_COLSUM,           // BICGK_FUSED
-    OP_ROWDOT,                       // GEMV_N
-    OP_COLSUM,                       // GEMV_T
-    OP_UPD1,                         // GER
-    OP_UPD1 | OP_UPD2 | OP_COLSUM,   // GEMVER_P1
-    OP_ROWDOT,                       // GEMVER_P2
-    OP_COLSUM,                       // DGEMVT_P1
-    OP_ROWDOT,                       // DGEMVT_P2
-};
-
-const char *const kSlotNames[SLOT_COUNT] = {
-    "bicgk_fused", "gemv_n", "gemv_t", "ger", "gemver_p1", "gemver_p2", "dgemvt_p1", "dgemvt_p2",
-};
-
 std::mutex g_cfg_mu;
-// Defaults: the best configurations the orthogonal search (fusion first,
-// then each sweep's tile shape, band height and walk order) found for
-// 16384 x 16384 on MI355X, each form searched separately.
-TileCfg g_cfg[SLOT_COUNT] = {
-    {5, 128, 0},  // BICGK_FUSED: 4 x 2 waves, 8 pairs per lane (32 KiB per row), 2 rows in flight
-    {4, 4, 1},    // GEMV_N: 4 waves across 4096 columns, one row per wave
-    {3, 512, 0},  // GEMV_T: 4 x 4 waves, 512-row bands
-    {8, 4, 0},    // GER: one row per wave, 512-column wave tiles
-    {10, 32, 1},  // GEMVER_P1: 16 waves down 256 columns, 2 rows each, 3 rows in flight
-    {4, 4, 1},    // GEMVER_P2: one row per wave, bands walked backwards
-    {3, 512, 1},  // DGEMVT_P1
-    {4, 4, 0},    // DGEMVT_P2
-};
+TileCfg g_cfg[SLOT_COUNT] = BTO_TUNED_DEFAULTS;
 
 constexpr int kMinKv = 2;
 constexpr int kMinRb = 32;
@@ -318,6 +280,7 @@ struct TimingRec {
 
 std::mutex g_tmu;
 bool g_tenabled = false;
+std::string g_tonly;   // when set, only launches of this name are timed
 std::vector<TimingRec> g_recs;
 std::vector<std::string> g_tnames;
 std::vector<double> g_tms;
@@ -362,6 +325,8 @@ void timing_begin(hipStream_t st, const char *name)
     std::lock_guard<std::mutex> g(g_tmu);
     t_start = nullptr;
     if (!g_tenabled || t_capturing)
+        return;
+    if (!g_tonly.empty() && g_tonly != name)
         return;
     hipEvent_t e = take_event();
     if (!e)
@@ -695,6 +660,13 @@ bto_status bto_timing_enable(int enable)
 {
     std::lock_guard<std::mutex> g(g_tmu);
     g_tenabled = enable != 0;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_timing_only(const char *name)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_tonly = name ? name : "";
     return BTO_SUCCESS;
 }
 

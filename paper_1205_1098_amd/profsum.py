@@ -21,8 +21,11 @@ import sqlite3
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# what defines the measured matrix and vector sweeps: their device code, the
+# shared device helpers and launch declarations, and the tuned configurations
 KERNEL_SOURCES = ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_vec.hip",
-                  "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_api.hip"]
+                  "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_internal.hpp",
+                  "paper_1205_1098_amd/csrc/bto_tuned.hpp"]
 COPY_BYTES = (1 << 28) * 8      # the copy probe reads and writes 2 GiB per launch
 
 
