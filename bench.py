@@ -197,9 +197,10 @@ def counter_traffic(kernel_name: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    from paper_1205_1098_amd.profsum import source_digest
+    from paper_1205_1098_amd.profsum import SOURCE_SETS, source_digest
 
-    if fields.get("source_digest") != source_digest():
+    sources = fields.get("source_set", "")
+    if sources not in SOURCE_SETS or fields.get("source_digest") != source_digest(sources):
         return None
     try:
         return float(fields["hbm_bytes_per_launch"])

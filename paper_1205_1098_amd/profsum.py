@@ -21,17 +21,20 @@ import sqlite3
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-# what defines the measured matrix and vector sweeps: their device code, the
-# shared device helpers and launch declarations, and the tuned configurations
-KERNEL_SOURCES = ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_vec.hip",
-                  "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_internal.hpp",
-                  "paper_1205_1098_amd/csrc/bto_tuned.hpp"]
+# what defines a measured kernel: its device code, the shared device helpers
+# and launch declarations, and (matrix sweeps) the tuned configurations
+SOURCE_SETS = {
+    "matrix": ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_dev.hpp",
+               "paper_1205_1098_amd/csrc/bto_internal.hpp", "paper_1205_1098_amd/csrc/bto_tuned.hpp"],
+    "vector": ["paper_1205_1098_amd/csrc/bto_vec.hip", "paper_1205_1098_amd/csrc/bto_dev.hpp",
+               "paper_1205_1098_amd/csrc/bto_internal.hpp"],
+}
 COPY_BYTES = (1 << 28) * 8      # the copy probe reads and writes 2 GiB per launch
 
 
-def source_digest() -> str:
+def source_digest(source_set: str = "matrix") -> str:
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in SOURCE_SETS[source_set]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -67,7 +70,7 @@ def trace_summary(db: str, label: str, command: str) -> str:
 
 
 def counters_summary(fetch: str, write: str, cfetch: str, cwrite: str, kernel: str,
-                     label: str, alg_bytes: float, command: str) -> str:
+                     label: str, alg_bytes: float, command: str, sources: str = "matrix") -> str:
     def per_dispatch(rows, sub):
         vals = [v for name, v in rows if sub in name]
         if not vals:
@@ -102,7 +105,8 @@ def counters_summary(fetch: str, write: str, cfetch: str, cwrite: str, kernel: s
         f"hbm_bytes_per_launch: {fb + wb:.0f}",
         f"alg_bytes_per_launch: {alg_bytes:.0f}",
         f"amplification: {(fb + wb) / alg_bytes:.4f}",
-        f"source_digest: {source_digest()}",
+        f"source_set: {sources}",
+        f"source_digest: {source_digest(sources)}",
     ]
     return "\n".join(lines) + "\n"
 
@@ -116,6 +120,8 @@ def main(argv=None) -> int:
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel"):
         c.add_argument(a, required=True)
     c.add_argument("--alg-bytes", type=float, required=True)
+    c.add_argument("--sources", choices=sorted(SOURCE_SETS), default="matrix",
+                   help="the source set whose digest the summary records")
     for p in (t, c):
         p.add_argument("--label", required=True)
         p.add_argument("--command", required=True)
@@ -125,7 +131,8 @@ def main(argv=None) -> int:
         text = trace_summary(args.db, args.label, args.command)
     else:
         text = counters_summary(args.fetch, args.write, args.copy_fetch, args.copy_write,
-                                args.kernel, args.label, args.alg_bytes, args.command)
+                                args.kernel, args.label, args.alg_bytes, args.command,
+                                args.sources)
     with open(args.out, "w") as f:
         f.write(text)
     print(text)
