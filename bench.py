@@ -46,7 +46,7 @@ def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="gemver",
                     choices=["gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd"])
     ap.add_argument("--no-suite", action="store_true")
