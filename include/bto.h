@@ -292,6 +292,17 @@ const char *bto_tune_slot_name(int slot);
 int bto_tune_slot_ops(int slot);
 bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev);
 bto_status bto_tune_set(int slot, int shape, int rb, int rev);
+
+/* Configurations are kept per size bucket: problems are grouped by
+ * max(m, n) into <= 256, <= 512, ..., <= 16384 and larger
+ * (bto_tune_bucket_count() buckets; bto_tune_bucket(size) gives the index).
+ * The _for calls address the bucket of a problem with max(m, n) = size; size
+ * 0 addresses every bucket (set) or the 16384 bucket (get), which is what
+ * bto_tune_set and bto_tune_get do. */
+bto_status bto_tune_get_for(int slot, int64_t size, int *shape, int *rb, int *rev);
+bto_status bto_tune_set_for(int slot, int64_t size, int shape, int rb, int rev);
+int bto_tune_bucket_count(void);
+int bto_tune_bucket(int64_t size);
 bto_status bto_tune_shape(int shape, int *kv, int *depth, int *waves_across,
                           int *waves_down);
 

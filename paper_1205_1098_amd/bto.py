@@ -68,6 +68,10 @@ _SIGS = {
     "bto_tune_get": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int)],
                      _int),
     "bto_tune_set": ([_int, _int, _int, _int], _int),
+    "bto_tune_get_for": ([_int, _i64, _ptr, _ptr, _ptr], _int),
+    "bto_tune_set_for": ([_int, _i64, _int, _int, _int], _int),
+    "bto_tune_bucket_count": ([], _int),
+    "bto_tune_bucket": ([_i64], _int),
     "bto_tune_shape": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
                         ctypes.POINTER(_int)], _int),
     "bto_synth_fill": ([_ptr, _i64, _i64, _i64, ctypes.c_uint64, _i64, _int, _int, _int, _ptr],
@@ -378,15 +382,26 @@ def tune_slot_ops(slot: int) -> int:
     return int(_lib.bto_tune_slot_ops(slot))
 
 
-def tune_get(slot: int) -> tuple:
-    """(shape, rb, rev) of a slot."""
+def tune_get(slot: int, size: int = 0) -> tuple:
+    """(shape, rb, rev) of a slot for problems with max(m, n) = size (0: the
+    16384 bucket)."""
     a, b, c = _int(), _int(), _int()
-    _check(_lib.bto_tune_get(slot, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    _check(_lib.bto_tune_get_for(slot, int(size), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c)))
     return int(a.value), int(b.value), int(c.value)
 
 
-def tune_set(slot: int, shape: int, rb: int, rev: int = 0) -> None:
-    _check(_lib.bto_tune_set(slot, shape, rb, rev))
+def tune_set(slot: int, shape: int, rb: int, rev: int = 0, size: int = 0) -> None:
+    """Set a slot's configuration for the size bucket of `size` (0: all)."""
+    _check(_lib.bto_tune_set_for(slot, int(size), shape, rb, rev))
+
+
+def tune_buckets() -> int:
+    return int(_lib.bto_tune_bucket_count())
+
+
+def tune_bucket(size: int) -> int:
+    return int(_lib.bto_tune_bucket(int(size)))
 
 
 def tune_shape(shape: int) -> dict:

@@ -33,15 +33,15 @@ bto_status fail(bto_status s, const std::string &msg)
 // arguments alone.
 
 std::mutex g_cfg_mu;
-TileCfg g_cfg[SLOT_COUNT] = BTO_TUNED_DEFAULTS;
+TileCfg g_cfg[SLOT_COUNT][kSizeBuckets] = BTO_TUNED_DEFAULTS;
 
 constexpr int kMinKv = 2;
 constexpr int kMinRb = 32;
 
-TileCfg cfg_of(Slot s)
+TileCfg cfg_of(Slot s, int64_t m, int64_t n)
 {
     std::lock_guard<std::mutex> g(g_cfg_mu);
-    return g_cfg[s];
+    return g_cfg[s][size_bucket(m, n)];
 }
 
 int64_t max_ncols(int64_t n) { return ceil_div(n, 128 * kMinKv); }
@@ -241,7 +241,7 @@ bto_status unsupported(Slot s)
 bto_status gemv_n(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *xr,
                   double scale, double *out, double *Prow, hipStream_t st)
 {
-    TileCfg c = cfg_of(s);
+    TileCfg c = cfg_of(s, m, n);
     TileArgs a = targs(m, n, A, lda);
     a.xr = xr;
     a.Prow = Prow;
@@ -256,7 +256,7 @@ bto_status gemv_n(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, co
 bto_status gemv_t(Slot s, int64_t m, int64_t n, const double *A, int64_t lda, const double *yc,
                   double scale, const double *add, double *out, double *Pcol, hipStream_t st)
 {
-    TileCfg c = cfg_of(s);
+    TileCfg c = cfg_of(s, m, n);
     TileArgs a = targs(m, n, A, lda);
     a.yc = yc;
     a.Pcol = Pcol;
@@ -400,7 +400,7 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
                            vspan("s", s, n, true), wspan(ws, need_ws)},
                           {}));
 
-    const int bt = form == BTO_FUSED ? get_bicgk_rowres_threads() : 0;
+    const int bt = form == BTO_FUSED ? get_bicgk_rowres_threads(size_bucket(m, n)) : 0;
     const int64_t G = bt ? rowres_parts(m, n, bt, true) : 0;
     if (G > 0) {
         // row-resident sweep: q rows directly, s from G partial vectors
@@ -414,7 +414,7 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
     double *Prow = cv.take(max_ncols(n) * m);
     double *Pcol = cv.take(max_nbands(m) * n);
     if (form == BTO_FUSED && m > 0 && n > 0) {
-        TileCfg c = cfg_of(SLOT_BICGK_FUSED);
+        TileCfg c = cfg_of(SLOT_BICGK_FUSED, m, n);
         TileArgs a = targs(m, n, A, lda);
         a.xr = p;
         a.yc = r;
@@ -467,7 +467,7 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
     double *Pcol = cv.take(max_nbands(m) * n);
     if (form == BTO_FUSED) {
         // pass 1: B = A + u1 v1^T + u2 v2^T and the partial sums of B^T y
-        TileCfg c = cfg_of(SLOT_GEMVER_P1);
+        TileCfg c = cfg_of(SLOT_GEMVER_P1, m, n);
         TileArgs a = targs(m, n, A, lda);
         a.B = B;
         a.ldb = ldb;
@@ -484,7 +484,7 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
         // pass 2: w = alpha B x
         BTO_TRY(gemv_n(SLOT_GEMVER_P2, m, n, B, ldb, x, alpha, w, Prow, st));
     } else {
-        TileCfg c = cfg_of(SLOT_GER);
+        TileCfg c = cfg_of(SLOT_GER, m, n);
         TileArgs a = targs(m, n, A, lda);
         a.B = B;
         a.ldb = ldb;
@@ -520,7 +520,7 @@ bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const do
                            vspan("y", y, n, true), wspan(ws, need_ws)},
                           {}));
 
-    const int threads = get_rowres_threads();
+    const int threads = get_rowres_threads(size_bucket(m, n));
     const int64_t G = form == BTO_FUSED ? atax_rowres_parts(m, n, threads) : 0;
     Carve cv(ws);
     if (G > 0) {
@@ -744,39 +744,64 @@ int bto_tune_slot_ops(int slot)
     return (slot >= 0 && slot < SLOT_COUNT) ? kSlotOps[slot] : 0;
 }
 
-bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
+// The size bucket a tuning call addresses: that of a problem of max(m, n)
+// = size, or every bucket for size 0 (get: the 16384 bucket).
+static bool tune_buckets(int64_t size, int &lo, int &hi)
+{
+    if (size < 0)
+        return false;
+    if (size == 0) {
+        lo = 0;
+        hi = kSizeBuckets - 1;
+    } else {
+        lo = hi = size_bucket(size, size);
+    }
+    return true;
+}
+
+bto_status bto_tune_get_for(int slot, int64_t size, int *shape, int *rb, int *rev)
 {
     t_error.clear();
+    int lo, hi;
+    if (!tune_buckets(size, lo, hi))
+        return fail(BTO_ERR_INVALID_ARG, "negative size");
+    const int b = size == 0 ? size_bucket(16384, 16384) : lo;
     if (slot == kRowresSlot || slot == kBicgkRowresSlot) {
         std::lock_guard<std::mutex> g(g_cfg_mu);
         if (shape)
-            *shape = slot == kRowresSlot ? get_rowres_threads() : get_bicgk_rowres_threads();
+            *shape = slot == kRowresSlot ? get_rowres_threads(b) : get_bicgk_rowres_threads(b);
         if (rb) *rb = 0;
         if (rev) *rev = 0;
         return BTO_SUCCESS;
     }
     if (slot < 0 || slot >= SLOT_COUNT)
         return fail(BTO_ERR_INVALID_ARG, "slot out of range");
-    TileCfg c = cfg_of(static_cast<Slot>(slot));
+    std::lock_guard<std::mutex> g(g_cfg_mu);
+    const TileCfg c = g_cfg[slot][b];
     if (shape) *shape = c.shape;
     if (rb) *rb = c.rb;
     if (rev) *rev = c.rev;
     return BTO_SUCCESS;
 }
 
-bto_status bto_tune_set(int slot, int shape, int rb, int rev)
+bto_status bto_tune_set_for(int slot, int64_t size, int shape, int rb, int rev)
 {
     t_error.clear();
-    if (slot == kRowresSlot) {
+    int lo, hi;
+    if (!tune_buckets(size, lo, hi))
+        return fail(BTO_ERR_INVALID_ARG, "negative size");
+    if (slot == kRowresSlot || slot == kBicgkRowresSlot) {
+        const bool atax = slot == kRowresSlot;
+        const bool ok_threads = shape == 256 || shape == 512 || shape == 1024 ||
+                                (!atax && shape == 0);
+        if (rb != 0 || rev != 0 || !ok_threads)
+            return fail(BTO_ERR_INVALID_ARG, atax ? "atax_rowres takes (256|512|1024, 0, 0)"
+                                                  : "bicgk_rowres takes (0|256|512|1024, 0, 0)");
         std::lock_guard<std::mutex> g(g_cfg_mu);
-        if (rb != 0 || rev != 0 || !set_rowres_threads(shape))
-            return fail(BTO_ERR_INVALID_ARG, "atax_rowres takes (256|512|1024, 0, 0)");
-        return BTO_SUCCESS;
-    }
-    if (slot == kBicgkRowresSlot) {
-        std::lock_guard<std::mutex> g(g_cfg_mu);
-        if (rb != 0 || rev != 0 || !set_bicgk_rowres_threads(shape))
-            return fail(BTO_ERR_INVALID_ARG, "bicgk_rowres takes (0|256|512|1024, 0, 0)");
+        for (int b = lo; b <= hi; ++b) {
+            if (atax) set_rowres_threads(b, shape);
+            else set_bicgk_rowres_threads(b, shape);
+        }
         return BTO_SUCCESS;
     }
     if (slot < 0 || slot >= SLOT_COUNT)
@@ -785,9 +810,24 @@ bto_status bto_tune_set(int slot, int shape, int rb, int rev)
     if (!tile_cfg_supported(kSlotOps[slot], c))
         return fail(BTO_ERR_INVALID_ARG, "tile configuration not supported for this slot");
     std::lock_guard<std::mutex> g(g_cfg_mu);
-    g_cfg[slot] = c;
+    for (int b = lo; b <= hi; ++b)
+        g_cfg[slot][b] = c;
     return BTO_SUCCESS;
 }
+
+bto_status bto_tune_get(int slot, int *shape, int *rb, int *rev)
+{
+    return bto_tune_get_for(slot, 0, shape, rb, rev);
+}
+
+bto_status bto_tune_set(int slot, int shape, int rb, int rev)
+{
+    return bto_tune_set_for(slot, 0, shape, rb, rev);
+}
+
+int bto_tune_bucket_count(void) { return kSizeBuckets; }
+
+int bto_tune_bucket(int64_t size) { return size < 0 ? -1 : size_bucket(size, size); }
 
 bto_status bto_tune_shape(int shape, int *kv, int *depth, int *waves_across, int *waves_down)
 {

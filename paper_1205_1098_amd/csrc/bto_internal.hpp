@@ -113,10 +113,11 @@ inline int64_t atax_rowres_parts(int64_t m, int64_t n, int threads)
     return rowres_parts(m, n, threads, false);
 }
 inline int64_t atax_rowres_max_parts(int64_t m, int64_t n) { return rowres_max_parts(m, n, false); }
-bool set_rowres_threads(int t);                        // 256, 512 or 1024
-int get_rowres_threads();
-bool set_bicgk_rowres_threads(int t);                  // 0 (tile kernel), 256, 512 or 1024
-int get_bicgk_rowres_threads();
+// workgroup sizes of the row-resident sweeps, per size bucket
+bool set_rowres_threads(int bucket, int t);            // 256, 512 or 1024
+int get_rowres_threads(int bucket);
+bool set_bicgk_rowres_threads(int bucket, int t);      // 0 (tile kernel), 256, 512 or 1024
+int get_bicgk_rowres_threads(int bucket);
 void launch_bicgk_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *p,
                          const double *r, double *q, double *P, int threads, hipStream_t st);
 void launch_atax_rowres(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,

@@ -23,9 +23,11 @@
 // run-time choice.
 
 #include <atomic>
+#include <mutex>
 
 #include "bto_dev.hpp"
 #include "bto_internal.hpp"
+#include "bto_tuned.hpp"
 
 namespace bto {
 
@@ -556,8 +558,23 @@ struct RowresShape {
     int T, NPT;
 };
 
-std::atomic<int> g_rowres_threads{512};   // preferred workgroup size (tunable; best at n = 16384)
-std::atomic<int> g_bicgk_rowres_threads{512};   // the same for BiCGK; 0 selects the tile kernel
+// preferred workgroup size of the row-resident sweeps per size bucket
+// (tunable); for BiCGK 0 selects the tile kernel
+const int kAtaxRowresDefaults[kSizeBuckets] = BTO_TUNED_ATAX_ROWRES;
+const int kBicgkRowresDefaults[kSizeBuckets] = BTO_TUNED_BICGK_ROWRES;
+std::atomic<int> g_rowres_threads[kSizeBuckets];
+std::atomic<int> g_bicgk_rowres_threads[kSizeBuckets];
+std::once_flag g_rowres_once;
+
+void rowres_init()
+{
+    std::call_once(g_rowres_once, [] {
+        for (int b = 0; b < kSizeBuckets; ++b) {
+            g_rowres_threads[b] = kAtaxRowresDefaults[b];
+            g_bicgk_rowres_threads[b] = kBicgkRowresDefaults[b];
+        }
+    });
+}
 
 // The workgroup size T (the preferred one first) and the fewest doubles per
 // thread NPT (even) with T*NPT >= n.
@@ -639,25 +656,35 @@ void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, h
     launch(name, k_finish, dim3((unsigned)(nb0 + nb1)), dim3(256), st, j0, j1, nb0);
 }
 
-bool set_rowres_threads(int t)
+bool set_rowres_threads(int bucket, int t)
 {
     if (t != 256 && t != 512 && t != 1024)
         return false;
-    g_rowres_threads = t;
+    rowres_init();
+    g_rowres_threads[bucket] = t;
     return true;
 }
 
-int get_rowres_threads() { return g_rowres_threads.load(); }
+int get_rowres_threads(int bucket)
+{
+    rowres_init();
+    return g_rowres_threads[bucket].load();
+}
 
-bool set_bicgk_rowres_threads(int t)
+bool set_bicgk_rowres_threads(int bucket, int t)
 {
     if (t != 0 && t != 256 && t != 512 && t != 1024)
         return false;
-    g_bicgk_rowres_threads = t;
+    rowres_init();
+    g_bicgk_rowres_threads[bucket] = t;
     return true;
 }
 
-int get_bicgk_rowres_threads() { return g_bicgk_rowres_threads.load(); }
+int get_bicgk_rowres_threads(int bucket)
+{
+    rowres_init();
+    return g_bicgk_rowres_threads[bucket].load();
+}
 
 // Workgroups of a row-resident sweep: as many as fit at once, but no more
 // than give each at least kMinRowsPerGroup rows (each writes an n-long

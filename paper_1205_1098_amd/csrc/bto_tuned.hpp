@@ -2,11 +2,12 @@
 //
 // Each matrix sweep the entry points launch has a slot whose tile
 // configuration (shape, band height, walk order) can be changed at run time
-// through bto_tune_set.  The defaults are the best configurations the
-// orthogonal search (fusion first, then each sweep's tile shape, band height
-// and walk order) found for 16384 x 16384 on MI355X, each form searched
-// separately.  The row-resident sweeps' workgroup sizes live with their
-// kernels.
+// through bto_tune_set / bto_tune_set_for, per size bucket.  The defaults are
+// the best configurations the orthogonal search (fusion first, then each
+// sweep's tile shape, band height and walk order, pruned by modeled
+// partial-sum bytes) found on MI355X: both forms at 16384 x 16384 (which
+// also serves larger problems), and the fused form at one square size per
+// smaller bucket (256, 362, 724, 1448, 2896, 5792).
 #pragma once
 
 #include "bto_internal.hpp"
@@ -40,17 +41,35 @@ inline constexpr const char *kSlotNames[SLOT_COUNT] = {
     "bicgk_fused", "gemv_n", "gemv_t", "ger", "gemver_p1", "gemver_p2", "dgemvt_p1", "dgemvt_p2",
 };
 
-// {shape, rb, rev} per slot
+// Problems are grouped into size buckets by max(m, n): <= 256, <= 512, ...,
+// <= 16384, and larger.  Each slot has a configuration per bucket.
+constexpr int kSizeBuckets = 8;
+
+inline int size_bucket(int64_t m, int64_t n)
+{
+    const int64_t s = m > n ? m : n;
+    int b = 0;
+    while (b < kSizeBuckets - 1 && (int64_t(256) << b) < s)
+        ++b;
+    return b;
+}
+
+// {shape, rb, rev} per slot and size bucket (written by `python -m paper_1205_1098_amd.tune --write-header`)
 #define BTO_TUNED_DEFAULTS                                                                        \
     {                                                                                             \
-        {5, 128, 0},  /* BICGK_FUSED: 4 x 2 waves, 8 pairs per lane, 2 rows in flight */          \
-        {4, 4, 1},    /* GEMV_N: 4 waves across 4096 columns, one row per wave */                 \
-        {3, 512, 0},  /* GEMV_T: 4 x 4 waves, 512-row bands */                                    \
-        {8, 4, 0},    /* GER: one row per wave, 512-column wave tiles */                          \
-        {10, 32, 1},  /* GEMVER_P1: 16 waves down 256 columns, 2 rows each, 3 rows in flight */   \
-        {4, 4, 1},    /* GEMVER_P2: one row per wave, bands walked backwards */                   \
-        {3, 512, 1},  /* DGEMVT_P1 */                                                             \
-        {4, 4, 0},    /* DGEMVT_P2 */                                                             \
+        {{5, 32, 0}, {0, 64, 1}, {2, 128, 0}, {5, 64, 0}, {5, 32, 0}, {2, 64, 1}, {5, 128, 0}, {5, 128, 0}},  /* BICGK_FUSED */ \
+        {{4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}},  /* GEMV_N */ \
+        {{3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}},  /* GEMV_T */ \
+        {{8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}},  /* GER */ \
+        {{9, 64, 1}, {10, 32, 1}, {7, 32, 0}, {6, 32, 1}, {6, 32, 1}, {10, 32, 0}, {10, 32, 1}, {10, 32, 1}},  /* GEMVER_P1 */ \
+        {{4, 4, 1}, {4, 4, 1}, {3, 16, 0}, {4, 4, 1}, {4, 8, 0}, {4, 8, 0}, {4, 4, 1}, {4, 4, 1}},  /* GEMVER_P2 */ \
+        {{3, 32, 1}, {1, 32, 1}, {3, 32, 1}, {1, 32, 0}, {3, 32, 0}, {1, 64, 0}, {3, 512, 1}, {3, 512, 1}},  /* DGEMVT_P1 */ \
+        {{1, 4, 0}, {3, 8, 1}, {3, 8, 0}, {1, 8, 1}, {4, 8, 0}, {4, 8, 1}, {4, 4, 0}, {4, 4, 0}},  /* DGEMVT_P2 */ \
     }
+
+// workgroup size of the row-resident ATAX and BiCGK sweeps per size bucket
+// (BiCGK: 0 selects the tile sweep of slot bicgk_fused)
+#define BTO_TUNED_ATAX_ROWRES {512, 1024, 1024, 512, 1024, 1024, 512, 512}
+#define BTO_TUNED_BICGK_ROWRES {512, 1024, 1024, 1024, 512, 512, 512, 512}
 
 }  // namespace bto

@@ -74,17 +74,42 @@ class Organism:
 @dataclass
 class Space:
     """The legal tile configurations of every slot (queried from the library,
-    which rejects what a slot cannot run)."""
+    which rejects what a slot cannot run), with what the byte model needs."""
 
     legal: dict = field(default_factory=dict)   # slot -> list[(shape, rb, rev)]
     defaults: dict = field(default_factory=dict)  # slot -> (shape, rb, rev)
+    ops: dict = field(default_factory=dict)     # slot -> OP_* bits (0: not a tile sweep)
+    kv: dict = field(default_factory=dict)      # shape -> 16-byte pairs per lane
+
+    def partial_bytes(self, slot: int, cfg: tuple, m: int, n: int) -> int:
+        """Modeled partial-sum traffic of one sweep (written, then read by the
+        finish): row-dot partials per wave tile of 128*kv columns, column-sum
+        partials per band of rb rows."""
+        ops = self.ops.get(slot, 0)
+        shape, rb, _ = cfg
+        total = 0
+        if ops & 1 and shape in self.kv:
+            total += 2 * 8 * m * -(-n // (128 * self.kv[shape]))
+        if ops & 2 and rb > 0:
+            total += 2 * 8 * n * -(-m // rb)
+        return total
+
+    def pruned(self, slot: int, m: int, n: int, ratio: float) -> list:
+        """The legal configurations whose partials stay within `ratio` of one
+        matrix pass (the coarse analytic pruning the paper applies before
+        measuring); all of them if none would."""
+        keep = [c for c in self.legal[slot] if self.partial_bytes(slot, c, m, n) <= ratio * 8 * m * n]
+        return keep or list(self.legal[slot])
 
     @classmethod
     def from_library(cls, bto, nshapes: int = 11) -> "Space":
         sp = cls()
+        for shape in range(nshapes):
+            sp.kv[shape] = bto.tune_shape(shape)["kv"]
         for slot in range(len(bto.tune_slots())):
             default = bto.tune_get(slot)
             sp.defaults[slot] = default
+            sp.ops[slot] = bto.tune_slot_ops(slot)
             legal = []
             shapes, rbs = range(nshapes), RB_CHOICES
             if slot == SLOT_ATAX_ROWRES:
@@ -108,8 +133,11 @@ class Tuner:
     """Search driver.  `evaluate(kernel, m, n, organism) -> seconds` does
     the measurement; results are cached by organism key."""
 
-    def __init__(self, space: Space, evaluate, cache_path: str | None = None, seed: int = 0):
+    def __init__(self, space: Space, evaluate, cache_path: str | None = None, seed: int = 0,
+                 prune: float = 0.25):
         self.space = space
+        self.prune = prune
+        self._kernel, self._m, self._n = None, 1024, 1024   # the GA's current problem
         self.evaluate = evaluate
         self.cache_path = cache_path
         self.cache: dict = {}
@@ -163,7 +191,7 @@ class Tuner:
             best = self.organism(kernel, form)
             cfg = best.cfg()
             for slot in KERNEL_SLOTS[(kernel, form)]:
-                for c in self.space.legal[slot]:
+                for c in self.space.pruned(slot, m, n, self.prune):
                     trial = self.organism(kernel, form, {**cfg, slot: c})
                     if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
                         best, cfg = trial, trial.cfg()
@@ -181,7 +209,7 @@ class Tuner:
             return self.organism_like(org, "unfused" if org.form == "fused" else "fused")
         slot = self.rng.choice(slots)
         shape, rb, rev = org.cfg()[slot]
-        legal = self.space.legal[slot]
+        legal = self.space.pruned(slot, self._m, self._n, self.prune)
         if kind == 1:                                  # change the partition level (rb)
             pool = [c for c in legal if c[0] == shape and c[2] == rev and c[1] != rb]
         elif kind == 2:                                # change the partition axis (shape)
@@ -214,7 +242,7 @@ class Tuner:
 
     def mfga(self, kernel: str, m: int, n: int, population: int = 20, generations: int = 6,
              k: int = 2, mutation_rate: float = 0.3) -> Organism:
-        self._kernel = kernel
+        self._kernel, self._m, self._n = kernel, m, n
         fit = lambda o: self.fitness(kernel, m, n, o)
         mf = self.max_fuse(kernel)
         pop = [mf] + [self.mutate(mf) for _ in range(population - 1)]
@@ -237,7 +265,7 @@ class Tuner:
         best = org
         for slot in KERNEL_SLOTS[(kernel, org.form)]:
             shape, _, rev = best.cfg()[slot]
-            for c in self.space.legal[slot]:
+            for c in self.space.pruned(slot, m, n, self.prune):
                 if c[0] == shape and c[2] == rev:
                     trial = Organism(best.form, tuple(sorted({**best.cfg(), slot: c}.items())))
                     if self.fitness(kernel, m, n, trial) < self.fitness(kernel, m, n, best):
@@ -247,10 +275,11 @@ class Tuner:
 
 # ---- applying results --------------------------------------------------------------
 
-def apply(bto, org: Organism) -> None:
-    """Load an organism's slot configurations into the library."""
+def apply(bto, org: Organism, size: int = 0) -> None:
+    """Load an organism's slot configurations into the library, for the size
+    bucket of max(m, n) = size (0: every bucket)."""
     for slot, c in org.slots:
-        bto.tune_set(slot, *c)
+        bto.tune_set(slot, *c, size=size)
 
 
 def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3):
@@ -265,9 +294,10 @@ def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3):
             torch.cuda.empty_cache()
             cache[key] = make_workload(kernel, m, n)
         wl = cache[key]
-        saved = {s: bto.tune_get(s) for s, _ in org.slots}
+        size = max(m, n)
+        saved = {s: bto.tune_get(s, size) for s, _ in org.slots}
         try:
-            apply(bto, org)
+            apply(bto, org, size)
             for _ in range(warmup):
                 wl.run(org.form)
             start = torch.cuda.Event(enable_timing=True)
@@ -280,7 +310,7 @@ def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3):
             return start.elapsed_time(stop) / reps * 1e-3
         finally:
             for s, c in saved.items():
-                bto.tune_set(s, *c)
+                bto.tune_set(s, *c, size=size)
 
     return evaluate
 
@@ -322,6 +352,45 @@ class _MatrixWorkload:
             b.dgemvt(self.A, self.y, self.z, 1.5, 0.7, form=form, x=self.x, w=self.w, ws=ws)
 
 
+HEADER = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", "bto_tuned.hpp")
+TILE_SLOT_NAMES = ["BICGK_FUSED", "GEMV_N", "GEMV_T", "GER", "GEMVER_P1", "GEMVER_P2",
+                   "DGEMVT_P1", "DGEMVT_P2"]
+
+
+def render_defaults(table: dict, nbuckets: int = 8) -> str:
+    """The per-bucket default block of bto_tuned.hpp from
+    table[slot][bucket] = (shape, rb, rev)."""
+    lines = ["// {shape, rb, rev} per slot and size bucket (written by "
+             "`python -m paper_1205_1098_amd.tune --write-header`)",
+             "#define BTO_TUNED_DEFAULTS                                                "
+             "                        \\", "    {                                        "
+             "                                                     \\"]
+    for slot, name in enumerate(TILE_SLOT_NAMES):
+        cfgs = ", ".join("{%d, %d, %d}" % tuple(table[slot][b]) for b in range(nbuckets))
+        lines.append(f"        {{{cfgs}}},  /* {name} */ \\")
+    lines.append("    }")
+    lines.append("")
+    lines.append("// workgroup size of the row-resident ATAX and BiCGK sweeps per size bucket")
+    lines.append("// (BiCGK: 0 selects the tile sweep of slot bicgk_fused)")
+    for slot, macro in ((SLOT_ATAX_ROWRES, "BTO_TUNED_ATAX_ROWRES"),
+                        (SLOT_BICGK_ROWRES, "BTO_TUNED_BICGK_ROWRES")):
+        vals = ", ".join(str(table[slot][b][0]) for b in range(nbuckets))
+        lines.append(f"#define {macro} {{{vals}}}")
+    return "\n".join(lines) + "\n"
+
+
+def write_header(table: dict, path: str = HEADER) -> None:
+    """Replace the default block of bto_tuned.hpp (between the size-bucket
+    definitions and the end of the namespace)."""
+    with open(path) as f:
+        text = f.read()
+    start = text.index("// {shape, rb, rev} per slot and size bucket")
+    end = text.index("}  // namespace bto")
+    text = text[:start] + render_defaults(table) + "\n" + text[end:]
+    with open(path, "w") as f:
+        f.write(text)
+
+
 def main(argv=None) -> int:
     import argparse
     import time
@@ -334,37 +403,59 @@ def main(argv=None) -> int:
     ap.add_argument("--kernels", nargs="+", default=["bicgk", "gemver", "dgemvt", "atax"])
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--sizes", type=int, nargs="*", default=None,
+                    help="square sizes to tune, each for its size bucket (instead of --m/--n)")
     ap.add_argument("--strategy", choices=["orth", "mfga"], default="orth")
     ap.add_argument("--cache", default=None, help="fitness cache (JSON) to resume from / write")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--forms", choices=["best", "both"], default="best",
-                    help="search the geometry of the better form only, or of both forms")
+    ap.add_argument("--forms", choices=["best", "both", "fused"], default="best",
+                    help="search the geometry of the better form only, of both forms, or of "
+                         "the fused form")
+    ap.add_argument("--prune", type=float, default=0.25,
+                    help="skip configurations whose modeled partial-sum traffic exceeds this "
+                         "fraction of one matrix pass")
+    ap.add_argument("--write-header", action="store_true",
+                    help="bake the winners into csrc/bto_tuned.hpp (per size bucket; sizes "
+                         "not tuned keep their current configuration)")
     args = ap.parse_args(argv)
 
     dev = torch.device("cuda:0")
     space = Space.from_library(bto)
     ev = gpu_evaluator(bto, torch, lambda k, m, n: _MatrixWorkload(bto, torch, synth, k, m, n, dev))
-    tuner = Tuner(space, ev, args.cache, args.seed)
+    tuner = Tuner(space, ev, args.cache, args.seed, args.prune)
+    names = bto.tune_slots()
+    nb = bto.tune_buckets()
+    table = {s: [bto.tune_get(s, 256 << b) for b in range(nb)] for s in range(len(names))}
+    shapes = [(n, n) for n in args.sizes] if args.sizes else [(args.m, args.n)]
     best = {}
-    for k in args.kernels:
-        t0 = time.perf_counter()
-        forms = list(FORMS) if args.forms == "both" else None
-        org = tuner.orthogonal(k, args.m, args.n, forms) if args.strategy == "orth" else \
-            tuner.mfga(k, args.m, args.n)
-        mf = tuner.fitness(k, args.m, args.n, tuner.max_fuse(k))
-        got = tuner.fitness(k, args.m, args.n, org)
-        names = bto.tune_slots()
-        best[k] = {"form": org.form, "slots": {names[s]: list(c) for s, c in org.slots},
-                   "ms": round(got * 1e3, 4), "max_fuse_ms": round(mf * 1e3, 4),
-                   "search_s": round(time.perf_counter() - t0, 2)}
-        if args.strategy == "orth" and forms:
-            best[k]["per_form"] = {
-                f: {"slots": {names[s]: list(c) for s, c in o.slots},
-                    "ms": round(tuner.fitness(k, args.m, args.n, o) * 1e3, 4)}
-                for f, o in tuner.form_best.items()}
-        print(json.dumps({k: best[k]}), flush=True)
-    tuner.save({"best": best, "device": torch.cuda.get_device_properties(0).gcnArchName,
-                "m": args.m, "n": args.n})
+    for m, n in shapes:
+        for k in args.kernels:
+            t0 = time.perf_counter()
+            forms = {"both": list(FORMS), "fused": ["fused"], "best": None}[args.forms]
+            org = tuner.orthogonal(k, m, n, forms) if args.strategy == "orth" else \
+                tuner.mfga(k, m, n)
+            apply(bto, org, max(m, n))
+            b = bto.tune_bucket(max(m, n))
+            for s, c in org.slots:
+                table[s][b] = tuple(c)
+                if b == nb - 2:        # the largest tuned bucket also serves larger sizes
+                    table[s][nb - 1] = tuple(c)
+            mf = tuner.fitness(k, m, n, tuner.max_fuse(k))
+            got = tuner.fitness(k, m, n, org)
+            key = f"{k}:{m}x{n}"
+            best[key] = {"form": org.form, "slots": {names[s]: list(c) for s, c in org.slots},
+                         "us": round(got * 1e6, 2), "max_fuse_us": round(mf * 1e6, 2),
+                         "search_s": round(time.perf_counter() - t0, 2)}
+            if args.strategy == "orth" and forms:
+                best[key]["per_form"] = {
+                    f: {"slots": {names[s]: list(c) for s, c in o.slots},
+                        "us": round(tuner.fitness(k, m, n, o) * 1e6, 2)}
+                    for f, o in tuner.form_best.items()}
+            print(json.dumps({key: best[key]}), flush=True)
+            tuner.save({"best": best, "device": torch.cuda.get_device_properties(0).gcnArchName})
+    if args.write_header:
+        write_header(table)
+        print(f"wrote {HEADER}", flush=True)
     return 0
 
 

@@ -124,3 +124,39 @@ def test_workspace_checked_before_overlap(bto):
     st = _call_bicgk(bto, m, n, v(base), n, v(base + (1 << 20)), v(base + (2 << 20)),
                      v(q), v(base + (4 << 20)), v(ws), 1024)
     assert st == 3
+
+
+def test_tuning_size_buckets(bto):
+    """Tile configurations are kept per size bucket of max(m, n)."""
+    nb = bto.tune_buckets()
+    assert nb == 8
+    assert [bto.tune_bucket(s) for s in (1, 256, 257, 512, 2048, 2049, 16384, 16385, 10**6)] == \
+        [0, 0, 1, 1, 3, 4, 6, 7, 7]
+    slots = bto.tune_slots()
+    p1 = slots.index("gemver_p1")
+    saved = {b: bto.tune_get(p1, 256 << b) for b in range(nb)}
+    try:
+        base = bto.tune_get(p1)                       # the 16384 bucket
+        assert base == saved[6]
+        other = (10, 64, 0) if base != (10, 64, 0) else (10, 128, 0)
+        bto.tune_set(p1, *other, size=3000)           # bucket of 3000: <= 4096
+        assert bto.tune_get(p1, 4096) == other and bto.tune_get(p1, 2049) == other
+        assert bto.tune_get(p1, 2048) == saved[3] and bto.tune_get(p1) == base
+        bto.tune_set(p1, *other)                      # size 0: every bucket
+        assert all(bto.tune_get(p1, 256 << b) == other for b in range(nb))
+        with pytest.raises(bto.BtoError):
+            bto.tune_set(p1, 999, 32, 0, size=1024)   # no such shape
+        with pytest.raises(bto.BtoError):
+            bto.tune_set(p1, *other, size=-1)
+    finally:
+        for b, c in saved.items():
+            bto.tune_set(p1, *c, size=256 << b)
+    assert all(bto.tune_get(p1, 256 << b) == saved[b] for b in range(nb))
+    # the row-resident slots take a workgroup size per bucket
+    rr = slots.index("bicgk_rowres")
+    keep = bto.tune_get(rr, 1024)
+    bto.tune_set(rr, 0, 0, 0, size=1024)
+    assert bto.tune_get(rr, 1024) == (0, 0, 0) and bto.tune_get(rr, 16384)[0] in (256, 512, 1024)
+    bto.tune_set(rr, *keep, size=1024)
+    with pytest.raises(bto.BtoError):
+        bto.tune_set(slots.index("atax_rowres"), 0, 0, 0, size=1024)   # ATAX has no tile fallback

@@ -110,13 +110,14 @@ def test_bicgk_fused_paths(env, threads, m, n, pad, kind):
     A, vec = inputs(kind, m, n, lda, 1, 7)
     p, r = vec(1, n), vec(2, m)
     q_ref, s_ref = oracle.bicgk(A, p, r, lda=lda)
-    saved = bto.tune_get(SLOT_BICGK_ROWRES)
+    saved = {b: bto.tune_get(SLOT_BICGK_ROWRES, 256 << b) for b in range(bto.tune_buckets())}
     bto.tune_set(SLOT_BICGK_ROWRES, threads, 0, 0)
     try:
         q, s = bto.bicgk(dmat(torch, dev, A, n), dvec(torch, dev, p), dvec(torch, dev, r))
         torch.cuda.synchronize()
     finally:
-        bto.tune_set(SLOT_BICGK_ROWRES, *saved)
+        for b, c in saved.items():
+            bto.tune_set(SLOT_BICGK_ROWRES, *c, size=256 << b)
     if kind == "int":
         assert np.array_equal(host(q), q_ref) and np.array_equal(host(s), s_ref)
     else:

@@ -168,11 +168,43 @@ def test_apply_sets_every_slot():
 
     class FakeLib:
         @staticmethod
-        def tune_set(slot, shape, rb, rev):
-            calls.append((slot, shape, rb, rev))
+        def tune_set(slot, shape, rb, rev, size=0):
+            calls.append((slot, shape, rb, rev, size))
 
     sp = fake_space()
     t = tune.Tuner(sp, Counter())
     org = t.orthogonal("gemver", 10, 10)
     tune.apply(FakeLib, org)
-    assert calls == [(s, *c) for s, c in org.slots]
+    assert calls == [(s, *c, 0) for s, c in org.slots]
+    calls.clear()
+    tune.apply(FakeLib, org, size=3000)          # only the bucket of 3000
+    assert calls == [(s, *c, 3000) for s, c in org.slots]
+
+
+def test_pruning_by_modeled_partial_bytes():
+    """Configurations whose partial sums would outweigh a fraction of the
+    matrix pass are not measured (unless nothing else is left)."""
+    sp = fake_space()
+    sp.ops = {s: 0 for s in SLOTS}
+    sp.ops[tune.SLOT_GEMVER_P1] = 4 | 8 | 2        # column sums: partials per row band
+    sp.ops[tune.SLOT_GEMVER_P2] = 1                # row dots: partials per wave tile
+    sp.kv = {s: 1 + s % 4 for s in SHAPES}
+    m = n = 1024
+    p1 = sp.pruned(tune.SLOT_GEMVER_P1, m, n, 0.2)
+    assert p1 and all(2 * 8 * n * -(-m // c[1]) <= 0.2 * 8 * m * n for c in p1)
+    assert len(p1) < len(sp.legal[tune.SLOT_GEMVER_P1])   # rb = 8 (2 MiB of 8) is out
+    assert all(c[1] >= 16 for c in p1)
+    p2 = sp.pruned(tune.SLOT_GEMVER_P2, 8, 4096, 0.01)
+    assert p2 == sp.legal[tune.SLOT_GEMVER_P2] or all(
+        sp.partial_bytes(tune.SLOT_GEMVER_P2, c, 8, 4096) <= 0.01 * 8 * 8 * 4096 for c in p2)
+    # a search over a pruned space only measures pruned configurations
+    seen = []
+
+    def ev(kernel, mm, nn, org):
+        seen.append(org.cfg())
+        return Counter()(kernel, mm, nn, org)
+
+    t = tune.Tuner(sp, ev, prune=0.2)
+    t.orthogonal("gemver", m, n, forms=["fused"])
+    assert all(cfg[tune.SLOT_GEMVER_P1] in p1 or cfg[tune.SLOT_GEMVER_P1] ==
+               sp.defaults[tune.SLOT_GEMVER_P1] for cfg in seen)
