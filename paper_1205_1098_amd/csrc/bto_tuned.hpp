@@ -6,8 +6,9 @@
 // the best configurations the orthogonal search (fusion first, then each
 // sweep's tile shape, band height and walk order, pruned by modeled
 // partial-sum bytes) found on MI355X: both forms at 16384 x 16384 (which
-// also serves larger problems), and the fused form at one square size per
-// smaller bucket (256, 362, 724, 1448, 2896, 5792).
+// also serves larger problems), and the fused form for each smaller bucket,
+// judged by the summed time of three square sizes across it (128/192/256,
+// 300/400/512, ..., 4800/6400/8192).
 #pragma once
 
 #include "bto_internal.hpp"
@@ -57,19 +58,19 @@ inline int size_bucket(int64_t m, int64_t n)
 // {shape, rb, rev} per slot and size bucket (written by `python -m paper_1205_1098_amd.tune --write-header`)
 #define BTO_TUNED_DEFAULTS                                                                        \
     {                                                                                             \
-        {{5, 32, 0}, {0, 64, 1}, {2, 128, 0}, {5, 64, 0}, {5, 32, 0}, {2, 64, 1}, {5, 128, 0}, {5, 128, 0}},  /* BICGK_FUSED */ \
+        {{5, 128, 0}, {5, 128, 0}, {2, 32, 1}, {2, 64, 1}, {3, 128, 0}, {5, 32, 1}, {5, 128, 0}, {5, 128, 0}},  /* BICGK_FUSED */ \
         {{4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}},  /* GEMV_N */ \
         {{3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}},  /* GEMV_T */ \
         {{8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}},  /* GER */ \
-        {{9, 64, 1}, {10, 32, 1}, {7, 32, 0}, {6, 32, 1}, {6, 32, 1}, {10, 32, 0}, {10, 32, 1}, {10, 32, 1}},  /* GEMVER_P1 */ \
-        {{4, 4, 1}, {4, 4, 1}, {3, 16, 0}, {4, 4, 1}, {4, 8, 0}, {4, 8, 0}, {4, 4, 1}, {4, 4, 1}},  /* GEMVER_P2 */ \
-        {{3, 32, 1}, {1, 32, 1}, {3, 32, 1}, {1, 32, 0}, {3, 32, 0}, {1, 64, 0}, {3, 512, 1}, {3, 512, 1}},  /* DGEMVT_P1 */ \
-        {{1, 4, 0}, {3, 8, 1}, {3, 8, 0}, {1, 8, 1}, {4, 8, 0}, {4, 8, 1}, {4, 4, 0}, {4, 4, 0}},  /* DGEMVT_P2 */ \
+        {{10, 32, 1}, {10, 32, 1}, {10, 32, 1}, {6, 32, 1}, {10, 32, 0}, {10, 32, 0}, {10, 32, 1}, {10, 32, 1}},  /* GEMVER_P1 */ \
+        {{5, 4, 1}, {4, 4, 1}, {4, 4, 1}, {3, 8, 1}, {2, 16, 0}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}},  /* GEMVER_P2 */ \
+        {{3, 32, 0}, {3, 32, 0}, {3, 32, 1}, {2, 32, 1}, {3, 32, 0}, {3, 64, 0}, {3, 512, 1}, {3, 512, 1}},  /* DGEMVT_P1 */ \
+        {{2, 8, 0}, {1, 4, 0}, {3, 4, 1}, {3, 8, 0}, {2, 16, 0}, {3, 64, 0}, {4, 4, 0}, {4, 4, 0}},  /* DGEMVT_P2 */ \
     }
 
 // workgroup size of the row-resident ATAX and BiCGK sweeps per size bucket
 // (BiCGK: 0 selects the tile sweep of slot bicgk_fused)
-#define BTO_TUNED_ATAX_ROWRES {512, 1024, 1024, 512, 1024, 1024, 512, 512}
-#define BTO_TUNED_BICGK_ROWRES {512, 1024, 1024, 1024, 512, 512, 512, 512}
+#define BTO_TUNED_ATAX_ROWRES {512, 1024, 512, 512, 1024, 512, 512, 512}
+#define BTO_TUNED_BICGK_ROWRES {256, 256, 1024, 256, 512, 512, 512, 512}
 
 }  // namespace bto

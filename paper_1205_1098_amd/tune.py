@@ -273,6 +273,15 @@ class Tuner:
         return best
 
 
+def bucket_evaluator(single, groups: dict):
+    """Fitness for a size bucket: the summed time over the bucket's sample
+    sizes (groups maps the bucket's largest sample to all of them), so a
+    configuration is judged over the range it will serve, not at one point."""
+    def evaluate(kernel, m, n, org):
+        return sum(single(kernel, s, s, org) for s in groups.get(max(m, n), [max(m, n)]))
+    return evaluate
+
+
 # ---- applying results --------------------------------------------------------------
 
 def apply(bto, org: Organism, size: int = 0) -> None:
@@ -282,16 +291,18 @@ def apply(bto, org: Organism, size: int = 0) -> None:
         bto.tune_set(slot, *c, size=size)
 
 
-def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3):
+def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3, keep: int = 4):
     """An evaluate() that times one call of a kernel on the current device.
-    `make_workload(kernel, m, n)` returns an object with run(form)."""
+    `make_workload(kernel, m, n)` returns an object with run(form); the last
+    `keep` workloads stay resident."""
     cache = {}
 
     def evaluate(kernel, m, n, org):
         key = (kernel, m, n)
         if key not in cache:
-            cache.clear()
-            torch.cuda.empty_cache()
+            if len(cache) >= keep:
+                cache.pop(next(iter(cache)))
+                torch.cuda.empty_cache()
             cache[key] = make_workload(kernel, m, n)
         wl = cache[key]
         size = max(m, n)
@@ -422,11 +433,20 @@ def main(argv=None) -> int:
     dev = torch.device("cuda:0")
     space = Space.from_library(bto)
     ev = gpu_evaluator(bto, torch, lambda k, m, n: _MatrixWorkload(bto, torch, synth, k, m, n, dev))
-    tuner = Tuner(space, ev, args.cache, args.seed, args.prune)
     names = bto.tune_slots()
     nb = bto.tune_buckets()
     table = {s: [bto.tune_get(s, 256 << b) for b in range(nb)] for s in range(len(names))}
-    shapes = [(n, n) for n in args.sizes] if args.sizes else [(args.m, args.n)]
+    if args.sizes:
+        # sizes of one bucket are searched together, judged by their summed time
+        groups = {}
+        for n in sorted(args.sizes):
+            groups.setdefault(bto.tune_bucket(n), []).append(n)
+        groups = {max(v): v for v in groups.values()}
+        ev = bucket_evaluator(ev, groups)
+        shapes = [(n, n) for n in groups]
+    else:
+        shapes = [(args.m, args.n)]
+    tuner = Tuner(space, ev, args.cache, args.seed, args.prune)
     best = {}
     for m, n in shapes:
         for k in args.kernels:

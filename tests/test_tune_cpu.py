@@ -208,3 +208,17 @@ def test_pruning_by_modeled_partial_bytes():
     t.orthogonal("gemver", m, n, forms=["fused"])
     assert all(cfg[tune.SLOT_GEMVER_P1] in p1 or cfg[tune.SLOT_GEMVER_P1] ==
                sp.defaults[tune.SLOT_GEMVER_P1] for cfg in seen)
+
+
+def test_bucket_fitness_sums_the_bucket_sizes():
+    calls = []
+
+    def single(kernel, m, n, org):
+        calls.append(n)
+        return n * 1e-6
+
+    ev = tune.bucket_evaluator(single, {4096: [2400, 3200, 4096]})
+    org = tune.Organism("fused", ())
+    assert ev("gemver", 4096, 4096, org) == pytest.approx((2400 + 3200 + 4096) * 1e-6)
+    assert calls == [2400, 3200, 4096]
+    assert ev("gemver", 16384, 16384, org) == pytest.approx(16384e-6)   # ungrouped: itself
