@@ -202,7 +202,7 @@ typedef struct {
 } bto_batch_desc;
 
 typedef struct {
-    int threads;       /* workgroup size: 256 or 512 (0 = default 256) */
+    int threads;       /* workgroup size: 256 or 512 (0 = default 512) */
     int wgs_per_cu;    /* persistent workgroups per compute unit, 1..8 (0 = default 2;
                           more than can be resident at once only queue) */
     int use_graph;     /* capture the launch in a HIP graph */

@@ -495,7 +495,7 @@ def batch_scratch_doubles(instances, split_bytes: int = 0) -> int:
         d.kind = KERNELS[inst["kind"]]
         d.form = _form(inst.get("form", "fused"))
         d.m, d.n = inst["A"].shape if "A" in inst else (inst["m"], inst["n"])
-    cfg = _Config(256, 0, 0, int(split_bytes))
+    cfg = _Config(0, 0, 0, int(split_bytes))
     need = _lib.bto_batch_scratch_doubles(ctypes.byref(descs), len(instances), ctypes.byref(cfg))
     if need < 0:
         raise ValueError("bad instance sizes")
@@ -514,7 +514,7 @@ class BatchPlan:
     batch on the current stream and allocates nothing.  A plan made with
     `BatchPlan.empty` is refilled with `reset` before each launch."""
 
-    def __init__(self, instances, threads: int = 256, wgs_per_cu: int = 0,
+    def __init__(self, instances, threads: int = 0, wgs_per_cu: int = 0,
                  use_graph: bool = True, split_bytes: int = 0, *, _capacity=None, _scratch=0,
                  _device=None):
         cfg = _Config(threads, wgs_per_cu, 1 if use_graph else 0, int(split_bytes))
@@ -535,7 +535,7 @@ class BatchPlan:
         self.capacity = self.count = len(instances)
 
     @classmethod
-    def empty(cls, capacity: int, scratch_doubles: int = 0, threads: int = 256,
+    def empty(cls, capacity: int, scratch_doubles: int = 0, threads: int = 0,
               wgs_per_cu: int = 0, use_graph: bool = True, device="cuda:0",
               split_bytes: int = 0) -> "BatchPlan":
         return cls(None, threads, wgs_per_cu, use_graph, split_bytes, _capacity=capacity,

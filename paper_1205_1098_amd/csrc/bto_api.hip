@@ -1179,10 +1179,10 @@ size_t stage_size(int capacity, int unit_capacity)
 static bto_status plan_alloc(int capacity, int unit_capacity, int64_t scratch_doubles,
                              const bto_batch_config *config, bto_batch_plan **out)
 {
-    bto_batch_config cfg{256, 0, 0, 0};
+    bto_batch_config cfg{kBatchDefaultThreads, 0, 0, 0};
     if (config) {
         cfg = *config;
-        if (cfg.threads == 0) cfg.threads = 256;
+        if (cfg.threads == 0) cfg.threads = kBatchDefaultThreads;
     }
     if (!batch_threads_supported(cfg.threads))
         return fail(BTO_ERR_INVALID_ARG, "threads must be 256 or 512");

@@ -39,9 +39,12 @@ struct BatchUnit {
 enum { kMetaNext = 0, kMetaUnits = 1, kMetaError = 2, kMetaItems = 3, kMetaInts = 4 };
 
 constexpr int kBatchMaxTiles = 64;                      // tiles per split instance
-// Persistent workgroups per compute unit by default: two (of the four that
-// fit) move the most bytes for mixed batches, whose workgroups each stream
-// a matrix of their own.
+// Defaults from the batch-knob search (4096 mixed GEMVER/BiCGK instances, n
+// log-uniform on [64, 2048], MI355X): fused instances, 512-thread
+// workgroups, two per compute unit (2, 3 or 4 tie within 0.1%), and row
+// tiles only for matrices above 16 MiB (no tiles, 16 or 32 MiB tie within
+// 0.6%; tiles bound the tail of a batch with one very large instance).
+constexpr int kBatchDefaultThreads = 512;
 constexpr int kBatchDefaultWgsPerCu = 2;
 constexpr int64_t kBatchSplitBytes = 16ll << 20;        // default matrix bytes per tile
 

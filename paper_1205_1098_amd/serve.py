@@ -381,7 +381,7 @@ class GpuExecutor:
     """
 
     def __init__(self, torch, bto, pool: MatrixPool, lanes: int = 2, capacity: int = 64,
-                 plans_per_lane: int = 4, batch_n: int | None = None, threads: int = 256,
+                 plans_per_lane: int = 4, batch_n: int | None = None, threads: int = 0,
                  wgs_per_cu: int = 0, seed: int = synth.SEED, keep_outputs: bool = False,
                  device="cuda:0"):
         """`batch_n`: requests with at most this many columns go through the

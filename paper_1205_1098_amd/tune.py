@@ -282,6 +282,41 @@ def bucket_evaluator(single, groups: dict):
     return evaluate
 
 
+# ---- batched execution -------------------------------------------------------------
+
+#: the batch plan's knobs and the values searched (the first is the library default)
+BATCH_SPACE = {
+    "form": ["fused", "unfused"],               # fuse-or-split of every instance
+    "threads": [256, 512],                      # workgroup size
+    "wgs_per_cu": [2, 1, 3, 4],                 # persistent workgroups per CU ("threads")
+    "split_bytes": [16 << 20, -1, 8 << 20, 32 << 20, 4 << 20],   # row tiles of large instances
+}
+
+
+def tune_batch(evaluate, space: dict | None = None, cache: dict | None = None) -> tuple:
+    """Orthogonal search over the batch plan's knobs: fusion first, then each
+    knob in turn over its values, keeping the best so far (the paper's
+    orthogonal strategy, Section V-D1).  `evaluate(cfg) -> seconds` for a
+    dict cfg; results are cached by the configuration.  Returns (best cfg,
+    its time, evaluations)."""
+    space = BATCH_SPACE if space is None else space
+    cache = {} if cache is None else cache
+
+    def fit(cfg):
+        key = json.dumps(cfg, sort_keys=True)
+        if key not in cache:
+            cache[key] = float(evaluate(dict(cfg)))
+        return cache[key]
+
+    best = {k: v[0] for k, v in space.items()}
+    for knob in space:                        # "form" first: fusion before geometry
+        for val in space[knob]:
+            trial = {**best, knob: val}
+            if fit(trial) < fit(best):
+                best = trial
+    return best, fit(best), len(cache)
+
+
 # ---- applying results --------------------------------------------------------------
 
 def apply(bto, org: Organism, size: int = 0) -> None:
@@ -425,12 +460,17 @@ def main(argv=None) -> int:
     ap.add_argument("--prune", type=float, default=0.25,
                     help="skip configurations whose modeled partial-sum traffic exceeds this "
                          "fraction of one matrix pass")
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the batch plan's knobs on 4096 mixed GEMVER/BiCGK instances "
+                         "(n log-uniform on [64, 2048]) instead of the tile slots")
     ap.add_argument("--write-header", action="store_true",
                     help="bake the winners into csrc/bto_tuned.hpp (per size bucket; sizes "
                          "not tuned keep their current configuration)")
     args = ap.parse_args(argv)
 
     dev = torch.device("cuda:0")
+    if args.batch:
+        return _tune_batch_main(torch, bto, args)
     space = Space.from_library(bto)
     ev = gpu_evaluator(bto, torch, lambda k, m, n: _MatrixWorkload(bto, torch, synth, k, m, n, dev))
     names = bto.tune_slots()
@@ -476,6 +516,48 @@ def main(argv=None) -> int:
     if args.write_header:
         write_header(table)
         print(f"wrote {HEADER}", flush=True)
+    return 0
+
+
+def _tune_batch_main(torch, bto, args) -> int:
+    from paper_1205_1098_amd import batch
+
+    sets = {}
+
+    def evaluate(cfg):
+        form = cfg["form"]
+        if form not in sets:
+            sets.clear()
+            torch.cuda.empty_cache()
+            sets[form] = batch.make_instances(torch, bto, 4096, 64, 2048,
+                                              {"gemver": 0.5, "bicgk": 0.5}, form=form)
+        insts, _ = sets[form]
+        plan = bto.BatchPlan(insts, threads=cfg["threads"], wgs_per_cu=cfg["wgs_per_cu"],
+                             split_bytes=cfg["split_bytes"])
+        for _ in range(2):
+            plan.launch()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            plan.launch()
+        b.record()
+        b.synchronize()
+        plan.close()
+        sec = a.elapsed_time(b) / 5 * 1e-3
+        print(json.dumps({"cfg": cfg, "ms": round(sec * 1e3, 3)}), flush=True)
+        return sec
+
+    cache = {}
+    if args.cache and os.path.exists(args.cache):
+        with open(args.cache) as f:
+            cache = json.load(f).get("batch_fitness", {})
+    best, sec, evals = tune_batch(evaluate, cache=cache)
+    out = {"best": best, "ms": round(sec * 1e3, 3), "evaluations": evals}
+    print(json.dumps(out), flush=True)
+    if args.cache:
+        with open(args.cache, "w") as f:
+            json.dump({"batch_fitness": cache, "batch_best": out}, f, indent=1, sort_keys=True)
     return 0
 
 

@@ -222,3 +222,27 @@ def test_bucket_fitness_sums_the_bucket_sizes():
     assert ev("gemver", 4096, 4096, org) == pytest.approx((2400 + 3200 + 4096) * 1e-6)
     assert calls == [2400, 3200, 4096]
     assert ev("gemver", 16384, 16384, org) == pytest.approx(16384e-6)   # ungrouped: itself
+
+
+def test_batch_knobs_orthogonal_search():
+    """The batch plan's knobs are searched one at a time from the library's
+    defaults, fusion first; each configuration is measured once."""
+    calls = []
+
+    def ev(cfg):
+        calls.append(cfg)
+        t = 1.0 if cfg["form"] == "fused" else 2.0
+        t += {256: 0.0, 512: 0.05}[cfg["threads"]]
+        t += {1: 0.2, 2: 0.0, 3: 0.03, 4: 0.1}[cfg["wgs_per_cu"]]
+        t += 0.0 if cfg["split_bytes"] == 8 << 20 else 0.02
+        return t
+
+    cache = {}
+    best, sec, evals = tune.tune_batch(ev, cache=cache)
+    assert best == {"form": "fused", "threads": 256, "wgs_per_cu": 2, "split_bytes": 8 << 20}
+    assert sec == pytest.approx(1.0)
+    keys = [json.dumps(c, sort_keys=True) for c in calls]
+    assert len(keys) == len(set(keys)) == evals           # no configuration measured twice
+    assert evals <= 1 + sum(len(v) - 1 for v in tune.BATCH_SPACE.values())
+    again, _, _ = tune.tune_batch(lambda c: pytest.fail("should be cached"), cache=cache)
+    assert again == best
