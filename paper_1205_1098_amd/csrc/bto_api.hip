@@ -2,6 +2,7 @@
 // fused / unfused kernel sequences for the seven Table I kernels.
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -1337,7 +1338,8 @@ bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
     if (!plan)
         return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
     *plan = nullptr;
-    if (capacity < 0 || capacity > (1 << 24))
+    // the unit queue holds up to kUnitsPerItem units per instance (an int)
+    if (capacity < 0 || capacity > INT_MAX / kUnitsPerItem)
         return fail(BTO_ERR_INVALID_ARG, "capacity out of range");
     return plan_alloc(capacity, capacity * kUnitsPerItem, scratch_doubles, config, plan);
 }

@@ -34,7 +34,7 @@ def desc(bto, kind, m, n, lda, base):
 def create(bto, descs):
     arr = (bto.Desc * len(descs))(*descs)
     plan = ctypes.c_void_p()
-    cfg = bto._Config(256, 2, 0)
+    cfg = bto._Config(256, 2, 0, 0)
     return bto._lib.bto_batch_plan_create(ctypes.byref(arr), len(descs), ctypes.byref(cfg),
                                           ctypes.byref(plan))
 
@@ -75,6 +75,58 @@ def test_rejects_cross_instance_output_overlap(bto):
 def test_rejects_bad_config(bto):
     arr = (bto.Desc * 1)(desc(bto, "bicgk", 10, 100, 100, FAKE))
     plan = ctypes.c_void_p()
-    cfg = bto._Config(384, 2, 0)
+    cfg = bto._Config(384, 2, 0, 0)
     assert bto._lib.bto_batch_plan_create(ctypes.byref(arr), 1, ctypes.byref(cfg),
                                           ctypes.byref(plan)) == 1
+
+
+def scratch(bto, descs, split=0):
+    arr = (bto.Desc * max(len(descs), 1))(*descs)
+    cfg = bto._Config(0, 0, 0, split)
+    return bto._lib.bto_batch_scratch_doubles(ctypes.byref(arr), len(descs), ctypes.byref(cfg))
+
+
+def test_scratch_sizes(bto):
+    small = desc(bto, "gemver", 100, 100, 104, FAKE)
+    assert scratch(bto, [small]) == 0                    # fits one workgroup: no tiles
+    unf = desc(bto, "atax", 100, 70, 70, FAKE)
+    unf.form = 1
+    assert scratch(bto, [unf]) == 128                    # m rounded up to 32
+    big = desc(bto, "bicgk", 20000, 2000, 2000, FAKE)    # 320 MB > 16 MiB: tiled
+    rows = -(-(16 << 20) // (8 * 2000))                  # rows per 16 MiB tile
+    rows = max(rows, -(-20000 // 64))
+    rows = -(-rows // 8) * 8
+    tiles = -(-20000 // rows)
+    assert scratch(bto, [big]) == tiles * 2016           # one partial (n rounded to 32) per tile
+    assert scratch(bto, [big], split=-1) == 0            # never split
+    # at most 64 tiles: 20000 / 64 -> 313 rows, rounded up to 320 -> 63 tiles
+    assert scratch(bto, [big], split=1 << 20) == 63 * 2016
+    assert scratch(bto, [big, unf, small]) == tiles * 2016 + 128
+    neg = desc(bto, "bicgk", -1, 10, 10, FAKE)
+    assert scratch(bto, [neg]) == -1
+    assert bto._lib.bto_batch_scratch_doubles(None, -1, None) == -1
+
+
+def test_rejects_misaligned_vectors(bto):
+    d = desc(bto, "gemver", 10, 100, 100, FAKE)
+    d.inp[2] = d.inp[2] + 8
+    assert create(bto, [d]) == 1
+    d = desc(bto, "bicgk", 10, 100, 100, FAKE)
+    d.out[1] = d.out[1] + 8
+    assert create(bto, [d]) == 1
+
+
+def test_empty_plan_argument_checks(bto):
+    plan = ctypes.c_void_p()
+    cfg = bto._Config(0, 0, 0, 0)
+    lib = bto._lib
+    assert lib.bto_batch_plan_create_empty(1 << 30, 0, ctypes.byref(cfg), ctypes.byref(plan)) == 1
+    assert lib.bto_batch_plan_create_empty(-1, 0, ctypes.byref(cfg), ctypes.byref(plan)) == 1
+    assert lib.bto_batch_plan_create_empty(4, -5, ctypes.byref(cfg), ctypes.byref(plan)) == 1
+    assert lib.bto_batch_plan_create_empty(4, 0, ctypes.byref(cfg), None) == 1
+    arr = (bto.Desc * 1)(desc(bto, "bicgk", 10, 100, 100, FAKE))
+    assert lib.bto_batch_plan_reset(None, ctypes.byref(arr), 1, None) == 1
+    assert lib.bto_batch_plan_launch(None, None) == 1
+    assert lib.bto_batch_plan_check(None, None) == 1
+    bad = bto._Config(0, 9, 0, 0)                     # more than 8 workgroups per CU
+    assert lib.bto_batch_plan_create_empty(4, 0, ctypes.byref(bad), ctypes.byref(plan)) == 1
