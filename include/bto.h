@@ -60,7 +60,16 @@
 extern "C" {
 #endif
 
-typedef enum { BTO_FUSED = 0, BTO_UNFUSED = 1 } bto_form;
+/* The input enumerations span the whole int range (the _RANGE_ members are
+ * never valid arguments), so any int a caller passes is a value of the type
+ * and is rejected with BTO_ERR_INVALID_ARG, rather than being a value the
+ * implementation's language leaves undefined. */
+typedef enum {
+    BTO_FUSED = 0,
+    BTO_UNFUSED = 1,
+    BTO_FORM_RANGE_MIN_ = -2147483647 - 1,
+    BTO_FORM_RANGE_MAX_ = 2147483647
+} bto_form;
 
 typedef enum {
     BTO_SUCCESS = 0,
@@ -78,7 +87,9 @@ typedef enum {
     BTO_K_DGEMVT = 3,
     BTO_K_AXPYDOT = 4,
     BTO_K_WAXPBY = 5,
-    BTO_K_VADD = 6
+    BTO_K_VADD = 6,
+    BTO_KERNEL_RANGE_MIN_ = -2147483647 - 1,
+    BTO_KERNEL_RANGE_MAX_ = 2147483647
 } bto_kernel;
 
 /* Library version, as 10000*major + 100*minor + patch. */

@@ -19,7 +19,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbto.so")
+# BTO_LIBRARY points the binding at another build of the same library (the
+# tests load a host-sanitized build this way); by default the in-tree one
+LIB_PATH = os.environ.get("BTO_LIBRARY") or os.path.join(_HERE, "libbto.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

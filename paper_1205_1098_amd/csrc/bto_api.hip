@@ -94,6 +94,8 @@ size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
     case BTO_K_WAXPBY:
     case BTO_K_VADD:
         return f == BTO_UNFUSED ? bytes_vec(n) : 0;
+    default:
+        break;
     }
     return 0;
 }
