@@ -56,6 +56,11 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--no-batch-loop", action="store_true",
+                    help="skip the per-instance launch loop the batch is compared with")
+    ap.add_argument("--batch-direct", action="store_true",
+                    help="launch the batch plan without its HIP graph (hardware counters "
+                         "are read per direct dispatch only)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=1000)
@@ -185,10 +190,10 @@ def time_steps(torch, fn, steps: int, warmup: int) -> float:
 
 # ---- hardware-counter traffic ------------------------------------------------------
 
-def counter_traffic(kernel_name: str):
-    """HBM bytes per launch of `kernel_name` from a committed counter summary,
-    or None when there is none for the current kernel sources."""
-    path = os.path.join(PROFILES, f"{kernel_name}_n16384_counters.txt")
+def counter_traffic(summary: str):
+    """HBM bytes per launch from the committed counter summary `summary`, or
+    None when there is none for the current kernel sources."""
+    path = os.path.join(PROFILES, summary)
     if not os.path.exists(path):
         return None
     fields = {}
@@ -247,7 +252,7 @@ def cpu_baseline(kernel: str, target_s: float):
     }
 
 
-def bench_batched(torch, bto, count: int) -> dict:
+def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
     fair seeded coin) in one graph-captured persistent launch."""
     from paper_1205_1098_amd import batch
@@ -255,7 +260,7 @@ def bench_batched(torch, bto, count: int) -> dict:
     insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
                                         {"gemver": 0.5, "bicgk": 0.5}, config=4)
     total = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in specs)
-    plan = bto.BatchPlan(insts, use_graph=True)
+    plan = bto.BatchPlan(insts, use_graph=graph)
     sec = time_steps(torch, plan.launch, 10, 2)
     plan.close()
     # the same instances launched one entry-point call at a time
@@ -266,7 +271,7 @@ def bench_batched(torch, bto, count: int) -> dict:
                            x=inst["out"][0], w=inst["out"][1])
             else:
                 bto.bicgk(inst["A"], *inst["in"], q=inst["out"][0], s=inst["out"][1])
-    sec_loop = time_steps(torch, loop, 2, 1)
+    sec_loop = time_steps(torch, loop, 2, 1) if with_loop else None
     return {
         "instances": count,
         "gemver": sum(1 for s in specs if s.kind == "gemver"),
@@ -276,8 +281,9 @@ def bench_batched(torch, bto, count: int) -> dict:
         "inst_per_s": round(count / sec, 1),
         "gbs": round(total / sec / 1e9, 1),
         "pct_peak": round(100 * total / sec / 1e9 / PEAK_GBS, 1),
-        "per_instance_loop_ms": round(sec_loop * 1e3, 2),
-        "speedup_vs_loop": round(sec_loop / sec, 2),
+        "traffic": counter_traffic("batch_mixed4096_counters.txt") if count == 4096 else None,
+        "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
+        "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,
     }
 
 
@@ -382,7 +388,7 @@ def main() -> int:
     launches, total_ms = times.get(dom_name, (0, 0.0))
     dom_ms = total_ms / launches if launches else float("nan")
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    traffic = counter_traffic(dom_name)
+    traffic = counter_traffic(f"{dom_name}_n16384_counters.txt")
 
     sec_unf = time_steps(torch, lambda: main_wl.run("unfused"), max(3, args.steps // 2), 2)
     result = {
@@ -462,7 +468,8 @@ def main() -> int:
     del main_wl
     torch.cuda.empty_cache()
     if not args.no_batch:
-        result["batched"] = bench_batched(torch, bto, args.batch_count)
+        result["batched"] = bench_batched(torch, bto, args.batch_count, not args.no_batch_loop,
+                                          not args.batch_direct)
         torch.cuda.empty_cache()
     if not args.no_serve:
         result["serving"] = bench_serving(torch, bto, args.serve_requests, args.serve_warmup)

@@ -28,6 +28,8 @@ SOURCE_SETS = {
                "paper_1205_1098_amd/csrc/bto_internal.hpp", "paper_1205_1098_amd/csrc/bto_tuned.hpp"],
     "vector": ["paper_1205_1098_amd/csrc/bto_vec.hip", "paper_1205_1098_amd/csrc/bto_dev.hpp",
                "paper_1205_1098_amd/csrc/bto_internal.hpp"],
+    "batch": ["paper_1205_1098_amd/csrc/bto_batch.hip", "paper_1205_1098_amd/csrc/bto_batch.hpp",
+              "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_internal.hpp"],
 }
 COPY_BYTES = (1 << 28) * 8      # the copy probe reads and writes 2 GiB per launch
 
