@@ -39,13 +39,19 @@ namespace {
 constexpr int kMaxN = 2048;
 constexpr int kMaxNT = 512;
 
+// Row dots of rows wider than a wave leave one partial per wave in LDS; a
+// sweep parks this many batches of them before one barrier adds them up.
+constexpr int kParkBatches = 8;
+
 enum SweepOps { SW_ROWDOT = 1, SW_COLSUM = 2, SW_UPD1 = 4, SW_UPD2 = 8, SW_ATAX = 16 };
 
 struct Lds {
     double xs[kMaxN];            // GEMVER's x, handed from pass 1 to pass 2
     double red[2 * kMaxNT];      // column sums of the row slots (one pair per thread)
     double red_last[kMaxNT];     // the odd column's sums of the row slots
-    double park[2][64];          // row-dot partials of rows wider than a wave
+    // row-dot partials of rows wider than a wave: up to kParkBatches
+    // batches of U <= 8 rows per row slot, NT / 64 waves' partials per slot
+    double park[2][kParkBatches * 8 * (kMaxNT / 64)];
     int last;                    // this workgroup finished an instance's last tile
 };
 
@@ -53,6 +59,50 @@ struct Lds {
 // (about a second); then it gives up, flags the launch as failed and
 // carries on, so every workgroup always reaches the end of the queue.
 constexpr int kSpinLimit = 1 << 22;
+
+// The instance table is read as words through scalar loads, which hides that
+// its pointers address device (global) memory.  Accessed as they are, they
+// compile to flat loads and stores, whose completion is also counted with
+// LDS and scalar-memory operations, so that every LDS or scalar wait would
+// stall behind the wave's outstanding row loads.  Every access through a
+// table pointer therefore goes through a global-address-space pointer.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T *;
+
+template <typename T>
+__device__ __forceinline__ gptr<T> gp(T *p)
+{
+    return (gptr<T>)(uintptr_t)p;
+}
+
+__device__ __forceinline__ d2 gld2(gptr<const double> p)
+{
+    return *reinterpret_cast<gptr<const d2>>(p);
+}
+
+__device__ __forceinline__ d2 gld2_nt(gptr<const double> p)
+{
+    return __builtin_nontemporal_load(reinterpret_cast<gptr<const d2>>(p));
+}
+
+__device__ __forceinline__ double gld1_nt(gptr<const double> p)
+{
+    return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ void gst2_nt(gptr<double> p, d2 v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<gptr<d2>>(p));
+}
+
+__device__ __forceinline__ void gst1_nt(gptr<double> p, double v)
+{
+    __builtin_nontemporal_store(v, p);
+}
+
+// 16 bytes from a vector in global memory or in LDS.
+__device__ __forceinline__ d2 ld2_any(gptr<const double> p) { return gld2(p); }
+__device__ __forceinline__ d2 ld2_any(const double *p) { return ld2(p); }
 
 // Where a thread sits for one instance.
 struct Geo {
@@ -89,24 +139,46 @@ __device__ __forceinline__ Geo geometry(int64_t n)
     return g;
 }
 
-// Sum over the aligned group of `tpr` lanes (tpr <= 64) holding one row.
-// Each step adds a lane's value to a partner's inside the group (the pairs
-// of the full-wave sum, see wave_sum); partners add the same two numbers, so
-// every lane of the group ends with the same, order-fixed sum.
-__device__ __forceinline__ double group_sum(double v, int tpr)
+// Row sums of U rows at once.  Each row lies on an aligned group of `tpr`
+// lanes (for tpr >= 64, on whole waves: the sum is then the wave's, as in
+// wave_sum).  Each step adds a lane's value to a partner's inside the group
+// (quad swaps, half-row and row mirrors, the lane 16 away, then the two
+// half-waves); partners add the same two numbers, so every lane of the group
+// ends with the same, order-fixed sum.  Every step runs over all U values
+// before the next, so the U dependency chains overlap.
+template <int U>
+__device__ __forceinline__ void group_sums(double (&v)[U], int tpr)
 {
-    if (tpr >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
-    if (tpr >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
-    if (tpr >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
-    if (tpr >= 16) v += dpp_f64<0x140>(v);  // row_mirror
-    if (tpr >= 32) v += swz16_f64(v);
-    if (tpr >= 64) v = readlane_f64(v, 0) + readlane_f64(v, 32);
-    return v;
+    if (tpr >= 2) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += dpp_f64<0xB1>(v[u]);    // quad_perm [1,0,3,2]
+    }
+    if (tpr >= 4) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += dpp_f64<0x4E>(v[u]);    // quad_perm [2,3,0,1]
+    }
+    if (tpr >= 8) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += dpp_f64<0x141>(v[u]);   // row_half_mirror
+    }
+    if (tpr >= 16) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += dpp_f64<0x140>(v[u]);   // row_mirror
+    }
+    if (tpr >= 32) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += swz16_f64(v[u]);
+    }
+    if (tpr >= 64) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = readlane_f64(v[u], 0) + readlane_f64(v[u], 32);
+    }
 }
 
-// Load the thread's pairs of a length-n vector (zeros where not owned).
-template <int NP>
-__device__ __forceinline__ void load_cols(const Geo &g, const double *v, int64_t n, d2 (&dst)[NP],
+// Load the thread's pairs of a length-n vector (zeros where not owned),
+// from global memory (a gptr) or from LDS.
+template <int NP, typename P>
+__device__ __forceinline__ void load_cols(const Geo &g, P v, int64_t n, d2 (&dst)[NP],
                                           double &last)
 {
     // unconditional loads (pair 0 stands in for a pair not owned), then
@@ -115,7 +187,7 @@ __device__ __forceinline__ void load_cols(const Geo &g, const double *v, int64_t
     for (int k = 0; k < NP; ++k) {
         const int64_t p = g.c + (int64_t)g.tpr * k;
         const bool own = p < g.npf;
-        const d2 val = g.npf > 0 ? ld2(v + (own ? 2 * p : 0)) : d2{0.0, 0.0};
+        const d2 val = g.npf > 0 ? ld2_any(v + (own ? 2 * p : 0)) : d2{0.0, 0.0};
         dst[k] = own ? val : d2{0.0, 0.0};
     }
     last = g.odd ? v[n - 1] : 0.0;
@@ -153,6 +225,8 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
     constexpr bool UPD2 = OPS & SW_UPD2;
     constexpr bool ATAX = OPS & SW_ATAX;
     constexpr bool DOT = ROWDOT || ATAX;
+    const gptr<const double> gsrc = gp(src), gu1 = gp(u1), gu2 = gp(u2), gyc = gp(yc);
+    const gptr<double> gdst = gp(dst), grow = gp(rowout);
     // pairs per thread per batch: fewer for the sweeps that update (two row
     // scalars and a store per row as well) or do two things with narrow rows
     constexpr int PIF = (UPD1 || (ROWDOT && COLSUM && NP == 1)) ? 4 : 8;
@@ -173,25 +247,27 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
         coff[k] = pv[k] ? 2 * p : 0;
     }
     const bool last_here = g.odd && lead;
-    int pb = 0;
+    int pb = 0;            // the park buffer being filled
+    int fb = 0;            // batches parked in it
+    int64_t gbase = 0;     // the first row parked in it
 
     auto load = [&](int64_t base, Batch &b) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t ri = base + (int64_t)u * g.rs + g.slot;
             const int64_t rc = ri < m ? ri : m - 1;
-            const double *row = src + rc * lds_;
+            const gptr<const double> row = gsrc + rc * lds_;
             // (a uniform test: with no whole pair, n <= 1, nothing is read
             // beyond column n-1, and A may be empty)
 #pragma unroll
             for (int k = 0; k < NP; ++k)
-                b.a[u][k] = g.npf > 0 ? ld2_nt(row + coff[k]) : d2{0.0, 0.0};
-            b.al[u] = g.odd ? ld1_nt(row + n - 1) : 0.0;
-            if (UPD1) b.s1[u] = u1[rc];
-            if (UPD2) b.s2[u] = u2[rc];
+                b.a[u][k] = g.npf > 0 ? gld2_nt(row + coff[k]) : d2{0.0, 0.0};
+            b.al[u] = g.odd ? gld1_nt(row + n - 1) : 0.0;
+            if (UPD1) b.s1[u] = gu1[rc];
+            if (UPD2) b.s2[u] = gu2[rc];
             // a vector load: the weights may have been written earlier in
             // this launch (the unfused ATAX temporary)
-            if (COLSUM) b.yw[u] = __builtin_nontemporal_load(yc + rc);
+            if (COLSUM) b.yw[u] = __builtin_nontemporal_load(gyc + rc);
         }
     };
 
@@ -210,19 +286,19 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
         if (UPD1) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                double *brow = dst + ri[u] * ldd;
+                const gptr<double> brow = gdst + ri[u] * ldd;
 #pragma unroll
                 for (int k = 0; k < NP; ++k) {
                     d2 v = b.a[u][k] + b.s1[u] * v1[k];
                     if (UPD2) v = v + b.s2[u] * v2[k];
                     b.a[u][k] = v;
-                    if (rv[u] && pv[k]) st2_nt(brow + coff[k], v);
+                    if (rv[u] && pv[k]) gst2_nt(brow + coff[k], v);
                 }
                 if (g.odd) {
                     double bl = b.al[u] + b.s1[u] * v1_last;
                     if (UPD2) bl = bl + b.s2[u] * v2_last;
                     b.al[u] = bl;
-                    if (rv[u] && lead) st1_nt(brow + n - 1, bl);
+                    if (rv[u] && lead) gst1_nt(brow + n - 1, bl);
                 }
                 if (!rv[u]) {
                     // keep the masked row zero for the sums below
@@ -246,15 +322,19 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
                     part += b.a[u][k].y * xr[k].y;
                 }
                 if (last_here) part += b.al[u] * xr_last;
-                dot[u] = wide ? wave_sum(part) : group_sum(part, g.tpr);
+                dot[u] = part;
             }
+            group_sums(dot, g.tpr);
             if (wide) {
-                // partials of each row's waves meet in LDS, added in wave order
+                // partials of each row's waves meet in LDS, added in wave
+                // order: at once where the row's dot weights its own column
+                // sums (ATAX), else once kParkBatches batches are parked
+                const int at = ATAX ? 0 : fb * (int)batch;
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (lane == 0) L.park[pb][(u * g.rs + g.slot) * nwr + wr] = dot[u];
-                lds_barrier();
+                    if (lane == 0) L.park[pb][(at + u * g.rs + g.slot) * nwr + wr] = dot[u];
                 if (ATAX) {
+                    lds_barrier();
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
                         const double *pp = &L.park[pb][(u * g.rs + g.slot) * nwr];
@@ -262,17 +342,12 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
                         for (int w = 1; w < nwr; ++w) t += pp[w];
                         dot[u] = t;
                     }
-                } else if (threadIdx.x < batch && base + (int64_t)threadIdx.x < m) {
-                    const double *pp = &L.park[pb][threadIdx.x * nwr];
-                    double t = pp[0];
-                    for (int w = 1; w < nwr; ++w) t += pp[w];
-                    rowout[base + threadIdx.x] = rscale * t;
+                    pb ^= 1;
                 }
-                pb ^= 1;
             } else if (ROWDOT) {
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    if (lead && rv[u]) rowout[ri[u]] = rscale * dot[u];
+                    if (lead && rv[u]) grow[ri[u]] = rscale * dot[u];
             }
         }
         if (COLSUM || ATAX) {
@@ -287,12 +362,30 @@ __device__ __forceinline__ void sweep(const Geo &g, int64_t m, int64_t n, const 
         }
     };
 
+    // the parked row dots of rows gbase, gbase + 1, ... (fb batches): the
+    // partials of row gbase + t sit at t * nwr, t < fb * batch <= NT / 2
+    auto flush = [&]() {
+        lds_barrier();
+        const int64_t t = threadIdx.x;
+        if (t < fb * batch && gbase + t < m) {
+            const double *pp = &L.park[pb][t * nwr];
+            double s = pp[0];
+            for (int w = 1; w < nwr; ++w) s += pp[w];
+            grow[gbase + t] = rscale * s;
+        }
+        pb ^= 1;
+        fb = 0;
+    };
+
     // all of a batch's loads are issued before any of its values is used;
     // the other workgroups on the compute unit cover the wait
     for (int64_t base = 0; base < m; base += batch) {
         Batch b;
         load(base, b);
+        if (fb == 0) gbase = base;
         process(base, b);
+        if (ROWDOT && !ATAX && wide && (++fb == kParkBatches || base + batch >= m))
+            flush();
     }
 }
 
@@ -303,21 +396,23 @@ __device__ __forceinline__ void finish_cols(const Geo &g, int64_t n, const d2 (&
                                             double acc_last, double scale, const double *add,
                                             double *out, double *keep, Lds &L)
 {
+    const gptr<const double> gadd = gp(add);
+    const gptr<double> gout = gp(out);
     if (g.rs == 1) {
 #pragma unroll
         for (int k = 0; k < NP; ++k) {
             const int64_t p = g.c + (int64_t)g.tpr * k;
             if (p < g.npf) {
                 d2 v = acc[k] * scale;
-                if (add) v += ld2(add + 2 * p);
-                *reinterpret_cast<d2 *>(out + 2 * p) = v;
+                if (add) v += gld2(gadd + 2 * p);
+                *reinterpret_cast<gptr<d2>>(gout + 2 * p) = v;
                 if (keep) *reinterpret_cast<d2 *>(keep + 2 * p) = v;
             }
         }
         if (g.odd && g.c == 0) {
             double v = acc_last * scale;
-            if (add) v += add[n - 1];
-            out[n - 1] = v;
+            if (add) v += gadd[n - 1];
+            gout[n - 1] = v;
             if (keep) keep[n - 1] = v;
         }
     } else {
@@ -330,16 +425,16 @@ __device__ __forceinline__ void finish_cols(const Geo &g, int64_t n, const d2 (&
             d2 v = r[p];
             for (int s = 1; s < g.rs; ++s) v += r[s * g.tpr + p];
             v = v * scale;
-            if (add) v += ld2(add + 2 * p);
-            *reinterpret_cast<d2 *>(out + 2 * p) = v;
+            if (add) v += gld2(gadd + 2 * p);
+            *reinterpret_cast<gptr<d2>>(gout + 2 * p) = v;
             if (keep) *reinterpret_cast<d2 *>(keep + 2 * p) = v;
         }
         if (g.odd && threadIdx.x == 0) {
             double v = L.red_last[0];
             for (int s = 1; s < g.rs; ++s) v += L.red_last[s];
             v = v * scale;
-            if (add) v += add[n - 1];
-            out[n - 1] = v;
+            if (add) v += gadd[n - 1];
+            gout[n - 1] = v;
             if (keep) keep[n - 1] = v;
         }
     }
@@ -369,7 +464,7 @@ __device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &
         // q = A p ; s = A^T r
         const double *p = it.vec[0], *r = it.vec[1];
         double *q = it.out[0], *s = it.out[1];
-        load_cols(g, p, n, xr, xr_l);
+        load_cols(g, gp(p), n, xr, xr_l);
         if (it.form == BTO_FUSED) {
             sweep<NT, NP, SW_ROWDOT | SW_COLSUM>(g, m, n, it.A, it.lda, nullptr, 0, nullptr,
                                                  nullptr, r, q, 1.0, xr, xr_l, v1, v1_l, v2,
@@ -386,9 +481,9 @@ __device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &
         const double *u1 = it.vec[0], *vv1 = it.vec[1], *u2 = it.vec[2], *vv2 = it.vec[3];
         const double *y = it.vec[4], *z = it.vec[5];
         double *x = it.out[0], *w = it.out[1];
-        load_cols(g, vv1, n, v1, v1_l);
+        load_cols(g, gp(vv1), n, v1, v1_l);
         if (it.form == BTO_FUSED) {
-            load_cols(g, vv2, n, v2, v2_l);
+            load_cols(g, gp(vv2), n, v2, v2_l);
             sweep<NT, NP, SW_UPD1 | SW_UPD2 | SW_COLSUM>(g, m, n, it.A, it.lda, it.B, it.ldb, u1,
                                                          u2, y, nullptr, 1.0, xr, xr_l, v1, v1_l,
                                                          v2, v2_l, acc, acc_l, L);
@@ -396,7 +491,7 @@ __device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &
             sweep<NT, NP, SW_UPD1>(g, m, n, it.A, it.lda, it.B, it.ldb, u1, nullptr, nullptr,
                                    nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
             __syncthreads();
-            load_cols(g, vv2, n, v1, v1_l);
+            load_cols(g, gp(vv2), n, v1, v1_l);
             sweep<NT, NP, SW_UPD1>(g, m, n, it.B, it.ldb, it.B, it.ldb, u2, nullptr, nullptr,
                                    nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
             __syncthreads();
@@ -411,7 +506,7 @@ __device__ __forceinline__ void run_item(const BatchItem &it, double *tmp, Lds &
         // ATAX: y = A^T (A x)
         const double *xv = it.vec[0];
         double *y = it.out[0];
-        load_cols(g, xv, n, xr, xr_l);
+        load_cols(g, gp(xv), n, xr, xr_l);
         if (it.form == BTO_FUSED) {
             sweep<NT, NP, SW_ATAX>(g, m, n, it.A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
                                    nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
@@ -457,18 +552,18 @@ __device__ __forceinline__ void run_tile(const BatchItem &it, const BatchUnit &u
     if (un.phase == 1) {
         const int t = (int)(r0 / it.tile_rows);
         if (it.kind == BTO_K_BICGK) {
-            load_cols(g, it.vec[0], n, xr, xr_l);
+            load_cols(g, gp(it.vec[0]), n, xr, xr_l);
             sweep<NT, NP, SW_ROWDOT | SW_COLSUM>(g, mt, n, A, it.lda, nullptr, 0, nullptr, nullptr,
                                                  it.vec[1] + r0, it.out[0] + r0, 1.0, xr, xr_l,
                                                  v1, v1_l, v2, v2_l, acc, acc_l, L);
         } else if (it.kind == BTO_K_GEMVER) {
-            load_cols(g, it.vec[1], n, v1, v1_l);
-            load_cols(g, it.vec[3], n, v2, v2_l);
+            load_cols(g, gp(it.vec[1]), n, v1, v1_l);
+            load_cols(g, gp(it.vec[3]), n, v2, v2_l);
             sweep<NT, NP, SW_UPD1 | SW_UPD2 | SW_COLSUM>(
                 g, mt, n, A, it.lda, it.B + r0 * it.ldb, it.ldb, it.vec[0] + r0, it.vec[2] + r0,
                 it.vec[4] + r0, nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
         } else {
-            load_cols(g, it.vec[0], n, xr, xr_l);
+            load_cols(g, gp(it.vec[0]), n, xr, xr_l);
             sweep<NT, NP, SW_ATAX>(g, mt, n, A, it.lda, nullptr, 0, nullptr, nullptr, nullptr,
                                    nullptr, 1.0, xr, xr_l, v1, v1_l, v2, v2_l, acc, acc_l, L);
         }
@@ -488,13 +583,15 @@ __device__ __forceinline__ void run_tile(const BatchItem &it, const BatchUnit &u
                 scale = it.beta;
                 add = it.vec[5];
             }
+            const gptr<const double> gadd = gp(add);
+            const gptr<double> gout = gp(out);
             for (int64_t j = threadIdx.x; j < n; j += NT) {
                 double v = part[j];
                 for (int k = 1; k < T; ++k)
                     v += part[k * ldp + j];
                 v = v * scale;
-                if (add) v += add[j];
-                out[j] = v;
+                if (add) v += gadd[j];
+                gout[j] = v;
             }
             if (it.kind == BTO_K_GEMVER) {
                 __threadfence();
@@ -517,7 +614,7 @@ __device__ __forceinline__ void run_tile(const BatchItem &it, const BatchUnit &u
         }
         __syncthreads();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        load_cols(g, it.out[0], n, xr, xr_l);
+        load_cols(g, gp(it.out[0]), n, xr, xr_l);
         sweep<NT, NP, SW_ROWDOT>(g, mt, n, it.B + r0 * it.ldb, it.ldb, nullptr, 0, nullptr, nullptr,
                                  nullptr, it.out[1] + r0, it.alpha, xr, xr_l, v1, v1_l, v2, v2_l,
                                  acc, acc_l, L);
