@@ -30,7 +30,8 @@ bto_status fail(bto_status s, const std::string &msg)
 //
 // Each matrix sweep has a slot whose tile shape can be changed at run time
 // (the autotuner does).  Workspace sizes are computed for the most demanding
-// shape any slot may take (kv >= 2, rb >= 32), so they depend on the
+// shape any slot may take (kv >= 2 for the row-dot sweeps, whose partials
+// are per wave tile; rb >= 32 for the column sums), so they depend on the
 // arguments alone.
 
 std::mutex g_cfg_mu;

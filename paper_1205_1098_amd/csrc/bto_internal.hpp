@@ -82,8 +82,8 @@ struct TileArgs {
     double *Pcol;      // [row bands][n]
 };
 
-// Shapes 0..5 serve read-only sweeps, 6..10 sweeps that store B.
-constexpr int kTileShapes = 11;
+// Shapes 0..5 serve read-only sweeps, 6..14 sweeps that store B.
+constexpr int kTileShapes = 15;
 bool tile_cfg_supported(int ops, const TileCfg &c);
 int tile_kv(const TileCfg &c);
 void tile_shape_info(int shape, int out[4]);   // kv, depth, waves across, waves down

@@ -235,8 +235,11 @@ const Shape kShapes[] = {
     {8, 2, 4, 1}, {8, 1, 4, 4}, {4, 2, 8, 2}, {4, 2, 4, 4}, {4, 4, 4, 1}, {8, 2, 4, 2},
     // sweeps that store B
     {2, 2, 1, 4}, {2, 4, 1, 4}, {4, 2, 1, 4}, {4, 4, 1, 4}, {2, 3, 1, 16},
+    // ... narrower wave rows (1 KiB), for short-lived workgroups
+    {1, 2, 1, 16}, {1, 4, 1, 8}, {2, 2, 1, 8}, {1, 2, 2, 8},
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+static_assert(kNumShapes == kTileShapes, "the shape table and the C interface disagree");
 constexpr int kFirstWriteShape = 6;
 
 bool shape_allowed(int ops, int shape)
@@ -293,6 +296,10 @@ void launch_tile_ops(const char *name, const TileCfg &c, const TileArgs &a, hipS
             BTO_SHAPE(8, 4, 2, 1, 4)
             BTO_SHAPE(9, 4, 4, 1, 4)
             BTO_SHAPE(10, 2, 3, 1, 16)
+            BTO_SHAPE(11, 1, 2, 1, 16)
+            BTO_SHAPE(12, 1, 4, 1, 8)
+            BTO_SHAPE(13, 2, 2, 1, 8)
+            BTO_SHAPE(14, 1, 2, 2, 8)
         default: return;
         }
     }

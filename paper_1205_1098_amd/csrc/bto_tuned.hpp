@@ -62,8 +62,8 @@ inline int size_bucket(int64_t m, int64_t n)
         {{4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}},  /* GEMV_N */ \
         {{3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}, {3, 512, 0}},  /* GEMV_T */ \
         {{8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}, {8, 4, 0}},  /* GER */ \
-        {{10, 32, 1}, {10, 32, 1}, {10, 32, 1}, {6, 32, 1}, {10, 32, 0}, {10, 32, 0}, {10, 32, 1}, {10, 32, 1}},  /* GEMVER_P1 */ \
-        {{5, 4, 1}, {4, 4, 1}, {4, 4, 1}, {3, 8, 1}, {2, 16, 0}, {4, 4, 1}, {4, 4, 1}, {4, 4, 1}},  /* GEMVER_P2 */ \
+        {{6, 128, 0}, {10, 32, 1}, {11, 128, 1}, {13, 32, 0}, {12, 32, 1}, {12, 32, 0}, {11, 32, 0}, {11, 32, 0}},  /* GEMVER_P1 */ \
+        {{4, 4, 1}, {4, 4, 1}, {2, 8, 1}, {3, 8, 0}, {4, 4, 0}, {3, 16, 0}, {4, 4, 1}, {4, 4, 1}},  /* GEMVER_P2 */ \
         {{3, 32, 0}, {3, 32, 0}, {3, 32, 1}, {2, 32, 1}, {3, 32, 0}, {3, 64, 0}, {3, 512, 1}, {3, 512, 1}},  /* DGEMVT_P1 */ \
         {{2, 8, 0}, {1, 4, 0}, {3, 4, 1}, {3, 8, 0}, {2, 16, 0}, {3, 64, 0}, {4, 4, 0}, {4, 4, 0}},  /* DGEMVT_P2 */ \
     }

@@ -102,12 +102,21 @@ class Space:
         return keep or list(self.legal[slot])
 
     @classmethod
-    def from_library(cls, bto, nshapes: int = 11) -> "Space":
+    def from_library(cls, bto) -> "Space":
         sp = cls()
-        for shape in range(nshapes):
-            sp.kv[shape] = bto.tune_shape(shape)["kv"]
+        nshapes = 0
+        while True:                      # the compiled shapes: 0, 1, ... until refused
+            try:
+                sp.kv[nshapes] = bto.tune_shape(nshapes)["kv"]
+            except bto.BtoError:
+                break
+            nshapes += 1
+        nb = bto.tune_buckets()
         for slot in range(len(bto.tune_slots())):
             default = bto.tune_get(slot)
+            # legality is probed by setting every bucket; each bucket's own
+            # configuration is put back afterwards
+            saved = [bto.tune_get(slot, 256 << b) for b in range(nb)]
             sp.defaults[slot] = default
             sp.ops[slot] = bto.tune_slot_ops(slot)
             legal = []
@@ -124,7 +133,8 @@ class Space:
                             legal.append((shape, rb, rev))
                         except bto.BtoError:
                             pass
-            bto.tune_set(slot, *default)
+            for b, cfg in enumerate(saved):
+                bto.tune_set(slot, *cfg, size=256 << b)
             sp.legal[slot] = legal
         return sp
 

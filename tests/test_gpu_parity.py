@@ -420,3 +420,75 @@ def test_full_vectors(env, kind):
                 assert np.array_equal(g, rf)
             else:
                 assert relerr(g, rf) <= TOL
+
+
+# ---- every compiled tile shape in every slot that can run it --------------------
+#
+# The autotuner may give a slot any shape the library accepts for it; each
+# such (slot, shape) runs here once on ragged shapes (odd n takes the
+# scalar path, even n with an odd padding the misaligned path) against the
+# oracle.  The slot's per-bucket table is restored afterwards.
+
+SLOT_KERNEL = {0: ("bicgk", "fused"), 1: ("bicgk", "unfused"), 2: ("bicgk", "unfused"),
+               3: ("gemver", "unfused"), 4: ("gemver", "fused"), 5: ("gemver", "fused"),
+               6: ("dgemvt", "fused"), 7: ("dgemvt", "fused")}
+
+
+def _run_kernel(torch, bto, dev, kernel, form, m, n, pad):
+    lda = _lda(n, pad)
+    d = lambda a: dvec(torch, dev, a)
+    if kernel == "bicgk":
+        A, vec = inputs("uniform", m, n, lda, 1, 11)
+        p, r = vec(1, n), vec(2, m)
+        ref = oracle.bicgk(A, p, r, lda=lda)
+        got = bto.bicgk(dmat(torch, dev, A, n), d(p), d(r), form=form)
+    elif kernel == "gemver":
+        A, vec = inputs("uniform", m, n, lda, 2, 11)
+        u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+        ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)
+        got = bto.gemver(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y), d(z),
+                         ALPHA, BETA, form=form)
+    else:
+        A, vec = inputs("uniform", m, n, lda, 4, 11)
+        y, z = vec(1, m), vec(2, n)
+        ref = oracle.dgemvt(A, y, z, ALPHA, BETA, lda=lda)
+        got = bto.dgemvt(dmat(torch, dev, A, n), d(y), d(z), ALPHA, BETA, form=form)
+    torch.cuda.synchronize()
+    return [host(g) for g in got], ref
+
+
+# shapes 0..5 serve the read-only sweeps (shape 1 cannot hold both BiCGK
+# vectors), 6..14 the sweeps that store B (slots 3 and 4)
+SHAPE_CASES = [(slot, shape) for slot in sorted(SLOT_KERNEL)
+               for shape in (range(6, 15) if slot in (3, 4) else range(6))
+               if not (slot == 0 and shape == 1)]
+
+
+@pytest.mark.parametrize("slot,shape", SHAPE_CASES)
+def test_every_tile_shape(env, slot, shape):
+    torch, bto, dev = env
+    kernel, form = SLOT_KERNEL[slot]
+    saved = {b: bto.tune_get(slot, 256 << b) for b in range(bto.tune_buckets())}
+    saved_rowres = {b: bto.tune_get(SLOT_BICGK_ROWRES, 256 << b)
+                    for b in range(bto.tune_buckets())}
+    try:
+        rb = None
+        for cand in (32, 64, 8, 4):
+            try:
+                bto.tune_set(slot, shape, cand, 1)
+                rb = cand
+                break
+            except bto.BtoError:
+                continue
+        assert rb is not None, f"slot {slot} refuses shape {shape}"
+        if slot == 0:
+            bto.tune_set(SLOT_BICGK_ROWRES, 0, 0, 0)     # the tile sweep, not the row-resident one
+        for m, n, pad in [(333, 1030, 3), (130, 517, 0), (1, 2, 0)]:
+            got, ref = _run_kernel(torch, bto, dev, kernel, form, m, n, pad)
+            for g, r in zip(got, ref):
+                assert relerr(g, r) <= TOL, (slot, shape, rb, m, n, pad)
+    finally:
+        for b, c in saved.items():
+            bto.tune_set(slot, *c, size=256 << b)
+        for b, c in saved_rowres.items():
+            bto.tune_set(SLOT_BICGK_ROWRES, *c, size=256 << b)

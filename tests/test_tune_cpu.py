@@ -246,3 +246,54 @@ def test_batch_knobs_orthogonal_search():
     assert evals <= 1 + sum(len(v) - 1 for v in tune.BATCH_SPACE.values())
     again, _, _ = tune.tune_batch(lambda c: pytest.fail("should be cached"), cache=cache)
     assert again == best
+
+
+def test_space_from_library_keeps_every_bucket():
+    """Probing legality sets a slot for all buckets; the per-bucket
+    configurations must be as before once the space is built."""
+
+    class FakeBto:
+        class BtoError(Exception):
+            pass
+
+        NB, NSLOTS, NSHAPES = 8, 10, 15
+
+        def __init__(self):
+            self.cfg = {(s, b): (s % 5 + b % 3, 32 << (b % 2), b % 2)
+                        for s in range(self.NSLOTS) for b in range(self.NB)}
+
+        def bucket(self, size):
+            b = 0
+            while b < self.NB - 1 and (256 << b) < size:
+                b += 1
+            return b
+
+        def tune_shape(self, shape):
+            if not 0 <= shape < self.NSHAPES:
+                raise self.BtoError("shape out of range")
+            return {"kv": 1 + shape % 4, "depth": 2, "wc": 1, "wr": 4}
+
+        def tune_slots(self):
+            return [f"slot{s}" for s in range(self.NSLOTS)]
+
+        def tune_buckets(self):
+            return self.NB
+
+        def tune_slot_ops(self, slot):
+            return slot
+
+        def tune_get(self, slot, size=0):
+            return self.cfg[(slot, self.bucket(16384 if size == 0 else size))]
+
+        def tune_set(self, slot, shape, rb, rev=0, size=0):
+            if rb not in (0, 32, 64) and slot < 8:
+                raise self.BtoError("illegal")
+            for b in (range(self.NB) if size == 0 else [self.bucket(size)]):
+                self.cfg[(slot, b)] = (shape, rb, rev)
+
+    lib = FakeBto()
+    before = dict(lib.cfg)
+    sp = tune.Space.from_library(lib)
+    assert lib.cfg == before
+    assert sorted(sp.kv) == list(range(FakeBto.NSHAPES))
+    assert all(sp.legal[s] for s in range(FakeBto.NSLOTS))
