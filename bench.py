@@ -263,6 +263,10 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
     plan = bto.BatchPlan(insts, use_graph=graph)
     sec = time_steps(torch, plan.launch, 10, 2)
     plan.close()
+    # the same instances as short-lived workgroup tiles (four launches in a graph)
+    tiled = bto.TiledBatch(insts, use_graph=graph)
+    sec_tiled = time_steps(torch, tiled.launch, 10, 2)
+    tiled.close()
     # the same instances launched one entry-point call at a time
     def loop():
         for inst in insts:
@@ -282,6 +286,13 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         "gbs": round(total / sec / 1e9, 1),
         "pct_peak": round(100 * total / sec / 1e9 / PEAK_GBS, 1),
         "traffic": counter_traffic("batch_mixed4096_counters.txt") if count == 4096 else None,
+        "tiled": {
+            "ms_per_batch": round(sec_tiled * 1e3, 3),
+            "inst_per_s": round(count / sec_tiled, 1),
+            "gbs": round(total / sec_tiled / 1e9, 1),
+            "pct_peak": round(100 * total / sec_tiled / 1e9 / PEAK_GBS, 1),
+            "speedup_vs_persistent": round(sec / sec_tiled, 3),
+        },
         "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
         "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,
     }

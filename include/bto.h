@@ -265,6 +265,35 @@ bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream);
 bto_status bto_batch_plan_check(bto_batch_plan *plan, hipStream_t stream);
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
 
+/* ---- tiled batches ---------------------------------------------------------
+ * The same fused GEMVER and BiCGK instances (descriptors as above; ATAX and
+ * the unfused form are refused with BTO_ERR_UNSUPPORTED) cut into
+ * short-lived workgroup tiles instead of one workgroup per instance: every
+ * instance's first sweep runs as tiles of 32 rows by 128 columns in one
+ * launch, a second launch adds each instance's partial sums (BiCGK's q and
+ * s, GEMVER's x = beta B^T y + z) in a fixed order, and GEMVER's second
+ * sweep (w = alpha B x) follows as a third launch of tiles and a fourth of
+ * sums.  The kernel boundaries order the phases, so no tile waits for
+ * another.  Each result depends only on its own instance (a fixed tile and
+ * summation order), not on the other instances or the launch; it rounds
+ * differently from the persistent plan's.  This is the loop partition of
+ * Section III-C (row bands across workgroups, columns across lanes)
+ * applied to many instances at once.
+ *
+ * bto_tiled_batch_create validates the instances as bto_batch_plan_create
+ * does, then allocates and fills the plan's device tables and partial-sum
+ * scratch (about 1/32 of each matrix for the column sums and 1/128 for the
+ * row dots), which the plan owns until it is destroyed.  With use_graph set
+ * the four launches are captured once in a HIP graph.
+ * bto_tiled_batch_launch enqueues them on `stream` and allocates nothing;
+ * launches of one plan must not overlap (they share its scratch). */
+typedef struct bto_tiled_batch bto_tiled_batch;
+
+bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int use_graph,
+                                  bto_tiled_batch **plan);
+bto_status bto_tiled_batch_launch(bto_tiled_batch *plan, hipStream_t stream);
+bto_status bto_tiled_batch_destroy(bto_tiled_batch *plan);
+
 /* ---- measurement support ------------------------------------------------
  * Per-kernel timing with HIP events recorded on the stream each kernel is
  * launched on.  While enabled, every kernel the library launches is

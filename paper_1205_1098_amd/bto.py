@@ -86,6 +86,9 @@ _SIGS = {
     "bto_batch_plan_reset": ([_ptr, _ptr, _int, _ptr], _int),
     "bto_batch_plan_launch": ([_ptr, _ptr], _int),
     "bto_batch_plan_destroy": ([_ptr], _int),
+    "bto_tiled_batch_create": ([_ptr, _int, _int, _ptr], _int),
+    "bto_tiled_batch_launch": ([_ptr, _ptr], _int),
+    "bto_tiled_batch_destroy": ([_ptr], _int),
 }
 
 for _name, (_args, _res) in _SIGS.items():
@@ -585,6 +588,41 @@ class BatchPlan:
     def close(self) -> None:
         if self._plan:
             _lib.bto_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+            self._keep = []
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TiledBatch:
+    """Fused GEMVER / BiCGK instances (the dicts BatchPlan takes) run as
+    short-lived workgroup tiles: four launches (first sweeps, their sums,
+    GEMVER's second sweeps, their sums), captured in a HIP graph with
+    `use_graph`.  launch() enqueues them on the current stream and
+    allocates nothing."""
+
+    def __init__(self, instances, use_graph: bool = True):
+        self._plan = ctypes.c_void_p()
+        descs, self._keep, dev = _batch_descs(instances)
+        self.device = dev if dev is not None else torch.device("cuda", torch.cuda.current_device())
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_tiled_batch_create(ctypes.byref(descs), len(instances),
+                                               1 if use_graph else 0, ctypes.byref(self._plan)))
+        self.count = len(instances)
+
+    def launch(self) -> None:
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_tiled_batch_launch(self._plan, _stream(self.device)))
+
+    def close(self) -> None:
+        if self._plan:
+            _lib.bto_tiled_batch_destroy(self._plan)
             self._plan = ctypes.c_void_p()
             self._keep = []
 

@@ -1409,3 +1409,282 @@ bto_status bto_batch_plan_destroy(bto_batch_plan *plan)
 }
 
 }  // extern "C"
+
+// ---- tiled batches ---------------------------------------------------------------
+//
+// Fused GEMVER and BiCGK instances cut into short-lived workgroup tiles:
+// every instance's first sweep in one launch (a unit per row band and
+// column block), its partial sums reduced by a second launch, GEMVER's
+// second sweep in a third and its row dots reduced by a fourth.  Kernel
+// boundaries order the phases, so no tile waits for another and no
+// device-scope fence is issued.
+
+struct bto_tiled_batch {
+    BTileEntry *d_entries = nullptr;
+    BTileUnit *d_units = nullptr;       // first-sweep units, then second-sweep units
+    FinishJob *d_jobs = nullptr;        // jobs after the first sweep, then after the second
+    BFinishUnit *d_funits = nullptr;
+    double *d_scratch = nullptr;
+    int64_t units[2] = {0, 0};          // per sweep
+    int64_t fin1 = 0, fin2 = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+};
+
+namespace {
+
+struct TiledImage {
+    std::vector<BTileEntry> entries;
+    std::vector<BTileUnit> units[2];      // per sweep
+    std::vector<FinishJob> jobs1, jobs2;
+    int64_t scratch = 32;   // doubles; offset 0 is left unused, so no area is at "null"
+};
+
+void tiled_free(bto_tiled_batch *p)
+{
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_entries) (void)hipFree(p->d_entries);
+    if (p->d_units) (void)hipFree(p->d_units);
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_funits) (void)hipFree(p->d_funits);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    delete p;
+}
+
+// Validate the instances and lay out entries, units, finish jobs and the
+// partial-sum areas (offsets into a scratch area starting at 0; pointers are
+// rebased once it is allocated).
+bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
+{
+    if (count < 0 || (count > 0 && !descs))
+        return fail(BTO_ERR_INVALID_ARG, "bad instance list");
+    std::vector<BSpan> spans;
+    std::vector<BatchItem> items((size_t)count);
+    int64_t unused = 0;
+    for (int i = 0; i < count; ++i) {
+        BTO_TRY(batch_check_one(descs[i], i, spans, items[i], unused, -1));
+        if (descs[i].kind == BTO_K_ATAX || descs[i].form != BTO_FUSED)
+            return fail(BTO_ERR_UNSUPPORTED, "instance " + std::to_string(i) +
+                                                 ": tiled batches run fused GEMVER and BiCGK");
+    }
+    BTO_TRY(batch_check_overlaps(spans));
+    // largest instances first, so that the small ones fill the end
+    std::vector<int> order((size_t)count);
+    for (int i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return (double)items[a].m * (double)items[a].n > (double)items[b].m * (double)items[b].n;
+    });
+    auto take = [&](int64_t doubles) {   // an offset, as a fake pointer until rebased
+        const int64_t off = img.scratch;
+        img.scratch += ceil_div(doubles > 0 ? doubles : 1, (int64_t)32) * 32;
+        return reinterpret_cast<double *>((uintptr_t)(off * 8));
+    };
+    // the rows of the instance in bands, each band's column blocks side by
+    // side, so that neighbouring workgroups read neighbouring memory
+    auto tiles = [&](std::vector<BTileUnit> &units, int entry, int64_t nb, int64_t nc) {
+        for (int64_t b = 0; b < nb; ++b)
+            for (int64_t c = 0; c < nc; ++c)
+                units.push_back({entry, (int32_t)b, (int32_t)c, 0});
+    };
+    // read-only sweeps of wider matrices take the wide blocks
+    auto read_shape = [](int64_t n) { return n > 512 ? BT_WIDE : BT_NARROW; };
+    for (int i : order) {
+        const BatchItem &it = items[i];
+        const int64_t m = it.m, n = it.n;
+        const bool some = m > 0 && n > 0;
+        const int64_t nb = some ? ceil_div(m, (int64_t)kBTileRows) : 0;
+        const int rs = read_shape(n);
+        const int64_t nc = some ? ceil_div(n, (int64_t)kBTileCols[rs]) : 0;   // read sweeps
+        const int64_t nwt = some ? ceil_div(n, (int64_t)kBTileWaveCols[rs]) : 0;   // their row-dot parts
+        const int64_t ncw = some ? ceil_div(n, (int64_t)kBTileCols[BT_NARROW]) : 0;
+        const bool rows16 = it.lda % 2 == 0 || m <= 1;
+        BTileEntry e{};
+        e.a.m = m;
+        e.a.n = n;
+        e.a.lda = it.lda;
+        e.a.ldb = it.ldb;
+        e.a.A = it.A;
+        if (it.kind == BTO_K_BICGK) {
+            // q = A p, s = A^T r: row dots per column block, column sums per band
+            double *prow = take(nwt * m), *pcol = take(nb * n);
+            e.a.xr = it.vec[0];
+            e.a.yc = it.vec[1];
+            e.a.Prow = prow;
+            e.a.Pcol = pcol;
+            e.ops = OP_ROWDOT | OP_COLSUM;
+            e.vec = aligned16(it.A) && rows16;
+            e.shape = (int16_t)rs;
+            if (some) {
+                img.entries.push_back(e);
+                tiles(img.units[0], (int)img.entries.size() - 1, nb, nc);
+            }
+            img.jobs1.push_back({prow, nwt, m, 1.0, nullptr, it.out[0]});
+            img.jobs1.push_back({pcol, nb, n, 1.0, nullptr, it.out[1]});
+        } else {
+            // B = A + u1 v1^T + u2 v2^T and x = beta B^T y + z, then w = alpha B x
+            double *pcol = take(nb * n), *prow = take(nwt * m);
+            e.a.B = it.B;
+            e.a.u1 = it.vec[0];
+            e.a.v1 = it.vec[1];
+            e.a.u2 = it.vec[2];
+            e.a.v2 = it.vec[3];
+            e.a.yc = it.vec[4];
+            e.a.Pcol = pcol;
+            e.ops = OP_UPD1 | OP_UPD2 | OP_COLSUM;
+            e.vec = aligned16(it.A) && aligned16(it.B) && rows16 && (it.ldb % 2 == 0 || m <= 1);
+            e.shape = BT_NARROW;
+            BTileEntry e2{};
+            e2.a.m = m;
+            e2.a.n = n;
+            e2.a.lda = it.ldb;
+            e2.a.ldb = it.ldb;
+            e2.a.A = it.B;
+            e2.a.xr = it.out[0];
+            e2.a.Prow = prow;
+            e2.ops = OP_ROWDOT;
+            e2.vec = aligned16(it.B) && (it.ldb % 2 == 0 || m <= 1);
+            e2.shape = (int16_t)rs;
+            if (some) {
+                img.entries.push_back(e);
+                tiles(img.units[0], (int)img.entries.size() - 1, nb, ncw);
+                img.entries.push_back(e2);
+                tiles(img.units[1], (int)img.entries.size() - 1, nb, nc);
+            }
+            img.jobs1.push_back({pcol, nb, n, it.beta, it.vec[5], it.out[0]});
+            img.jobs2.push_back({prow, nwt, m, it.alpha, nullptr, it.out[1]});
+        }
+        for (auto &list : img.units)
+            if ((int64_t)list.size() > INT_MAX)
+                return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch");
+        if ((int64_t)img.entries.size() > INT_MAX)
+            return fail(BTO_ERR_UNSUPPORTED, "too many instances for one launch");
+    }
+    return BTO_SUCCESS;
+}
+
+std::vector<BFinishUnit> finish_units(const std::vector<FinishJob> &jobs, int first_job)
+{
+    std::vector<BFinishUnit> u;
+    for (size_t j = 0; j < jobs.size(); ++j)
+        for (int64_t b = 0; b < ceil_div(jobs[j].len, (int64_t)64); ++b)
+            u.push_back({first_job + (int32_t)j, (int32_t)b});
+    return u;
+}
+
+void tiled_enqueue(const bto_tiled_batch *p, hipStream_t st)
+{
+    launch_btile(p->d_entries, p->d_units, p->units[0], st);
+    launch_bfinish(p->d_jobs, p->d_funits, p->fin1, st);
+    launch_btile(p->d_entries, p->d_units + p->units[0], p->units[1], st);
+    launch_bfinish(p->d_jobs, p->d_funits + p->fin1, p->fin2, st);
+}
+
+template <typename T>
+bool upload(T **dst, const std::vector<T> &a, const std::vector<T> &b)
+{
+    const size_t n = a.size() + b.size();
+    if (hipMalloc(dst, sizeof(T) * (n > 0 ? n : 1)) != hipSuccess)
+        return false;
+    if (!a.empty() && hipMemcpy(*dst, a.data(), sizeof(T) * a.size(), hipMemcpyHostToDevice) !=
+                          hipSuccess)
+        return false;
+    if (!b.empty() && hipMemcpy(*dst + a.size(), b.data(), sizeof(T) * b.size(),
+                                hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int use_graph,
+                                  bto_tiled_batch **plan)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    *plan = nullptr;
+    TiledImage img;
+    BTO_TRY(tiled_image(descs, count, img));
+    bto_tiled_batch *p = new bto_tiled_batch();
+    auto hip_fail = [&](const char *what) {
+        tiled_free(p);
+        return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
+    };
+    if (hipMalloc(&p->d_scratch, sizeof(double) * (size_t)(img.scratch > 0 ? img.scratch : 1)) !=
+        hipSuccess)
+        return hip_fail("hipMalloc");
+    // rebase the partial-sum offsets onto the scratch area
+    const uintptr_t base = reinterpret_cast<uintptr_t>(p->d_scratch);
+    auto rebase = [&](double *&q) {
+        if (q) q = reinterpret_cast<double *>(base + reinterpret_cast<uintptr_t>(q));
+    };
+    for (BTileEntry &e : img.entries) {
+        rebase(e.a.Prow);
+        rebase(e.a.Pcol);
+    }
+    for (auto *jobs : {&img.jobs1, &img.jobs2})
+        for (FinishJob &j : *jobs)
+            j.P = reinterpret_cast<const double *>(base + reinterpret_cast<uintptr_t>(j.P));
+    const std::vector<BFinishUnit> f1 = finish_units(img.jobs1, 0);
+    const std::vector<BFinishUnit> f2 = finish_units(img.jobs2, (int)img.jobs1.size());
+    p->units[0] = (int64_t)img.units[0].size();
+    p->units[1] = (int64_t)img.units[1].size();
+    p->fin1 = (int64_t)f1.size();
+    p->fin2 = (int64_t)f2.size();
+    if (p->fin1 > INT_MAX || p->fin2 > INT_MAX) {
+        tiled_free(p);
+        return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
+    }
+    const std::vector<BTileEntry> none_e;
+    if (!upload(&p->d_entries, img.entries, none_e) ||
+        !upload(&p->d_units, img.units[0], img.units[1]) ||
+        !upload(&p->d_jobs, img.jobs1, img.jobs2) || !upload(&p->d_funits, f1, f2))
+        return hip_fail("device table");
+    if (use_graph) {
+        if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+            return hip_fail("hipStreamCreate");
+        if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return hip_fail("hipStreamBeginCapture");
+        t_capturing = true;
+        tiled_enqueue(p, p->cap);
+        t_capturing = false;
+        if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
+            return hip_fail("hipStreamEndCapture");
+        if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+            return hip_fail("hipGraphInstantiate");
+    }
+    *plan = p;
+    return BTO_SUCCESS;
+}
+
+bto_status bto_tiled_batch_launch(bto_tiled_batch *plan, hipStream_t stream)
+{
+    t_error.clear();
+    if (!plan)
+        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->exec) {
+        timing_begin(stream, "tiled_batch_graph");
+        const hipError_t e = hipGraphLaunch(plan->exec, stream);
+        timing_end(stream);
+        if (e != hipSuccess)
+            return fail(BTO_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    } else {
+        tiled_enqueue(plan, stream);
+    }
+    return check_launch();
+}
+
+bto_status bto_tiled_batch_destroy(bto_tiled_batch *plan)
+{
+    t_error.clear();
+    tiled_free(plan);
+    return BTO_SUCCESS;
+}
+
+}  // extern "C"

@@ -103,6 +103,34 @@ struct FinishJob {
 };
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
 
+// Tiled batches: many instances' tile sweeps in one launch, one workgroup
+// per (sweep, row band, column block) unit, then their partial sums reduced
+// by one launch of finish units.  Bands are kBTileRows rows.  Two workgroup
+// shapes (16 waves each): narrow blocks of 128 columns (1 KiB wave rows, two
+// rows per wave) for the sweeps that store B and for narrow matrices, wide
+// blocks of 1024 columns (four 2 KiB wave rows side by side, eight rows per
+// wave) for read-only sweeps of wider ones.
+constexpr int kBTileRows = 32;
+enum BTileShape { BT_NARROW = 0, BT_WIDE = 1 };
+constexpr int kBTileCols[2] = {128, 1024};      // columns per workgroup block
+constexpr int kBTileWaveCols[2] = {128, 256};   // per wave tile: one row-dot partial each
+struct BTileEntry {     // one sweep of one instance
+    TileArgs a;
+    int32_t ops;        // OP_ROWDOT | OP_COLSUM, OP_UPD1 | OP_UPD2 | OP_COLSUM or OP_ROWDOT
+    int16_t vec;        // A (and B) 16-byte aligned with even leading dimensions
+    int16_t shape;      // BT_NARROW or BT_WIDE
+};
+struct BTileUnit {      // one workgroup of a tiled launch
+    int32_t entry, band, cblk, pad;
+};
+struct BFinishUnit {    // 64 outputs of one finish job
+    int32_t job, block;
+};
+void launch_btile(const BTileEntry *entries, const BTileUnit *units, int64_t nunits,
+                  hipStream_t st);
+void launch_bfinish(const FinishJob *jobs, const BFinishUnit *units, int64_t nunits,
+                    hipStream_t st);
+
 // Row-resident ATAX: each workgroup keeps one row of A on chip at a time.
 // Row-resident sweeps: the number of workgroups (partial column-sum
 // vectors) for a workgroup size, 0 when n is too wide or threads is 0.

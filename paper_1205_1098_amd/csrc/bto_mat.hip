@@ -155,15 +155,21 @@ __device__ __forceinline__ void tile_rows(const TileArgs &a, int64_t c0, int64_t
     }
 }
 
+// LDS of one workgroup tile: the WR row groups' column sums.
+template <int KV, int WC, int WR>
+constexpr int tile_lds_doubles() { return WR > 1 ? WR * WC * 128 * KV : 1; }
+
+// One workgroup tile: row band `band` (rows [band*rb, band*rb + rb)) and
+// column block `cblk` (WC wave tiles) of the sweep described by `a`.
 template <int KV, int D, int WC, int WR, int OPS, bool VEC>
-__global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int rev)
+__device__ __forceinline__ void tile_block(const TileArgs &a, int64_t band, int64_t cblk, int rb,
+                                           double *lds)
 {
     constexpr bool ROWDOT = OPS & OP_ROWDOT;
     constexpr bool COLSUM = OPS & OP_COLSUM;
     constexpr int CTW = 128 * KV;          // wave tile width (columns)
     constexpr int CTB = WC * CTW;          // workgroup tile width
     constexpr int NT = kWave * WC * WR;    // threads
-    __shared__ double lds[(COLSUM && WR > 1) ? WR * CTB : 1];
 
     // The wave index is uniform across the wave; saying so keeps every row
     // index scalar, so the per-row scalars (u1[i], y[i], ...) become scalar
@@ -171,8 +177,7 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wc = wave % WC, wr = wave / WC;
-    const int64_t band = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
-    const int64_t ctw = (int64_t)blockIdx.x * WC + wc;
+    const int64_t ctw = cblk * WC + wc;
     const int64_t c0 = ctw * CTW;
     const int rpw = rb / WR;
     const int64_t r0 = band * rb + (int64_t)wr * rpw;
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int 
                 lds[wr * CTB + c + 1] = acc[k].y;
             }
             lds_barrier();
-            const int64_t cb = (int64_t)blockIdx.x * CTB;
+            const int64_t cb = cblk * CTB;
             for (int c = threadIdx.x; c < CTB; c += NT) {
                 const int64_t j = cb + c;
                 if (j < a.n) {
@@ -224,6 +229,14 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int 
             }
         }
     }
+}
+
+template <int KV, int D, int WC, int WR, int OPS, bool VEC>
+__global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int rev)
+{
+    __shared__ double lds[(OPS & OP_COLSUM) ? tile_lds_doubles<KV, WC, WR>() : 1];
+    const int64_t band = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
+    tile_block<KV, D, WC, WR, OPS, VEC>(a, band, (int64_t)blockIdx.x, rb, lds);
 }
 
 // The tile shapes instantiated for each family of sweeps.
@@ -326,12 +339,8 @@ void dispatch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &
 // its lane's outputs sequentially (q = ceil(nparts/4)), then wave 0 adds
 // the four wave sums in order and applies the epilogue.
 
-__global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int64_t nb0)
+__device__ __forceinline__ void finish_block(const FinishJob &j, int64_t b, double (&lds)[4][64])
 {
-    __shared__ double lds[4][64];
-    const bool first = blockIdx.x < nb0;
-    const FinishJob &j = first ? j0 : j1;
-    const int64_t b = first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - nb0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t idx = b * 64 + lane;
     const int64_t q = (j.nparts + 3) / 4;
@@ -359,6 +368,14 @@ __global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int6
         double t = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
         j.out[idx] = j.add ? j.scale * t + j.add[idx] : j.scale * t;
     }
+}
+
+__global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int64_t nb0)
+{
+    __shared__ double lds[4][64];
+    const bool first = blockIdx.x < nb0;
+    const int64_t b = first ? (int64_t)blockIdx.x : (int64_t)blockIdx.x - nb0;
+    finish_block(first ? j0 : j1, b, lds);
 }
 
 // ---- row-resident sweeps (ATAX, BiCGK) ------------------------------------
@@ -615,7 +632,132 @@ int rowres_blocks_per_cu(const RowresShape &s, bool bicgk)
 
 constexpr int kCUs = 256;
 
+// ---- tiled batches ------------------------------------------------------------
+//
+// The sweeps of many instances in one launch: workgroup g runs unit g (a
+// sweep, a row band, a column block) with the same tile_block as k_tile.
+// Entries and units are read at a uniform index, so they come through
+// scalar loads.  Pointers read from memory are not known to address global
+// memory; accessed as they are they would compile to flat loads and stores,
+// whose completion is also counted with the scalar loads of the row
+// scalars, so that every wait for u1[i] or y[i] would also wait for the
+// wave's prefetched rows.  They are therefore recast to the global address
+// space first.
+
+template <typename T>
+__device__ __forceinline__ T *as_global(T *p)
+{
+    typedef __attribute__((address_space(1))) T gT;
+    return (T *)(gT *)(uintptr_t)p;
+}
+
+__device__ __forceinline__ void globalize(TileArgs &a)
+{
+    a.A = as_global(a.A);
+    a.B = as_global(a.B);
+    a.xr = as_global(a.xr);
+    a.yc = as_global(a.yc);
+    a.u1 = as_global(a.u1);
+    a.v1 = as_global(a.v1);
+    a.u2 = as_global(a.u2);
+    a.v2 = as_global(a.v2);
+    a.Prow = as_global(a.Prow);
+    a.Pcol = as_global(a.Pcol);
+}
+
+// the two workgroup shapes of the tiled batches: {KV, D, WC, WR}
+template <int SHAPE> struct BtShape;
+template <> struct BtShape<BT_NARROW> { static constexpr int kv = 1, d = 2, wc = 1, wr = 16; };
+template <> struct BtShape<BT_WIDE> { static constexpr int kv = 2, d = 2, wc = 4, wr = 4; };
+static_assert(BtShape<BT_NARROW>::wc * 128 * BtShape<BT_NARROW>::kv == kBTileCols[BT_NARROW], "");
+static_assert(BtShape<BT_WIDE>::wc * 128 * BtShape<BT_WIDE>::kv == kBTileCols[BT_WIDE], "");
+static_assert(kBTileRows % BtShape<BT_NARROW>::wr == 0 && kBTileRows % BtShape<BT_WIDE>::wr == 0 &&
+                  kBTileRows / BtShape<BT_WIDE>::wr <= kWave, "band height");
+
+template <int SHAPE, int OPS>
+__device__ __forceinline__ void btile_unit(const TileArgs &a, bool vec, int64_t band,
+                                           int64_t cblk, double *lds)
+{
+    typedef BtShape<SHAPE> S;
+    if (vec)
+        tile_block<S::kv, S::d, S::wc, S::wr, OPS, true>(a, band, cblk, kBTileRows, lds);
+    else
+        tile_block<S::kv, S::d, S::wc, S::wr, OPS, false>(a, band, cblk, kBTileRows, lds);
+}
+
+template <int SHAPE>
+__device__ __forceinline__ void btile_run(const BTileEntry &e, const BTileUnit &u, double *lds)
+{
+    TileArgs a = e.a;
+    globalize(a);
+    switch (e.ops) {
+    case OP_UPD1 | OP_UPD2 | OP_COLSUM:
+        if constexpr (SHAPE == BT_NARROW)
+            btile_unit<SHAPE, OP_UPD1 | OP_UPD2 | OP_COLSUM>(a, e.vec, u.band, u.cblk, lds);
+        break;
+    case OP_ROWDOT | OP_COLSUM:
+        btile_unit<SHAPE, OP_ROWDOT | OP_COLSUM>(a, e.vec, u.band, u.cblk, lds);
+        break;
+    case OP_ROWDOT:
+        btile_unit<SHAPE, OP_ROWDOT>(a, e.vec, u.band, u.cblk, lds);
+        break;
+    default:
+        break;
+    }
+}
+
+// Both shapes are 16 waves, so one launch runs units of either kind.
+static_assert(BtShape<BT_NARROW>::wc * BtShape<BT_NARROW>::wr ==
+                  BtShape<BT_WIDE>::wc * BtShape<BT_WIDE>::wr, "one workgroup size");
+constexpr int kBtThreads = kWave * BtShape<BT_WIDE>::wc * BtShape<BT_WIDE>::wr;
+constexpr int kBtLds = tile_lds_doubles<BtShape<BT_WIDE>::kv, BtShape<BT_WIDE>::wc,
+                                        BtShape<BT_WIDE>::wr>() >
+                               tile_lds_doubles<BtShape<BT_NARROW>::kv, BtShape<BT_NARROW>::wc,
+                                                BtShape<BT_NARROW>::wr>()
+                           ? tile_lds_doubles<BtShape<BT_WIDE>::kv, BtShape<BT_WIDE>::wc,
+                                              BtShape<BT_WIDE>::wr>()
+                           : tile_lds_doubles<BtShape<BT_NARROW>::kv, BtShape<BT_NARROW>::wc,
+                                              BtShape<BT_NARROW>::wr>();
+
+__global__ __launch_bounds__(kBtThreads) void k_btile(const BTileEntry *__restrict__ entries,
+                                                      const BTileUnit *__restrict__ units)
+{
+    __shared__ double lds[kBtLds];
+    const BTileUnit u = units[blockIdx.x];
+    const BTileEntry e = entries[u.entry];
+    if (e.shape == BT_WIDE)
+        btile_run<BT_WIDE>(e, u, lds);
+    else
+        btile_run<BT_NARROW>(e, u, lds);
+}
+
+__global__ __launch_bounds__(256) void k_bfinish(const FinishJob *__restrict__ jobs,
+                                                 const BFinishUnit *__restrict__ units)
+{
+    __shared__ double lds[4][64];
+    const BFinishUnit u = units[blockIdx.x];
+    FinishJob j = jobs[u.job];
+    j.P = as_global(j.P);
+    j.add = as_global(j.add);
+    j.out = as_global(j.out);
+    finish_block(j, u.block, lds);
+}
+
 }  // namespace
+
+void launch_btile(const BTileEntry *entries, const BTileUnit *units, int64_t nunits,
+                  hipStream_t st)
+{
+    if (nunits > 0)
+        launch("btile", k_btile, dim3((unsigned)nunits), dim3(kBtThreads), st, entries, units);
+}
+
+void launch_bfinish(const FinishJob *jobs, const BFinishUnit *units, int64_t nunits,
+                    hipStream_t st)
+{
+    if (nunits > 0)
+        launch("bfinish", k_bfinish, dim3((unsigned)nunits), dim3(256), st, jobs, units);
+}
 
 bool tile_cfg_supported(int ops, const TileCfg &c)
 {

@@ -130,3 +130,29 @@ def test_empty_plan_argument_checks(bto):
     assert lib.bto_batch_plan_check(None, None) == 1
     bad = bto._Config(0, 9, 0, 0)                     # more than 8 workgroups per CU
     assert lib.bto_batch_plan_create_empty(4, 0, ctypes.byref(bad), ctypes.byref(plan)) == 1
+
+
+def create_tiled(bto, descs):
+    arr = (bto.Desc * max(len(descs), 1))(*descs)
+    plan = ctypes.c_void_p()
+    return bto._lib.bto_tiled_batch_create(ctypes.byref(arr), len(descs), 0, ctypes.byref(plan))
+
+
+def test_tiled_batch_validation(bto):
+    """The tiled form takes fused GEMVER and BiCGK only, and checks instances
+    as the persistent plan does, before any device work."""
+    assert bto._lib.bto_tiled_batch_create(None, 0, 0, None) == 1          # plan is NULL
+    assert create_tiled(bto, [desc(bto, "atax", 10, 100, 100, FAKE)]) == 5
+    un = desc(bto, "gemver", 10, 100, 100, FAKE)
+    un.form = 1
+    assert create_tiled(bto, [un]) == 5
+    assert create_tiled(bto, [desc(bto, "gemver", 10, 2049, 2050, FAKE)]) == 5
+    assert create_tiled(bto, [desc(bto, "bicgk", 10, 100, 101, FAKE)]) == 1
+    a = desc(bto, "bicgk", 10, 100, 100, FAKE)
+    b = desc(bto, "bicgk", 10, 100, 100, FAKE + 1024 * MB)
+    b.out[0] = a.out[0]
+    assert create_tiled(bto, [a, b]) == 2
+    plan = ctypes.c_void_p()
+    assert bto._lib.bto_tiled_batch_create(None, -1, 0, ctypes.byref(plan)) == 1
+    assert bto._lib.bto_tiled_batch_launch(None, None) == 1
+    assert bto._lib.bto_tiled_batch_destroy(None) == 0

@@ -250,3 +250,123 @@ def test_tiled_instances(env, split):
                 assert all(torch.equal(a, b) for a, b in zip(first, cur)), (threads, wgs, rep)
         check_all(torch, insts, specs, exact=False)
         plan.close()
+
+
+# ---- tiled batches -----------------------------------------------------------------
+
+TILED_WEIGHTS = {"gemver": 0.5, "bicgk": 0.5}
+
+
+def _outputs(insts):
+    return [t.clone() for inst in insts for t in inst["out"]] + \
+        [inst["B"].clone() for inst in insts if "B" in inst]
+
+
+def _poison(insts):
+    for inst in insts:
+        for t in inst["out"]:
+            t.fill_(float("nan"))
+        if "B" in inst and inst["B"].data_ptr() != inst["A"].data_ptr():
+            inst["B"].fill_(float("nan"))
+
+
+@pytest.mark.parametrize("data", ["uniform", "int"])
+def test_tiled_batch_matches_oracle(env, data):
+    """Random sizes and the shapes around every tile edge (32-row bands,
+    128-column blocks, odd n, one row, one column)."""
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 120, 64, 2048, TILED_WEIGHTS, seed=31,
+                                        data=data, config=30)
+    shapes = [(1, 1), (1, 2048), (2, 2), (31, 127), (32, 128), (33, 129), (64, 255), (65, 257),
+              (300, 130), (5000, 3), (4097, 1), (129, 2047), (2048, 2048), (3, 1025)]
+    for k, kind in enumerate(TILED_WEIGHTS):
+        i, sp = batch.make_instances(torch, bto, len(shapes), 1, 2, {kind: 1.0}, seed=32,
+                                     config=31 + k, data=data, shapes=shapes)
+        insts += i
+        specs += sp
+    _poison(insts)
+    plan = bto.TiledBatch(insts)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=(data == "int"))
+    plan.close()
+
+
+def test_tiled_batch_in_place_and_empty(env):
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 30, 64, 1500, {"gemver": 1.0}, seed=33,
+                                        in_place=True, config=33)
+    plan = bto.TiledBatch(insts, use_graph=False)
+    plan.launch()
+    torch.cuda.synchronize()
+    check_all(torch, insts, specs, exact=False)
+    plan.close()
+    # no rows or no columns: x = z and w = 0 for GEMVER, s = 0 for BiCGK
+    dev = "cuda:0"
+    z = torch.arange(5, dtype=torch.float64, device=dev) + 1.0
+    empty_rows = {"kind": "gemver", "form": "fused", "A": torch.empty((0, 5), dtype=torch.float64,
+                                                                        device=dev),
+                  "B": torch.empty((0, 5), dtype=torch.float64, device=dev),
+                  "in": [torch.empty(0, dtype=torch.float64, device=dev), torch.ones(5, dtype=torch.float64, device=dev),
+                         torch.empty(0, dtype=torch.float64, device=dev), torch.ones(5, dtype=torch.float64, device=dev),
+                         torch.empty(0, dtype=torch.float64, device=dev), z],
+                  "out": [torch.full((5,), float("nan"), dtype=torch.float64, device=dev),
+                          torch.empty(0, dtype=torch.float64, device=dev)], "alpha": 2.0, "beta": 3.0}
+    no_cols = {"kind": "bicgk", "form": "fused",
+               "A": torch.empty((4, 2), dtype=torch.float64, device=dev)[:, :0],
+               "in": [torch.empty(0, dtype=torch.float64, device=dev), torch.ones(4, dtype=torch.float64, device=dev)],
+               "out": [torch.full((4,), float("nan"), dtype=torch.float64, device=dev),
+                       torch.empty(0, dtype=torch.float64, device=dev)]}
+    plan = bto.TiledBatch([empty_rows, no_cols])
+    plan.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(empty_rows["out"][0], z)
+    assert torch.equal(no_cols["out"][0], torch.zeros(4, dtype=torch.float64, device=dev))
+    plan.close()
+
+
+def test_tiled_batch_replays_and_independent_of_the_mix(env):
+    """Graph replays and direct launches give the same bits; an instance gives
+    the same bits alone as among 200 others."""
+    torch, bto = env
+    insts, specs = batch.make_instances(torch, bto, 200, 64, 2048, TILED_WEIGHTS, seed=34,
+                                        config=34)
+    first = None
+    for graph in (True, False):
+        plan = bto.TiledBatch(insts, use_graph=graph)
+        for rep in range(3):
+            _poison(insts)
+            plan.launch()
+            torch.cuda.synchronize()
+            cur = _outputs(insts)
+            first = first or cur
+            assert all(torch.equal(a, b) for a, b in zip(first, cur)), (graph, rep)
+        plan.close()
+    check_all(torch, insts, specs, exact=False)
+    for k in (0, 7, 199):
+        alone = [insts[k]]
+        _poison(alone)
+        plan = bto.TiledBatch(alone)
+        plan.launch()
+        torch.cuda.synchronize()
+        mine = [t for t in insts[k]["out"]]
+        lo = sum(len(insts[j]["out"]) for j in range(k))
+        assert all(torch.equal(a, b) for a, b in zip(mine, first[lo:lo + len(mine)]))
+        plan.close()
+
+
+def test_tiled_batch_refuses_other_work(env):
+    torch, bto = env
+    at, _ = batch.make_instances(torch, bto, 2, 64, 128, {"atax": 1.0}, seed=35)
+    with pytest.raises(bto.BtoError) as e:
+        bto.TiledBatch(at)
+    assert e.value.status == 5
+    un, _ = batch.make_instances(torch, bto, 2, 64, 128, {"gemver": 1.0}, seed=35,
+                                 form="unfused")
+    with pytest.raises(bto.BtoError):
+        bto.TiledBatch(un)
+    ov, _ = batch.make_instances(torch, bto, 3, 64, 128, {"bicgk": 1.0}, seed=36)
+    ov[1]["out"][0] = ov[0]["out"][0]
+    with pytest.raises(bto.BtoError) as e:
+        bto.TiledBatch(ov)
+    assert e.value.status == 2
