@@ -196,8 +196,20 @@ __global__ __launch_bounds__(kFinishBlock) void k_dot_finish(int64_t nparts,
                                                              const double *parts, double *r)
 {
     __shared__ double lds[kFinishBlock / kWave];
+    // thread t adds parts t, t + T, t + 2T, ... in that order; eight loads
+    // are issued before their sums so that they are in flight together
     double s = 0.0;
-    for (int64_t k = threadIdx.x; k < nparts; k += kFinishBlock)
+    int64_t k = threadIdx.x;
+    for (; k + 7 * kFinishBlock < nparts; k += 8 * kFinishBlock) {
+        double t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            t[e] = parts[k + e * kFinishBlock];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            s += t[e];
+    }
+    for (; k < nparts; k += kFinishBlock)
         s += parts[k];
     s = block_sum(s, lds, kFinishBlock / kWave);
     if (threadIdx.x == 0)
