@@ -1646,7 +1646,7 @@ bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int us
         !upload(&p->d_units, img.units[0], img.units[1]) ||
         !upload(&p->d_jobs, img.jobs1, img.jobs2) || !upload(&p->d_funits, f1, f2))
         return hip_fail("device table");
-    if (use_graph) {
+    if (use_graph && p->units[0] + p->units[1] + p->fin1 + p->fin2 > 0) {
         if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
             return hip_fail("hipStreamCreate");
         if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)

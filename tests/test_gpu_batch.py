@@ -323,6 +323,11 @@ def test_tiled_batch_in_place_and_empty(env):
     assert torch.equal(empty_rows["out"][0], z)
     assert torch.equal(no_cols["out"][0], torch.zeros(4, dtype=torch.float64, device=dev))
     plan.close()
+    for graph in (True, False):          # no instances at all: launches nothing
+        plan = bto.TiledBatch([], use_graph=graph)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.close()
 
 
 def test_tiled_batch_replays_and_independent_of_the_mix(env):
