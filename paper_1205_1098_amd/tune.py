@@ -296,7 +296,9 @@ def bucket_evaluator(single, groups: dict):
 
 #: the batch plan's knobs and the values searched (the first is the library default)
 BATCH_SPACE = {
-    "form": ["fused", "unfused"],               # fuse-or-split of every instance
+    # fuse-or-split of every instance; "tiled": fused, as short-lived tiles
+    # (bto_tiled_batch), to which the persistent plan's knobs below do not apply
+    "form": ["fused", "unfused", "tiled"],
     "threads": [256, 512],                      # workgroup size
     "wgs_per_cu": [2, 1, 3, 4],                 # persistent workgroups per CU ("threads")
     "split_bytes": [16 << 20, -1, 8 << 20, 32 << 20, 4 << 20],   # row tiles of large instances
@@ -320,6 +322,8 @@ def tune_batch(evaluate, space: dict | None = None, cache: dict | None = None) -
 
     best = {k: v[0] for k, v in space.items()}
     for knob in space:                        # "form" first: fusion before geometry
+        if knob != "form" and best.get("form") == "tiled":
+            continue                          # the persistent plan's knobs
         for val in space[knob]:
             trial = {**best, knob: val}
             if fit(trial) < fit(best):
@@ -540,10 +544,14 @@ def _tune_batch_main(torch, bto, args) -> int:
             sets.clear()
             torch.cuda.empty_cache()
             sets[form] = batch.make_instances(torch, bto, 4096, 64, 2048,
-                                              {"gemver": 0.5, "bicgk": 0.5}, form=form)
+                                              {"gemver": 0.5, "bicgk": 0.5},
+                                              form="fused" if form == "tiled" else form)
         insts, _ = sets[form]
-        plan = bto.BatchPlan(insts, threads=cfg["threads"], wgs_per_cu=cfg["wgs_per_cu"],
-                             split_bytes=cfg["split_bytes"])
+        if form == "tiled":
+            plan = bto.TiledBatch(insts)
+        else:
+            plan = bto.BatchPlan(insts, threads=cfg["threads"], wgs_per_cu=cfg["wgs_per_cu"],
+                                 split_bytes=cfg["split_bytes"])
         for _ in range(2):
             plan.launch()
         torch.cuda.synchronize()

@@ -297,3 +297,17 @@ def test_space_from_library_keeps_every_bucket():
     assert lib.cfg == before
     assert sorted(sp.kv) == list(range(FakeBto.NSHAPES))
     assert all(sp.legal[s] for s in range(FakeBto.NSLOTS))
+
+
+def test_batch_knobs_tiled_form_skips_plan_knobs():
+    """When the tiled form wins, the persistent plan's knobs (which it does
+    not use) are not searched."""
+    calls = []
+
+    def ev(cfg):
+        calls.append(cfg)
+        return {"fused": 1.0, "unfused": 2.0, "tiled": 0.9}[cfg["form"]]
+
+    best, sec, evals = tune.tune_batch(ev)
+    assert best["form"] == "tiled" and sec == pytest.approx(0.9)
+    assert evals == len(tune.BATCH_SPACE["form"])
