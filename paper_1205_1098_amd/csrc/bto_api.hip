@@ -1492,6 +1492,7 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
     };
     // read-only sweeps of wider matrices take the wide blocks
     auto read_shape = [](int64_t n) { return n > 512 ? BT_WIDE : BT_NARROW; };
+    int64_t fin_blocks = 0;   // an upper bound on the finish units of both sweeps
     for (int i : order) {
         const BatchItem &it = items[i];
         const int64_t m = it.m, n = it.n;
@@ -1501,6 +1502,17 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
         const int64_t nc = some ? ceil_div(n, (int64_t)kBTileCols[rs]) : 0;   // read sweeps
         const int64_t nwt = some ? ceil_div(n, (int64_t)kBTileWaveCols[rs]) : 0;   // their row-dot parts
         const int64_t ncw = some ? ceil_div(n, (int64_t)kBTileCols[BT_NARROW]) : 0;
+        // every launch indexes its units, and every finish its 64-output
+        // blocks, with an int: refuse before building lists that large
+        const int64_t first = nb * (it.kind == BTO_K_GEMVER ? ncw : nc);
+        const int64_t second = it.kind == BTO_K_GEMVER ? nb * nc : 0;
+        if ((int64_t)img.units[0].size() + first > INT_MAX ||
+            (int64_t)img.units[1].size() + second > INT_MAX)
+            return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch");
+        const int64_t blocks = 2 * ceil_div(m > n ? m : n, (int64_t)64);
+        fin_blocks += blocks;
+        if (fin_blocks > INT_MAX)
+            return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
         const bool rows16 = it.lda % 2 == 0 || m <= 1;
         BTileEntry e{};
         e.a.m = m;
@@ -1557,9 +1569,6 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
             img.jobs1.push_back({pcol, nb, n, it.beta, it.vec[5], it.out[0]});
             img.jobs2.push_back({prow, nwt, m, it.alpha, nullptr, it.out[1]});
         }
-        for (auto &list : img.units)
-            if ((int64_t)list.size() > INT_MAX)
-                return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch");
         if ((int64_t)img.entries.size() > INT_MAX)
             return fail(BTO_ERR_UNSUPPORTED, "too many instances for one launch");
     }

@@ -156,3 +156,22 @@ def test_tiled_batch_validation(bto):
     assert bto._lib.bto_tiled_batch_create(None, -1, 0, ctypes.byref(plan)) == 1
     assert bto._lib.bto_tiled_batch_launch(None, None) == 1
     assert bto._lib.bto_tiled_batch_destroy(None) == 0
+
+
+def test_tiled_batch_refuses_more_tiles_than_a_launch_indexes(bto):
+    """An instance whose tiles would not fit an int launch index is refused
+    before any list is built (fake, non-overlapping addresses)."""
+    m, n = 1 << 40, 2048
+    d = bto.Desc()
+    d.kind = bto.KERNELS["gemver"]
+    d.form = 0
+    d.m, d.n, d.lda, d.ldb = m, n, n, n
+    d.alpha, d.beta = 1.5, 0.7
+    d.A = 1 << 40
+    d.B = 1 << 56
+    for k in range(6):
+        d.inp[k] = (1 << 57) + k * (1 << 45)
+    for k in range(2):
+        d.out[k] = (1 << 58) + k * (1 << 45)
+    assert create_tiled(bto, [d]) == 5
+    assert "tiles" in bto._lib.bto_last_error().decode()
