@@ -5,6 +5,7 @@
 #include <climits>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -206,6 +207,20 @@ bto_status check_ws(void *ws, size_t have, size_t needed)
     if (needed > 0 && (reinterpret_cast<uintptr_t>(ws) & 255u))
         return fail(BTO_ERR_INVALID_ARG, "ws is not 256-byte aligned");
     return BTO_SUCCESS;
+}
+
+// Host containers throw std::bad_alloc when memory runs out; no exception
+// may cross the C boundary, so the plan builders report it as a status.
+template <typename F>
+bto_status host_guard(F &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(BTO_ERR_UNSUPPORTED, "out of host memory while building the plan");
+    } catch (...) {
+        return fail(BTO_ERR_UNSUPPORTED, "host error while building the plan");
+    }
 }
 
 bto_status check_launch()
@@ -1313,59 +1328,65 @@ int64_t bto_batch_scratch_doubles(const bto_batch_desc *descs, int count,
 bto_status bto_batch_plan_create(const bto_batch_desc *descs, int count,
                                  const bto_batch_config *config, bto_batch_plan **plan)
 {
-    t_error.clear();
-    if (!plan)
-        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
-    *plan = nullptr;
-    std::vector<BatchItem> items;
-    std::vector<BatchUnit> units;
-    int64_t scratch = 0;
-    BTO_TRY(plan_image(descs, count, split_of(config), items, units, scratch));
-    bto_batch_plan *p = nullptr;
-    BTO_TRY(plan_alloc(count, (int)units.size(), scratch, config, &p));
-    bto_status s = plan_store(p, items, units, p->cap ? p->cap : nullptr);
-    if (s == BTO_SUCCESS && hipEventSynchronize(p->staged) != hipSuccess)
-        s = fail(BTO_ERR_HIP, "hipEventSynchronize");
-    if (s != BTO_SUCCESS) {
-        plan_free(p);
-        return s;
-    }
-    *plan = p;
-    return BTO_SUCCESS;
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        *plan = nullptr;
+        std::vector<BatchItem> items;
+        std::vector<BatchUnit> units;
+        int64_t scratch = 0;
+        BTO_TRY(plan_image(descs, count, split_of(config), items, units, scratch));
+        bto_batch_plan *p = nullptr;
+        BTO_TRY(plan_alloc(count, (int)units.size(), scratch, config, &p));
+        bto_status s = plan_store(p, items, units, p->cap ? p->cap : nullptr);
+        if (s == BTO_SUCCESS && hipEventSynchronize(p->staged) != hipSuccess)
+            s = fail(BTO_ERR_HIP, "hipEventSynchronize");
+        if (s != BTO_SUCCESS) {
+            plan_free(p);
+            return s;
+        }
+        *plan = p;
+        return BTO_SUCCESS;
+    });
 }
 
 bto_status bto_batch_plan_create_empty(int capacity, int64_t scratch_doubles,
                                        const bto_batch_config *config, bto_batch_plan **plan)
 {
-    t_error.clear();
-    if (!plan)
-        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
-    *plan = nullptr;
-    // the unit queue holds up to kUnitsPerItem units per instance (an int)
-    if (capacity < 0 || capacity > INT_MAX / kUnitsPerItem)
-        return fail(BTO_ERR_INVALID_ARG, "capacity out of range");
-    return plan_alloc(capacity, capacity * kUnitsPerItem, scratch_doubles, config, plan);
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        *plan = nullptr;
+        // the unit queue holds up to kUnitsPerItem units per instance (an int)
+        if (capacity < 0 || capacity > INT_MAX / kUnitsPerItem)
+            return fail(BTO_ERR_INVALID_ARG, "capacity out of range");
+        return plan_alloc(capacity, capacity * kUnitsPerItem, scratch_doubles, config, plan);
+    });
 }
 
 bto_status bto_batch_plan_reset(bto_batch_plan *plan, const bto_batch_desc *descs, int count,
                                 hipStream_t stream)
 {
-    t_error.clear();
-    if (!plan)
-        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
-    if (count > plan->capacity)
-        return fail(BTO_ERR_INVALID_ARG, "more instances than the plan's capacity");
-    std::vector<BatchItem> items;
-    std::vector<BatchUnit> units;
-    int64_t scratch = 0;
-    BTO_TRY(plan_image(descs, count, plan->split_bytes, items, units, scratch));
-    if (scratch > plan->scratch_cap)
-        return fail(BTO_ERR_WORKSPACE, "the instances need " + std::to_string(scratch) +
-                                           " doubles of scratch, the plan has " +
-                                           std::to_string(plan->scratch_cap));
-    if ((int64_t)units.size() > plan->unit_capacity)
-        return fail(BTO_ERR_INVALID_ARG, "more work units than the plan can queue");
-    return plan_store(plan, items, units, stream);
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        if (count > plan->capacity)
+            return fail(BTO_ERR_INVALID_ARG, "more instances than the plan's capacity");
+        std::vector<BatchItem> items;
+        std::vector<BatchUnit> units;
+        int64_t scratch = 0;
+        BTO_TRY(plan_image(descs, count, plan->split_bytes, items, units, scratch));
+        if (scratch > plan->scratch_cap)
+            return fail(BTO_ERR_WORKSPACE, "the instances need " + std::to_string(scratch) +
+                                               " doubles of scratch, the plan has " +
+                                               std::to_string(plan->scratch_cap));
+        if ((int64_t)units.size() > plan->unit_capacity)
+            return fail(BTO_ERR_INVALID_ARG, "more work units than the plan can queue");
+        return plan_store(plan, items, units, stream);
+    });
 }
 
 bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream)
@@ -1614,62 +1635,65 @@ extern "C" {
 bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int use_graph,
                                   bto_tiled_batch **plan)
 {
-    t_error.clear();
-    if (!plan)
-        return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
-    *plan = nullptr;
-    TiledImage img;
-    BTO_TRY(tiled_image(descs, count, img));
-    bto_tiled_batch *p = new bto_tiled_batch();
-    auto hip_fail = [&](const char *what) {
-        tiled_free(p);
-        return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
-    };
-    if (hipMalloc(&p->d_scratch, sizeof(double) * (size_t)(img.scratch > 0 ? img.scratch : 1)) !=
-        hipSuccess)
-        return hip_fail("hipMalloc");
-    // rebase the partial-sum offsets onto the scratch area
-    const uintptr_t base = reinterpret_cast<uintptr_t>(p->d_scratch);
-    auto rebase = [&](double *&q) {
-        if (q) q = reinterpret_cast<double *>(base + reinterpret_cast<uintptr_t>(q));
-    };
-    for (BTileEntry &e : img.entries) {
-        rebase(e.a.Prow);
-        rebase(e.a.Pcol);
-    }
-    for (auto *jobs : {&img.jobs1, &img.jobs2})
-        for (FinishJob &j : *jobs)
-            j.P = reinterpret_cast<const double *>(base + reinterpret_cast<uintptr_t>(j.P));
-    const std::vector<BFinishUnit> f1 = finish_units(img.jobs1, 0);
-    const std::vector<BFinishUnit> f2 = finish_units(img.jobs2, (int)img.jobs1.size());
-    p->units[0] = (int64_t)img.units[0].size();
-    p->units[1] = (int64_t)img.units[1].size();
-    p->fin1 = (int64_t)f1.size();
-    p->fin2 = (int64_t)f2.size();
-    if (p->fin1 > INT_MAX || p->fin2 > INT_MAX) {
-        tiled_free(p);
-        return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
-    }
-    const std::vector<BTileEntry> none_e;
-    if (!upload(&p->d_entries, img.entries, none_e) ||
-        !upload(&p->d_units, img.units[0], img.units[1]) ||
-        !upload(&p->d_jobs, img.jobs1, img.jobs2) || !upload(&p->d_funits, f1, f2))
-        return hip_fail("device table");
-    if (use_graph && p->units[0] + p->units[1] + p->fin1 + p->fin2 > 0) {
-        if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
-            return hip_fail("hipStreamCreate");
-        if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-            return hip_fail("hipStreamBeginCapture");
-        t_capturing = true;
-        tiled_enqueue(p, p->cap);
-        t_capturing = false;
-        if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
-            return hip_fail("hipStreamEndCapture");
-        if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-            return hip_fail("hipGraphInstantiate");
-    }
-    *plan = p;
-    return BTO_SUCCESS;
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        *plan = nullptr;
+        TiledImage img;
+        BTO_TRY(tiled_image(descs, count, img));
+        // every host list is built before the plan owns device memory
+        std::vector<BFinishUnit> f1 = finish_units(img.jobs1, 0);
+        std::vector<BFinishUnit> f2 = finish_units(img.jobs2, (int)img.jobs1.size());
+        bto_tiled_batch *p = new bto_tiled_batch();
+        auto hip_fail = [&](const char *what) {
+            tiled_free(p);
+            return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
+        };
+        if (hipMalloc(&p->d_scratch, sizeof(double) * (size_t)(img.scratch > 0 ? img.scratch : 1)) !=
+            hipSuccess)
+            return hip_fail("hipMalloc");
+        // rebase the partial-sum offsets onto the scratch area
+        const uintptr_t base = reinterpret_cast<uintptr_t>(p->d_scratch);
+        auto rebase = [&](double *&q) {
+            if (q) q = reinterpret_cast<double *>(base + reinterpret_cast<uintptr_t>(q));
+        };
+        for (BTileEntry &e : img.entries) {
+            rebase(e.a.Prow);
+            rebase(e.a.Pcol);
+        }
+        for (auto *jobs : {&img.jobs1, &img.jobs2})
+            for (FinishJob &j : *jobs)
+                j.P = reinterpret_cast<const double *>(base + reinterpret_cast<uintptr_t>(j.P));
+        p->units[0] = (int64_t)img.units[0].size();
+        p->units[1] = (int64_t)img.units[1].size();
+        p->fin1 = (int64_t)f1.size();
+        p->fin2 = (int64_t)f2.size();
+        if (p->fin1 > INT_MAX || p->fin2 > INT_MAX) {
+            tiled_free(p);
+            return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
+        }
+        const std::vector<BTileEntry> none_e;
+        if (!upload(&p->d_entries, img.entries, none_e) ||
+            !upload(&p->d_units, img.units[0], img.units[1]) ||
+            !upload(&p->d_jobs, img.jobs1, img.jobs2) || !upload(&p->d_funits, f1, f2))
+            return hip_fail("device table");
+        if (use_graph && p->units[0] + p->units[1] + p->fin1 + p->fin2 > 0) {
+            if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+                return hip_fail("hipStreamCreate");
+            if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+                return hip_fail("hipStreamBeginCapture");
+            t_capturing = true;
+            tiled_enqueue(p, p->cap);
+            t_capturing = false;
+            if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
+                return hip_fail("hipStreamEndCapture");
+            if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+                return hip_fail("hipGraphInstantiate");
+        }
+        *plan = p;
+        return BTO_SUCCESS;
+    });
 }
 
 bto_status bto_tiled_batch_launch(bto_tiled_batch *plan, hipStream_t stream)
