@@ -14,10 +14,16 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
               counter summary for the current kernel source is committed
   suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26
   stream      measured copy / read / triad ceilings at 2 GiB per array
+  batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
+              one persistent graph-captured launch, and the same instances as
+              a tiled batch (four graph-captured launches of short-lived tiles)
+  serving     Poisson and saturated request streams through the server
+              (req/s, p50 / p99 latency), continuous batching against FIFO
   cpu_baseline  the CPU oracle timed on the host cores on the same workload
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload gemver|bicgk|...]
-       [--no-suite] [--no-cpu] [--no-stream]
+       [--no-suite] [--no-cpu] [--no-stream] [--no-batch] [--no-serve]
+       [--batch-direct] [--no-batch-loop] [--copy-probe]
 """
 
 from __future__ import annotations
