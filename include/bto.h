@@ -88,6 +88,8 @@ typedef enum {
     BTO_K_AXPYDOT = 4,
     BTO_K_WAXPBY = 5,
     BTO_K_VADD = 6,
+    BTO_K_GEMVER_CONTRACTED = 7,   /* GEMVER without B (bto_gemver_contracted) */
+    BTO_K_BATAX = 8,               /* y <- beta A^T A x (bto_batax) */
     BTO_KERNEL_RANGE_MIN_ = -2147483647 - 1,
     BTO_KERNEL_RANGE_MAX_ = 2147483647
 } bto_kernel;
@@ -128,6 +130,30 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta,
                       const double *y, const double *z,
                       double *B, int64_t ldb, double *x, double *w,
                       void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* GEMVER with its B contracted away: the same x and w as bto_gemver, for
+ * a caller that does not need B.  Contracting a temporary that only feeds
+ * the later statements is the heuristic of Section III-E; here it turns
+ * B's store and re-read into two reads of A:
+ *   x <- beta (A^T y + v1 (u1.y) + v2 (u2.y)) + z
+ *   w <- alpha (A x + u1 (v1.x) + u2 (v2.x))              (new x)
+ * which equal beta B^T y + z and alpha B x for B = A + u1 v1^T + u2 v2^T
+ * (up to rounding order).  Shapes as bto_gemver; there is no unfused form
+ * (the unfused GEMVER must materialize B).  Pass 1 forms A^T y's partial
+ * sums and the two dots with y in one sweep of A, pass 2 A x's partial
+ * sums and the dots with x; each finish adds its rank-2 correction. */
+bto_status bto_gemver_contracted(int64_t m, int64_t n, double alpha, double beta,
+                                 const double *A, int64_t lda,
+                                 const double *u1, const double *v1,
+                                 const double *u2, const double *v2,
+                                 const double *y, const double *z, double *x, double *w,
+                                 void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* BATAX:  y <- beta A^T A x, ATAX with its result scaled (the scale is
+ * applied after the reduction).  Arguments and forms as bto_atax. */
+bto_status bto_batax(int64_t m, int64_t n, double beta, const double *A, int64_t lda,
+                     const double *x, double *y,
+                     void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
 
 /* ATAX (Table I):  y <- A^T A x.  A: m x n (lda); x, y: n.
  * Fused: each row of A is read once and kept on chip while its dot with x

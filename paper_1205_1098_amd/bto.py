@@ -32,7 +32,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 FUSED, UNFUSED = 0, 1
 FORMS = {"fused": FUSED, "unfused": UNFUSED}
-KERNELS = {"bicgk": 0, "gemver": 1, "atax": 2, "dgemvt": 3, "axpydot": 4, "waxpby": 5, "vadd": 6}
+KERNELS = {"bicgk": 0, "gemver": 1, "atax": 2, "dgemvt": 3, "axpydot": 4, "waxpby": 5, "vadd": 6,
+           "gemver_contracted": 7, "batax": 8}
 STATUS = {0: "success", 1: "invalid argument", 2: "illegal operand overlap",
           3: "workspace too small", 4: "HIP error", 5: "unsupported"}
 
@@ -48,6 +49,9 @@ _SIGS = {
     "bto_gemver": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr,
                     _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_atax": ([_i64, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_batax": ([_i64, _i64, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_gemver_contracted": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr,
+                               _ptr, _ptr, _ptr, _ptr, _sz, _ptr], _int),
     "bto_dgemvt": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz,
                     _int, _ptr], _int),
     "bto_axpydot": ([_i64, _dbl, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
@@ -246,6 +250,42 @@ def gemver(A, u1, v1, u2, v2, y, z, alpha, beta, form="fused", B=None, x=None, w
                                _ptr_of(B), ldb, _ptr_of(x), _ptr_of(w), _ptr_of(ws), wsb, f,
                                _stream(dev)))
     return B, x, w
+
+
+def gemver_contracted(A, u1, v1, u2, v2, y, z, alpha, beta, x=None, w=None, ws=None):
+    """GEMVER's x and w with B = A + u1 v1^T + u2 v2^T never stored.
+    Returns (x, w)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    x = _empty(n, dev) if x is None else x
+    w = _empty(m, dev) if w is None else w
+    for t, nm in ((u1, "u1"), (v1, "v1"), (u2, "u2"), (v2, "v2"), (y, "y"), (z, "z"),
+                  (x, "x"), (w, "w")):
+        _check_vec(t, nm, dev)
+    ws, wsb = _ws("gemver_contracted", m, n, 0, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_gemver_contracted(m, n, float(alpha), float(beta), _ptr_of(A), lda,
+                                          _ptr_of(u1), _ptr_of(v1), _ptr_of(u2), _ptr_of(v2),
+                                          _ptr_of(y), _ptr_of(z), _ptr_of(x), _ptr_of(w),
+                                          _ptr_of(ws), wsb, _stream(dev)))
+    return x, w
+
+
+def batax(A, x, beta, form="fused", y=None, ws=None):
+    """y = beta A^T (A x)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    y = _empty(n, dev) if y is None else y
+    _check_vec(x, "x", dev)
+    _check_vec(y, "y", dev)
+    f = _form(form)
+    ws, wsb = _ws("batax", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_batax(m, n, float(beta), _ptr_of(A), lda, _ptr_of(x), _ptr_of(y),
+                              _ptr_of(ws), wsb, f, _stream(dev)))
+    return y
 
 
 def atax(A, x, form="fused", y=None, ws=None):

@@ -82,6 +82,11 @@ size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
     case BTO_K_GEMVER:
     case BTO_K_DGEMVT:
         return bytes_rowparts(m, n) + bytes_colparts(m, n);
+    case BTO_K_GEMVER_CONTRACTED:
+        // the tile partials, then the two passes' auxiliary dot parts
+        return bytes_rowparts(m, n) + bytes_colparts(m, n) + bytes_vec(2 * max_nbands(m)) +
+               bytes_vec(2 * max_ncols(n));
+    case BTO_K_BATAX:
     case BTO_K_ATAX: {
         size_t split = bytes_vec(m) + bytes_rowparts(m, n) + bytes_colparts(m, n);
         if (f == BTO_UNFUSED)
@@ -525,15 +530,18 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
 
 // ---- ATAX --------------------------------------------------------------------
 
-bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
-                    double *y, void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+namespace {
+
+// y = scale * A^T (A x): ATAX (scale 1) and BATAX
+bto_status atax_scaled(bto_kernel kind, int64_t m, int64_t n, double scale, const double *A,
+                       int64_t lda, const double *x, double *y, void *ws, size_t ws_bytes_,
+                       bto_form form, hipStream_t st)
 {
-    t_error.clear();
     BTO_TRY(check_form(form));
     BTO_TRY(check_matrix(m, n, A, lda, "A"));
     BTO_TRY(check_vec(x, n, "x"));
     BTO_TRY(check_vec(y, n, "y"));
-    const size_t need_ws = ws_bytes(BTO_K_ATAX, m, n, form);
+    const size_t need_ws = ws_bytes(kind, m, n, form);
     BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
     BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("x", x, n, false),
                            vspan("y", y, n, true), wspan(ws, need_ws)},
@@ -545,14 +553,94 @@ bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const do
     if (G > 0) {
         double *P = cv.take(G * n);
         launch_atax_rowres(m, n, A, lda, x, P, threads, st);
-        launch_finish("finish", fjob(P, G, n, 1.0, nullptr, y), kNoJob, st);
+        launch_finish("finish", fjob(P, G, n, scale, nullptr, y), kNoJob, st);
     } else {
         double *t = cv.take(m);
         double *Prow = cv.take(max_ncols(n) * m);
         double *Pcol = cv.take(max_nbands(m) * n);
         BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, A, lda, x, 1.0, t, Prow, st));
-        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, t, 1.0, nullptr, y, Pcol, st));
+        BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, t, scale, nullptr, y, Pcol, st));
     }
+    return check_launch();
+}
+
+}  // namespace
+
+bto_status bto_atax(int64_t m, int64_t n, const double *A, int64_t lda, const double *x,
+                    double *y, void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    return atax_scaled(BTO_K_ATAX, m, n, 1.0, A, lda, x, y, ws, ws_bytes_, form, st);
+}
+
+bto_status bto_batax(int64_t m, int64_t n, double beta, const double *A, int64_t lda,
+                     const double *x, double *y, void *ws, size_t ws_bytes_, bto_form form,
+                     hipStream_t st)
+{
+    t_error.clear();
+    return atax_scaled(BTO_K_BATAX, m, n, beta, A, lda, x, y, ws, ws_bytes_, form, st);
+}
+
+// ---- GEMVER with B contracted ---------------------------------------------------
+
+bto_status bto_gemver_contracted(int64_t m, int64_t n, double alpha, double beta,
+                                 const double *A, int64_t lda, const double *u1,
+                                 const double *v1, const double *u2, const double *v2,
+                                 const double *y, const double *z, double *x, double *w,
+                                 void *ws, size_t ws_bytes_, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_vec(u1, m, "u1"));
+    BTO_TRY(check_vec(v1, n, "v1"));
+    BTO_TRY(check_vec(u2, m, "u2"));
+    BTO_TRY(check_vec(v2, n, "v2"));
+    BTO_TRY(check_vec(y, m, "y"));
+    BTO_TRY(check_vec(z, n, "z"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(w, m, "w"));
+    const size_t need_ws = ws_bytes(BTO_K_GEMVER_CONTRACTED, m, n, BTO_FUSED);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("u1", u1, m, false),
+                           vspan("v1", v1, n, false), vspan("u2", u2, m, false),
+                           vspan("v2", v2, n, false), vspan("y", y, m, false),
+                           vspan("z", z, n, false), vspan("x", x, n, true),
+                           vspan("w", w, m, true), wspan(ws, need_ws)},
+                          {}));
+
+    Carve cv(ws);
+    double *Prow = cv.take(max_ncols(n) * m);
+    double *Pcol = cv.take(max_nbands(m) * n);
+    double *aux1 = cv.take(2 * max_nbands(m));   // u1.y, u2.y per row band
+    double *aux2 = cv.take(2 * max_ncols(n));    // v1.x, v2.x per wave tile
+
+    // pass 1: A^T y per band, and the band's u1.y and u2.y
+    const TileCfg c1 = cfg_of(SLOT_DGEMVT_P1, m, n);
+    TileArgs a1 = targs(m, n, A, lda);
+    a1.yc = y;
+    a1.u1 = u1;
+    a1.u2 = u2;
+    a1.Pcol = Pcol;
+    a1.Prow = aux1;
+    if (!launch_tile(kSlotNames[SLOT_DGEMVT_P1], OP_COLSUM | OP_AUX, c1, a1, st))
+        return unsupported(SLOT_DGEMVT_P1);
+    const int64_t nb = m > 0 ? tile_nbands(c1, m) : 0;
+    launch_finish_aux("finish", {fjob(Pcol, nb, n, beta, z, x), aux1, n > 0 ? nb : 0, v1, v2},
+                      st);
+
+    // pass 2: A x per wave tile, and the tile's v1.x and v2.x
+    const TileCfg c2 = cfg_of(SLOT_DGEMVT_P2, m, n);
+    TileArgs a2 = targs(m, n, A, lda);
+    a2.xr = x;
+    a2.v1 = v1;
+    a2.v2 = v2;
+    a2.Prow = Prow;
+    a2.Pcol = aux2;
+    if (!launch_tile(kSlotNames[SLOT_DGEMVT_P2], OP_ROWDOT | OP_AUX, c2, a2, st))
+        return unsupported(SLOT_DGEMVT_P2);
+    const int64_t nt = n > 0 ? tile_ncols(c2, n) : 0;
+    launch_finish_aux("finish", {fjob(Prow, nt, m, alpha, nullptr, w), aux2, m > 0 ? nt : 0, u1, u2},
+                      st);
     return check_launch();
 }
 

@@ -63,6 +63,11 @@ enum TileOps {
     OP_COLSUM = 2,  // partial column sums weighted by yc, per row band
     OP_UPD1 = 4,    // B = A + u1 v1^T  (stored)
     OP_UPD2 = 8,    // ... + u2 v2^T    (with OP_UPD1)
+    // the two dots of a rank-2 correction, for sweeps that leave B = A +
+    // u1 v1^T + u2 v2^T unformed: with OP_COLSUM the band's u1.yc and u2.yc
+    // into Prow[2 band], Prow[2 band + 1]; with OP_ROWDOT the wave tile's
+    // v1.xr and v2.xr into Pcol[2 t], Pcol[2 t + 1]
+    OP_AUX = 16,
 };
 
 struct TileCfg {
@@ -102,6 +107,15 @@ struct FinishJob {
     double *out;
 };
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
+// out[i] = scale * (sum_k P[k*len + i] + c1[i] S1 + c2[i] S2) + add[i], where
+// S1 = sum_k aux[2k] and S2 = sum_k aux[2k + 1] (k < naux), in fixed orders
+struct FinishAux {
+    FinishJob j;
+    const double *aux;
+    int64_t naux;
+    const double *c1, *c2;
+};
+void launch_finish_aux(const char *name, const FinishAux &f, hipStream_t st);
 
 // Tiled batches: many instances' tile sweeps in one launch, one workgroup
 // per (sweep, row band, column block) unit, then their partial sums reduced

@@ -155,9 +155,10 @@ __device__ __forceinline__ void tile_rows(const TileArgs &a, int64_t c0, int64_t
     }
 }
 
-// LDS of one workgroup tile: the WR row groups' column sums.
+// LDS of one workgroup tile: the WR row groups' column sums, then two
+// doubles per row group for the auxiliary dots.
 template <int KV, int WC, int WR>
-constexpr int tile_lds_doubles() { return WR > 1 ? WR * WC * 128 * KV : 1; }
+constexpr int tile_lds_doubles() { return WR > 1 ? WR * WC * 128 * KV + 2 * WR : 2 * WR; }
 
 // One workgroup tile: row band `band` (rows [band*rb, band*rb + rb)) and
 // column block `cblk` (WC wave tiles) of the sweep described by `a`.
@@ -229,12 +230,67 @@ __device__ __forceinline__ void tile_block(const TileArgs &a, int64_t band, int6
             }
         }
     }
+    if constexpr ((OPS & OP_AUX) && COLSUM) {
+        // the first column block's waves add u1_i yc_i and u2_i yc_i over
+        // their rows; the row groups' sums meet in LDS in row-group order
+        if (cblk == 0) {
+            double *aux = lds + (WR > 1 ? WR * CTB : 0);
+            if (wc == 0) {
+                double s1 = 0.0, s2 = 0.0;
+                for (int64_t i = r0 + lane; i < r1; i += kWave) {
+                    const double yi = a.yc[i];
+                    s1 += a.u1[i] * yi;
+                    s2 += a.u2[i] * yi;
+                }
+                s1 = wave_sum(s1);
+                s2 = wave_sum(s2);
+                if (lane == 0) {
+                    aux[2 * wr] = s1;
+                    aux[2 * wr + 1] = s2;
+                }
+            }
+            lds_barrier();
+            if (threadIdx.x == 0) {
+                double s1 = aux[0], s2 = aux[1];
+                for (int r = 1; r < WR; ++r) {
+                    s1 += aux[2 * r];
+                    s2 += aux[2 * r + 1];
+                }
+                a.Prow[2 * band] = s1;
+                a.Prow[2 * band + 1] = s2;
+            }
+        }
+    }
+    if constexpr ((OPS & OP_AUX) && ROWDOT) {
+        // the first band's waves add v1_j xr_j and v2_j xr_j over their
+        // wave tile's columns (pairs in the sweep's lane order)
+        if (band == 0 && wr == 0 && c0 < a.n) {
+            double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < KV; ++k) {
+                const int64_t j = c0 + 2 * (lane + kWave * k);
+                const d2 x2 = load_vec_pair(a.xr, j, a.n);
+                const d2 p1 = load_vec_pair(a.v1, j, a.n);
+                const d2 p2 = load_vec_pair(a.v2, j, a.n);
+                t1 += p1.x * x2.x;
+                t1 += p1.y * x2.y;
+                t2 += p2.x * x2.x;
+                t2 += p2.y * x2.y;
+            }
+            t1 = wave_sum(t1);
+            t2 = wave_sum(t2);
+            if (lane == 0) {
+                a.Pcol[2 * ctw] = t1;
+                a.Pcol[2 * ctw + 1] = t2;
+            }
+        }
+    }
 }
 
 template <int KV, int D, int WC, int WR, int OPS, bool VEC>
 __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int rev)
 {
-    __shared__ double lds[(OPS & OP_COLSUM) ? tile_lds_doubles<KV, WC, WR>() : 1];
+    __shared__ double lds[(OPS & (OP_COLSUM | OP_AUX)) ? tile_lds_doubles<KV, WC, WR>() : 1];
     const int64_t band = rev ? (int64_t)gridDim.y - 1 - blockIdx.y : (int64_t)blockIdx.y;
     tile_block<KV, D, WC, WR, OPS, VEC>(a, band, (int64_t)blockIdx.x, rb, lds);
 }
@@ -329,6 +385,8 @@ void dispatch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &
     case OP_UPD1 | OP_UPD2 | OP_COLSUM:
         launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_COLSUM>(name, c, a, st);
         break;
+    case OP_COLSUM | OP_AUX: launch_tile_ops<OP_COLSUM | OP_AUX>(name, c, a, st); break;
+    case OP_ROWDOT | OP_AUX: launch_tile_ops<OP_ROWDOT | OP_AUX>(name, c, a, st); break;
     default: break;
     }
 }
@@ -366,6 +424,57 @@ __device__ __forceinline__ void finish_block(const FinishJob &j, int64_t b, doub
     lds_barrier();
     if (wave == 0 && idx < j.len) {
         double t = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
+        j.out[idx] = j.add ? j.scale * t + j.add[idx] : j.scale * t;
+    }
+}
+
+// The finish of a sweep with a rank-2 correction: every workgroup first adds
+// the auxiliary parts (wave 0, lanes in order, then the wave sum), then its
+// 64 outputs as in finish_block, then applies the correction.
+__global__ __launch_bounds__(256) void k_finish_aux(FinishAux f)
+{
+    __shared__ double lds[4][64];
+    __shared__ double S[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (wave == 0) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int64_t k = lane; k < f.naux; k += kWave) {
+            s1 += f.aux[2 * k];
+            s2 += f.aux[2 * k + 1];
+        }
+        s1 = wave_sum(s1);
+        s2 = wave_sum(s2);
+        if (lane == 0) {
+            S[0] = s1;
+            S[1] = s2;
+        }
+    }
+    const FinishJob &j = f.j;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t q = (j.nparts + 3) / 4;
+    const int64_t k0 = wave * q;
+    const int64_t k1 = k0 + q < j.nparts ? k0 + q : j.nparts;
+    double s = 0.0;
+    if (idx < j.len) {
+        const double *p = j.P + idx;
+        int64_t k = k0;
+        for (; k + 8 <= k1; k += 8) {
+            double t[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                t[e] = p[(k + e) * j.len];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                s += t[e];
+        }
+        for (; k < k1; ++k)
+            s += p[k * j.len];
+    }
+    lds[wave][lane] = s;
+    lds_barrier();
+    if (wave == 0 && idx < j.len) {
+        double t = ((lds[0][lane] + lds[1][lane]) + lds[2][lane]) + lds[3][lane];
+        t = (t + f.c1[idx] * S[0]) + f.c2[idx] * S[1];
         j.out[idx] = j.add ? j.scale * t + j.add[idx] : j.scale * t;
     }
 }
@@ -797,6 +906,13 @@ bool launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a,
         return true;
     dispatch_tile(name, ops, c, a, st);
     return true;
+}
+
+void launch_finish_aux(const char *name, const FinishAux &f, hipStream_t st)
+{
+    const int64_t nb = ceil_div(f.j.len, 64);
+    if (nb > 0)
+        launch(name, k_finish_aux, dim3((unsigned)nb), dim3(256), st, f);
 }
 
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st)

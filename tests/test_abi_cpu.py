@@ -160,3 +160,35 @@ def test_tuning_size_buckets(bto):
     bto.tune_set(rr, *keep, size=1024)
     with pytest.raises(bto.BtoError):
         bto.tune_set(slots.index("atax_rowres"), 0, 0, 0, size=1024)   # ATAX has no tile fallback
+
+
+def test_contracted_gemver_and_batax_checks(bto):
+    """GEMVER without B and BATAX: workspace sizes and the argument checks,
+    before anything is enqueued."""
+    v = ctypes.c_void_p
+    n = 16384
+    wc = bto.workspace_bytes("gemver_contracted", n, n)
+    assert bto.workspace_bytes("gemver", n, n) < wc < 0.05 * n * n * 8 and wc % 256 == 0
+    assert bto.workspace_bytes("batax", n, n, "fused") == bto.workspace_bytes("atax", n, n, "fused")
+    assert bto.workspace_bytes("batax", 300, 40, "unfused") == \
+        bto.workspace_bytes("atax", 300, 40, "unfused")
+    m = k = 256
+    base = FAKE
+    ptr = lambda i: v(base + (i << 20))
+    need = bto.workspace_bytes("gemver_contracted", m, k)
+
+    def gc(A=ptr(0), lda=k, x=ptr(7), w=ptr(8), ws=ptr(16), wsb=need, mm=m, nn=k):
+        return bto._lib.bto_gemver_contracted(mm, nn, 1.5, 0.7, A, lda, ptr(1), ptr(2), ptr(3),
+                                              ptr(4), ptr(5), ptr(6), x, w, ws, wsb, None)
+
+    assert gc(mm=-1) == 1
+    assert gc(A=None) == 1
+    assert gc(lda=k - 1) == 1
+    assert gc(wsb=need - 1) == 3
+    assert gc(x=ptr(5)) == 2                       # x on top of y
+    assert gc(w=v(base + 8)) == 2                  # w inside A
+    wb = bto.workspace_bytes("batax", m, k, "fused")
+    assert bto._lib.bto_batax(m, k, 2.0, ptr(0), k, ptr(1), ptr(1), ptr(16), wb, 0, None) == 2
+    assert bto._lib.bto_batax(m, k, 2.0, ptr(0), k, ptr(1), ptr(2), ptr(16), wb - 256, 0,
+                              None) == 3
+    assert bto._lib.bto_batax(m, k, 2.0, ptr(0), k, ptr(1), ptr(2), ptr(16), wb, 7, None) == 1

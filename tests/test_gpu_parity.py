@@ -448,6 +448,12 @@ def _run_kernel(torch, bto, dev, kernel, form, m, n, pad):
         ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)
         got = bto.gemver(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y), d(z),
                          ALPHA, BETA, form=form)
+    elif kernel == "gemver_contracted":
+        A, vec = inputs("uniform", m, n, lda, 2, 12)
+        u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+        ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)[1:]
+        got = bto.gemver_contracted(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y),
+                                    d(z), ALPHA, BETA)
     else:
         A, vec = inputs("uniform", m, n, lda, 4, 11)
         y, z = vec(1, m), vec(2, n)
@@ -487,8 +493,70 @@ def test_every_tile_shape(env, slot, shape):
             got, ref = _run_kernel(torch, bto, dev, kernel, form, m, n, pad)
             for g, r in zip(got, ref):
                 assert relerr(g, r) <= TOL, (slot, shape, rb, m, n, pad)
+            if kernel == "dgemvt":   # the same slots serve GEMVER without B
+                got, ref = _run_kernel(torch, bto, dev, "gemver_contracted", form, m, n, pad)
+                for g, r in zip(got, ref):
+                    assert relerr(g, r) <= TOL, ("contracted", slot, shape, rb, m, n, pad)
     finally:
         for b, c in saved.items():
             bto.tune_set(slot, *c, size=256 << b)
         for b, c in saved_rowres.items():
             bto.tune_set(SLOT_BICGK_ROWRES, *c, size=256 << b)
+
+
+# ---- GEMVER with B contracted away, and BATAX ---------------------------------------
+
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_gemver_contracted(env, m, n, pad):
+    """x and w without B: the oracle's GEMVER (which forms B) gives the
+    reference; the two differ only in rounding order."""
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 2, 5)
+    u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+    _, x_ref, w_ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)
+    d = lambda a: dvec(torch, dev, a)
+    x, w = bto.gemver_contracted(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y), d(z),
+                                 ALPHA, BETA)
+    assert relerr(host(x), x_ref) <= TOL
+    assert relerr(host(w), w_ref) <= TOL
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 127), (513, 1000), (2047, 2049), (3000, 64)])
+def test_gemver_contracted_integers_exact(env, m, n):
+    torch, bto, dev = env
+    A, vec = inputs("int", m, n, n, 2, 6)
+    u1, v1, u2, v2, y, z = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, m), vec(6, n)
+    _, x_ref, w_ref = oracle.gemver(A, u1, v1, u2, v2, y, z, 2.0, 3.0)
+    d = lambda a: dvec(torch, dev, a)
+    x, w = bto.gemver_contracted(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y), d(z),
+                                 2.0, 3.0)
+    assert np.array_equal(host(x), x_ref) and np.array_equal(host(w), w_ref)
+
+
+def test_gemver_contracted_empty_extents(env):
+    torch, bto, dev = env
+    rnd = lambda k, s: dvec(torch, dev, synth.uniform(SEED, s, k))
+    z = rnd(5, 3)
+    x, w = bto.gemver_contracted(torch.zeros((0, 5), dtype=torch.float64, device=dev), rnd(0, 1),
+                                 rnd(5, 2), rnd(0, 4), rnd(5, 5), rnd(0, 6), z, ALPHA, BETA)
+    assert np.array_equal(host(x), host(z)) and host(w).size == 0
+    A = torch.empty((4, 2), dtype=torch.float64, device=dev)[:, :0]
+    x, w = bto.gemver_contracted(A, rnd(4, 1), rnd(0, 2), rnd(4, 4), rnd(0, 5), rnd(4, 6),
+                                 rnd(0, 7), ALPHA, BETA)
+    assert host(x).size == 0 and np.all(host(w) == 0)
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 127), (513, 1000), (4097, 300), (300, 16384)])
+def test_batax(env, m, n, form):
+    """y = beta A^T A x: the oracle's ATAX, scaled after its reduction."""
+    torch, bto, dev = env
+    A, vec = inputs("uniform", m, n, n, 3, 7)
+    x = vec(1, n)
+    y_ref = BETA * oracle.atax(A, x)
+    y = bto.batax(dmat(torch, dev, A, n), dvec(torch, dev, x), BETA, form=form)
+    assert relerr(host(y), y_ref) <= TOL
+    yi = bto.batax(dmat(torch, dev, A, n), dvec(torch, dev, x), 1.0, form=form)
+    assert torch.equal(yi, bto.atax(dmat(torch, dev, A, n), dvec(torch, dev, x), form=form))
