@@ -12,7 +12,9 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
               its stream during the timed region, against the 8 TB/s peak;
               traffic = HBM bytes per launch from hardware counters when a
               counter summary for the current kernel source is committed
-  suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26
+  suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26, plus
+              GEMVER with B contracted away (against GEMVER's two forms) and
+              BATAX (y = beta A^T A x)
   stream      measured copy / read / triad ceilings at 2 GiB per array
   batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
               one persistent graph-captured launch, and the same instances as
@@ -100,6 +102,8 @@ def alg_bytes(kernel: str, form: str, n: int = N, nv: int = NV) -> int:
         "axpydot": 4 * V,            # w v u in, z out
         "waxpby": 3 * V,             # x y in, w out
         "vadd": 4 * V,               # w y z in, x out
+        "gemver_contracted": 2 * M + 8 * v,   # two reads of A; B never stored
+        "batax": M + 2 * v,          # as ATAX; beta applied after the reduction
     }
     unfused = {
         "gemver": 6 * M + 12 * v,    # ger (2M), ger (2M), gemv_t (M), gemv_n (M)
@@ -109,6 +113,7 @@ def alg_bytes(kernel: str, form: str, n: int = N, nv: int = NV) -> int:
         "axpydot": 5 * V,            # axpy (3V) + dot (2V)
         "waxpby": 5 * V,             # scal (2V) + axpy (3V)
         "vadd": 6 * V,               # add (3V) + add (3V)
+        "batax": 2 * M + 4 * v,
     }
     return (fused if form == "fused" else unfused)[kernel]
 
@@ -135,15 +140,18 @@ class Workload:
     def __init__(self, torch, bto, synth, kernel, dev, shared=None):
         self.kernel, self.bto, self.torch = kernel, bto, torch
         seed = synth.SEED
-        sid = lambda op: synth.stream_id(2 if kernel == "gemver" else 3, op)
+        sid = lambda op: synth.stream_id(2 if kernel.startswith("gemver") else 3, op)
         d = lambda a: torch.from_numpy(a).to(dev)
         shared = {} if shared is None else shared
-        if kernel in ("gemver", "bicgk", "atax", "dgemvt"):
+        if kernel in ("gemver", "gemver_contracted", "bicgk", "atax", "batax", "dgemvt"):
             if "A" not in shared:
                 shared["A"] = d(synth.matrix(seed, sid(0), N, N))
             self.A = shared["A"]
             vec = lambda op: d(synth.uniform(seed, sid(op), N))
-            if kernel == "gemver":
+            if kernel == "gemver_contracted":
+                self.vs = [vec(k) for k in range(1, 7)]
+                self.x, self.w = vec(7), vec(8)
+            elif kernel == "gemver":
                 self.vs = [vec(k) for k in range(1, 7)]
                 if "B" not in shared:
                     shared["B"] = torch.empty_like(self.A)
@@ -151,7 +159,7 @@ class Workload:
                 self.x, self.w = vec(7), vec(8)
             elif kernel == "bicgk":
                 self.p, self.r, self.q, self.s = vec(1), vec(2), vec(3), vec(4)
-            elif kernel == "atax":
+            elif kernel in ("atax", "batax"):
                 self.x, self.y = vec(1), vec(2)
             else:
                 self.y, self.z, self.x, self.w = vec(1), vec(2), vec(3), vec(4)
@@ -168,6 +176,10 @@ class Workload:
         b, k, ws = self.bto, self.kernel, self.ws[form]
         if k == "gemver":
             b.gemver(self.A, *self.vs, ALPHA, BETA, form=form, B=self.B, x=self.x, w=self.w, ws=ws)
+        elif k == "gemver_contracted":
+            b.gemver_contracted(self.A, *self.vs, ALPHA, BETA, x=self.x, w=self.w, ws=ws)
+        elif k == "batax":
+            b.batax(self.A, self.x, BETA, form=form, y=self.y, ws=ws)
         elif k == "bicgk":
             b.bicgk(self.A, self.p, self.r, form=form, q=self.q, s=self.s, ws=ws)
         elif k == "atax":
@@ -453,15 +465,22 @@ def main() -> int:
 
     if not args.no_suite:
         suite = {}
-        for k in ("gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd"):
+        for k in ("gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd",
+                  "gemver_contracted", "batax"):
             wl = main_wl if k == args.workload else Workload(torch, bto, synth, k, dev, shared)
             ent = {}
-            for form in ("fused", "unfused"):
+            for form in ("fused",) if k == "gemver_contracted" else ("fused", "unfused"):
                 s = time_steps(torch, lambda: wl.run(form), 20, 3)
                 ent[form + "_ms"] = round(s * 1e3, 4)
                 ent[form + "_gbs"] = round(alg_bytes(k, form) / s / 1e9, 1)
             ent["fused_pct_peak"] = round(100 * ent["fused_gbs"] / PEAK_GBS, 1)
-            ent["speedup"] = round(ent["unfused_ms"] / ent["fused_ms"], 3)
+            if k == "gemver_contracted":
+                # same x and w as GEMVER, without storing B
+                g = suite["gemver"]
+                ent["vs_gemver_fused"] = round(g["fused_ms"] / ent["fused_ms"], 3)
+                ent["vs_gemver_unfused"] = round(g["unfused_ms"] / ent["fused_ms"], 3)
+            else:
+                ent["speedup"] = round(ent["unfused_ms"] / ent["fused_ms"], 3)
             suite[k] = ent
             if wl is not main_wl and k in ("axpydot", "waxpby", "vadd"):
                 del wl
