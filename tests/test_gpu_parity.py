@@ -359,6 +359,13 @@ def test_full_bicgk_and_atax(env, kind):
                 assert np.array_equal(got, ref)
             else:
                 assert relerr(got, ref) <= TOL
+    be = 3.0 if kind == "int" else BETA
+    for form in FORMS:
+        y = host(bto.batax(Ad, pd, be, form=form))
+        if kind == "int":
+            assert np.array_equal(y, be * y_ref)
+        else:
+            assert relerr(y, be * y_ref) <= TOL
     q, s, _ = outs["fused"]
     lhs, rhs = float(r @ q), float(s @ p)
     assert abs(lhs - rhs) <= 1e-12 * float(np.abs(r) @ np.abs(q) + np.abs(s) @ np.abs(p))
@@ -381,6 +388,12 @@ def test_full_gemver(env, kind):
             else:
                 assert relerr(got, ref) <= TOL
         del B
+    x, w = bto.gemver_contracted(Ad, *dv, al, be)
+    for got, ref in zip((host(x), host(w)), (x_ref, w_ref)):
+        if kind == "int":
+            assert np.array_equal(got, ref)
+        else:
+            assert relerr(got, ref) <= TOL
 
 
 @pytest.mark.parametrize("kind", ["uniform", "int"])
