@@ -1,4 +1,4 @@
-"""CPU oracle for the seven BTO kernels (Table I of the paper).
+"""CPU oracle for the nine BTO kernels (Table I of the paper).
 
 TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the GPU library never does, and this
@@ -61,6 +61,8 @@ def bind(lib):
                           ptr, ptr, ptr, i64, ptr, ptr],
         "oracle_atax": [i64, i64, ptr, i64, ptr, ptr],
         "oracle_dgemvt": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr, ptr],
+        "oracle_dgemv": [i64, i64, dbl, dbl, ptr, i64, ptr, ptr, ptr],
+        "oracle_gesummv": [i64, i64, dbl, dbl, ptr, i64, ptr, i64, ptr, ptr],
         "oracle_axpydot": [i64, dbl, ptr, ptr, ptr, ptr, ptr],
         "oracle_waxpby": [i64, dbl, ptr, dbl, ptr, ptr],
         "oracle_vadd": [i64, ptr, ptr, ptr, ptr],
@@ -150,6 +152,29 @@ def dgemvt(A, y, z, alpha, beta, lda=None):
     _load().oracle_dgemvt(m, n, float(alpha), float(beta), _p(A), lda,
                           _p(y), _p(z), _p(x), _p(w))
     return x, w
+
+
+def dgemv(A, x, y, alpha, beta, lda=None):
+    """z = alpha A x + beta y."""
+    m, n = y.shape[0], x.shape[0]
+    A, lda = _mat(A, m, n, lda)
+    x, y = _vec(x, n, "x"), _vec(y, m, "y")
+    z = np.empty(m)
+    _load().oracle_dgemv(m, n, float(alpha), float(beta), _p(A), lda, _p(x), _p(y), _p(z))
+    return z
+
+
+def gesummv(A, B, x, alpha, beta, m=None, lda=None, ldb=None):
+    """y = alpha A x + beta B x (A and B both m x n)."""
+    n = x.shape[0]
+    m = np.asarray(A).shape[0] if m is None else m
+    A, lda = _mat(A, m, n, lda)
+    B, ldb = _mat(B, m, n, ldb)
+    x = _vec(x, n, "x")
+    y = np.empty(m)
+    _load().oracle_gesummv(m, n, float(alpha), float(beta), _p(A), lda, _p(B), ldb, _p(x),
+                           _p(y))
+    return y
 
 
 def axpydot(w, v, u, alpha):

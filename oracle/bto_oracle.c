@@ -1,5 +1,6 @@
 /*
- * Reference oracle for the seven fused BLAS-1/2 kernels of Belter, Jessup,
+ * Reference oracle for the nine BLAS-1/2 kernels of Table I (and BATAX's
+ * building block, ATAX) of Belter, Jessup,
  * Nelson, Norris and Siek, "Reliable Generation of High-Performance Matrix
  * Algebra" (the Build to Order BLAS).
  *
@@ -177,6 +178,46 @@ void oracle_dgemvt(int64_t m, int64_t n, double alpha, double beta,
     rowdots(m, n, A, lda, x, w);
     for (int64_t i = 0; i < m; ++i)
         w[i] = alpha * w[i];
+}
+
+/* DGEMV, Table I:  z <- alpha A x + beta y,
+ *   z[i] = alpha * (sum_j A[i,j]*x[j]) + beta * y[i].
+ * One BLAS call (Section V-A).  z may be the same array as y: the row dots
+ * go to a temporary first. */
+void oracle_dgemv(int64_t m, int64_t n, double alpha, double beta,
+                  const double *A, int64_t lda, const double *x,
+                  const double *y, double *z)
+{
+    double *t = (double *)malloc((size_t)(m > 0 ? m : 1) * sizeof(double));
+    if (!t)
+        abort();
+    rowdots(m, n, A, lda, x, t);
+    for (int64_t i = 0; i < m; ++i) {
+        double a = alpha * t[i];
+        double b = beta * y[i];
+        z[i] = a + b;
+    }
+    free(t);
+}
+
+/* GESUMMV, Table I:  y <- alpha A x + beta B x,
+ *   y[i] = alpha * (sum_j A[i,j]*x[j]) + beta * (sum_j B[i,j]*x[j]).
+ * A and B are both m x n, row-major, with their own leading dimensions. */
+void oracle_gesummv(int64_t m, int64_t n, double alpha, double beta,
+                    const double *A, int64_t lda, const double *B, int64_t ldb,
+                    const double *x, double *y)
+{
+    double *t = (double *)malloc((size_t)(m > 0 ? 2 * m : 2) * sizeof(double));
+    if (!t)
+        abort();
+    rowdots(m, n, A, lda, x, t);
+    rowdots(m, n, B, ldb, x, t + m);
+    for (int64_t i = 0; i < m; ++i) {
+        double a = alpha * t[i];
+        double b = beta * t[m + i];
+        y[i] = a + b;
+    }
+    free(t);
 }
 
 /* AXPYDOT, Table I (its scalar result is named beta there, r here):

@@ -80,6 +80,26 @@ def dgemvt(A, y, z, alpha, beta, absolute=False):
     return x, w
 
 
+def dgemv(A, x, y, alpha, beta, absolute=False):
+    A, x, y = _m(A), _f(x), _f(y)
+    alpha, beta = F(float(alpha)), F(float(beta))
+    if absolute:
+        A, x, y, alpha, beta = _abs_m(A), _abs_v(x), _abs_v(y), abs(alpha), abs(beta)
+    m, n = len(y), len(x)
+    return [alpha * sum((A[i][j] * x[j] for j in range(n)), F(0)) + beta * y[i]
+            for i in range(m)]
+
+
+def gesummv(A, B, x, alpha, beta, absolute=False):
+    A, B, x = _m(A), _m(B), _f(x)
+    alpha, beta = F(float(alpha)), F(float(beta))
+    if absolute:
+        A, B, x, alpha, beta = _abs_m(A), _abs_m(B), _abs_v(x), abs(alpha), abs(beta)
+    m, n = len(A), len(x)
+    return [alpha * sum((A[i][j] * x[j] for j in range(n)), F(0))
+            + beta * sum((B[i][j] * x[j] for j in range(n)), F(0)) for i in range(m)]
+
+
 def axpydot(w, v, u, alpha, absolute=False):
     w, v, u, alpha = _f(w), _f(v), _f(u), F(float(alpha))
     if absolute:

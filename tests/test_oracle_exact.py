@@ -81,6 +81,18 @@ def test_dgemvt_rational(orc, m, n):
         assert ex.within(w[i], we[i], wa[i], K)
 
 
+@pytest.mark.parametrize("m,n", [(1, 1), (2, 3), (3, 2), (5, 5), (8, 3), (3, 8)])
+def test_dgemv_gesummv_rational(orc, m, n):
+    A, B, x, y = _A(70, m, n), _A(71, m, n), _u(72, n), _u(73, m)
+    z = orc.dgemv(A, x, y, 1.5, -0.7)
+    ze, za = ex.dgemv(A, x, y, 1.5, -0.7), ex.dgemv(A, x, y, 1.5, -0.7, absolute=True)
+    g = orc.gesummv(A, B, x, 1.5, -0.7)
+    ge, ga = ex.gesummv(A, B, x, 1.5, -0.7), ex.gesummv(A, B, x, 1.5, -0.7, absolute=True)
+    for i in range(m):
+        assert ex.within(z[i], ze[i], za[i], n + 2)
+        assert ex.within(g[i], ge[i], ga[i], n + 2)
+
+
 @pytest.mark.parametrize("n", SIZES + [127, 128, 129, 300])
 def test_axpydot_rational(orc, n):
     w, v, u = _u(40, n), _u(41, n), _u(42, n)
@@ -153,6 +165,12 @@ def test_golden_hand_worked(orc):
     assert orc.waxpby(a(c["x"], float), a(c["y"], float), c["alpha"], c["beta"]).tolist() == c["w"]
     c = g["vadd"]
     assert orc.vadd(a(c["w"], float), a(c["y"], float), a(c["z"], float)).tolist() == c["x"]
+    c = g["dgemv"]
+    z = orc.dgemv(a(c["A"], float), a(c["x"], float), a(c["y"], float), c["alpha"], c["beta"])
+    assert z.tolist() == c["z"]
+    c = g["gesummv"]
+    y = orc.gesummv(a(c["A"], float), a(c["B"], float), a(c["x"], float), c["alpha"], c["beta"])
+    assert y.tolist() == c["y"]
 
 
 # ---- exact integer arithmetic at sizes that span many blocks -------------
@@ -197,6 +215,13 @@ def test_integer_exact_matrix_kernels(orc, m, n):
     xi = 3 * (Ai.T @ I(y)) + I(z)
     assert np.array_equal(xd, xi.astype(float))
     assert np.array_equal(wd, (2 * (Ai @ xi)).astype(float))
+
+    Bm = _imat(12, m, n)
+    xv, yv = _ints(13, n), _ints(14, m)
+    zi = 2 * (Ai @ I(xv)) - 3 * I(yv)
+    assert np.array_equal(orc.dgemv(A, xv, yv, 2.0, -3.0), zi.astype(float))
+    gi = 2 * (Ai @ I(xv)) + 3 * (I(Bm) @ I(xv))
+    assert np.array_equal(orc.gesummv(A, Bm, xv, 2.0, 3.0), gi.astype(float))
 
 
 @pytest.mark.parametrize("n", [1, 127, 128, 129, 4097, 1 << 20])

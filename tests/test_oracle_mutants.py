@@ -37,13 +37,20 @@ MUTANTS = {
                               "        x[j] = alpha * x[j] + z[j];\n    rowdots(m, n, B"),
     "atax_skips_Ax": ("    rowdots(m, n, A, lda, x, t);\n    colsums(m, n, A, lda, t, y);",
                       "    for (int64_t i = 0; i < m; ++i) t[i] = 1.0;\n    colsums(m, n, A, lda, t, y);"),
-    "dgemvt_alpha_is_beta": ("        w[i] = alpha * w[i];\n}\n\n/* AXPYDOT",
-                             "        w[i] = beta * w[i];\n}\n\n/* AXPYDOT"),
+    "dgemvt_alpha_is_beta": ("        w[i] = alpha * w[i];\n}\n\n/* DGEMV",
+                             "        w[i] = beta * w[i];\n}\n\n/* DGEMV"),
     "axpydot_plus": ("z[k] = w[k] - alpha * v[k];", "z[k] = w[k] + alpha * v[k];"),
     "pairwise_drops_element": ("pairwise_dot(x + h, y + h, len - h)", "pairwise_dot(x + h, y + h, len - h - 1)"),
     "pairwise_wrong_offset": ("pairwise_dot(x + h, y + h, len - h)", "pairwise_dot(x + h, y, len - h)"),
     "waxpby_beta_x": ("double b = beta * y[k];", "double b = beta * x[k];"),
     "vadd_adds_y_twice": ("x[k] = t + z[k];", "x[k] = t + y[k];"),
+    "dgemv_drops_beta_y": ("        double b = beta * y[i];\n        z[i] = a + b;",
+                           "        double b = beta * y[i];\n        z[i] = a + 0.0 * b;"),
+    "dgemv_beta_times_dot": ("double b = beta * y[i];", "double b = beta * t[i];"),
+    "gesummv_reads_A_twice": ("rowdots(m, n, B, ldb, x, t + m);", "rowdots(m, n, A, lda, x, t + m);"),
+    "gesummv_ignores_ldb": ("rowdots(m, n, B, ldb, x, t + m);", "rowdots(m, n, B, lda, x, t + m);"),
+    "gesummv_scales_swapped": ("double a = alpha * t[i];\n        double b = beta * t[m + i];",
+                               "double a = beta * t[i];\n        double b = alpha * t[m + i];"),
 }
 
 
@@ -54,6 +61,7 @@ def _checks():
         lambda o: tx.test_gemver_rational(o, 3, 8),
         lambda o: tx.test_atax_rational(o, 5, 3),
         lambda o: tx.test_dgemvt_rational(o, 3, 8),
+        lambda o: tx.test_dgemv_gesummv_rational(o, 3, 8),
         lambda o: tx.test_axpydot_rational(o, 300),
         lambda o: tx.test_waxpby_vadd_rational(o, 5),
         lambda o: tx.test_golden_hand_worked(o),

@@ -42,6 +42,11 @@ def test_identity(orc, n):
     x2, w2 = orc.dgemvt(I, y, z, 1.5, 0.7)
     assert np.array_equal(x2, 0.7 * y + z)
     assert np.array_equal(w2, 1.5 * x2)
+    # DGEMV with A = I: z = alpha x + beta y
+    assert np.array_equal(orc.dgemv(I, y, z, 1.5, 0.7), 1.5 * y + 0.7 * z)
+    # GESUMMV with A = I and B the reversal permutation: alpha x + beta (reversed x)
+    P = np.ascontiguousarray(I[::-1])
+    assert np.array_equal(orc.gesummv(I, P, y, 1.5, 0.7), 1.5 * y + 0.7 * y[::-1])
 
 
 @pytest.mark.parametrize("n", [2, 64, 257])
@@ -109,6 +114,11 @@ def test_empty_extents(orc):
     assert np.array_equal(orc.atax(np.zeros((0, 4)), U(6, 4)), np.zeros(4))
     z, r = orc.axpydot(np.zeros(0), np.zeros(0), np.zeros(0), 1.5)
     assert r == 0.0
+    y = U(7, 3)
+    assert np.array_equal(orc.dgemv(np.zeros((3, 0)), np.zeros(0), y, 1.5, 0.7), 0.7 * y)
+    assert orc.dgemv(np.zeros((0, 4)), U(8, 4), np.zeros(0), 1.5, 0.7).shape == (0,)
+    assert np.array_equal(orc.gesummv(np.zeros((3, 0)), np.zeros((3, 0)), np.zeros(0), 1.5, 0.7),
+                          np.zeros(3))
 
 
 # ---- invariants -----------------------------------------------------------
@@ -184,6 +194,27 @@ def test_threads_bitwise(orc):
     assert np.array_equal(flat(outs[0]), flat(outs[1]))
 
 
+@pytest.mark.parametrize("m,n", [(200, 150), (1000, 1000)])
+def test_dgemv_gesummv_invariants(orc, m, n):
+    A, B = synth.matrix(SEED, 90, m, n), synth.matrix(SEED, 91, m, n)
+    x, y, v = U(92, n), U(93, m), U(94, m)
+    # the two terms of GESUMMV are symmetric: swapping (A, alpha) and (B, beta)
+    # changes nothing, and B = A with beta = -alpha cancels exactly
+    assert np.array_equal(orc.gesummv(A, B, x, 1.5, 0.7), orc.gesummv(B, A, x, 0.7, 1.5))
+    assert np.array_equal(orc.gesummv(A, A, x, 1.5, -1.5), np.zeros(m))
+    # v^T z = alpha (A^T v)^T x + beta v^T y, with A^T v from the column sums
+    z = orc.dgemv(A, x, y, 1.5, 0.7)
+    _, s = orc.bicgk(A, x, v)
+    lhs, rhs = float(v @ z), 1.5 * float(s @ x) + 0.7 * float(v @ y)
+    mag = 1.5 * float(np.abs(v) @ (np.abs(A) @ np.abs(x))) + 0.7 * float(np.abs(v) @ np.abs(y))
+    assert abs(lhs - rhs) <= 4 * (m + n) * 2.0 ** -53 * mag
+    # GESUMMV = alpha A x + beta B x as two DGEMV calls (the BLAS form)
+    g = orc.gesummv(A, B, x, 1.5, 0.7)
+    two = orc.dgemv(B, x, orc.dgemv(A, x, np.zeros(m), 1.5, 0.0), 0.7, 1.0)
+    assert np.max(np.abs(g - two)) <= 4 * 2.0 ** -53 * np.max(
+        1.5 * (np.abs(A) @ np.abs(x)) + 0.7 * (np.abs(B) @ np.abs(x)))
+
+
 # ---- leading dimension ----------------------------------------------------
 
 @pytest.mark.parametrize("m,n,lda", [(5, 3, 4), (64, 65, 80), (130, 257, 300)])
@@ -201,3 +232,8 @@ def test_lda_padding_is_ignored(orc, m, n, lda):
         assert np.array_equal(a, b)
     for a, b in zip(orc.dgemvt(Ap, r, p, 1.5, 0.7, lda=lda), orc.dgemvt(Ac, r, p, 1.5, 0.7)):
         assert np.array_equal(a, b)
+    assert np.array_equal(orc.dgemv(Ap, p, r, 1.5, 0.7, lda=lda), orc.dgemv(Ac, p, r, 1.5, 0.7))
+    Bp = synth.matrix(SEED, 79, m, n, lda=lda + 5)
+    Bc = np.ascontiguousarray(Bp[:, :n])
+    assert np.array_equal(orc.gesummv(Ap, Bp, p, 1.5, 0.7, lda=lda, ldb=lda + 5),
+                          orc.gesummv(Ac, Bc, p, 1.5, 0.7))

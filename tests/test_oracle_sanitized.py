@@ -39,6 +39,10 @@ for threads in (1, 4):
             B, x, w = oracle.gemver(A, v(m), v(n), v(m), v(n), v(m), v(n), 1.5, 0.7, lda=lda)
             y = oracle.atax(A, v(n), lda=lda)
             x2, w2 = oracle.dgemvt(A, v(m), v(n), 1.5, 0.7, lda=lda)
+            z = oracle.dgemv(A, v(n), v(m), 1.5, 0.7, lda=lda)
+            ldb = max(n, 1) + 2 * pad
+            g = oracle.gesummv(A, mat(m, n, ldb), v(n), 1.5, 0.7, m=m, lda=lda, ldb=ldb)
+            assert z.shape == g.shape == (m,) and np.all(np.isfinite(z)) and np.all(np.isfinite(g))
             assert q.shape == (m,) and s.shape == (n,) and B.shape[0] == m and y.shape == (n,)
             assert np.all(np.isfinite(q)) and np.all(np.isfinite(s)) and np.all(np.isfinite(w))
     for N in (0, 1, 2, 127, 128, 129, 1000, 4097):
