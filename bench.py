@@ -12,9 +12,9 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
               its stream during the timed region, against the 8 TB/s peak;
               traffic = HBM bytes per launch from hardware counters when a
               counter summary for the current kernel source is committed
-  suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26, plus
-              GEMVER with B contracted away (against GEMVER's two forms) and
-              BATAX (y = beta A^T A x)
+  suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26
+              (DGEMV and GESUMMV included), plus GEMVER with B contracted away
+              (against GEMVER's two forms) and BATAX (y = beta A^T A x)
   stream      measured copy / read / triad ceilings at 2 GiB per array
   batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
               one persistent graph-captured launch, and the same instances as
@@ -104,6 +104,8 @@ def alg_bytes(kernel: str, form: str, n: int = N, nv: int = NV) -> int:
         "vadd": 4 * V,               # w y z in, x out
         "gemver_contracted": 2 * M + 8 * v,   # two reads of A; B never stored
         "batax": M + 2 * v,          # as ATAX; beta applied after the reduction
+        "dgemv": M + 3 * v,          # read A; x y in, z out
+        "gesummv": 2 * M + 2 * v,    # read A and B; x in, y out
     }
     unfused = {
         "gemver": 6 * M + 12 * v,    # ger (2M), ger (2M), gemv_t (M), gemv_n (M)
@@ -114,6 +116,8 @@ def alg_bytes(kernel: str, form: str, n: int = N, nv: int = NV) -> int:
         "waxpby": 5 * V,             # scal (2V) + axpy (3V)
         "vadd": 6 * V,               # add (3V) + add (3V)
         "batax": 2 * M + 4 * v,
+        "dgemv": M + 3 * v,          # one BLAS call either way
+        "gesummv": 2 * M + 5 * v,    # dgemv (t = alpha A x), dgemv (y = beta B x + t)
     }
     return (fused if form == "fused" else unfused)[kernel]
 
@@ -143,7 +147,8 @@ class Workload:
         sid = lambda op: synth.stream_id(2 if kernel.startswith("gemver") else 3, op)
         d = lambda a: torch.from_numpy(a).to(dev)
         shared = {} if shared is None else shared
-        if kernel in ("gemver", "gemver_contracted", "bicgk", "atax", "batax", "dgemvt"):
+        if kernel in ("gemver", "gemver_contracted", "bicgk", "atax", "batax", "dgemvt", "dgemv",
+                      "gesummv"):
             if "A" not in shared:
                 shared["A"] = d(synth.matrix(seed, sid(0), N, N))
             self.A = shared["A"]
@@ -160,6 +165,14 @@ class Workload:
             elif kernel == "bicgk":
                 self.p, self.r, self.q, self.s = vec(1), vec(2), vec(3), vec(4)
             elif kernel in ("atax", "batax"):
+                self.x, self.y = vec(1), vec(2)
+            elif kernel == "dgemv":
+                self.x, self.y, self.z = vec(1), vec(2), vec(3)
+            elif kernel == "gesummv":
+                if "B2" not in shared:
+                    shared["B2"] = torch.empty_like(self.A)
+                    bto.synth_fill(shared["B2"], synth.stream_state(seed, sid(9)))
+                self.B2 = shared["B2"]
                 self.x, self.y = vec(1), vec(2)
             else:
                 self.y, self.z, self.x, self.w = vec(1), vec(2), vec(3), vec(4)
@@ -180,6 +193,10 @@ class Workload:
             b.gemver_contracted(self.A, *self.vs, ALPHA, BETA, x=self.x, w=self.w, ws=ws)
         elif k == "batax":
             b.batax(self.A, self.x, BETA, form=form, y=self.y, ws=ws)
+        elif k == "dgemv":
+            b.dgemv(self.A, self.x, self.y, ALPHA, BETA, form=form, z=self.z, ws=ws)
+        elif k == "gesummv":
+            b.gesummv(self.A, self.B2, self.x, ALPHA, BETA, form=form, y=self.y, ws=ws)
         elif k == "bicgk":
             b.bicgk(self.A, self.p, self.r, form=form, q=self.q, s=self.s, ws=ws)
         elif k == "atax":
@@ -466,7 +483,7 @@ def main() -> int:
     if not args.no_suite:
         suite = {}
         for k in ("gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd",
-                  "gemver_contracted", "batax"):
+                  "gemver_contracted", "batax", "dgemv", "gesummv"):
             wl = main_wl if k == args.workload else Workload(torch, bto, synth, k, dev, shared)
             ent = {}
             for form in ("fused",) if k == "gemver_contracted" else ("fused", "unfused"):

@@ -90,6 +90,8 @@ typedef enum {
     BTO_K_VADD = 6,
     BTO_K_GEMVER_CONTRACTED = 7,   /* GEMVER without B (bto_gemver_contracted) */
     BTO_K_BATAX = 8,               /* y <- beta A^T A x (bto_batax) */
+    BTO_K_DGEMV = 9,               /* z <- alpha A x + beta y (bto_dgemv) */
+    BTO_K_GESUMMV = 10,            /* y <- alpha A x + beta B x (bto_gesummv) */
     BTO_KERNEL_RANGE_MIN_ = -2147483647 - 1,
     BTO_KERNEL_RANGE_MAX_ = 2147483647
 } bto_kernel;
@@ -174,6 +176,32 @@ bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta,
                       const double *A, int64_t lda, const double *y, const double *z,
                       double *x, double *w,
                       void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
+
+/* DGEMV (Table I):  z <- alpha A x + beta y, each scale applied after its
+ * reduction: z_i = alpha * (sum_j A_ij x_j) + beta * y_i.
+ * A: m x n (lda); x: n; y, z: m.  z may be exactly y (the in-place BLAS
+ * call); no other overlap with an operand is allowed.  A single BLAS
+ * operation (Section V-A), so both forms run the same sweep: row dots of A
+ * per column tile, then a fixed-order reduction whose epilogue adds beta y.
+ * ws: bto_workspace_bytes(BTO_K_DGEMV, m, n, form) bytes of device scratch. */
+bto_status bto_dgemv(int64_t m, int64_t n, double alpha, double beta,
+                     const double *A, int64_t lda, const double *x, const double *y,
+                     double *z, void *ws, size_t ws_bytes, bto_form form,
+                     hipStream_t stream);
+
+/* GESUMMV (Table I):  y <- alpha A x + beta B x, i.e.
+ * y_i = alpha * (sum_j A_ij x_j) + beta * (sum_j B_ij x_j).
+ * A (lda) and B (ldb) are both m x n; x: n; y: m.  B may be exactly A
+ * (same pointer and leading dimension); y may not overlap any input.
+ * Fused: the row dots of A, then of B, into separate partials, and one
+ * reduction that forms y.  The two matrices share only x, so the fusion
+ * saves the temporary and a reduction, not matrix traffic (a single launch
+ * over both matrices measured slower than two).  Unfused: the BLAS form,
+ * dgemv into a temporary t = alpha A x, then y = beta B x + t. */
+bto_status bto_gesummv(int64_t m, int64_t n, double alpha, double beta,
+                       const double *A, int64_t lda, const double *B, int64_t ldb,
+                       const double *x, double *y, void *ws, size_t ws_bytes,
+                       bto_form form, hipStream_t stream);
 
 /* AXPYDOT (Table I, whose scalar result is named beta there):
  *   z <- w - alpha v ;  r <- z^T u.

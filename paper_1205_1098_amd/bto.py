@@ -33,7 +33,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 FUSED, UNFUSED = 0, 1
 FORMS = {"fused": FUSED, "unfused": UNFUSED}
 KERNELS = {"bicgk": 0, "gemver": 1, "atax": 2, "dgemvt": 3, "axpydot": 4, "waxpby": 5, "vadd": 6,
-           "gemver_contracted": 7, "batax": 8}
+           "gemver_contracted": 7, "batax": 8, "dgemv": 9, "gesummv": 10}
 STATUS = {0: "success", 1: "invalid argument", 2: "illegal operand overlap",
           3: "workspace too small", 4: "HIP error", 5: "unsupported"}
 
@@ -54,6 +54,10 @@ _SIGS = {
                                _ptr, _ptr, _ptr, _ptr, _sz, _ptr], _int),
     "bto_dgemvt": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz,
                     _int, _ptr], _int),
+    "bto_dgemv": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr],
+                  _int),
+    "bto_gesummv": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int,
+                     _ptr], _int),
     "bto_axpydot": ([_i64, _dbl, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_waxpby": ([_i64, _dbl, _ptr, _dbl, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_vadd": ([_i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
@@ -320,6 +324,43 @@ def dgemvt(A, y, z, alpha, beta, form="fused", x=None, w=None, ws=None):
                                _ptr_of(z), _ptr_of(x), _ptr_of(w), _ptr_of(ws), wsb, f,
                                _stream(dev)))
     return x, w
+
+
+def dgemv(A, x, y, alpha, beta, form="fused", z=None, ws=None):
+    """z = alpha A x + beta y (z may be y itself)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    z = _empty(m, dev) if z is None else z
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _check_vec(t, nm, dev)
+    f = _form(form)
+    ws, wsb = _ws("dgemv", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_dgemv(m, n, float(alpha), float(beta), _ptr_of(A), lda, _ptr_of(x),
+                              _ptr_of(y), _ptr_of(z), _ptr_of(ws), wsb, f, _stream(dev)))
+    return z
+
+
+def gesummv(A, B, x, alpha, beta, form="fused", y=None, ws=None):
+    """y = alpha A x + beta B x (A and B of the same extents; B may be A)."""
+    lda = _check_mat(A, "A")
+    ldb = _check_mat(B, "B")
+    m, n = A.shape
+    if tuple(B.shape) != (m, n):
+        raise ValueError("A and B must have the same extents")
+    dev = A.device
+    if B.device != dev:
+        raise ValueError("A and B must be on the same device")
+    y = _empty(m, dev) if y is None else y
+    _check_vec(x, "x", dev)
+    _check_vec(y, "y", dev)
+    f = _form(form)
+    ws, wsb = _ws("gesummv", m, n, f, dev, ws)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_gesummv(m, n, float(alpha), float(beta), _ptr_of(A), lda, _ptr_of(B), ldb,
+                                _ptr_of(x), _ptr_of(y), _ptr_of(ws), wsb, f, _stream(dev)))
+    return y
 
 
 def axpydot(w, v, u, alpha, form="fused", z=None, r=None, ws=None):

@@ -96,6 +96,12 @@ size_t ws_bytes(bto_kernel k, int64_t m, int64_t n, bto_form f)
         size_t rowres = round256((size_t)(g * n) * 8);
         return g > 0 ? rowres : split;
     }
+    case BTO_K_DGEMV:
+        return bytes_rowparts(m, n);
+    case BTO_K_GESUMMV:
+        // fused: both matrices' row-dot partials; unfused: one set, reused,
+        // and the temporary alpha A x
+        return f == BTO_FUSED ? 2 * bytes_rowparts(m, n) : bytes_rowparts(m, n) + bytes_vec(m);
     case BTO_K_AXPYDOT:
         return round256((size_t)dot_parts(n) * 8);
     case BTO_K_WAXPBY:
@@ -673,6 +679,98 @@ bto_status bto_dgemvt(int64_t m, int64_t n, double alpha, double beta, const dou
     } else {
         BTO_TRY(gemv_t(SLOT_GEMV_T, m, n, A, lda, y, beta, z, x, Pcol, st));
         BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, A, lda, x, alpha, w, Prow, st));
+    }
+    return check_launch();
+}
+
+// ---- DGEMV and GESUMMV -------------------------------------------------------
+
+namespace {
+
+FinishLin flin(const double *P, int64_t np, int64_t len, double scale, const double *P2,
+               int64_t np2, double scale2, const double *add, double add_scale, double *out)
+{
+    return FinishLin{fjob(P, np, len, scale, add, out), P2, np2, scale2, add_scale};
+}
+
+}  // namespace
+
+bto_status bto_dgemv(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                     int64_t lda, const double *x, const double *y, double *z, void *ws,
+                     size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(y, m, "y"));
+    BTO_TRY(check_vec(z, m, "z"));
+    const size_t need_ws = ws_bytes(BTO_K_DGEMV, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), vspan("x", x, n, false),
+                           vspan("y", y, m, false), vspan("z", z, m, true),
+                           wspan(ws, need_ws)},
+                          {{"z", "y"}}));
+
+    // one BLAS operation: both forms are the same sweep and reduction
+    double *Prow = Carve(ws).take(max_ncols(n) * m);
+    const TileCfg c = cfg_of(SLOT_GEMV_N, m, n);
+    TileArgs a = targs(m, n, A, lda);
+    a.xr = x;
+    a.Prow = Prow;
+    if (!launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, a, st))
+        return unsupported(SLOT_GEMV_N);
+    const int64_t np = n > 0 ? tile_ncols(c, n) : 0;
+    launch_finish_lin("finish", flin(Prow, np, m, alpha, nullptr, 0, 0.0, y, beta, z), st);
+    return check_launch();
+}
+
+bto_status bto_gesummv(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                       int64_t lda, const double *B, int64_t ldb, const double *x, double *y,
+                       void *ws, size_t ws_bytes_, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(check_matrix(m, n, A, lda, "A"));
+    BTO_TRY(check_matrix(m, n, B, ldb, "B"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(y, m, "y"));
+    const size_t need_ws = ws_bytes(BTO_K_GESUMMV, m, n, form);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    BTO_TRY(check_aliases({mspan("A", A, m, n, lda, false), mspan("B", B, m, n, ldb, false),
+                           vspan("x", x, n, false), vspan("y", y, m, true),
+                           wspan(ws, need_ws)},
+                          {}));
+
+    Carve cv(ws);
+    const TileCfg c = cfg_of(SLOT_GEMV_N, m, n);
+    const int64_t np = n > 0 ? tile_ncols(c, n) : 0;
+    TileArgs a = targs(m, n, A, lda);
+    a.xr = x;
+    a.Prow = cv.take(max_ncols(n) * m);
+    if (form == BTO_FUSED) {
+        // both matrices' row dots, then one reduction that forms y
+        TileArgs b = targs(m, n, B, ldb);
+        b.xr = x;
+        b.Prow = cv.take(max_ncols(n) * m);
+        if (!launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, a, st) ||
+            !launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, b, st))
+            return unsupported(SLOT_GEMV_N);
+        launch_finish_lin("finish", flin(a.Prow, np, m, alpha, b.Prow, np, beta, nullptr, 0.0, y),
+                          st);
+    } else {
+        double *t = cv.take(m);
+        // t = alpha A x, then y = beta B x + t
+        if (!launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, a, st))
+            return unsupported(SLOT_GEMV_N);
+        launch_finish_lin("finish", flin(a.Prow, np, m, alpha, nullptr, 0, 0.0, nullptr, 0.0, t),
+                          st);
+        TileArgs b = targs(m, n, B, ldb);
+        b.xr = x;
+        b.Prow = a.Prow;
+        if (!launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, b, st))
+            return unsupported(SLOT_GEMV_N);
+        launch_finish_lin("finish", flin(a.Prow, np, m, beta, nullptr, 0, 0.0, t, 1.0, y), st);
     }
     return check_launch();
 }

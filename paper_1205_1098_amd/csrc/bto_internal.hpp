@@ -107,6 +107,15 @@ struct FinishJob {
     double *out;
 };
 void launch_finish(const char *name, const FinishJob &j0, const FinishJob &j1, hipStream_t st);
+// out[i] = scale * sum_k P[k*len + i] + scale2 * sum_k P2[k*len + i]
+//          + add_scale * add[i]   (the P2 term when P2 is set, the last when add is)
+struct FinishLin {
+    FinishJob j;
+    const double *P2;
+    int64_t nparts2;
+    double scale2, add_scale;
+};
+void launch_finish_lin(const char *name, const FinishLin &f, hipStream_t st);
 // out[i] = scale * (sum_k P[k*len + i] + c1[i] S1 + c2[i] S2) + add[i], where
 // S1 = sum_k aux[2k] and S2 = sum_k aux[2k + 1] (k < naux), in fixed orders
 struct FinishAux {

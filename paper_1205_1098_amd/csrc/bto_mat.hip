@@ -487,6 +487,62 @@ __global__ __launch_bounds__(256) void k_finish(FinishJob j0, FinishJob j1, int6
     finish_block(first ? j0 : j1, b, lds);
 }
 
+// Wave `wave`'s share of sum_k P[k*len + idx], parts [wave*q, (wave+1)*q),
+// in increasing k (the split and order of finish_block).
+__device__ __forceinline__ double part_share(const double *P, int64_t nparts, int64_t len,
+                                             int64_t idx, int wave)
+{
+    const int64_t q = (nparts + 3) / 4;
+    const int64_t k0 = wave * q;
+    const int64_t k1 = k0 + q < nparts ? k0 + q : nparts;
+    double s = 0.0;
+    const double *p = P + idx;
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        double t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            t[e] = p[(k + e) * len];
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            s += t[e];
+    }
+    for (; k < k1; ++k)
+        s += p[k * len];
+    return s;
+}
+
+// out = scale * sum P + scale2 * sum P2 + add_scale * add: each sum in the
+// order of finish_block, the terms added left to right.
+__global__ __launch_bounds__(256) void k_finish_lin(FinishLin f)
+{
+    __shared__ double lds[2][4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const FinishJob &j = f.j;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    double s1 = 0.0, s2 = 0.0;
+    if (idx < j.len) {
+        s1 = part_share(j.P, j.nparts, j.len, idx, wave);
+        if (f.P2)
+            s2 = part_share(f.P2, f.nparts2, j.len, idx, wave);
+    }
+    lds[0][wave][lane] = s1;
+    lds[1][wave][lane] = s2;
+    lds_barrier();
+    if (wave == 0 && idx < j.len) {
+        const double t1 = ((lds[0][0][lane] + lds[0][1][lane]) + lds[0][2][lane]) + lds[0][3][lane];
+        double v = j.scale * t1;
+        if (f.P2) {
+            const double t2 =
+                ((lds[1][0][lane] + lds[1][1][lane]) + lds[1][2][lane]) + lds[1][3][lane];
+            v = v + f.scale2 * t2;
+        }
+        if (j.add)
+            v = v + f.add_scale * j.add[idx];
+        j.out[idx] = v;
+    }
+}
+
 // ---- row-resident sweeps (ATAX, BiCGK) ------------------------------------
 //
 // Workgroup g owns rows [g*m/G, (g+1)*m/G) and reads each of them once,
@@ -898,14 +954,36 @@ void tile_shape_info(int shape, int out[4])
 
 int64_t tile_ncols(const TileCfg &c, int64_t n) { return ceil_div(n, 128 * kShapes[c.shape].kv); }
 
+// The grid's y extent holds at most 65535 row bands.  A configuration whose
+// bands are too short for m gets taller ones (a multiple of its row groups):
+// a row's dot partials and the column sums' band count as seen by the caller
+// do not change, since column-sum sweeps already use bands of 32 rows or more
+// and the entry points refuse more than 65535 * 32 rows.
+TileCfg fit_grid(TileCfg c, int64_t m)
+{
+    const int64_t need = ceil_div(m, 65535);
+    if (c.rb < need) {
+        const int wr = kShapes[c.shape].wr;
+        c.rb = (int)(ceil_div(need, wr) * wr);
+    }
+    return c;
+}
+
 bool launch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &a, hipStream_t st)
 {
     if (!tile_cfg_supported(ops, c))
         return false;
     if (a.m <= 0 || a.n <= 0)
         return true;
-    dispatch_tile(name, ops, c, a, st);
+    dispatch_tile(name, ops, fit_grid(c, a.m), a, st);
     return true;
+}
+
+void launch_finish_lin(const char *name, const FinishLin &f, hipStream_t st)
+{
+    const int64_t nb = ceil_div(f.j.len, 64);
+    if (nb > 0)
+        launch(name, k_finish_lin, dim3((unsigned)nb), dim3(256), st, f);
 }
 
 void launch_finish_aux(const char *name, const FinishAux &f, hipStream_t st)

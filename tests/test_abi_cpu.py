@@ -162,6 +162,50 @@ def test_tuning_size_buckets(bto):
         bto.tune_set(slots.index("atax_rowres"), 0, 0, 0, size=1024)   # ATAX has no tile fallback
 
 
+def test_dgemv_and_gesummv_checks(bto):
+    """DGEMV and GESUMMV: workspace sizes and the argument checks, before
+    anything is enqueued."""
+    v = ctypes.c_void_p
+    n = 16384
+    wd = bto.workspace_bytes("dgemv", n, n)
+    assert 0 < wd < 0.01 * n * n * 8 and wd % 256 == 0
+    assert bto.workspace_bytes("dgemv", n, n, "unfused") == wd
+    assert bto.workspace_bytes("gesummv", n, n, "fused") == 2 * wd
+    assert bto.workspace_bytes("gesummv", n, n, "unfused") == wd + n * 8
+    m = k = 256
+    base = FAKE
+    ptr = lambda i: v(base + (i << 20))
+    need = bto.workspace_bytes("dgemv", m, k)
+
+    def dg(A=ptr(0), lda=k, x=ptr(1), y=ptr(2), z=ptr(3), ws=ptr(16), wsb=need, form=0,
+           mm=m, nn=k):
+        return bto._lib.bto_dgemv(mm, nn, 1.5, 0.7, A, lda, x, y, z, ws, wsb, form, None)
+
+    assert dg(mm=-1) == 1 and dg(nn=-1) == 1
+    assert dg(A=None) == 1 and dg(x=None) == 1 and dg(z=None) == 1
+    assert dg(lda=k - 1) == 1
+    assert dg(form=2) == 1
+    assert dg(wsb=need - 1) == 3 and dg(ws=None) == 1
+    assert dg(z=ptr(1)) == 2                       # z on top of x
+    assert dg(z=v(base + 8)) == 2                  # z inside A
+    assert dg(z=v(base + (2 << 20) + 8)) == 2      # z partly over y
+    assert dg(z=ptr(16)) == 2                      # z inside the workspace
+    assert dg(mm=65535 * 32 + 1, nn=1, lda=1) == 5  # more rows than the grid addresses
+    gneed = bto.workspace_bytes("gesummv", m, k, "fused")
+
+    def gs(A=ptr(0), lda=k, B=ptr(4), ldb=k, x=ptr(1), y=ptr(3), ws=ptr(16), wsb=gneed,
+           form=0):
+        return bto._lib.bto_gesummv(m, k, 1.5, 0.7, A, lda, B, ldb, x, y, ws, wsb, form, None)
+
+    assert gs(B=None) == 1 and gs(ldb=k - 1) == 1 and gs(form=-1) == 1
+    assert gs(wsb=gneed - 256) == 3
+    assert gs(y=ptr(1)) == 2                       # y on top of x
+    assert gs(y=v(base + (4 << 20) + 16)) == 2     # y inside B
+    assert gs(y=ptr(0)) == 2                       # y on top of A
+    uneed = bto.workspace_bytes("gesummv", m, k, "unfused")
+    assert gs(form=1, wsb=uneed - 1) == 3
+
+
 def test_contracted_gemver_and_batax_checks(bto):
     """GEMVER without B and BATAX: workspace sizes and the argument checks,
     before anything is enqueued."""

@@ -397,6 +397,25 @@ def test_full_gemver(env, kind):
 
 
 @pytest.mark.parametrize("kind", ["uniform", "int"])
+def test_full_dgemv_gesummv(env, kind):
+    torch, bto, dev, A, vec = _full_matrix_case(env, kind, 13)
+    B = synth.matrix(SEED, synth.stream_id(3, 9, 13), N, N, kind=kind)
+    x, y = vec(1, N), vec(2, N)
+    al, be = (2.0, 3.0) if kind == "int" else (ALPHA, BETA)
+    z_ref = oracle.dgemv(A, x, y, al, be)
+    g_ref = oracle.gesummv(A, B, x, al, be)
+    Ad, Bd, xd, yd = (dvec(torch, dev, t) for t in (A, B, x, y))
+    for form in FORMS:
+        got = (host(bto.dgemv(Ad, xd, yd, al, be, form=form)),
+               host(bto.gesummv(Ad, Bd, xd, al, be, form=form)))
+        for g, ref in zip(got, (z_ref, g_ref)):
+            if kind == "int":
+                assert np.array_equal(g, ref)
+            else:
+                assert relerr(g, ref) <= TOL
+
+
+@pytest.mark.parametrize("kind", ["uniform", "int"])
 def test_full_dgemvt(env, kind):
     torch, bto, dev, A, vec = _full_matrix_case(env, kind, 12)
     y, z = vec(1, N), vec(2, N)
@@ -467,6 +486,15 @@ def _run_kernel(torch, bto, dev, kernel, form, m, n, pad):
         ref = oracle.gemver(A, u1, v1, u2, v2, y, z, ALPHA, BETA, lda=lda)[1:]
         got = bto.gemver_contracted(dmat(torch, dev, A, n), d(u1), d(v1), d(u2), d(v2), d(y),
                                     d(z), ALPHA, BETA)
+    elif kernel == "gesummv":     # with DGEMV: both are row-dot sweeps of slot gemv_n
+        A, vec = inputs("uniform", m, n, lda, 4, 24)
+        B = synth.matrix(SEED, synth.stream_id(4, 9, 24), m, n, lda=lda)
+        x, y = vec(1, n), vec(2, m)
+        ref = [oracle.dgemv(A, x, y, ALPHA, BETA, lda=lda),
+               oracle.gesummv(A, B, x, ALPHA, BETA, m=m, lda=lda, ldb=lda)]
+        Ad = dmat(torch, dev, A, n)
+        got = [bto.dgemv(Ad, d(x), d(y), ALPHA, BETA, form=form),
+               bto.gesummv(Ad, dmat(torch, dev, B, n), d(x), ALPHA, BETA, form=form)]
     else:
         A, vec = inputs("uniform", m, n, lda, 4, 11)
         y, z = vec(1, m), vec(2, n)
@@ -510,11 +538,104 @@ def test_every_tile_shape(env, slot, shape):
                 got, ref = _run_kernel(torch, bto, dev, "gemver_contracted", form, m, n, pad)
                 for g, r in zip(got, ref):
                     assert relerr(g, r) <= TOL, ("contracted", slot, shape, rb, m, n, pad)
+            if slot == 1:            # and gemv_n serves DGEMV and GESUMMV
+                for f in FORMS:
+                    got, ref = _run_kernel(torch, bto, dev, "gesummv", f, m, n, pad)
+                    for g, r in zip(got, ref):
+                        assert relerr(g, r) <= TOL, ("gesummv", f, shape, rb, m, n, pad)
     finally:
         for b, c in saved.items():
             bto.tune_set(slot, *c, size=256 << b)
         for b, c in saved_rowres.items():
             bto.tune_set(SLOT_BICGK_ROWRES, *c, size=256 << b)
+
+
+# ---- DGEMV and GESUMMV --------------------------------------------------------
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_dgemv(env, m, n, pad, form):
+    torch, bto, dev = env
+    lda = _lda(n, pad)
+    A, vec = inputs("uniform", m, n, lda, 4, 20)
+    x, y = vec(1, n), vec(2, m)
+    z_ref = oracle.dgemv(A, x, y, ALPHA, BETA, lda=lda)
+    z = bto.dgemv(dmat(torch, dev, A, n), dvec(torch, dev, x), dvec(torch, dev, y), ALPHA, BETA,
+                  form=form)
+    assert relerr(host(z), z_ref) <= TOL
+    # in place: z is y itself, as in the BLAS call
+    yd = dvec(torch, dev, y)
+    bto.dgemv(dmat(torch, dev, A, n), dvec(torch, dev, x), yd, ALPHA, BETA, form=form, z=yd)
+    assert np.array_equal(host(yd), host(z))
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("pad", LDA_PAD)
+@pytest.mark.parametrize("m,n", MSHAPES)
+def test_gesummv(env, m, n, pad, form):
+    """A and B with different leading dimensions (B's padding is A's + 5)."""
+    torch, bto, dev = env
+    lda, ldb = _lda(n, pad), _lda(n, pad + 5)
+    A, vec = inputs("uniform", m, n, lda, 4, 21)
+    B = synth.matrix(SEED, synth.stream_id(4, 9, 21), m, n, lda=ldb)
+    x = vec(1, n)
+    y_ref = oracle.gesummv(A, B, x, ALPHA, BETA, m=m, lda=lda, ldb=ldb)
+    y = bto.gesummv(dmat(torch, dev, A, n), dmat(torch, dev, B, n), dvec(torch, dev, x), ALPHA,
+                    BETA, form=form)
+    assert relerr(host(y), y_ref) <= TOL
+
+
+@pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("m,n", [(1, 1), (65, 127), (513, 1000), (2047, 2049), (3000, 64)])
+def test_dgemv_gesummv_integers_exact(env, m, n, form):
+    torch, bto, dev = env
+    A, vec = inputs("int", m, n, n, 4, 22)
+    B = synth.matrix(SEED, synth.stream_id(4, 9, 22), m, n, kind="int")
+    x, y = vec(1, n), vec(2, m)
+    Ad, Bd, xd = dmat(torch, dev, A, n), dmat(torch, dev, B, n), dvec(torch, dev, x)
+    z = bto.dgemv(Ad, xd, dvec(torch, dev, y), 2.0, -3.0, form=form)
+    assert np.array_equal(host(z), oracle.dgemv(A, x, y, 2.0, -3.0))
+    g = bto.gesummv(Ad, Bd, xd, 2.0, 3.0, form=form)
+    assert np.array_equal(host(g), oracle.gesummv(A, B, x, 2.0, 3.0))
+    # B may be A itself; with beta = -alpha the two terms cancel exactly
+    g = bto.gesummv(Ad, Ad, xd, 2.0, -2.0, form=form)
+    assert np.array_equal(host(g), np.zeros(m))
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_dgemv_gesummv_empty_extents(env, form):
+    torch, bto, dev = env
+    rnd = lambda k, s: dvec(torch, dev, synth.uniform(SEED, s, k))
+    y = rnd(4, 2)
+    A = torch.empty((4, 2), dtype=torch.float64, device=dev)[:, :0]
+    z = bto.dgemv(A, rnd(0, 1), y, ALPHA, BETA, form=form)
+    assert np.array_equal(host(z), BETA * host(y))
+    g = bto.gesummv(A, A, rnd(0, 3), ALPHA, BETA, form=form)
+    assert np.array_equal(host(g), np.zeros(4))
+    E = torch.zeros((0, 5), dtype=torch.float64, device=dev)
+    assert bto.dgemv(E, rnd(5, 4), rnd(0, 5), ALPHA, BETA, form=form).numel() == 0
+    assert bto.gesummv(E, E, rnd(5, 6), ALPHA, BETA, form=form).numel() == 0
+
+
+# more row bands than one grid dimension holds with the tuned band height:
+# the launch takes taller bands (up to the most rows the entry points take)
+@pytest.mark.parametrize("m,n", [(300000, 5), (2097100, 2)])
+def test_row_dots_past_the_grid_extent(env, m, n):
+    torch, bto, dev = env
+    A, vec = inputs("uniform", m, n, n, 4, 23)
+    B = synth.matrix(SEED, synth.stream_id(4, 9, 23), m, n)
+    x, y, r = vec(1, n), vec(2, m), vec(3, m)
+    Ad, Bd, xd = dmat(torch, dev, A, n), dmat(torch, dev, B, n), dvec(torch, dev, x)
+    z = bto.dgemv(Ad, xd, dvec(torch, dev, y), ALPHA, BETA)
+    assert relerr(host(z), oracle.dgemv(A, x, y, ALPHA, BETA)) <= TOL
+    g_ref = oracle.gesummv(A, B, x, ALPHA, BETA)
+    for form in FORMS:
+        g = bto.gesummv(Ad, Bd, xd, ALPHA, BETA, form=form)
+        assert relerr(host(g), g_ref) <= TOL
+    q, s = bto.bicgk(Ad, xd, dvec(torch, dev, r), form="unfused")
+    q_ref, s_ref = oracle.bicgk(A, x, r)
+    assert relerr(host(q), q_ref) <= TOL and relerr(host(s), s_ref) <= TOL
 
 
 # ---- GEMVER with B contracted away, and BATAX ---------------------------------------
