@@ -203,6 +203,56 @@ bto_status bto_gesummv(int64_t m, int64_t n, double alpha, double beta,
                        const double *x, double *y, void *ws, size_t ws_bytes,
                        bto_form form, hipStream_t stream);
 
+/* ---- one fused pass over a matrix ----------------------------------------
+ * The building block that the spec compiler (paper_1205_1098_amd/btoc.py)
+ * lowers a program to: one sweep of a row-major m x n matrix with the loop
+ * bodies fused (Section III-C's {p(i){i{j ...}}} nest), then the fixed-order
+ * reductions of its partial sums with their epilogues.  M below is A, or
+ * A + u1 v1^T + u2 v2^T when STORE or CONTRACT is set (pass zero vectors
+ * for a rank-1 update).
+ *   ROWDOT    row_out = row_scale * (M x) + row_add_scale * row_add      (m)
+ *   COLSUM    col_out = col_scale * (M^T y) + col_add_scale * col_add    (n)
+ *   STORE     M is formed and written to B (B may be exactly A, ldb == lda)
+ *   CONTRACT  M is never formed: M x = A x + u1 (v1.x) + u2 (v2.x) and
+ *             M^T y = A^T y + v1 (u1.y) + v2 (u2.y)  (Section III-E); with
+ *             ROWDOT or COLSUM (not both), and an add scale of 1
+ *   CHAIN     with ROWDOT | COLSUM over A alone: the column sums are
+ *             weighted by the row dots themselves, col_out = col_scale *
+ *             A^T (A x), with the row held on chip (ATAX's one-pass form,
+ *             Section IV-A); row_out, y and col_add must be NULL
+ * A NULL row_add or col_add adds nothing.  row_out may be exactly row_add
+ * and col_out exactly col_add; no other output may overlap an operand.
+ * ws: bto_pass_workspace_bytes(ops, m, n) bytes. */
+enum {
+    BTO_PASS_ROWDOT = 1,
+    BTO_PASS_COLSUM = 2,
+    BTO_PASS_STORE = 4,
+    BTO_PASS_CONTRACT = 8,
+    BTO_PASS_CHAIN = 16
+};
+typedef struct {
+    int ops;                      /* BTO_PASS_* flags */
+    int64_t m, n;
+    const double *A;
+    int64_t lda;
+    double *B;                    /* STORE only */
+    int64_t ldb;
+    const double *u1, *v1, *u2, *v2;   /* STORE, CONTRACT: u m, v n */
+    const double *x;              /* ROWDOT weights, n */
+    const double *y;              /* COLSUM weights, m */
+    double *row_out;
+    double row_scale;
+    const double *row_add;
+    double row_add_scale;
+    double *col_out;
+    double col_scale;
+    const double *col_add;
+    double col_add_scale;
+} bto_pass_desc;
+
+size_t bto_pass_workspace_bytes(int ops, int64_t m, int64_t n);
+bto_status bto_pass(const bto_pass_desc *desc, void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* AXPYDOT (Table I, whose scalar result is named beta there):
  *   z <- w - alpha v ;  r <- z^T u.
  * Vectors of length n; r points to ONE double in device memory.  z may be

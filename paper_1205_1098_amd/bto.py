@@ -40,6 +40,22 @@ STATUS = {0: "success", 1: "invalid argument", 2: "illegal operand overlap",
 _i64, _dbl, _ptr, _sz, _int = (ctypes.c_int64, ctypes.c_double, ctypes.c_void_p,
                                ctypes.c_size_t, ctypes.c_int)
 
+class PassDesc(ctypes.Structure):
+    """bto_pass_desc: one fused pass over a row-major matrix."""
+    _fields_ = [("ops", ctypes.c_int), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("u1", ctypes.c_void_p), ("v1", ctypes.c_void_p),
+                ("u2", ctypes.c_void_p), ("v2", ctypes.c_void_p),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("row_out", ctypes.c_void_p), ("row_scale", ctypes.c_double),
+                ("row_add", ctypes.c_void_p), ("row_add_scale", ctypes.c_double),
+                ("col_out", ctypes.c_void_p), ("col_scale", ctypes.c_double),
+                ("col_add", ctypes.c_void_p), ("col_add_scale", ctypes.c_double)]
+
+
+PASS_ROWDOT, PASS_COLSUM, PASS_STORE, PASS_CONTRACT, PASS_CHAIN = 1, 2, 4, 8, 16
+
 _SIGS = {
     "bto_version": ([], _int),
     "bto_workspace_bytes": ([_int, _i64, _i64, _int], _sz),
@@ -58,6 +74,8 @@ _SIGS = {
                   _int),
     "bto_gesummv": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int,
                      _ptr], _int),
+    "bto_pass_workspace_bytes": ([_int, _i64, _i64], _sz),
+    "bto_pass": ([ctypes.POINTER(PassDesc), _ptr, _sz, _ptr], _int),
     "bto_axpydot": ([_i64, _dbl, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_waxpby": ([_i64, _dbl, _ptr, _dbl, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_vadd": ([_i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
@@ -179,9 +197,13 @@ def _stream(dev: torch.device):
     return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
 
 
-def _check_vec(t: torch.Tensor, name: str, dev) -> None:
+def _check_vec(t: torch.Tensor, name: str, dev, n: int | None = None) -> None:
+    """Validate a vector operand; with n, also its length (the C entry points
+    take lengths from the matrix extents and cannot check them)."""
     if t.dtype != torch.float64 or t.dim() != 1:
         raise TypeError(f"{name}: expected a 1-D float64 tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name}: length {t.numel()}, expected {n}")
     if t.device != dev:
         raise ValueError(f"{name}: on {t.device}, expected {dev}")
     if t.numel() > 1 and t.stride(0) != 1:
@@ -221,8 +243,8 @@ def bicgk(A, p, r, form="fused", q=None, s=None, ws=None):
     dev = A.device
     q = _empty(m, dev) if q is None else q
     s = _empty(n, dev) if s is None else s
-    for t, nm in ((p, "p"), (r, "r"), (q, "q"), (s, "s")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((p, "p", n), (r, "r", m), (q, "q", m), (s, "s", n)):
+        _check_vec(t, nm, dev, k)
     f = _form(form)
     ws, wsb = _ws("bicgk", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -241,11 +263,13 @@ def gemver(A, u1, v1, u2, v2, y, z, alpha, beta, form="fused", B=None, x=None, w
     dev = A.device
     B = torch.empty((m, n), dtype=torch.float64, device=dev) if B is None else B
     ldb = _check_mat(B, "B")
+    if tuple(B.shape) != (m, n) or B.device != dev:
+        raise ValueError("B must have A's extents and device")
     x = _empty(n, dev) if x is None else x
     w = _empty(m, dev) if w is None else w
-    for t, nm in ((u1, "u1"), (v1, "v1"), (u2, "u2"), (v2, "v2"), (y, "y"), (z, "z"),
-                  (x, "x"), (w, "w")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((u1, "u1", m), (v1, "v1", n), (u2, "u2", m), (v2, "v2", n), (y, "y", m),
+                     (z, "z", n), (x, "x", n), (w, "w", m)):
+        _check_vec(t, nm, dev, k)
     f = _form(form)
     ws, wsb = _ws("gemver", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -264,9 +288,9 @@ def gemver_contracted(A, u1, v1, u2, v2, y, z, alpha, beta, x=None, w=None, ws=N
     dev = A.device
     x = _empty(n, dev) if x is None else x
     w = _empty(m, dev) if w is None else w
-    for t, nm in ((u1, "u1"), (v1, "v1"), (u2, "u2"), (v2, "v2"), (y, "y"), (z, "z"),
-                  (x, "x"), (w, "w")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((u1, "u1", m), (v1, "v1", n), (u2, "u2", m), (v2, "v2", n), (y, "y", m),
+                     (z, "z", n), (x, "x", n), (w, "w", m)):
+        _check_vec(t, nm, dev, k)
     ws, wsb = _ws("gemver_contracted", m, n, 0, dev, ws)
     with torch.cuda.device(dev):
         _check(_lib.bto_gemver_contracted(m, n, float(alpha), float(beta), _ptr_of(A), lda,
@@ -282,8 +306,8 @@ def batax(A, x, beta, form="fused", y=None, ws=None):
     m, n = A.shape
     dev = A.device
     y = _empty(n, dev) if y is None else y
-    _check_vec(x, "x", dev)
-    _check_vec(y, "y", dev)
+    _check_vec(x, "x", dev, n)
+    _check_vec(y, "y", dev, n)
     f = _form(form)
     ws, wsb = _ws("batax", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -298,8 +322,8 @@ def atax(A, x, form="fused", y=None, ws=None):
     m, n = A.shape
     dev = A.device
     y = _empty(n, dev) if y is None else y
-    _check_vec(x, "x", dev)
-    _check_vec(y, "y", dev)
+    _check_vec(x, "x", dev, n)
+    _check_vec(y, "y", dev, n)
     f = _form(form)
     ws, wsb = _ws("atax", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -315,8 +339,8 @@ def dgemvt(A, y, z, alpha, beta, form="fused", x=None, w=None, ws=None):
     dev = A.device
     x = _empty(n, dev) if x is None else x
     w = _empty(m, dev) if w is None else w
-    for t, nm in ((y, "y"), (z, "z"), (x, "x"), (w, "w")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((y, "y", m), (z, "z", n), (x, "x", n), (w, "w", m)):
+        _check_vec(t, nm, dev, k)
     f = _form(form)
     ws, wsb = _ws("dgemvt", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -332,8 +356,8 @@ def dgemv(A, x, y, alpha, beta, form="fused", z=None, ws=None):
     m, n = A.shape
     dev = A.device
     z = _empty(m, dev) if z is None else z
-    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((x, "x", n), (y, "y", m), (z, "z", m)):
+        _check_vec(t, nm, dev, k)
     f = _form(form)
     ws, wsb = _ws("dgemv", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -353,8 +377,8 @@ def gesummv(A, B, x, alpha, beta, form="fused", y=None, ws=None):
     if B.device != dev:
         raise ValueError("A and B must be on the same device")
     y = _empty(m, dev) if y is None else y
-    _check_vec(x, "x", dev)
-    _check_vec(y, "y", dev)
+    _check_vec(x, "x", dev, n)
+    _check_vec(y, "y", dev, m)
     f = _form(form)
     ws, wsb = _ws("gesummv", m, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -363,14 +387,54 @@ def gesummv(A, B, x, alpha, beta, form="fused", y=None, ws=None):
     return y
 
 
+def pass_workspace_bytes(ops: int, m: int, n: int) -> int:
+    return int(_lib.bto_pass_workspace_bytes(int(ops), m, n))
+
+
+def fused_pass(ops, A, *, B=None, u1=None, v1=None, u2=None, v2=None, x=None, y=None,
+               row_out=None, row_scale=1.0, row_add=None, row_add_scale=1.0,
+               col_out=None, col_scale=1.0, col_add=None, col_add_scale=1.0, ws=None):
+    """One fused pass over A (bto_pass): the row dots and/or column sums of
+    A, or of A + u1 v1^T + u2 v2^T (stored in B with PASS_STORE, never
+    formed with PASS_CONTRACT), each reduced with its scale and add.
+    Every output must be given; nothing is allocated but the workspace
+    when ws is None."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    ldb = 0
+    if B is not None:
+        ldb = _check_mat(B, "B")
+        if tuple(B.shape) != (m, n):
+            raise ValueError("B must have A's extents")
+    for t, nm, k in ((u1, "u1", m), (v1, "v1", n), (u2, "u2", m), (v2, "v2", n), (x, "x", n),
+                     (y, "y", m), (row_out, "row_out", m), (row_add, "row_add", m),
+                     (col_out, "col_out", n), (col_add, "col_add", n)):
+        if t is not None:
+            _check_vec(t, nm, dev, k)
+    need = pass_workspace_bytes(ops, m, n)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    d = PassDesc(int(ops), m, n, A.data_ptr(), lda, _addr(B), ldb, _addr(u1), _addr(v1),
+                 _addr(u2), _addr(v2), _addr(x), _addr(y), _addr(row_out), float(row_scale),
+                 _addr(row_add), float(row_add_scale), _addr(col_out), float(col_scale),
+                 _addr(col_add), float(col_add_scale))
+    with torch.cuda.device(dev):
+        _check(_lib.bto_pass(ctypes.byref(d), _ptr_of(ws), ws.numel(), _stream(dev)))
+
+
+def _addr(t):
+    return None if t is None else t.data_ptr()
+
+
 def axpydot(w, v, u, alpha, form="fused", z=None, r=None, ws=None):
     """z = w - alpha v ; r = z^T u.  Returns (z, r) with r a 1-element tensor."""
     dev = w.device
     n = w.numel()
     z = _empty(n, dev) if z is None else z
     r = _empty(1, dev) if r is None else r
-    for t, nm in ((w, "w"), (v, "v"), (u, "u"), (z, "z"), (r, "r")):
-        _check_vec(t, nm, dev)
+    for t, nm, k in ((w, "w", n), (v, "v", n), (u, "u", n), (z, "z", n), (r, "r", 1)):
+        _check_vec(t, nm, dev, k)
     f = _form(form)
     ws, wsb = _ws("axpydot", 0, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -385,7 +449,7 @@ def waxpby(x, y, alpha, beta, form="fused", w=None, ws=None):
     n = x.numel()
     w = _empty(n, dev) if w is None else w
     for t, nm in ((x, "x"), (y, "y"), (w, "w")):
-        _check_vec(t, nm, dev)
+        _check_vec(t, nm, dev, n)
     f = _form(form)
     ws, wsb = _ws("waxpby", 0, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -400,7 +464,7 @@ def vadd(w, y, z, form="fused", x=None, ws=None):
     n = w.numel()
     x = _empty(n, dev) if x is None else x
     for t, nm in ((w, "w"), (y, "y"), (z, "z"), (x, "x")):
-        _check_vec(t, nm, dev)
+        _check_vec(t, nm, dev, n)
     f = _form(form)
     ws, wsb = _ws("vadd", 0, n, f, dev, ws)
     with torch.cuda.device(dev):
@@ -560,12 +624,18 @@ def _batch_descs(instances):
             refs.append(B)
         else:
             d.ldb = lda
+        m_, n_ = A.shape
+        lens_in, lens_out = {"gemver": ((m_, n_, m_, n_, m_, n_), (n_, m_)),
+                             "bicgk": ((n_, m_), (m_, n_)),
+                             "atax": ((n_,), (n_,))}.get(inst["kind"], ((), ()))
+        if len(inst["in"]) != len(lens_in) or len(inst["out"]) != len(lens_out):
+            raise ValueError(f"instance {i}: wrong number of vector operands")
         for k, t in enumerate(inst["in"]):
-            _check_vec(t, f"in[{k}]", A.device)
+            _check_vec(t, f"in[{k}]", A.device, lens_in[k])
             d.inp[k] = t.data_ptr()
             refs.append(t)
         for k, t in enumerate(inst["out"]):
-            _check_vec(t, f"out[{k}]", A.device)
+            _check_vec(t, f"out[{k}]", A.device, lens_out[k])
             d.out[k] = t.data_ptr()
             refs.append(t)
         keep.append(refs)

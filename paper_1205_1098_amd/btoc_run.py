@@ -1,0 +1,144 @@
+"""Runs a compiled specification (btoc.Program) on a ROCm device.
+
+Every step is one call of the C library on the current torch stream: a
+fused pass (``bto_pass``) or a scaled vector sum (``bto_waxpby``).  This
+module only binds names to tensors, allocates what the program writes and
+is not given, and evaluates the scalar coefficients (products of input
+scalars and literals) on the host.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import bto
+from .btoc import Pass, SpecError, VecOp
+
+
+def _coef(c, scalars):
+    v = c[0]
+    for s in c[1]:
+        v *= scalars[s]
+    return v
+
+
+def run(prog, bound: dict, ws=None) -> dict:
+    """Enqueue the program.  `bound` maps every input to a tensor (matrices
+    (m, n) row-major float64, vectors 1-D float64) or a float (scalars); an
+    output may be bound too, to a tensor of the right shape that receives
+    it.  Returns the outputs by name."""
+    env, scalars = {}, {}
+    dev = None
+    for name in prog.inputs:
+        if name not in bound:
+            raise SpecError(f"input {name} is not bound")
+        if prog.kinds[name] == "scalar":
+            scalars[name] = float(bound[name])
+        else:
+            t = bound[name]
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+                raise SpecError(f"{name}: expected a float64 tensor")
+            want = 2 if prog.kinds[name] == "matrix" else 1
+            if t.dim() != want:
+                raise SpecError(f"{name}: expected a {want}-D tensor")
+            dev = t.device if dev is None else dev
+            env[name] = t
+    if dev is None:
+        raise SpecError("the program has no tensor input")
+    given = {o: bound[o] for o in prog.outputs if o in bound}
+    zeros = {}
+
+    def zero(k):
+        if k not in zeros:
+            zeros[k] = torch.zeros(k, dtype=torch.float64, device=dev)
+        return zeros[k]
+
+    def vec_out(name, k):
+        if name in env:
+            t = env[name]
+        elif name in given:
+            t = given[name]
+        else:
+            t = torch.empty(k, dtype=torch.float64, device=dev)
+        if t.dim() != 1 or t.numel() != k:
+            raise SpecError(f"{name}: expected a vector of length {k}")
+        env[name] = t
+        return t
+
+    def mat_out(name, m, n):
+        t = env.get(name, given.get(name))
+        if t is None:
+            t = torch.empty((m, n), dtype=torch.float64, device=dev)
+        if tuple(t.shape) != (m, n):
+            raise SpecError(f"{name}: expected an ({m}, {n}) matrix")
+        env[name] = t
+        return t
+
+    def get(name):
+        if name not in env:
+            raise SpecError(f"{name} is read before it is written")
+        return env[name]
+
+    need = max([bto.pass_workspace_bytes(_ops(s), *get_shape(s, env)) for s in prog.steps
+                if isinstance(s, Pass) and s.base in env] + [1])
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+
+    for s in prog.steps:
+        if isinstance(s, VecOp):
+            x, y = get(s.x), get(s.y)
+            out = vec_out(s.out, x.numel())
+            bto.waxpby(x, y, _coef(s.a, scalars), _coef(s.b, scalars), w=out)
+            continue
+        A = get(s.base)
+        m, n = A.shape
+        kw = {}
+        if s.store or s.contract:
+            us = [get(u) for u, _ in s.terms] + [zero(m)] * (2 - len(s.terms))
+            vs = [get(v) for _, v in s.terms] + [zero(n)] * (2 - len(s.terms))
+            kw.update(u1=us[0], v1=vs[0], u2=us[1], v2=vs[1])
+        if s.store:
+            kw["B"] = mat_out(s.store, m, n)
+        if s.row is not None:
+            r = s.row
+            kw["x"] = get(r["x"])
+            if r["out"] is not None:
+                kw["row_out"] = vec_out(r["out"], m)
+                kw["row_scale"] = _coef(r["scale"], scalars)
+                if r["add"] is not None:
+                    kw["row_add"] = get(r["add"])
+                    kw["row_add_scale"] = _coef(r["add_scale"], scalars)
+        if s.col is not None:
+            c = s.col
+            if c["y"] is not None:
+                kw["y"] = get(c["y"])
+            kw["col_out"] = vec_out(c["out"], n)
+            kw["col_scale"] = _coef(c["scale"], scalars)
+            if c["add"] is not None:
+                kw["col_add"] = get(c["add"])
+                kw["col_add_scale"] = _coef(c["add_scale"], scalars)
+        # the workspace need depends on the pass's extents, known only now
+        k = bto.pass_workspace_bytes(_ops(s), m, n)
+        if ws.numel() < k:
+            ws = torch.empty(k, dtype=torch.uint8, device=dev)
+        bto.fused_pass(_ops(s), A, ws=ws, **kw)
+    return {o: env[o] for o in prog.outputs}
+
+
+def get_shape(s, env):
+    return tuple(env[s.base].shape)
+
+
+def _ops(s: Pass) -> int:
+    ops = 0
+    if s.row is not None:
+        ops |= bto.PASS_ROWDOT
+    if s.col is not None:
+        ops |= bto.PASS_COLSUM
+    if s.store:
+        ops |= bto.PASS_STORE
+    if s.contract:
+        ops |= bto.PASS_CONTRACT
+    if s.chain:
+        ops |= bto.PASS_CHAIN
+    return ops

@@ -38,7 +38,7 @@ bto_status fail(bto_status s, const std::string &msg)
 std::mutex g_cfg_mu;
 TileCfg g_cfg[SLOT_COUNT][kSizeBuckets] = BTO_TUNED_DEFAULTS;
 
-constexpr int kMinKv = 2;
+constexpr int kMinKv = kMinTileKv;
 constexpr int kMinRb = 32;
 
 TileCfg cfg_of(Slot s, int64_t m, int64_t n)
@@ -771,6 +771,151 @@ bto_status bto_gesummv(int64_t m, int64_t n, double alpha, double beta, const do
         if (!launch_tile(kSlotNames[SLOT_GEMV_N], OP_ROWDOT, c, b, st))
             return unsupported(SLOT_GEMV_N);
         launch_finish_lin("finish", flin(a.Prow, np, m, beta, nullptr, 0, 0.0, t, 1.0, y), st);
+    }
+    return check_launch();
+}
+
+// ---- one fused pass -----------------------------------------------------------
+
+size_t bto_pass_workspace_bytes(int ops, int64_t m, int64_t n)
+{
+    if (m < 0 || n < 0 || (ops & ~31) != 0)
+        return 0;
+    if (ops & BTO_PASS_CHAIN)
+        return ws_bytes(BTO_K_ATAX, m, n, BTO_FUSED);
+    // the tile partials and the auxiliary dots of a contracted pass
+    return ws_bytes(BTO_K_GEMVER_CONTRACTED, m, n, BTO_FUSED);
+}
+
+bto_status bto_pass(const bto_pass_desc *d, void *ws, size_t ws_bytes_, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(d != nullptr, "pass descriptor is NULL"));
+    const int ops = d->ops;
+    const bool R = ops & BTO_PASS_ROWDOT, C = ops & BTO_PASS_COLSUM;
+    const bool S = ops & BTO_PASS_STORE, K = ops & BTO_PASS_CONTRACT, H = ops & BTO_PASS_CHAIN;
+    const int64_t m = d->m, n = d->n;
+    BTO_TRY(need((ops & ~31) == 0, "unknown pass operation"));
+    BTO_TRY(need(R || C || S, "the pass computes nothing"));
+    BTO_TRY(need(!(S && K), "STORE and CONTRACT exclude each other"));
+    BTO_TRY(need(!K || R || C, "CONTRACT needs ROWDOT or COLSUM"));
+    BTO_TRY(need(!H || (R && C && !S && !K), "CHAIN takes ROWDOT | COLSUM over A alone"));
+    BTO_TRY(check_matrix(m, n, d->A, d->lda, "A"));
+    if (H) {
+        BTO_TRY(need(!d->row_out && !d->y && !d->col_add && !d->row_add,
+                     "CHAIN takes no row output, column weights or adds"));
+        return atax_scaled(BTO_K_ATAX, m, n, d->col_scale, d->A, d->lda, d->x, d->col_out, ws,
+                           ws_bytes_, BTO_FUSED, st);
+    }
+    if (K && R && C)
+        return fail(BTO_ERR_UNSUPPORTED, "a contracted pass takes row dots or column sums, not both");
+    if (K && ((R && d->row_add && d->row_add_scale != 1.0) ||
+              (C && d->col_add && d->col_add_scale != 1.0)))
+        return fail(BTO_ERR_UNSUPPORTED, "a contracted pass adds its vector with scale 1");
+    if (S)
+        BTO_TRY(check_matrix(m, n, d->B, d->ldb, "B"));
+    if (S || K) {
+        BTO_TRY(check_vec(d->u1, m, "u1"));
+        BTO_TRY(check_vec(d->v1, n, "v1"));
+        BTO_TRY(check_vec(d->u2, m, "u2"));
+        BTO_TRY(check_vec(d->v2, n, "v2"));
+    }
+    if (R) {
+        BTO_TRY(check_vec(d->x, n, "x"));
+        BTO_TRY(check_vec(d->row_out, m, "row_out"));
+    }
+    if (C) {
+        BTO_TRY(check_vec(d->y, m, "y"));
+        BTO_TRY(check_vec(d->col_out, n, "col_out"));
+    }
+    const size_t need_ws = bto_pass_workspace_bytes(ops, m, n);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    const bool UV = S || K;
+    // operands the pass does not use (or leaves NULL) take part as empty spans
+    auto vs = [](const char *nm, const void *p, int64_t k, bool out, bool used) {
+        return vspan(nm, p, used && p ? k : 0, out);
+    };
+    BTO_TRY(check_aliases(
+        {mspan("A", d->A, m, n, d->lda, false), mspan("B", d->B, S ? m : 0, n, d->ldb, true),
+         vs("u1", d->u1, m, false, UV), vs("v1", d->v1, n, false, UV),
+         vs("u2", d->u2, m, false, UV), vs("v2", d->v2, n, false, UV),
+         vs("x", d->x, n, false, R), vs("y", d->y, m, false, C),
+         vs("row_out", d->row_out, m, true, R), vs("row_add", d->row_add, m, false, R),
+         vs("col_out", d->col_out, n, true, C), vs("col_add", d->col_add, n, false, C),
+         wspan(ws, need_ws)},
+        {{"B", "A"}, {"row_out", "row_add"}, {"col_out", "col_add"}}));
+
+    Carve cv(ws);
+    double *Prow = cv.take(max_ncols(n) * m);
+    double *Pcol = cv.take(max_nbands(m) * n);
+    double *aux1 = cv.take(2 * max_nbands(m));   // u1.y, u2.y per row band
+    double *aux2 = cv.take(2 * max_ncols(n));    // v1.x, v2.x per wave tile
+    TileArgs a = targs(m, n, d->A, d->lda);
+    int tops = 0;
+    if (UV) {
+        a.u1 = d->u1;
+        a.v1 = d->v1;
+        a.u2 = d->u2;
+        a.v2 = d->v2;
+    }
+    if (S) {
+        a.B = d->B;
+        a.ldb = d->ldb;
+        tops |= OP_UPD1 | OP_UPD2;
+    }
+    if (R) {
+        a.xr = d->x;
+        a.Prow = Prow;
+        tops |= OP_ROWDOT;
+    }
+    if (C) {
+        a.yc = d->y;
+        a.Pcol = Pcol;
+        tops |= OP_COLSUM;
+    }
+    if (K) {
+        tops |= OP_AUX;
+        if (C)
+            a.Prow = aux1;
+        else
+            a.Pcol = aux2;
+    }
+    // the slot whose tuned configuration serves this operation mix
+    Slot slot;
+    if (S)
+        slot = SLOT_GEMVER_P1;
+    else if (K)
+        slot = C ? SLOT_DGEMVT_P1 : SLOT_DGEMVT_P2;
+    else if (R && C)
+        slot = SLOT_BICGK_FUSED;
+    else
+        slot = R ? SLOT_GEMV_N : SLOT_GEMV_T;
+    const TileCfg c = cfg_of(slot, m, n);
+    if (!launch_tile(kSlotNames[slot], tops, c, a, st))
+        return unsupported(slot);
+    if (R) {
+        const int64_t np = n > 0 ? tile_ncols(c, n) : 0;
+        if (K)
+            launch_finish_aux("finish",
+                              {fjob(Prow, np, m, d->row_scale, d->row_add, d->row_out), aux2,
+                               m > 0 ? np : 0, d->u1, d->u2},
+                              st);
+        else
+            launch_finish_lin("finish", flin(Prow, np, m, d->row_scale, nullptr, 0, 0.0, d->row_add,
+                                             d->row_add_scale, d->row_out),
+                              st);
+    }
+    if (C) {
+        const int64_t nb = m > 0 ? tile_nbands(c, m) : 0;
+        if (K)
+            launch_finish_aux("finish",
+                              {fjob(Pcol, nb, n, d->col_scale, d->col_add, d->col_out), aux1,
+                               n > 0 ? nb : 0, d->v1, d->v2},
+                              st);
+        else
+            launch_finish_lin("finish", flin(Pcol, nb, n, d->col_scale, nullptr, 0, 0.0, d->col_add,
+                                             d->col_add_scale, d->col_out),
+                              st);
     }
     return check_launch();
 }

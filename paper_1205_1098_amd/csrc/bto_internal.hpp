@@ -89,6 +89,9 @@ struct TileArgs {
 
 // Shapes 0..5 serve read-only sweeps, 6..14 sweeps that store B.
 constexpr int kTileShapes = 15;
+// The narrowest wave tile of any shape, in 16-byte pairs per lane: row-dot
+// partials ([wave tiles][m]) are sized for it.
+constexpr int kMinTileKv = 1;
 bool tile_cfg_supported(int ops, const TileCfg &c);
 int tile_kv(const TileCfg &c);
 void tile_shape_info(int shape, int out[4]);   // kv, depth, waves across, waves down

@@ -299,7 +299,7 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_tile(TileArgs a, int rb, int 
 struct Shape {
     int kv, d, wc, wr;
 };
-const Shape kShapes[] = {
+constexpr Shape kShapes[] = {
     // read-only sweeps (row dots, column sums, both)
     {8, 2, 4, 1}, {8, 1, 4, 4}, {4, 2, 8, 2}, {4, 2, 4, 4}, {4, 4, 4, 1}, {8, 2, 4, 2},
     // sweeps that store B
@@ -309,6 +309,11 @@ const Shape kShapes[] = {
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 static_assert(kNumShapes == kTileShapes, "the shape table and the C interface disagree");
+constexpr bool kv_at_least(int i, int kv)
+{
+    return i == kNumShapes || (kShapes[i].kv >= kv && kv_at_least(i + 1, kv));
+}
+static_assert(kv_at_least(0, kMinTileKv), "a shape is narrower than the row-dot partials allow");
 constexpr int kFirstWriteShape = 6;
 
 bool shape_allowed(int ops, int shape)
@@ -384,6 +389,13 @@ void dispatch_tile(const char *name, int ops, const TileCfg &c, const TileArgs &
     case OP_UPD1: launch_tile_ops<OP_UPD1>(name, c, a, st); break;
     case OP_UPD1 | OP_UPD2 | OP_COLSUM:
         launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_COLSUM>(name, c, a, st);
+        break;
+    case OP_UPD1 | OP_UPD2: launch_tile_ops<OP_UPD1 | OP_UPD2>(name, c, a, st); break;
+    case OP_UPD1 | OP_UPD2 | OP_ROWDOT:
+        launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_ROWDOT>(name, c, a, st);
+        break;
+    case OP_UPD1 | OP_UPD2 | OP_ROWDOT | OP_COLSUM:
+        launch_tile_ops<OP_UPD1 | OP_UPD2 | OP_ROWDOT | OP_COLSUM>(name, c, a, st);
         break;
     case OP_COLSUM | OP_AUX: launch_tile_ops<OP_COLSUM | OP_AUX>(name, c, a, st); break;
     case OP_ROWDOT | OP_AUX: launch_tile_ops<OP_ROWDOT | OP_AUX>(name, c, a, st); break;

@@ -165,10 +165,17 @@ def test_in_place_gemver_batch(env):
 def test_batch_rejects_overlap(env):
     torch, bto = env
     insts, _ = batch.make_instances(torch, bto, 3, 64, 128, {"bicgk": 1.0}, seed=14)
-    insts[1]["out"][0] = insts[0]["out"][0]       # two instances write one vector
+    # two instances' outputs share an element: views of one buffer, each of
+    # its instance's length
+    n0, n1 = insts[0]["out"][0].numel(), insts[1]["out"][0].numel()
+    buf = torch.empty(n0 + n1 - 1, dtype=torch.float64, device=insts[0]["A"].device)
+    insts[0]["out"][0], insts[1]["out"][0] = buf[:n0], buf[n0 - 1:]
     with pytest.raises(bto.BtoError) as e:
         bto.BatchPlan(insts)
     assert e.value.status == 2
+    insts[1]["out"][0] = torch.empty(n1 + 1, dtype=torch.float64, device=buf.device)
+    with pytest.raises(ValueError, match="length"):
+        bto.BatchPlan(insts)
 
 
 def test_refilled_plan_matches_fresh_plans(env):
@@ -371,7 +378,9 @@ def test_tiled_batch_refuses_other_work(env):
     with pytest.raises(bto.BtoError):
         bto.TiledBatch(un)
     ov, _ = batch.make_instances(torch, bto, 3, 64, 128, {"bicgk": 1.0}, seed=36)
-    ov[1]["out"][0] = ov[0]["out"][0]
+    n0, n1 = ov[0]["out"][0].numel(), ov[1]["out"][0].numel()
+    buf = torch.empty(n0 + n1 - 1, dtype=torch.float64, device=ov[0]["A"].device)
+    ov[0]["out"][0], ov[1]["out"][0] = buf[:n0], buf[n0 - 1:]   # one shared element
     with pytest.raises(bto.BtoError) as e:
         bto.TiledBatch(ov)
     assert e.value.status == 2

@@ -1,0 +1,132 @@
+"""Compiled specifications on the GPU against the reference evaluation of
+the same specification (oracle/spec_eval.py): every Table I kernel, Fig. 1's
+BATAX, GEMVER with B contracted, and programs outside the paper's suite,
+in both forms, on ragged shapes; integer-valued data must match bitwise."""
+
+import numpy as np
+import pytest
+
+from oracle import spec_eval
+from paper_1205_1098_amd import synth
+from tests import specs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+SEED = synth.SEED
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_1205_1098_amd import btoc
+
+    return torch, btoc, torch.device("cuda:0")
+
+
+# input name -> "A" (an m x n matrix), "m" / "n" (vector lengths) or a scalar value
+GEMVER_IN = dict(A="A", u1="m", v1="n", u2="m", v2="n", y="m", z="n", alpha=1.5, beta=0.7)
+PROGRAMS = {
+    "bicgk": (specs.TABLE_I["bicgk"], dict(A="A", p="n", r="m"), False),
+    "gemver": (specs.TABLE_I["gemver"], GEMVER_IN, False),
+    "atax": (specs.TABLE_I["atax"], dict(A="A", x="n"), False),
+    "dgemvt": (specs.TABLE_I["dgemvt"], dict(A="A", y="m", z="n", alpha=1.5, beta=0.7), False),
+    "dgemv": (specs.TABLE_I["dgemv"], dict(A="A", x="n", y="m", alpha=1.5, beta=0.7), False),
+    "gesummv": (specs.TABLE_I["gesummv"], dict(A="A", B="A", x="n", alpha=1.5, beta=0.7), False),
+    "batax": (specs.BATAX, dict(A="A", x="n", beta=0.7), False),
+    "gemver_contracted": (specs.GEMVER_CONTRACTED, GEMVER_IN, False),
+    "both_ways": (specs.NOVEL["both_ways"], dict(A="A", x="n", w="m"), True),
+    "atax_plus": (specs.NOVEL["atax_plus"], dict(A="A", x="n", z="n"), False),
+    "rank1_stored": (specs.NOVEL["rank1_stored"], dict(A="A", u="m", v="n", p="n", r="m"),
+                     False),
+    "rank1_contracted": (specs.NOVEL["rank1_contracted"],
+                         dict(A="A", u="m", v="n", x="n", y="m", gamma=1.25), False),
+    "two_dots": (specs.NOVEL["two_dots"], dict(A="A", x="n"), True),
+    "mixed": (specs.NOVEL["mixed"], dict(A="A", x="n", y="m", w="m", alpha=0.5), False),
+}
+SHAPES = [(1, 1), (65, 127), (513, 1000), (300, 4097), (2047, 2049)]
+SQUARE = [(1, 1), (127, 127), (1000, 1000), (2049, 2049)]
+
+
+def _inputs(kinds, m, n, kind, case):
+    host = {}
+    for k, (name, what) in enumerate(sorted(kinds.items())):
+        stream = synth.stream_id(9, k, case)
+        if what == "A":
+            # a second matrix operand ("B") gets its own stream
+            host[name] = synth.matrix(SEED, stream, m, n, kind=kind)
+        elif what in ("m", "n"):
+            host[name] = synth.vector(SEED, stream, m if what == "m" else n, kind)
+        else:
+            host[name] = float(what) if kind == "uniform" else float(round(2 * what) or 2)
+    return host
+
+
+def _relerr(got, ref):
+    got, ref = np.asarray(got), np.asarray(ref)
+    assert got.shape == ref.shape
+    if ref.size == 0:
+        return 0.0
+    den = float(np.max(np.abs(ref)))
+    num = float(np.max(np.abs(got - ref)))
+    return num / den if den > 0 else num
+
+
+def _cases():
+    out = []
+    for name, (_, _, square) in sorted(PROGRAMS.items()):
+        for m, n in (SQUARE if square else SHAPES):
+            out.append((name, m, n))
+    return out
+
+
+@pytest.mark.parametrize("form", ["fused", "unfused"])
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+@pytest.mark.parametrize("name,m,n", _cases())
+def test_compiled_program(env, name, m, n, kind, form):
+    torch, btoc, dev = env
+    text, kinds, _ = PROGRAMS[name]
+    case = 31 * m + n
+    host = _inputs(kinds, m, n, kind, case)
+    ref = spec_eval.evaluate(text, host)
+    prog = btoc.compile_spec(text, form)
+    bound = {k: (torch.from_numpy(np.ascontiguousarray(v)).to(dev) if isinstance(v, np.ndarray)
+                 else v) for k, v in host.items()}
+    out = prog.run(**bound)
+    torch.cuda.synchronize()
+    for o, r in ref.items():
+        got = out[o].cpu().numpy()
+        if kind == "int":
+            assert np.array_equal(got, r), (name, o)
+        else:
+            assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
+
+
+def test_outputs_bound_by_the_caller_receive_the_results(env):
+    torch, btoc, dev = env
+    text, kinds, _ = PROGRAMS["gemver"]
+    host = _inputs(kinds, 300, 200, "uniform", 5)
+    d = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+         for k, v in host.items()}
+    B = torch.empty((300, 200), dtype=torch.float64, device=dev)
+    x = torch.empty(200, dtype=torch.float64, device=dev)
+    w = torch.empty(300, dtype=torch.float64, device=dev)
+    out = btoc.compile_spec(text).run(**d, B=B, x=x, w=w)
+    assert out["B"] is B and out["x"] is x and out["w"] is w
+    ref = spec_eval.evaluate(text, host)
+    for o, t in (("B", B), ("x", x), ("w", w)):
+        assert _relerr(t.cpu().numpy(), ref[o]) <= TOL
+
+
+def test_wrong_lengths_are_refused_before_launch(env):
+    torch, btoc, dev = env
+    prog = btoc.compile_spec(specs.TABLE_I["dgemv"])
+    A = torch.zeros((40, 30), dtype=torch.float64, device=dev)
+    x = torch.zeros(31, dtype=torch.float64, device=dev)
+    y = torch.zeros(40, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError, match="length"):
+        prog.run(A=A, x=x, y=y, alpha=1.0, beta=1.0)
+    with pytest.raises(btoc.SpecError, match="not bound"):
+        prog.run(A=A, x=x[:30], alpha=1.0, beta=1.0)

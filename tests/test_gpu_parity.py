@@ -322,8 +322,10 @@ def test_errors_raise(env):
         bto.bicgk(A, p, p, ws=small)
     assert e.value.status == 3
     with pytest.raises(bto.BtoError) as e:
-        bto.bicgk(A, p, p, q=A[0], s=A[0, 1:].clone())
-    assert e.value.status == 2
+        bto.bicgk(A, p, p, q=A[0], s=torch.empty(64, dtype=torch.float64, device=dev))
+    assert e.value.status == 2          # q lies inside A
+    with pytest.raises(ValueError, match="length"):
+        bto.bicgk(A, p, p, s=torch.empty(63, dtype=torch.float64, device=dev))
     with pytest.raises(bto.BtoError) as e:
         buf = torch.zeros(200, dtype=torch.float64, device=dev)
         bto.vadd(buf[:100], buf[100:], buf[100:], x=buf[50:150])
@@ -548,6 +550,45 @@ def test_every_tile_shape(env, slot, shape):
             bto.tune_set(slot, *c, size=256 << b)
         for b, c in saved_rowres.items():
             bto.tune_set(SLOT_BICGK_ROWRES, *c, size=256 << b)
+
+
+# ---- one fused pass (bto_pass) on every shape of the sweeps that store B ---------
+#
+# A pass that stores the update and also takes row dots runs the store
+# shapes, some of them one 16-byte pair wide per lane: its row-dot partials
+# must fit the workspace next to the column-sum partials.
+
+@pytest.mark.parametrize("shape", range(6, 15))
+def test_store_pass_every_shape(env, shape):
+    torch, bto, dev = env
+    slot = 4     # gemver_p1: the configuration a storing pass takes
+    saved = {b: bto.tune_get(slot, 256 << b) for b in range(bto.tune_buckets())}
+    try:
+        for b in range(bto.tune_buckets()):
+            bto.tune_set(slot, shape, 32, 1, size=256 << b)
+        for m, n, pad in [(513, 1000, 0), (300, 300, 3), (65, 127, 0)]:
+            lda = _lda(n, pad)
+            A, vec = inputs("uniform", m, n, lda, 2, 25)
+            u1, v1, u2, v2, p, r = vec(1, m), vec(2, n), vec(3, m), vec(4, n), vec(5, n), vec(6, m)
+            B_ref = oracle.gemver(A, u1, v1, u2, v2, r, p, 1.0, 1.0, lda=lda)[0]
+            q_ref, s_ref = oracle.bicgk(B_ref, p, r)
+            d = lambda a: dvec(torch, dev, a)
+            for ops in (bto.PASS_STORE | bto.PASS_ROWDOT,
+                        bto.PASS_STORE | bto.PASS_ROWDOT | bto.PASS_COLSUM):
+                Bd = torch.empty((m, n), dtype=torch.float64, device=dev)
+                q = torch.empty(m, dtype=torch.float64, device=dev)
+                s = torch.empty(n, dtype=torch.float64, device=dev)
+                kw = dict(B=Bd, u1=d(u1), v1=d(v1), u2=d(u2), v2=d(v2), x=d(p), row_out=q)
+                if ops & bto.PASS_COLSUM:
+                    kw.update(y=d(r), col_out=s)
+                bto.fused_pass(ops, dmat(torch, dev, A, n), **kw)
+                assert relerr(host(Bd), B_ref) <= TOL, (shape, m, n, ops)   # FMA may form B
+                assert relerr(host(q), q_ref) <= TOL, (shape, m, n, ops)
+                if ops & bto.PASS_COLSUM:
+                    assert relerr(host(s), s_ref) <= TOL, (shape, m, n, ops)
+    finally:
+        for b, c in saved.items():
+            bto.tune_set(slot, *c, size=256 << b)
 
 
 # ---- DGEMV and GESUMMV --------------------------------------------------------
