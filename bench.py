@@ -15,6 +15,8 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
   suite       every Table I kernel, fused and unfused, at n = 16384 / 2^26
               (DGEMV and GESUMMV included), plus GEMVER with B contracted away
               (against GEMVER's two forms) and BATAX (y = beta A^T A x)
+  generated   the same kernels compiled from their specifications (btoc),
+              against the hand-written fused entry points
   stream      measured copy / read / triad ceilings at 2 GiB per array
   batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
               one persistent graph-captured launch, and the same instances as
@@ -287,6 +289,58 @@ def cpu_baseline(kernel: str, target_s: float):
     }
 
 
+# the compiled specifications timed against the hand-written fused entry
+# points (same algorithmic bytes); input name -> "A", "B" (matrices), "m" /
+# "n" (vectors) or a scalar value
+GENERATED = {
+    "gemver": dict(A="A", u1="m", v1="n", u2="m", v2="n", y="m", z="n", alpha=ALPHA, beta=BETA),
+    "gemver_contracted": dict(A="A", u1="m", v1="n", u2="m", v2="n", y="m", z="n",
+                              alpha=ALPHA, beta=BETA),
+    "bicgk": dict(A="A", p="n", r="m"),
+    "atax": dict(A="A", x="n"),
+    "batax": dict(A="A", x="n", beta=BETA),
+    "dgemvt": dict(A="A", y="m", z="n", alpha=ALPHA, beta=BETA),
+    "dgemv": dict(A="A", x="n", y="m", alpha=ALPHA, beta=BETA),
+    "gesummv": dict(A="A", B="B", x="n", alpha=ALPHA, beta=BETA),
+}
+
+
+def bench_generated(torch, bto, synth, shared, suite) -> dict:
+    """Each kernel compiled from its specification (btoc) and run through
+    the fused-pass entry point, against the suite's hand-written fused time."""
+    from paper_1205_1098_amd import bto_specs, btoc
+
+    dev = shared["A"].device
+    out = {}
+    for k, kinds in GENERATED.items():
+        text = {"batax": bto_specs.BATAX, "gemver_contracted": bto_specs.GEMVER_CONTRACTED}.get(
+            k, bto_specs.TABLE_I.get(k))
+        prog = btoc.compile_spec(text, "fused")
+        bound = {}
+        for j, (name, what) in enumerate(sorted(kinds.items())):
+            if what == "A":
+                bound[name] = shared["A"]
+            elif what == "B":
+                bound[name] = shared["B2"]
+            elif what in ("m", "n"):
+                bound[name] = torch.from_numpy(synth.uniform(synth.SEED, 900 + j, N)).to(dev)
+            else:
+                bound[name] = what
+        for o in prog.outputs:   # outputs preallocated: the loop allocates nothing
+            if prog.kinds[o] == "matrix":
+                bound[o] = shared["B"]
+            else:
+                bound[o] = torch.empty(N, dtype=torch.float64, device=dev)
+        ws = torch.empty(max(bto.pass_workspace_bytes(o, N, N) for o in range(1, 32)),
+                         dtype=torch.uint8, device=dev)
+        sec = time_steps(torch, lambda: prog.run(ws=ws, **bound), 20, 3)
+        hand = suite.get(k, {}).get("fused_ms")
+        out[k] = {"passes": len(prog.passes()), "ms": round(sec * 1e3, 4),
+                  "gbs": round(alg_bytes(k, "fused") / sec / 1e9, 1),
+                  "vs_hand_fused": round(hand / (sec * 1e3), 3) if hand else None}
+    return out
+
+
 def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
     fair seeded coin) in one graph-captured persistent launch."""
@@ -502,6 +556,7 @@ def main() -> int:
             if wl is not main_wl and k in ("axpydot", "waxpby", "vadd"):
                 del wl
         result["suite"] = suite
+        result["generated"] = bench_generated(torch, bto, synth, shared, suite)
 
     if not args.no_stream:
         n = 1 << 28   # 2 GiB per array

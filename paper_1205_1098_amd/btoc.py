@@ -451,9 +451,10 @@ class Program:
     def passes(self):
         return [s for s in self.steps if isinstance(s, Pass)]
 
-    def run(self, **bound):
+    def run(self, ws=None, **bound):
+        """Enqueue the program on the current stream (see btoc_run.run)."""
         from . import btoc_run
-        return btoc_run.run(self, bound)
+        return btoc_run.run(self, bound, ws)
 
 
 def _uses(defs, name):

@@ -783,8 +783,11 @@ size_t bto_pass_workspace_bytes(int ops, int64_t m, int64_t n)
         return 0;
     if (ops & BTO_PASS_CHAIN)
         return ws_bytes(BTO_K_ATAX, m, n, BTO_FUSED);
-    // the tile partials and the auxiliary dots of a contracted pass
-    return ws_bytes(BTO_K_GEMVER_CONTRACTED, m, n, BTO_FUSED);
+    // the tile partials and the auxiliary dots of a contracted pass, or the
+    // row-resident sweep's partials (row dots and column sums of A alone)
+    const size_t tiles = ws_bytes(BTO_K_GEMVER_CONTRACTED, m, n, BTO_FUSED);
+    const size_t both = ws_bytes(BTO_K_BICGK, m, n, BTO_FUSED);
+    return tiles > both ? tiles : both;
 }
 
 bto_status bto_pass(const bto_pass_desc *d, void *ws, size_t ws_bytes_, hipStream_t st)
@@ -845,6 +848,20 @@ bto_status bto_pass(const bto_pass_desc *d, void *ws, size_t ws_bytes_, hipStrea
          wspan(ws, need_ws)},
         {{"B", "A"}, {"row_out", "row_add"}, {"col_out", "col_add"}}));
 
+    if (R && C && !S && !K && d->row_scale == 1.0 && !d->row_add) {
+        // BiCGK's pass: the row-resident sweep when tuning selects it, as in
+        // bto_bicgk (it writes the row dots whole, unscaled)
+        const int bt = get_bicgk_rowres_threads(size_bucket(m, n));
+        const int64_t G = bt ? rowres_parts(m, n, bt, true) : 0;
+        if (G > 0) {
+            double *P = Carve(ws).take(G * n);
+            launch_bicgk_rowres(m, n, d->A, d->lda, d->x, d->y, d->row_out, P, bt, st);
+            launch_finish_lin("finish", flin(P, G, n, d->col_scale, nullptr, 0, 0.0, d->col_add,
+                                             d->col_add_scale, d->col_out),
+                              st);
+            return check_launch();
+        }
+    }
     Carve cv(ws);
     double *Prow = cv.take(max_ncols(n) * m);
     double *Pcol = cv.take(max_nbands(m) * n);

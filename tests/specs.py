@@ -1,85 +1,8 @@
-"""Kernel specifications in the input language of Section II (Fig. 1): the
-nine kernels of Table I, BATAX, GEMVER with its B a temporary, and a few
-programs of the same language that are not in the paper's suite."""
+"""Kernel specifications for the tests: the library's (Table I, BATAX,
+GEMVER with B a temporary) and a few programs of the same language that are
+not in the paper's suite."""
 
-TABLE_I = {
-    "bicgk": """BICGK
-in:  A : matrix(row), p : vector(column), r : vector(column)
-out: q : vector(column), s : vector(column)
-{
-  q = A * p
-  s = A' * r
-}""",
-    "gemver": """GEMVER
-in:  A : matrix(row), u1 : vector(column), v1 : vector(column), u2 : vector(column),
-     v2 : vector(column), y : vector(column), z : vector(column),
-     alpha : scalar, beta : scalar
-out: B : matrix(row), x : vector(column), w : vector(column)
-{
-  B = A + u1 * v1' + u2 * v2'
-  x = beta * B' * y + z
-  w = alpha * B * x
-}""",
-    "atax": """ATAX
-in:  A : matrix(row), x : vector(column)
-out: y : vector(column)
-{
-  y = A' * (A * x)
-}""",
-    "dgemvt": """DGEMVT
-in:  A : matrix(row), y : vector(column), z : vector(column), alpha : scalar, beta : scalar
-out: x : vector(column), w : vector(column)
-{
-  x = beta * A' * y + z
-  w = alpha * A * x
-}""",
-    "dgemv": """DGEMV
-in:  A : matrix(row), x : vector(column), y : vector(column), alpha : scalar, beta : scalar
-out: z : vector(column)
-{
-  z = alpha * A * x + beta * y
-}""",
-    "gesummv": """GESUMMV
-in:  A : matrix(row), B : matrix(row), x : vector(column), alpha : scalar, beta : scalar
-out: y : vector(column)
-{
-  y = alpha * A * x + beta * B * x
-}""",
-    "waxpby": """WAXPBY
-in:  x : vector(column), y : vector(column), alpha : scalar, beta : scalar
-out: w : vector(column)
-{
-  w = alpha * x + beta * y
-}""",
-    "vadd": """VADD
-in:  w : vector(column), y : vector(column), z : vector(column)
-out: x : vector(column)
-{
-  x = w + y + z
-}""",
-}
-
-# Fig. 1, as printed (declarations over several lines)
-BATAX = """BATAX
-in:
-    x : vector(column), beta : scalar,
-    A : matrix(row)
-out:
-    y : vector(column)
-{
-    y = beta * A' * (A * x)
-}"""
-
-GEMVER_CONTRACTED = """GEMVERC
-in:  A : matrix(row), u1 : vector(column), v1 : vector(column), u2 : vector(column),
-     v2 : vector(column), y : vector(column), z : vector(column),
-     alpha : scalar, beta : scalar
-out: x : vector(column), w : vector(column)
-{
-  B = A + u1 * v1' + u2 * v2'
-  x = beta * B' * y + z
-  w = alpha * B * x
-}"""
+from paper_1205_1098_amd.bto_specs import BATAX, GEMVER_CONTRACTED, TABLE_I  # noqa: F401
 
 # programs outside the paper's suite; A is square where both products meet
 NOVEL = {
