@@ -335,9 +335,19 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
                          dtype=torch.uint8, device=dev)
         sec = time_steps(torch, lambda: prog.run(ws=ws, **bound), 20, 3)
         hand = suite.get(k, {}).get("fused_ms")
-        out[k] = {"passes": len(prog.passes()), "ms": round(sec * 1e3, 4),
-                  "gbs": round(alg_bytes(k, "fused") / sec / 1e9, 1),
-                  "vs_hand_fused": round(hand / (sec * 1e3), 3) if hand else None}
+        ent = {"passes": len(prog.passes()), "ms": round(sec * 1e3, 4),
+               "gbs": round(alg_bytes(k, "fused") / sec / 1e9, 1),
+               "vs_hand_fused": round(hand / (sec * 1e3), 3) if hand else None}
+        if k in ("gemver", "bicgk", "atax", "dgemv"):
+            # the same program with its matrices stored by columns (transposed
+            # views of the same storage): the schedule follows the layout
+            cprog = btoc.compile_spec(text.replace("matrix(row)", "matrix(column)"), "fused")
+            cb = {name: (t.t() if isinstance(t, torch.Tensor) and t.dim() == 2 else t)
+                  for name, t in bound.items()}
+            csec = time_steps(torch, lambda: cprog.run(ws=ws, **cb), 20, 3)
+            ent["column_major"] = {"passes": len(cprog.passes()), "ms": round(csec * 1e3, 4),
+                                   "vs_row_major": round(sec / csec, 3)}
+        out[k] = ent
     return out
 
 

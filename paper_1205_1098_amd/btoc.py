@@ -269,12 +269,16 @@ class _Typer:
 
     def __init__(self, spec: Spec):
         self.kinds = {}
+        self.colmajor = set()        # matrices stored by columns
+        declared_col = set()
         for d in spec.inputs + spec.outputs:
             if d.name in self.kinds:
                 raise SpecError(f"{d.name} declared twice")
-            if d.kind == "matrix" and d.orient != "row":
-                raise SpecError(f"{d.name}: only row-major matrices are supported")
             self.kinds[d.name] = d.kind
+            if d.kind == "matrix" and d.orient == "column":
+                declared_col.add(d.name)
+        self.declared_col = declared_col
+        self.colmajor |= {d.name for d in spec.inputs if d.name in declared_col}
         self.inputs = {d.name for d in spec.inputs}
         self.outputs = [d.name for d in spec.outputs]
         self.defs = []               # (name, Lin | Mat) in program order
@@ -299,6 +303,12 @@ class _Typer:
             self.kinds.setdefault(lhs, "matrix")
             if self.kinds[lhs] != "matrix":
                 raise SpecError(f"{lhs} is not declared a matrix")
+            # an update is stored like the matrix it updates
+            if val.base in self.colmajor:
+                self.colmajor.add(lhs)
+            if lhs in self.outputs and (lhs in self.declared_col) != (val.base in self.colmajor):
+                raise SpecError(f"{lhs}: stored by {'columns' if lhs in self.declared_col else 'rows'}"
+                                f" but {val.base} is not")
             self.mats[lhs] = val
         elif isinstance(val, Lin):
             self.kinds.setdefault(lhs, "vector")
@@ -435,6 +445,7 @@ class Program:
     steps: list
     temps: list                   # vector temporaries
     temp_mats: dict               # stored updates that are not outputs: name -> source
+    colmajor: set = field(default_factory=set)   # matrices stored by columns
 
     def describe(self):
         lines = []
@@ -483,7 +494,7 @@ def compile_spec(text: str, form: str = "fused") -> Program:
             raise SpecError(f"output {o} is never assigned")
     fused = form == "fused"
     outputs = set(ty.outputs)
-    sched = _Scheduler(fused)
+    sched = _Scheduler(fused, ty.colmajor)
     sched.temps = [n for n, v in ty.defs if isinstance(v, Lin) and n not in outputs]
     for name in ty.inputs:
         sched.avail[name] = 0
@@ -501,12 +512,17 @@ def compile_spec(text: str, form: str = "fused") -> Program:
             sched.define(ty, name, val, outputs)
 
     return Program(spec.name, form, [d.name for d in spec.inputs], ty.outputs, ty.kinds,
-                   _ordered(sched.steps), sched.temps, sched.temp_mats)
+                   _ordered(sched.steps), sched.temps, sched.temp_mats, set(ty.colmajor))
 
 
 class _Scheduler:
-    def __init__(self, fused: bool):
+    """Passes are planned on the matrices as stored: an m x n matrix stored
+    by columns is the row-major n x m matrix of its transpose, so its
+    products swap row dots and column sums and its updates swap u and v."""
+
+    def __init__(self, fused: bool, colmajor=()):
         self.fused = fused
+        self.colmajor = set(colmajor)
         self.avail = {}          # vector or matrix -> first level that may read it
         self.steps = []
         self.temps = []
@@ -520,6 +536,10 @@ class _Scheduler:
         self.temps.append(name)
         return name
 
+    def phys(self, base, terms):
+        """Rank-1 terms of an update as the stored matrix sees them."""
+        return tuple((v, u) for u, v in terms) if base in self.colmajor else tuple(terms)
+
     def store(self, name, val: Mat, is_output: bool):
         lvl = max([self.avail.get(s, 0) for uv in val.terms for s in uv]
                   + [self.avail.get(val.base, 0)])
@@ -527,13 +547,13 @@ class _Scheduler:
         if not is_output:
             self.temp_mats[name] = val.base
         if self.fused:
-            self.steps.append(Pass(lvl, val.base, val.terms, store=name))
+            self.steps.append(Pass(lvl, val.base, self.phys(val.base, val.terms), store=name))
             self.avail[name] = lvl    # products over the update may fuse into its pass
         else:
             # the BLAS way: one rank-1 sweep per term, in place after the first
             src = val.base
             for k, uv in enumerate(val.terms):
-                self.steps.append(Pass(lvl + k, src, (uv,), store=name))
+                self.steps.append(Pass(lvl + k, src, self.phys(val.base, (uv,)), store=name))
                 src = name
             self.avail[name] = lvl + len(val.terms)
 
@@ -561,8 +581,10 @@ class _Scheduler:
         """Schedule out = coef * (M v) [+ add_scale * add]; returns the level
         from which out may be read."""
         base, terms = self.resolve(t.mat)
+        terms = self.phys(base, terms)
+        trans = t.mat.trans != (base in self.colmajor)     # as the stored matrix sees it
         lvl = max(self.avail.get(t.vec, 0), self.avail.get(base, 0), add_level)
-        if self.fused and t.mat.trans and not t.mat.terms and add is None:
+        if self.fused and trans and not t.mat.terms and add is None:
             src = self.chain_source(ty, t, base, outputs)
             if src is not None:
                 src.chain = True
@@ -576,7 +598,7 @@ class _Scheduler:
             tmp = self.temp()
             self.vec_sum(tmp, [(add_scale, add)], add_level)
             add, add_scale = tmp, ONE
-        kind = "col" if t.mat.trans else "row"
+        kind = "col" if trans else "row"
         spec_ = {"x" if kind == "row" else "y": t.vec, "out": out, "scale": coef,
                  "add": add, "add_scale": add_scale}
         p = self.place(lvl, base, terms, kind, spec_)

@@ -24,9 +24,14 @@ def _coef(c, scalars):
 
 def run(prog, bound: dict, ws=None) -> dict:
     """Enqueue the program.  `bound` maps every input to a tensor (matrices
-    (m, n) row-major float64, vectors 1-D float64) or a float (scalars); an
-    output may be bound too, to a tensor of the right shape that receives
-    it.  Returns the outputs by name."""
+    (m, n) float64, row-major, or column-major where the specification says
+    matrix(column), i.e. unit stride down a column; vectors 1-D float64) or
+    a float (scalars); an output may be bound too, to a tensor of the right
+    shape and layout that receives it.  Returns the outputs by name; a
+    column-major matrix is returned as an (m, n) view of its storage.
+
+    Passes run on matrices as stored: a column-major matrix is handed to the
+    library as the row-major matrix of its transpose."""
     env, scalars = {}, {}
     dev = None
     for name in prog.inputs:
@@ -42,7 +47,7 @@ def run(prog, bound: dict, ws=None) -> dict:
             if t.dim() != want:
                 raise SpecError(f"{name}: expected a {want}-D tensor")
             dev = t.device if dev is None else dev
-            env[name] = t
+            env[name] = _stored(name, t, prog)
     if dev is None:
         raise SpecError("the program has no tensor input")
     given = {o: bound[o] for o in prog.outputs if o in bound}
@@ -66,7 +71,9 @@ def run(prog, bound: dict, ws=None) -> dict:
         return t
 
     def mat_out(name, m, n):
-        t = env.get(name, given.get(name))
+        t = env.get(name)
+        if t is None and name in given:
+            t = _stored(name, given[name], prog)
         if t is None:
             t = torch.empty((m, n), dtype=torch.float64, device=dev)
         if tuple(t.shape) != (m, n):
@@ -122,7 +129,18 @@ def run(prog, bound: dict, ws=None) -> dict:
         if ws.numel() < k:
             ws = torch.empty(k, dtype=torch.uint8, device=dev)
         bto.fused_pass(_ops(s), A, ws=ws, **kw)
-    return {o: env[o] for o in prog.outputs}
+    return {o: (env[o].t() if o in prog.colmajor else env[o]) for o in prog.outputs}
+
+
+def _stored(name, t, prog):
+    """The row-major matrix the library sweeps for matrix `name`: the tensor
+    itself, or for a column-major one the transpose view of its storage."""
+    if t.dim() != 2 or name not in prog.colmajor:
+        return t
+    m, n = t.shape
+    if m > 1 and t.stride(0) != 1:
+        raise SpecError(f"{name}: declared matrix(column) but not stored by columns")
+    return t.t()
 
 
 def get_shape(s, env):

@@ -104,6 +104,43 @@ def test_compiled_program(env, name, m, n, kind, form):
             assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
 
 
+COLUMN_PROGRAMS = ["bicgk", "gemver", "atax", "dgemvt", "dgemv", "gesummv", "batax",
+                   "gemver_contracted", "rank1_stored", "rank1_contracted", "both_ways"]
+
+
+@pytest.mark.parametrize("form", ["fused", "unfused"])
+@pytest.mark.parametrize("kind", ["uniform", "int"])
+@pytest.mark.parametrize("m,n", [(65, 127), (513, 1000), (2047, 2049)])
+@pytest.mark.parametrize("name", COLUMN_PROGRAMS)
+def test_compiled_program_column_major(env, name, m, n, kind, form):
+    """The same programs with every matrix stored by columns (tensors with
+    unit stride down a column), against the same reference values."""
+    torch, btoc, dev = env
+    text, kinds, square = PROGRAMS[name]
+    if square:
+        n = m
+    text = text.replace("matrix(row)", "matrix(column)")
+    host = _inputs(kinds, m, n, kind, 7 * m + n)
+    ref = spec_eval.evaluate(text, host)
+    prog = btoc.compile_spec(text, form)
+    bound = {}
+    for k, v in host.items():
+        if isinstance(v, np.ndarray) and v.ndim == 2:
+            bound[k] = torch.from_numpy(np.ascontiguousarray(v.T)).to(dev).t()
+        elif isinstance(v, np.ndarray):
+            bound[k] = torch.from_numpy(v).to(dev)
+        else:
+            bound[k] = v
+    out = prog.run(**bound)
+    torch.cuda.synchronize()
+    for o, r in ref.items():
+        got = out[o].cpu().numpy()
+        if kind == "int":
+            assert np.array_equal(got, r), (name, o)
+        else:
+            assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
+
+
 def test_outputs_bound_by_the_caller_receive_the_results(env):
     torch, btoc, dev = env
     text, kinds, _ = PROGRAMS["gemver"]
