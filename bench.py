@@ -302,6 +302,9 @@ GENERATED = {
     "dgemvt": dict(A="A", y="m", z="n", alpha=ALPHA, beta=BETA),
     "dgemv": dict(A="A", x="n", y="m", alpha=ALPHA, beta=BETA),
     "gesummv": dict(A="A", B="B", x="n", alpha=ALPHA, beta=BETA),
+    "axpydot": dict(w="V", v="V", u="V", alpha=ALPHA),
+    "waxpby": dict(x="V", y="V", alpha=ALPHA, beta=BETA),
+    "vadd": dict(w="V", y="V", z="V"),
 }
 
 
@@ -316,21 +319,23 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
         text = {"batax": bto_specs.BATAX, "gemver_contracted": bto_specs.GEMVER_CONTRACTED}.get(
             k, bto_specs.TABLE_I.get(k))
         prog = btoc.compile_spec(text, "fused")
+        length = NV if "V" in kinds.values() else N
         bound = {}
         for j, (name, what) in enumerate(sorted(kinds.items())):
             if what == "A":
                 bound[name] = shared["A"]
             elif what == "B":
                 bound[name] = shared["B2"]
-            elif what in ("m", "n"):
-                bound[name] = torch.from_numpy(synth.uniform(synth.SEED, 900 + j, N)).to(dev)
+            elif what in ("m", "n", "V"):
+                bound[name] = torch.from_numpy(synth.uniform(synth.SEED, 900 + j, length)).to(dev)
             else:
                 bound[name] = what
         for o in prog.outputs:   # outputs preallocated: the loop allocates nothing
             if prog.kinds[o] == "matrix":
                 bound[o] = shared["B"]
             else:
-                bound[o] = torch.empty(N, dtype=torch.float64, device=dev)
+                bound[o] = torch.empty(1 if prog.kinds[o] == "scalar" else length,
+                                       dtype=torch.float64, device=dev)
         ws = torch.empty(max(bto.pass_workspace_bytes(o, N, N) for o in range(1, 32)),
                          dtype=torch.uint8, device=dev)
         sec = time_steps(torch, lambda: prog.run(ws=ws, **bound), 20, 3)

@@ -261,6 +261,14 @@ bto_status bto_axpydot(int64_t n, double alpha, const double *w, const double *v
                        const double *u, double *z, double *r,
                        void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
 
+/* r <- x^T y: the dot product of AXPYDOT's second statement on its own
+ * (Table I), with the same pairwise-order partial sums and fixed-order
+ * finish.  Length n; r points to ONE double in device memory.
+ * ws: bto_dot_workspace_bytes(n) bytes. */
+size_t bto_dot_workspace_bytes(int64_t n);
+bto_status bto_dot(int64_t n, const double *x, const double *y, double *r,
+                   void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* WAXPBY (Table I):  w <- alpha x + beta y.  Length n; w may be exactly x
  * or exactly y.  Unfused: scal into a temporary, then axpy. */
 bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta,

@@ -13,7 +13,8 @@ assignments in order, in binary64 with numpy, by their plain meaning:
 * a product of a scaled matrix with a vector is reduced first and scaled
   after (every scale applied after its reduction, as in the statements of
   Table I);
-* sums of vectors are added left to right.
+* sums of vectors are added left to right;
+* a row vector times a column vector is their dot product (a scalar).
 
 Products use numpy's matrix-vector product as a library step.
 """
@@ -71,6 +72,8 @@ class _Eval:
             self.env[lhs.strip()] = ("mat", v, 1.0, False)
         elif kind == "vec":
             self.env[lhs.strip()] = ("vec", v)
+        elif kind == "scal":
+            self.env[lhs.strip()] = ("scal", v)
         else:
             raise ValueError(f"unsupported result in {stmt!r}")
 
@@ -147,6 +150,8 @@ class _Eval:
             raise ValueError("unsupported scaling")
         if a[0] == "vec" and b[0] == "row":
             return ("outer", np.outer(a[1], b[1]))
+        if a[0] == "row" and b[0] == "vec":
+            return ("scal", float(np.dot(a[1], b[1])))
         if a[0] == "mat" and b[0] == "vec":
             M = a[1].T if a[3] else a[1]
             r = M @ b[1]

@@ -74,6 +74,8 @@ _SIGS = {
                   _int),
     "bto_gesummv": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int,
                      _ptr], _int),
+    "bto_dot_workspace_bytes": ([_i64], _sz),
+    "bto_dot": ([_i64, _ptr, _ptr, _ptr, _ptr, _sz, _ptr], _int),
     "bto_pass_workspace_bytes": ([_int, _i64, _i64], _sz),
     "bto_pass": ([ctypes.POINTER(PassDesc), _ptr, _sz, _ptr], _int),
     "bto_axpydot": ([_i64, _dbl, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
@@ -421,6 +423,22 @@ def fused_pass(ops, A, *, B=None, u1=None, v1=None, u2=None, v2=None, x=None, y=
                  _addr(col_add), float(col_add_scale))
     with torch.cuda.device(dev):
         _check(_lib.bto_pass(ctypes.byref(d), _ptr_of(ws), ws.numel(), _stream(dev)))
+
+
+def dot(x, y, r=None, ws=None):
+    """r = x^T y, into a 1-element tensor on the device."""
+    dev = x.device
+    n = x.numel()
+    r = _empty(1, dev) if r is None else r
+    for t, nm, k in ((x, "x", n), (y, "y", n), (r, "r", 1)):
+        _check_vec(t, nm, dev, k)
+    need = int(_lib.bto_dot_workspace_bytes(n))
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_dot(n, _ptr_of(x), _ptr_of(y), _ptr_of(r), _ptr_of(ws), ws.numel(),
+                            _stream(dev)))
+    return r
 
 
 def _addr(t):

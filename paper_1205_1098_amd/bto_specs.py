@@ -44,6 +44,13 @@ out: y : vector(column)
 {
   y = alpha * A * x + beta * B * x
 }""",
+    "axpydot": """AXPYDOT
+in:  w : vector(column), v : vector(column), u : vector(column), alpha : scalar
+out: z : vector(column), r : scalar
+{
+  z = w - alpha * v
+  r = z' * u
+}""",
     "waxpby": """WAXPBY
 in:  x : vector(column), y : vector(column), alpha : scalar, beta : scalar
 out: w : vector(column)

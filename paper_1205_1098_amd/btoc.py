@@ -34,10 +34,14 @@ what is left runs as scaled vector sums.  ``form="unfused"`` lowers the same
 program the BLAS way: one pass per operation, every temporary stored, each
 update applied as its own rank-1 sweep.
 
+Vector statements fuse too: a sum of three vectors is one pass, and a dot
+product of a vector just formed as w - alpha v runs in the same pass that
+forms it (AXPYDOT).  A matrix stored by columns is planned as the row-major
+matrix of its transpose.
+
 The result is a ``Program`` whose ``run`` enqueues the passes on the current
-stream through the C entry points (``bto_pass``, ``bto_waxpby``); nothing is
-computed in Python.  Dot products (a vector times a vector) and
-column-major storage are not supported.
+stream through the C entry points (``bto_pass``, ``bto_waxpby``,
+``bto_vadd``, ``bto_axpydot``, ``bto_dot``); nothing is computed in Python.
 """
 
 from __future__ import annotations
@@ -263,6 +267,12 @@ class Outer:
     v: str
 
 
+@dataclass
+class Dot:
+    x: str
+    y: str
+
+
 class _Typer:
     """Turns statement trees into typed values, introducing temporaries for
     products whose vector operand is not a plain symbol."""
@@ -315,6 +325,10 @@ class _Typer:
             if self.kinds[lhs] != "vector":
                 raise SpecError(f"{lhs} is not declared a vector")
             self.defs.append((lhs, val))
+        elif isinstance(val, Dot):
+            if self.kinds.get(lhs) != "scalar" or lhs not in self.outputs:
+                raise SpecError(f"{lhs}: a dot product goes to a scalar output")
+            self.defs.append((lhs, val))
         else:
             raise SpecError(f"{lhs}: scalar and outer-product results are not supported")
         if lhs in self.defined and lhs not in self.mats:
@@ -333,6 +347,8 @@ class _Typer:
                 raise SpecError(f"{name} is used before it is defined")
             kind = self.kinds[name]
             if kind == "scalar":
+                if name not in self.inputs:
+                    raise SpecError(f"{name}: a computed scalar cannot scale later statements")
                 return ("scalar", (1.0, (name,)))
             if kind == "matrix":
                 return self.mats[name]
@@ -395,7 +411,11 @@ class _Typer:
                 return Outer(a.terms[0][1], b[1])
             raise SpecError("an outer product takes vector symbols")
         if isinstance(a, tuple) and a[0] == "rowvec":
-            raise SpecError("dot products and row-vector products are not supported")
+            if (isinstance(b, Lin) and len(b.terms) == 1 and isinstance(b.terms[0][1], str)
+                    and b.terms[0][0] == ONE):
+                return Dot(a[1], b.terms[0][1])
+            raise SpecError("a dot product takes vector symbols; row-vector products are "
+                            "not supported")
         if isinstance(a, Mat) and isinstance(b, Lin):
             if len(b.terms) == 1 and isinstance(b.terms[0][1], str) and b.terms[0][0] == ONE:
                 vec = b.terms[0][1]
@@ -436,6 +456,37 @@ class VecOp:
 
 
 @dataclass
+class Vadd:
+    """out = (a + b) + c in one pass (bto_vadd)."""
+    level: int
+    out: str
+    a: str
+    b: str
+    c: str
+
+
+@dataclass
+class AxpyDot:
+    """z = w - alpha v and r = z . u in one pass (bto_axpydot)."""
+    level: int
+    z: str
+    w: str
+    v: str
+    alpha: tuple
+    u: str
+    r: str
+
+
+@dataclass
+class DotOp:
+    """r = x . y (bto_dot)."""
+    level: int
+    r: str
+    x: str
+    y: str
+
+
+@dataclass
 class Program:
     name: str
     form: str
@@ -455,8 +506,14 @@ class Program:
                                        ("CHAIN", s.chain), ("ROWDOT", s.row),
                                        ("COLSUM", s.col)) if on]
                 lines.append(f"pass {s.level}: {s.base} {'|'.join(ops)}")
-            else:
+            elif isinstance(s, VecOp):
                 lines.append(f"vec {s.level}: {s.out} = a*{s.x} + b*{s.y}")
+            elif isinstance(s, Vadd):
+                lines.append(f"vadd {s.level}: {s.out} = {s.a} + {s.b} + {s.c}")
+            elif isinstance(s, AxpyDot):
+                lines.append(f"axpydot {s.level}: {s.z} = {s.w} - alpha*{s.v}; {s.r} = {s.z}.{s.u}")
+            else:
+                lines.append(f"dot {s.level}: {s.r} = {s.x}.{s.y}")
         return lines
 
     def passes(self):
@@ -510,6 +567,8 @@ def compile_spec(text: str, form: str = "fused") -> Program:
     for name, val in ty.defs:
         if isinstance(val, Lin):
             sched.define(ty, name, val, outputs)
+        elif isinstance(val, Dot):
+            sched.dot(name, val)
 
     return Program(spec.name, form, [d.name for d in spec.inputs], ty.outputs, ty.kinds,
                    _ordered(sched.steps), sched.temps, sched.temp_mats, set(ty.colmajor))
@@ -567,7 +626,11 @@ class _Scheduler:
         return m.base, m.terms
 
     def vec_sum(self, out, terms, lvl):
-        """out = sum of c_k t_k as scaled vector sums (bto_waxpby)."""
+        """out = sum of c_k t_k as scaled vector sums (bto_waxpby), or as one
+        three-way sum (bto_vadd) when fused and every coefficient is 1."""
+        if self.fused and len(terms) == 3 and all(c == ONE for c, _ in terms):
+            self.steps.append(Vadd(lvl, out, terms[0][1], terms[1][1], terms[2][1]))
+            return
         c0, t0 = terms[0]
         if len(terms) == 1:
             self.steps.append(VecOp(lvl, out, c0, t0, (0.0, ()), t0))
@@ -634,6 +697,26 @@ class _Scheduler:
         self.vec_sum(name, parts + vecs, lvl)
         self.avail[name] = lvl
 
+    def dot(self, name, d: Dot):
+        """r = x . y; fused with the scaled difference that forms one of its
+        operands (z = w - alpha v, then z . u: AXPYDOT's one pass)."""
+        lvl = max(self.avail.get(d.x, 0), self.avail.get(d.y, 0))
+        if self.fused:
+            for z, u in ((d.x, d.y), (d.y, d.x)):
+                writers = [i for i, s in enumerate(self.steps) if getattr(s, "out", None) == z]
+                if len(writers) != 1:
+                    continue
+                i = writers[0]
+                s = self.steps[i]
+                # z = w - alpha v formed in one step, and u ready by then
+                if (isinstance(s, VecOp) and s.a == ONE and s.x != s.y and u != z
+                        and self.avail.get(u, 0) <= s.level):
+                    self.steps[i] = AxpyDot(s.level, z, s.x, s.y, (-s.b[0], s.b[1]), u, name)
+                    self.avail[name] = s.level
+                    return
+        self.steps.append(DotOp(lvl, name, d.x, d.y))
+        self.avail[name] = lvl
+
     def chain_source(self, ty, t: Prod, base, outputs):
         """The pass that forms t.vec as plain row dots of t's matrix, when
         t = A' * (A x) can run as one row-resident pass: t.vec a temporary
@@ -678,5 +761,5 @@ def _ordered(steps):
     passes of level L - 1 have finished)."""
     keyed = []
     for i, s in enumerate(steps):
-        keyed.append(((s.level, 0 if isinstance(s, VecOp) else 1, i), s))
+        keyed.append(((s.level, 1 if isinstance(s, Pass) else 0, i), s))
     return [s for _, s in sorted(keyed, key=lambda kv: kv[0])]

@@ -12,7 +12,7 @@ from __future__ import annotations
 import torch
 
 from . import bto
-from .btoc import Pass, SpecError, VecOp
+from .btoc import AxpyDot, DotOp, Pass, SpecError, Vadd, VecOp
 
 
 def _coef(c, scalars):
@@ -86,7 +86,7 @@ def run(prog, bound: dict, ws=None) -> dict:
             raise SpecError(f"{name} is read before it is written")
         return env[name]
 
-    need = max([bto.pass_workspace_bytes(_ops(s), *get_shape(s, env)) for s in prog.steps
+    need = max([bto.pass_workspace_bytes(_ops(s), *_shape(s, env)) for s in prog.steps
                 if isinstance(s, Pass) and s.base in env] + [1])
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
@@ -96,6 +96,18 @@ def run(prog, bound: dict, ws=None) -> dict:
             x, y = get(s.x), get(s.y)
             out = vec_out(s.out, x.numel())
             bto.waxpby(x, y, _coef(s.a, scalars), _coef(s.b, scalars), w=out)
+            continue
+        if isinstance(s, Vadd):
+            a = get(s.a)
+            bto.vadd(a, get(s.b), get(s.c), x=vec_out(s.out, a.numel()))
+            continue
+        if isinstance(s, AxpyDot):
+            w = get(s.w)
+            bto.axpydot(w, get(s.v), get(s.u), _coef(s.alpha, scalars),
+                        z=vec_out(s.z, w.numel()), r=vec_out(s.r, 1))
+            continue
+        if isinstance(s, DotOp):
+            bto.dot(get(s.x), get(s.y), r=vec_out(s.r, 1))
             continue
         A = get(s.base)
         m, n = A.shape
@@ -143,7 +155,7 @@ def _stored(name, t, prog):
     return t.t()
 
 
-def get_shape(s, env):
+def _shape(s, env):
     return tuple(env[s.base].shape)
 
 

@@ -994,6 +994,28 @@ bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta, con
     return check_launch();
 }
 
+// ---- DOT -----------------------------------------------------------------------
+
+size_t bto_dot_workspace_bytes(int64_t n) { return n < 0 ? 0 : round256((size_t)dot_parts(n) * 8); }
+
+bto_status bto_dot(int64_t n, const double *x, const double *y, double *r, void *ws,
+                   size_t ws_bytes_, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(check_vec(x, n, "x"));
+    BTO_TRY(check_vec(y, n, "y"));
+    BTO_TRY(check_vec(r, 1, "r"));
+    const size_t need_ws = bto_dot_workspace_bytes(n);
+    BTO_TRY(check_ws(ws, ws_bytes_, need_ws));
+    BTO_TRY(check_aliases({vspan("x", x, n, false), vspan("y", y, n, false),
+                           vspan("r", r, 1, true), wspan(ws, need_ws)},
+                          {}));
+    double *parts = Carve(ws).take(dot_parts(n));
+    launch_dot(false, n, 0.0, x, nullptr, y, nullptr, parts, r, st);
+    return check_launch();
+}
+
 // ---- VADD --------------------------------------------------------------------
 
 bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z, double *x,

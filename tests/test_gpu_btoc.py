@@ -36,6 +36,9 @@ PROGRAMS = {
     "dgemv": (specs.TABLE_I["dgemv"], dict(A="A", x="n", y="m", alpha=1.5, beta=0.7), False),
     "gesummv": (specs.TABLE_I["gesummv"], dict(A="A", B="A", x="n", alpha=1.5, beta=0.7), False),
     "batax": (specs.BATAX, dict(A="A", x="n", beta=0.7), False),
+    "axpydot": (specs.TABLE_I["axpydot"], dict(w="n", v="n", u="n", alpha=1.5), False),
+    "waxpby": (specs.TABLE_I["waxpby"], dict(x="n", y="n", alpha=1.5, beta=0.7), False),
+    "vadd": (specs.TABLE_I["vadd"], dict(w="n", y="n", z="n"), False),
     "gemver_contracted": (specs.GEMVER_CONTRACTED, GEMVER_IN, False),
     "both_ways": (specs.NOVEL["both_ways"], dict(A="A", x="n", w="m"), True),
     "atax_plus": (specs.NOVEL["atax_plus"], dict(A="A", x="n", z="n"), False),
@@ -97,7 +100,7 @@ def test_compiled_program(env, name, m, n, kind, form):
     out = prog.run(**bound)
     torch.cuda.synchronize()
     for o, r in ref.items():
-        got = out[o].cpu().numpy()
+        got, r = out[o].cpu().numpy().reshape(np.shape(r)), np.asarray(r)
         if kind == "int":
             assert np.array_equal(got, r), (name, o)
         else:
