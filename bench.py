@@ -315,6 +315,7 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
 
     dev = shared["A"].device
     out = {}
+    texts, bounds = {}, {}
     for k, kinds in GENERATED.items():
         text = {"batax": bto_specs.BATAX, "gemver_contracted": bto_specs.GEMVER_CONTRACTED}.get(
             k, bto_specs.TABLE_I.get(k))
@@ -353,6 +354,16 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
             ent["column_major"] = {"passes": len(cprog.passes()), "ms": round(csec * 1e3, 4),
                                    "vs_row_major": round(sec / csec, 3)}
         out[k] = ent
+        texts[k], bounds[k] = text, bound
+    # the empirical search over fusion decisions, on the same inputs
+    search = {}
+    for k in ("gemver_contracted", "atax", "bicgk", "axpydot"):
+        best, table = btoc.search(texts[k], bounds[k], reps=5, ws=ws)
+        search[k] = {"best": best.describe(),
+                     "variants": [{"off": off if isinstance(off, str) else list(off),
+                                   "steps": len(sched), "ms": round(ms, 4)}
+                                  for off, sched, ms in table]}
+    out["search"] = search
     return out
 
 

@@ -525,6 +525,12 @@ class Program:
         return btoc_run.run(self, bound, ws)
 
 
+def search(text: str, bound: dict, **kw):
+    """Fastest schedule of `text` on the bound inputs (btoc_run.search)."""
+    from . import btoc_run
+    return btoc_run.search(text, bound, **kw)
+
+
 def _uses(defs, name):
     n = 0
     for _, val in defs:
@@ -538,10 +544,21 @@ def _uses(defs, name):
     return n
 
 
-def compile_spec(text: str, form: str = "fused") -> Program:
-    """Parse, type and schedule a specification (see the module text)."""
+# The fusion decisions the schedule makes, each of which can be switched off
+# (the choices the paper's search explores, Section IV): products of one
+# matrix share a sweep; an update that is not an output is contracted; a
+# row dot feeding the column sums of its matrix runs row-resident; vector
+# statements fuse (three-way sums, AXPYDOT).
+DECISIONS = ("share", "contract", "chain", "vector")
+
+
+def compile_spec(text: str, form: str = "fused", off=()) -> Program:
+    """Parse, type and schedule a specification (see the module text).
+    `off` names fusion decisions (DECISIONS) not to take in the fused form."""
     if form not in ("fused", "unfused"):
         raise SpecError("form must be 'fused' or 'unfused'")
+    if any(d not in DECISIONS for d in off):
+        raise SpecError(f"unknown fusion decision in {tuple(off)}")
     spec = parse(text)
     ty = _Typer(spec)
     for lhs, tree in spec.statements:
@@ -551,7 +568,8 @@ def compile_spec(text: str, form: str = "fused") -> Program:
             raise SpecError(f"output {o} is never assigned")
     fused = form == "fused"
     outputs = set(ty.outputs)
-    sched = _Scheduler(fused, ty.colmajor)
+    on = {d: fused and d not in off for d in DECISIONS}
+    sched = _Scheduler(fused, ty.colmajor, on)
     sched.temps = [n for n, v in ty.defs if isinstance(v, Lin) and n not in outputs]
     for name in ty.inputs:
         sched.avail[name] = 0
@@ -561,7 +579,7 @@ def compile_spec(text: str, form: str = "fused") -> Program:
             raise SpecError(f"{name}: a matrix output must update a matrix input")
     # matrix updates: stored when an output (or always, unfused), else contracted
     for name, val in ty.defs:
-        if isinstance(val, Mat) and val.terms and (name in outputs or not fused):
+        if isinstance(val, Mat) and val.terms and (name in outputs or not on["contract"]):
             sched.store(name, val, name in outputs)
 
     for name, val in ty.defs:
@@ -579,8 +597,9 @@ class _Scheduler:
     by columns is the row-major n x m matrix of its transpose, so its
     products swap row dots and column sums and its updates swap u and v."""
 
-    def __init__(self, fused: bool, colmajor=()):
+    def __init__(self, fused: bool, colmajor=(), on=None):
         self.fused = fused
+        self.on = on if on is not None else {d: fused for d in DECISIONS}
         self.colmajor = set(colmajor)
         self.avail = {}          # vector or matrix -> first level that may read it
         self.steps = []
@@ -628,7 +647,7 @@ class _Scheduler:
     def vec_sum(self, out, terms, lvl):
         """out = sum of c_k t_k as scaled vector sums (bto_waxpby), or as one
         three-way sum (bto_vadd) when fused and every coefficient is 1."""
-        if self.fused and len(terms) == 3 and all(c == ONE for c, _ in terms):
+        if self.on["vector"] and len(terms) == 3 and all(c == ONE for c, _ in terms):
             self.steps.append(Vadd(lvl, out, terms[0][1], terms[1][1], terms[2][1]))
             return
         c0, t0 = terms[0]
@@ -647,7 +666,7 @@ class _Scheduler:
         terms = self.phys(base, terms)
         trans = t.mat.trans != (base in self.colmajor)     # as the stored matrix sees it
         lvl = max(self.avail.get(t.vec, 0), self.avail.get(base, 0), add_level)
-        if self.fused and trans and not t.mat.terms and add is None:
+        if self.on["chain"] and trans and not t.mat.terms and add is None:
             src = self.chain_source(ty, t, base, outputs)
             if src is not None:
                 src.chain = True
@@ -701,7 +720,7 @@ class _Scheduler:
         """r = x . y; fused with the scaled difference that forms one of its
         operands (z = w - alpha v, then z . u: AXPYDOT's one pass)."""
         lvl = max(self.avail.get(d.x, 0), self.avail.get(d.y, 0))
-        if self.fused:
+        if self.on["vector"]:
             for z, u in ((d.x, d.y), (d.y, d.x)):
                 writers = [i for i, s in enumerate(self.steps) if getattr(s, "out", None) == z]
                 if len(writers) != 1:
@@ -734,7 +753,7 @@ class _Scheduler:
     def place(self, lvl, base, terms, kind, spec_):
         """Fuse into a pass over the same matrix at the same level that has
         this kind of reduction free; otherwise open a pass."""
-        if self.fused:
+        if self.on["share"]:
             for s in self.steps:
                 if not isinstance(s, Pass) or s.level != lvl or s.chain:
                     continue

@@ -172,3 +172,41 @@ def _ops(s: Pass) -> int:
     if s.chain:
         ops |= bto.PASS_CHAIN
     return ops
+
+
+def search(text: str, bound: dict, reps: int = 5, warmup: int = 1, ws=None):
+    """Empirical search over the fusion decisions (the paper's search,
+    Section IV, over this compiler's choices): compile every distinct
+    schedule that switching decisions off gives, plus the unfused form,
+    time each on the bound inputs (HIP events on the current stream, `reps`
+    runs after `warmup`), and return (fastest program, [(decisions off,
+    schedule, ms per run)]).  Every variant computes the same outputs."""
+    import itertools
+
+    from .btoc import DECISIONS, compile_spec
+
+    variants, seen = [], set()
+    for k in range(len(DECISIONS) + 1):
+        for off in itertools.combinations(DECISIONS, k):
+            prog = compile_spec(text, "fused", off)
+            key = tuple(prog.describe())
+            if key not in seen:
+                seen.add(key)
+                variants.append((off, prog))
+    unf = compile_spec(text, "unfused")
+    if tuple(unf.describe()) not in seen:
+        variants.append(("unfused", unf))
+    table = []
+    for off, prog in variants:
+        for _ in range(warmup):
+            prog.run(ws=ws, **bound)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            prog.run(ws=ws, **bound)
+        e1.record()
+        e1.synchronize()
+        table.append((off, prog.describe(), e0.elapsed_time(e1) / reps, prog))
+    best = min(table, key=lambda t: t[2])
+    return best[3], [(off, d, ms) for off, d, ms, _ in table]

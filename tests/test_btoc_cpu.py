@@ -119,6 +119,32 @@ def test_column_major_update_swaps_its_terms():
         btoc.compile_spec(bad)
 
 
+VARIANTS = {
+    "atax": [((), ["pass 0: A CHAIN|ROWDOT|COLSUM"]),
+             (("chain",), ["pass 0: A ROWDOT", "pass 1: A COLSUM"])],
+    "bicgk": [(("share",), ["pass 0: A ROWDOT", "pass 0: A COLSUM"])],
+    "gemver": [(("share",), ["pass 0: A STORE", "pass 0: B COLSUM", "pass 1: B ROWDOT"])],
+    "vadd": [(("vector",), ["vec 0: x = a*w + b*y", "vec 0: x = a*x + b*z"])],
+    "axpydot": [(("vector",), ["vec 0: z = a*w + b*v", "dot 0: r = z.u"])],
+}
+
+
+@pytest.mark.parametrize("kernel", sorted(VARIANTS))
+def test_fusion_decisions_switch_off(kernel):
+    """Each fusion decision the search may switch off gives the schedule
+    that decision saves a pass or a step over."""
+    for off, sched in VARIANTS[kernel]:
+        assert btoc.compile_spec(specs.TABLE_I[kernel], "fused", off).describe() == sched
+
+
+def test_contraction_switched_off_stores_a_temporary():
+    p = btoc.compile_spec(specs.GEMVER_CONTRACTED, "fused", ("contract",))
+    assert p.describe() == ["pass 0: A STORE|COLSUM", "pass 1: B ROWDOT"]
+    assert p.temp_mats == {"B": "A"}
+    with pytest.raises(btoc.SpecError, match="unknown fusion decision"):
+        btoc.compile_spec(specs.GEMVER_CONTRACTED, "fused", ("tile",))
+
+
 def test_unfused_is_one_operation_per_pass():
     for src in list(specs.TABLE_I.values()) + list(specs.NOVEL.values()):
         for s in btoc.compile_spec(src, "unfused").passes():

@@ -144,6 +144,30 @@ def test_compiled_program_column_major(env, name, m, n, kind, form):
             assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
 
 
+@pytest.mark.parametrize("name", ["gemver_contracted", "atax", "bicgk", "axpydot", "vadd"])
+def test_search_times_only_correct_schedules(env, name):
+    """Every schedule the search times computes the reference outputs, and
+    it returns one of them."""
+    torch, btoc, dev = env
+    text, kinds, _ = PROGRAMS[name]
+    host = _inputs(kinds, 700, 900, "uniform", 3)
+    ref = spec_eval.evaluate(text, host)
+    bound = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+             for k, v in host.items()}
+    best, table = btoc.search(text, bound, reps=2)
+    assert len(table) >= 2
+    for off, sched, ms in table:
+        assert ms > 0
+        prog = (btoc.compile_spec(text, "unfused") if off == "unfused"
+                else btoc.compile_spec(text, "fused", off))
+        assert prog.describe() == sched
+        out = prog.run(**bound)
+        for o, r in ref.items():
+            got = out[o].cpu().numpy().reshape(np.shape(r))
+            assert _relerr(got, np.asarray(r)) <= TOL, (name, off, o)
+    assert best.describe() in [sched for _, sched, _ in table]
+
+
 def test_outputs_bound_by_the_caller_receive_the_results(env):
     torch, btoc, dev = env
     text, kinds, _ = PROGRAMS["gemver"]
