@@ -206,6 +206,55 @@ def test_dgemv_and_gesummv_checks(bto):
     assert gs(form=1, wsb=uneed - 1) == 3
 
 
+def test_pass_and_dot_checks(bto):
+    """The fused pass and the plain dot: refusals before anything is enqueued."""
+    v = ctypes.c_void_p
+    m = n = 256
+    ptr = lambda i: FAKE + (i << 20)
+    R, C, S, K, H = (bto.PASS_ROWDOT, bto.PASS_COLSUM, bto.PASS_STORE, bto.PASS_CONTRACT,
+                     bto.PASS_CHAIN)
+    assert bto.pass_workspace_bytes(R | C, 16384, 16384) >= bto.workspace_bytes("bicgk", 16384,
+                                                                               16384)
+    assert bto.pass_workspace_bytes(R | C | H, 300, 40) == bto.workspace_bytes("atax", 300, 40)
+    assert bto.pass_workspace_bytes(64, 5, 5) == 0 and bto.pass_workspace_bytes(R, -1, 5) == 0
+
+    def call(ops, wsb=None, **kw):
+        d = bto.PassDesc(ops, kw.get("m", m), kw.get("n", n), kw.get("A", ptr(0)),
+                         kw.get("lda", n), kw.get("B", ptr(1)), kw.get("ldb", n),
+                         kw.get("u1", ptr(2)), kw.get("v1", ptr(3)), kw.get("u2", ptr(4)),
+                         kw.get("v2", ptr(5)), kw.get("x", ptr(6)), kw.get("y", ptr(7)),
+                         kw.get("row_out", ptr(8)), 1.0, kw.get("row_add"),
+                         kw.get("row_add_scale", 1.0), kw.get("col_out", ptr(9)), 1.0,
+                         kw.get("col_add"), kw.get("col_add_scale", 1.0))
+        need = bto.pass_workspace_bytes(ops, d.m, d.n)
+        return bto._lib.bto_pass(ctypes.byref(d), v(ptr(16)), need if wsb is None else wsb,
+                                 None)
+
+    assert bto._lib.bto_pass(None, None, 0, None) == 1
+    assert call(0) == 1                         # computes nothing
+    assert call(64 | R) == 1                    # unknown flag
+    assert call(R | S | K) == 1                 # store and contract
+    assert call(K) == 1                         # contract without a reduction
+    assert call(R | H) == 1                     # chain without column sums
+    assert call(R | C | H, y=None, col_add=ptr(10)) == 1     # chain takes no add
+    assert call(R | C | K) == 5                 # a contracted pass does one of the two
+    assert call(R | K, row_add=ptr(10), row_add_scale=2.0) == 5
+    assert call(R, x=None) == 1 and call(C, col_out=None) == 1 and call(S | C, u1=None) == 1
+    assert call(R, lda=n - 1) == 1 and call(S, ldb=n - 1) == 1
+    assert call(R, wsb=0) == 3
+    assert call(R, row_out=ptr(0) + 8) == 2     # row output inside A
+    assert call(R | C, col_out=ptr(8)) == 2     # the two outputs meet
+    assert call(S | C, B=ptr(0) + 8) == 2       # B overlaps A without being A
+    assert call(R, row_add=ptr(8) + 8) == 2     # the add partly over the output
+    dn = bto._lib.bto_dot_workspace_bytes(1000)
+    assert dn > 0 and bto._lib.bto_dot_workspace_bytes(-1) == 0
+    assert bto._lib.bto_dot(-1, v(ptr(0)), v(ptr(1)), v(ptr(2)), v(ptr(16)), dn, None) == 1
+    assert bto._lib.bto_dot(1000, None, v(ptr(1)), v(ptr(2)), v(ptr(16)), dn, None) == 1
+    assert bto._lib.bto_dot(1000, v(ptr(0)), v(ptr(1)), v(ptr(2)), v(ptr(16)), dn - 1, None) == 3
+    assert bto._lib.bto_dot(1000, v(ptr(0)), v(ptr(1)), v(ptr(0) + 8), v(ptr(16)), dn,
+                            None) == 2
+
+
 def test_contracted_gemver_and_batax_checks(bto):
     """GEMVER without B and BATAX: workspace sizes and the argument checks,
     before anything is enqueued."""
