@@ -364,6 +364,31 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
                                    "steps": len(sched), "ms": round(ms, 4)}
                                   for off, sched, ms in table]}
     out["search"] = search
+    # at small sizes a program costs its launches: eager calls against one
+    # captured HIP graph replay per call
+    small = {}
+    for k in ("gemver", "bicgk", "atax"):
+        ns = 512
+        prog = btoc.compile_spec(texts[k], "fused")
+        sb = {}
+        for j, (name, what) in enumerate(sorted(GENERATED[k].items())):
+            if what == "A":
+                sb[name] = torch.from_numpy(synth.matrix(synth.SEED, 950 + j, ns, ns)).to(dev)
+            elif what in ("m", "n"):
+                sb[name] = torch.from_numpy(synth.uniform(synth.SEED, 950 + j, ns)).to(dev)
+            else:
+                sb[name] = what
+        for o in prog.outputs:
+            sb[o] = (torch.empty((ns, ns), dtype=torch.float64, device=dev)
+                     if prog.kinds[o] == "matrix" else torch.empty(ns, dtype=torch.float64,
+                                                                   device=dev))
+        eager = time_steps(torch, lambda: prog.run(ws=ws, **sb), 200, 20)
+        cap = prog.capture(**sb)
+        graph = time_steps(torch, cap.replay, 200, 20)
+        small[k] = {"n": ns, "eager_us": round(eager * 1e6, 2), "graph_us": round(graph * 1e6, 2),
+                    "speedup": round(eager / graph, 2)}
+        del cap
+    out["graph_small"] = small
     return out
 
 

@@ -519,6 +519,12 @@ class Program:
     def passes(self):
         return [s for s in self.steps if isinstance(s, Pass)]
 
+    def capture(self, ws=None, **bound):
+        """The program captured in a HIP graph on these tensors
+        (btoc_run.Captured): replay() reruns it with one launch."""
+        from . import btoc_run
+        return btoc_run.Captured(self, bound, ws)
+
     def run(self, ws=None, **bound):
         """Enqueue the program on the current stream (see btoc_run.run)."""
         from . import btoc_run

@@ -210,3 +210,42 @@ def search(text: str, bound: dict, reps: int = 5, warmup: int = 1, ws=None):
         table.append((off, prog.describe(), e0.elapsed_time(e1) / reps, prog))
     best = min(table, key=lambda t: t[2])
     return best[3], [(off, d, ms) for off, d, ms, _ in table]
+
+
+class Captured:
+    """A compiled program captured once in a HIP graph on fixed tensors.
+
+    `replay()` enqueues every pass of the program as one graph launch on the
+    current stream.  The tensors bound at capture are the program's inputs
+    and outputs from then on: to run on new data, copy it into them first.
+    Scalars are taken at capture.  Temporaries and the workspace belong to
+    the capture and stay allocated with it."""
+
+    def __init__(self, prog, bound: dict, ws=None):
+        first = run(prog, bound, ws)                    # outputs allocated eagerly
+        self.bound = dict(bound)
+        self.bound.update(first)
+        self.outputs = first
+        dev = next(t.device for t in first.values())
+        if ws is None:
+            need = max([bto.pass_workspace_bytes(_ops(s), *_shape(s, _env_of(prog, self.bound)))
+                        for s in prog.steps if isinstance(s, Pass)] + [1])
+            ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.ws = ws
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            run(prog, self.bound, self.ws)              # warm-up off the capture
+        torch.cuda.current_stream(dev).wait_stream(side)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            run(prog, self.bound, self.ws)
+
+    def replay(self) -> dict:
+        self.graph.replay()
+        return self.outputs
+
+
+def _env_of(prog, bound):
+    """Stored views of the bound matrices (for workspace sizing)."""
+    return {k: _stored(k, v, prog) for k, v in bound.items() if isinstance(v, torch.Tensor)}

@@ -168,6 +168,32 @@ def test_search_times_only_correct_schedules(env, name):
     assert best.describe() in [sched for _, sched, _ in table]
 
 
+@pytest.mark.parametrize("name", ["gemver", "atax", "axpydot", "gemver_contracted"])
+def test_captured_program_replays(env, name):
+    """A program captured in a HIP graph: each replay, on inputs rewritten in
+    place between replays (with eager work and synchronizations in between),
+    gives the bits of the same program run eagerly on the same inputs."""
+    torch, btoc, dev = env
+    text, kinds, _ = PROGRAMS[name]
+    prog = btoc.compile_spec(text)
+    d = lambda h: {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+                   for k, v in h.items()}
+    bound = d(_inputs(kinds, 300, 200, "uniform", 1))
+    cap = prog.capture(**bound)
+    for rep in range(3):
+        fresh = d(_inputs(kinds, 300, 200, "uniform", 10 + rep))
+        for k, t in fresh.items():
+            if isinstance(t, torch.Tensor):
+                bound[k].copy_(t)
+        torch.cuda.synchronize()
+        out = cap.replay()
+        torch.cuda.synchronize()
+        eager = prog.run(**fresh)
+        torch.cuda.synchronize()
+        for o in eager:
+            assert torch.equal(out[o], eager[o]), (name, rep, o)
+
+
 def test_outputs_bound_by_the_caller_receive_the_results(env):
     torch, btoc, dev = env
     text, kinds, _ = PROGRAMS["gemver"]
