@@ -306,6 +306,8 @@ class _Typer:
     def statement(self, lhs, tree):
         if lhs in self.inputs:
             raise SpecError(f"{lhs} is an input and cannot be assigned")
+        if lhs in self.defined:
+            raise SpecError(f"{lhs} is assigned twice")
         val = self.value(tree)
         if isinstance(val, Mat):
             if val.trans or val.coef != ONE:
@@ -331,8 +333,6 @@ class _Typer:
             self.defs.append((lhs, val))
         else:
             raise SpecError(f"{lhs}: scalar and outer-product results are not supported")
-        if lhs in self.defined and lhs not in self.mats:
-            raise SpecError(f"{lhs} is assigned twice")
         self.defined.add(lhs)
         if isinstance(val, Mat):
             self.defs.append((lhs, val))

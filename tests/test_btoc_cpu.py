@@ -191,6 +191,10 @@ out: r : scalar, y : vector(column)
     ("K\nin: A : matrix(row), x : vector(column)\nout: y : vector(column)\n{ y = A * x x }",
      "expected"),
     ("K\nin: x : tensor(row)\nout: y : vector(column)\n{ y = x }", "unknown type"),
+    ("K\nin: A : matrix(row), u : vector(column), x : vector(column)\nout: y : vector(column)\n"
+     "{ B = A + u * u'\n B = A\n y = B * x }", "assigned twice"),
+    ("K\nin: x : vector(column)\nout: y : vector(column)\n{ y = x\n y = 2 * x }",
+     "assigned twice"),
 ])
 def test_refusals(text, message):
     with pytest.raises(btoc.SpecError, match=message):
