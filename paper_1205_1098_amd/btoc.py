@@ -788,3 +788,40 @@ def _ordered(steps):
     for i, s in enumerate(steps):
         keyed.append(((s.level, 1 if isinstance(s, Pass) else 0, i), s))
     return [s for _, s in sorted(keyed, key=lambda kv: kv[0])]
+
+
+def main(argv=None) -> int:
+    """python -m paper_1205_1098_amd.btoc SPEC [--unfused] [--off DECISION ...]
+
+    Prints the schedule of a specification file (or of a kernel of the
+    library's set: bicgk, gemver, atax, dgemvt, dgemv, gesummv, axpydot,
+    waxpby, vadd, batax, gemver_contracted)."""
+    import argparse
+
+    from . import bto_specs
+
+    ap = argparse.ArgumentParser(description="schedule of a BTO kernel specification")
+    ap.add_argument("spec")
+    ap.add_argument("--unfused", action="store_true")
+    ap.add_argument("--off", nargs="*", default=[], choices=DECISIONS)
+    args = ap.parse_args(argv)
+    named = dict(bto_specs.TABLE_I, batax=bto_specs.BATAX,
+                 gemver_contracted=bto_specs.GEMVER_CONTRACTED)
+    if args.spec in named:
+        text = named[args.spec]
+    else:
+        with open(args.spec) as f:
+            text = f.read()
+    try:
+        prog = compile_spec(text, "unfused" if args.unfused else "fused", tuple(args.off))
+    except SpecError as e:
+        print(f"error: {e}")
+        return 1
+    print(f"{prog.name}: {len(prog.passes())} pass(es) over matrices, {len(prog.steps)} step(s)")
+    for line in prog.describe():
+        print("  " + line)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -290,3 +290,14 @@ def test_evaluator_integers_exact():
     assert np.array_equal(ev("two_dots", A=A, x=x)["y"], 2 * (Ai @ (Ai @ i64(x))))
     g = ev("mixed", A=A, x=x, y=y, w=w, alpha=2.0)
     assert np.array_equal(g["z"], -(Ai @ i64(x)) + i64(y) - 2 * i64(w))
+
+
+def test_command_line(capsys, tmp_path):
+    assert btoc.main(["batax"]) == 0
+    assert "pass 0: A CHAIN|ROWDOT|COLSUM" in capsys.readouterr().out
+    f = tmp_path / "k.bto"
+    f.write_text(specs.NOVEL["two_dots"])
+    assert btoc.main([str(f), "--unfused"]) == 0
+    assert "pass 1: A ROWDOT" in capsys.readouterr().out
+    f.write_text("K\nin: x : vector(column)\nout: y : vector(column)\n{ y = z }")
+    assert btoc.main([str(f)]) == 1
