@@ -194,6 +194,45 @@ def test_captured_program_replays(env, name):
             assert torch.equal(out[o], eager[o]), (name, rep, o)
 
 
+@pytest.mark.parametrize("name,kind", [("gemver", "int"), ("gemver", "uniform"),
+                                       ("gemver_contracted", "uniform"), ("bicgk", "uniform"),
+                                       ("atax", "uniform")])
+def test_full_size_compiled(env, name, kind):
+    """n = 16384, the size the benchmark times the compiled programs at,
+    against the C oracle's kernels (integer data bitwise)."""
+    import oracle
+
+    torch, btoc, dev = env
+    N = 16384
+    text, kinds, _ = PROGRAMS[name]
+    host = _inputs(kinds, N, N, kind, 99)
+    if kind == "int":
+        host.update(alpha=2.0, beta=3.0)
+    d = {k: (torch.from_numpy(v).to(dev) if isinstance(v, np.ndarray) else v)
+         for k, v in host.items()}
+    out = btoc.compile_spec(text).run(**d)
+    h = host
+    if name == "gemver":
+        B, x, w = oracle.gemver(h["A"], h["u1"], h["v1"], h["u2"], h["v2"], h["y"], h["z"],
+                                h["alpha"], h["beta"])
+        ref = {"B": B, "x": x, "w": w}
+    elif name == "gemver_contracted":
+        _, x, w = oracle.gemver(h["A"], h["u1"], h["v1"], h["u2"], h["v2"], h["y"], h["z"],
+                                h["alpha"], h["beta"])
+        ref = {"x": x, "w": w}
+    elif name == "bicgk":
+        q, s_ = oracle.bicgk(h["A"], h["p"], h["r"])
+        ref = {"q": q, "s": s_}
+    else:
+        ref = {"y": oracle.atax(h["A"], h["x"])}
+    for o, r in ref.items():
+        got = out[o].cpu().numpy()
+        if kind == "int":
+            assert np.array_equal(got, r), (name, o)
+        else:
+            assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
+
+
 def test_outputs_bound_by_the_caller_receive_the_results(env):
     torch, btoc, dev = env
     text, kinds, _ = PROGRAMS["gemver"]
