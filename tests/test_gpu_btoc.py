@@ -233,6 +233,32 @@ def test_full_size_compiled(env, name, kind):
             assert _relerr(got, r) <= TOL, (name, o, _relerr(got, r))
 
 
+@pytest.mark.parametrize("form", ["fused", "unfused"])
+@pytest.mark.parametrize("m,n", [(0, 5), (5, 0), (0, 0)])
+@pytest.mark.parametrize("name", ["bicgk", "gemver", "atax", "dgemvt", "dgemv", "gesummv",
+                                  "batax", "gemver_contracted", "rank1_stored"])
+def test_compiled_program_empty_extents(env, name, m, n, form):
+    """m or n = 0: empty sums are 0, and every output is still written."""
+    torch, btoc, dev = env
+    text, kinds, _ = PROGRAMS[name]
+    host = _inputs(kinds, m, n, "uniform", 2)
+    ref = spec_eval.evaluate(text, host)
+    bound = {}
+    for k, v in host.items():
+        if isinstance(v, np.ndarray) and v.ndim == 2:
+            bound[k] = torch.empty((max(m, 1), max(n, 2)), dtype=torch.float64,
+                                   device=dev)[:m, :n]
+        elif isinstance(v, np.ndarray):
+            bound[k] = torch.from_numpy(v).to(dev)
+        else:
+            bound[k] = v
+    out = btoc.compile_spec(text, form).run(**bound)
+    for o, r in ref.items():
+        got = out[o].cpu().numpy()
+        assert got.shape == np.shape(r), (name, o)
+        assert np.array_equal(got, np.asarray(r)), (name, o)
+
+
 def test_outputs_bound_by_the_caller_receive_the_results(env):
     torch, btoc, dev = env
     text, kinds, _ = PROGRAMS["gemver"]
