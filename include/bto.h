@@ -269,6 +269,14 @@ size_t bto_dot_workspace_bytes(int64_t n);
 bto_status bto_dot(int64_t n, const double *x, const double *y, double *r,
                    void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* out <- coef[0] x[0] + coef[1] x[1] + ... + coef[count-1] x[count-1], added
+ * left to right, in one pass: the scaled vector sums of a statement fused
+ * (Section III-E), for the spec compiler.  count is 1 to 8; x and coef are
+ * HOST arrays of count entries (device vector pointers, scalars); vectors
+ * of length n.  out may be exactly one of the x[k]; no other overlap. */
+bto_status bto_lincomb(int64_t n, int count, const double *const *x, const double *coef,
+                       double *out, hipStream_t stream);
+
 /* WAXPBY (Table I):  w <- alpha x + beta y.  Length n; w may be exactly x
  * or exactly y.  Unfused: scal into a temporary, then axpy. */
 bto_status bto_waxpby(int64_t n, double alpha, const double *x, double beta,

@@ -74,6 +74,8 @@ _SIGS = {
                   _int),
     "bto_gesummv": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int,
                      _ptr], _int),
+    "bto_lincomb": ([_i64, _int, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_dbl), _ptr,
+                     _ptr], _int),
     "bto_dot_workspace_bytes": ([_i64], _sz),
     "bto_dot": ([_i64, _ptr, _ptr, _ptr, _ptr, _sz, _ptr], _int),
     "bto_pass_workspace_bytes": ([_int, _i64, _i64], _sz),
@@ -423,6 +425,23 @@ def fused_pass(ops, A, *, B=None, u1=None, v1=None, u2=None, v2=None, x=None, y=
                  _addr(col_add), float(col_add_scale))
     with torch.cuda.device(dev):
         _check(_lib.bto_pass(ctypes.byref(d), _ptr_of(ws), ws.numel(), _stream(dev)))
+
+
+def lincomb(xs, coefs, out=None):
+    """out = sum_k coefs[k] * xs[k] (left to right, one pass; up to 8 terms)."""
+    if not 1 <= len(xs) <= 8 or len(coefs) != len(xs):
+        raise ValueError("1 to 8 vectors, one coefficient each")
+    dev = xs[0].device
+    n = xs[0].numel()
+    out = _empty(n, dev) if out is None else out
+    for k, t in enumerate(xs):
+        _check_vec(t, f"x{k}", dev, n)
+    _check_vec(out, "out", dev, n)
+    ptrs = (ctypes.c_void_p * len(xs))(*[t.data_ptr() for t in xs])
+    cs = (ctypes.c_double * len(xs))(*[float(c) for c in coefs])
+    with torch.cuda.device(dev):
+        _check(_lib.bto_lincomb(n, len(xs), ptrs, cs, _ptr_of(out), _stream(dev)))
+    return out
 
 
 def dot(x, y, r=None, ws=None):

@@ -466,6 +466,14 @@ class Vadd:
 
 
 @dataclass
+class LinComb:
+    """out = sum of c_k t_k, left to right, in one pass (bto_lincomb)."""
+    level: int
+    out: str
+    terms: list
+
+
+@dataclass
 class AxpyDot:
     """z = w - alpha v and r = z . u in one pass (bto_axpydot)."""
     level: int
@@ -510,6 +518,9 @@ class Program:
                 lines.append(f"vec {s.level}: {s.out} = a*{s.x} + b*{s.y}")
             elif isinstance(s, Vadd):
                 lines.append(f"vadd {s.level}: {s.out} = {s.a} + {s.b} + {s.c}")
+            elif isinstance(s, LinComb):
+                lines.append(f"lincomb {s.level}: {s.out} = "
+                             + " + ".join(f"c*{t}" for _, t in s.terms))
             elif isinstance(s, AxpyDot):
                 lines.append(f"axpydot {s.level}: {s.z} = {s.w} - alpha*{s.v}; {s.r} = {s.z}.{s.u}")
             else:
@@ -651,10 +662,19 @@ class _Scheduler:
         return m.base, m.terms
 
     def vec_sum(self, out, terms, lvl):
-        """out = sum of c_k t_k as scaled vector sums (bto_waxpby), or as one
-        three-way sum (bto_vadd) when fused and every coefficient is 1."""
+        """out = sum of c_k t_k: one three-way sum (bto_vadd) when every
+        coefficient is 1, one pass per eight terms (bto_lincomb) otherwise,
+        or, with vector fusion off, scaled sums of two (bto_waxpby)."""
         if self.on["vector"] and len(terms) == 3 and all(c == ONE for c, _ in terms):
             self.steps.append(Vadd(lvl, out, terms[0][1], terms[1][1], terms[2][1]))
+            return
+        if self.on["vector"] and len(terms) >= 3:
+            # one pass per eight terms: the sum so far is the first of the next
+            self.steps.append(LinComb(lvl, out, list(terms[:8])))
+            rest = list(terms[8:])
+            while rest:
+                self.steps.append(LinComb(lvl, out, [(ONE, out)] + rest[:7]))
+                rest = rest[7:]
             return
         c0, t0 = terms[0]
         if len(terms) == 1:

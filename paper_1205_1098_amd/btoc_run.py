@@ -12,7 +12,7 @@ from __future__ import annotations
 import torch
 
 from . import bto
-from .btoc import AxpyDot, DotOp, Pass, SpecError, Vadd, VecOp
+from .btoc import AxpyDot, DotOp, LinComb, Pass, SpecError, Vadd, VecOp
 
 
 def _coef(c, scalars):
@@ -100,6 +100,11 @@ def run(prog, bound: dict, ws=None) -> dict:
         if isinstance(s, Vadd):
             a = get(s.a)
             bto.vadd(a, get(s.b), get(s.c), x=vec_out(s.out, a.numel()))
+            continue
+        if isinstance(s, LinComb):
+            xs = [get(t) for _, t in s.terms]
+            bto.lincomb(xs, [_coef(c, scalars) for c, _ in s.terms],
+                        out=vec_out(s.out, xs[0].numel()))
             continue
         if isinstance(s, AxpyDot):
             w = get(s.w)

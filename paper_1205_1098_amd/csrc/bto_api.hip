@@ -1016,6 +1016,34 @@ bto_status bto_dot(int64_t n, const double *x, const double *y, double *r, void 
     return check_launch();
 }
 
+// ---- linear combination --------------------------------------------------------
+
+bto_status bto_lincomb(int64_t n, int count, const double *const *x, const double *coef,
+                       double *out, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(need(n >= 0, "negative size"));
+    BTO_TRY(need(count >= 1 && count <= kMaxLin, "count must be 1 to 8"));
+    BTO_TRY(need(x != nullptr && coef != nullptr, "x and coef are host arrays of count entries"));
+    static const char *names[kMaxLin] = {"x0", "x1", "x2", "x3", "x4", "x5", "x6", "x7"};
+    LinArgs a{};
+    std::vector<Span> spans;
+    std::vector<AllowedAlias> ok;
+    for (int k = 0; k < count; ++k) {
+        BTO_TRY(check_vec(x[k], n, names[k]));
+        a.x[k] = x[k];
+        a.c[k] = coef[k];
+        spans.push_back(vspan(names[k], x[k], n, false));
+        ok.push_back({"out", names[k]});
+    }
+    BTO_TRY(check_vec(out, n, "out"));
+    a.out = out;
+    spans.push_back(vspan("out", out, n, true));
+    BTO_TRY(check_aliases(spans, ok));
+    launch_lincomb(n, count, a, st);
+    return check_launch();
+}
+
 // ---- VADD --------------------------------------------------------------------
 
 bto_status bto_vadd(int64_t n, const double *w, const double *y, const double *z, double *x,

@@ -41,6 +41,15 @@ enum EwOp {
     EW_AXMY,     // out = a - s0*b
 };
 
+// out = sum_k c[k] x[k], k = 0..count-1 added left to right, in one pass
+constexpr int kMaxLin = 8;
+struct LinArgs {
+    const double *x[kMaxLin];
+    double c[kMaxLin];
+    double *out;
+};
+void launch_lincomb(int64_t n, int count, const LinArgs &a, hipStream_t st);
+
 void launch_ew(EwOp op, int64_t n, const double *a, const double *b, const double *c,
                double s0, double s1, double *out, hipStream_t st);
 

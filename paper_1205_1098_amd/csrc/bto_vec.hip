@@ -83,6 +83,67 @@ __global__ __launch_bounds__(kEwBlock) void k_ew(int64_t n, const double *a, con
     }
 }
 
+// Kernel-argument pointers inside a struct are not known to address global
+// memory; say so, so that the loads are global (not flat) loads.
+__device__ __forceinline__ const double *glob(const double *p)
+{
+    return (const double *)(const __attribute__((address_space(1))) double *)(uintptr_t)p;
+}
+
+// out = c[0] x[0] + c[1] x[1] + ... (left to right), K inputs, one pass.
+template <int K, bool VEC>
+__global__ __launch_bounds__(kEwBlock) void k_lincomb(int64_t n, LinArgs a)
+{
+    if constexpr (VEC) {
+        const int64_t p = (int64_t)blockIdx.x * kEwBlock + threadIdx.x;
+        if (p < (n >> 1)) {
+            d2 v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[k] = ld2_nt(glob(a.x[k]) + 2 * p);
+            d2 acc = a.c[0] * v[0];
+#pragma unroll
+            for (int k = 1; k < K; ++k)
+                acc = acc + a.c[k] * v[k];
+            st2_nt(a.out + 2 * p, acc);
+        }
+        if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const int64_t i = n - 1;
+            double acc = a.c[0] * glob(a.x[0])[i];
+#pragma unroll
+            for (int k = 1; k < K; ++k)
+                acc = acc + a.c[k] * glob(a.x[k])[i];
+            a.out[i] = acc;
+        }
+    } else {
+        const int64_t base = (int64_t)blockIdx.x * (2 * kEwBlock) + threadIdx.x;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t i = base + (int64_t)u * kEwBlock;
+            if (i < n) {
+                double acc = a.c[0] * glob(a.x[0])[i];
+#pragma unroll
+                for (int k = 1; k < K; ++k)
+                    acc = acc + a.c[k] * glob(a.x[k])[i];
+                a.out[i] = acc;
+            }
+        }
+    }
+}
+
+template <int K>
+void launch_lincomb_t(int64_t n, const LinArgs &a, hipStream_t st)
+{
+    bool vec = aligned16(a.out);
+    for (int k = 0; k < K; ++k)
+        vec = vec && aligned16(a.x[k]);
+    dim3 grid((unsigned)ceil_div(n, 2 * kEwBlock));
+    if (vec)
+        launch("ew_lincomb", k_lincomb<K, true>, grid, dim3(kEwBlock), st, n, a);
+    else
+        launch("ew_lincomb", k_lincomb<K, false>, grid, dim3(kEwBlock), st, n, a);
+}
+
 template <int OP>
 void launch_ew_t(int64_t n, const double *a, const double *b, const double *c, double s0,
                  double s1, double *out, hipStream_t st)
@@ -224,6 +285,23 @@ __global__ __launch_bounds__(kEwBlock) void k_copy(int64_t npair, const double *
 }
 
 }  // namespace
+
+void launch_lincomb(int64_t n, int count, const LinArgs &a, hipStream_t st)
+{
+    if (n <= 0)
+        return;
+    switch (count) {
+    case 1: launch_lincomb_t<1>(n, a, st); break;
+    case 2: launch_lincomb_t<2>(n, a, st); break;
+    case 3: launch_lincomb_t<3>(n, a, st); break;
+    case 4: launch_lincomb_t<4>(n, a, st); break;
+    case 5: launch_lincomb_t<5>(n, a, st); break;
+    case 6: launch_lincomb_t<6>(n, a, st); break;
+    case 7: launch_lincomb_t<7>(n, a, st); break;
+    case 8: launch_lincomb_t<8>(n, a, st); break;
+    default: break;
+    }
+}
 
 void launch_ew(EwOp op, int64_t n, const double *a, const double *b, const double *c,
                double s0, double s1, double *out, hipStream_t st)

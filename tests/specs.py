@@ -42,6 +42,13 @@ out: y : vector(column)
   t = A * x
   y = 2 * A * t
 }""",
+    "lin4": """LIN4
+in:  w : vector(column), y : vector(column), z : vector(column), v : vector(column),
+     a : scalar
+out: x : vector(column)
+{
+  x = a * w + y - 2 * z + v
+}""",
     "mixed": """MIXED
 in:  A : matrix(row), x : vector(column), y : vector(column), w : vector(column),
      alpha : scalar

@@ -78,6 +78,7 @@ NOVEL_SCHEDULES = {
     "rank1_contracted": ["vec 0: _s1 = a*y + b*y", "pass 0: A CONTRACT|ROWDOT"],
     "two_dots": ["pass 0: A ROWDOT", "pass 1: A ROWDOT"],
     "mixed": ["vec 0: _s1 = a*y + b*w", "pass 0: A ROWDOT"],
+    "lin4": ["lincomb 0: x = c*w + c*y + c*z + c*v"],
 }
 
 
@@ -290,6 +291,8 @@ def test_evaluator_integers_exact():
     assert np.array_equal(ev("two_dots", A=A, x=x)["y"], 2 * (Ai @ (Ai @ i64(x))))
     g = ev("mixed", A=A, x=x, y=y, w=w, alpha=2.0)
     assert np.array_equal(g["z"], -(Ai @ i64(x)) + i64(y) - 2 * i64(w))
+    g = ev("lin4", w=w, y=y, z=z, v=v, a=3.0)
+    assert np.array_equal(g["x"], 3 * i64(w) + i64(y) - 2 * i64(z) + i64(v))
 
 
 def test_command_line(capsys, tmp_path):

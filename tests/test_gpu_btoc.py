@@ -48,6 +48,7 @@ PROGRAMS = {
                          dict(A="A", u="m", v="n", x="n", y="m", gamma=1.25), False),
     "two_dots": (specs.NOVEL["two_dots"], dict(A="A", x="n"), True),
     "mixed": (specs.NOVEL["mixed"], dict(A="A", x="n", y="m", w="m", alpha=0.5), False),
+    "lin4": (specs.NOVEL["lin4"], dict(w="n", y="n", z="n", v="n", a=1.5), False),
 }
 SHAPES = [(1, 1), (65, 127), (513, 1000), (300, 4097), (2047, 2049)]
 SQUARE = [(1, 1), (127, 127), (1000, 1000), (2049, 2049)]

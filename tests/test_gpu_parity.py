@@ -591,6 +591,34 @@ def test_store_pass_every_shape(env, shape):
             bto.tune_set(slot, *c, size=256 << b)
 
 
+# ---- linear combination of up to eight vectors (bto_lincomb) --------------------
+
+@pytest.mark.parametrize("count", range(1, 9))
+@pytest.mark.parametrize("n,offset", [(0, 0), (1, 0), (1025, 0), (1 << 20, 1), (4097, 1)])
+def test_lincomb(env, count, n, offset):
+    """Against sums left to right of the oracle's scaled vectors (WAXPBY with
+    a zero second scale is the plain product), and bitwise on integers; the
+    output may be one of the inputs."""
+    torch, bto, dev = env
+    coefs = [1.5 - 0.25 * k for k in range(count)]
+    xs = [synth.uniform(SEED, synth.stream_id(5, k, n), n) for k in range(count)]
+    ref = oracle.waxpby(xs[0], xs[0], coefs[0], 0.0)
+    for k in range(1, count):
+        ref = oracle.vadd(ref, oracle.waxpby(xs[k], xs[k], coefs[k], 0.0), np.zeros(n))
+    dx = []
+    for x in xs:     # offset 1: storage misaligned by one element (scalar path)
+        buf = torch.empty(n + offset, dtype=torch.float64, device=dev)
+        buf[offset:] = torch.from_numpy(x).to(dev)
+        dx.append(buf[offset:])
+    out = bto.lincomb(dx, coefs)
+    assert relerr(host(out), ref) <= TOL
+    ints = [synth.vector(SEED, synth.stream_id(5, 10 + k, n), n, "int") for k in range(count)]
+    di = [dvec(torch, dev, v) for v in ints]
+    got = bto.lincomb(di, [k - 3.0 for k in range(count)], out=di[-1])   # in place
+    want = sum((k - 3) * v.astype(np.int64) for k, v in enumerate(ints))
+    assert np.array_equal(host(got), np.asarray(want, dtype=np.float64).reshape(n))
+
+
 # ---- DGEMV and GESUMMV --------------------------------------------------------
 
 @pytest.mark.parametrize("form", FORMS)
