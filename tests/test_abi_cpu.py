@@ -255,6 +255,22 @@ def test_pass_and_dot_checks(bto):
                             None) == 2
 
 
+def test_lincomb_checks(bto):
+    """Refusals of the linear combination before anything is enqueued."""
+    P = ctypes.c_void_p
+    ptrs = lambda *a: (P * len(a))(*[P(x) for x in a])
+    cs = lambda k: (ctypes.c_double * k)(*([1.0] * k))
+    x = [FAKE + (k << 20) for k in range(9)]
+    call = lambda n, k, xs, out: bto._lib.bto_lincomb(n, k, xs, cs(max(k, 1)), P(out), None)
+    assert call(10, 0, ptrs(x[0]), x[8]) == 1               # no term
+    assert call(10, 9, ptrs(*x), x[8]) == 1                 # more than eight
+    assert call(-1, 1, ptrs(x[0]), x[8]) == 1
+    assert bto._lib.bto_lincomb(10, 1, None, cs(1), P(x[8]), None) == 1
+    assert call(10, 2, ptrs(x[0], 0), x[8]) == 1            # a NULL vector
+    assert call(10, 2, ptrs(x[0], x[1]), x[1] + 8) == 2     # out partly over x1
+    assert call(10, 2, ptrs(x[0], x[1]), x[0] + 8) == 2     # out partly over x0
+
+
 def test_contracted_gemver_and_batax_checks(bto):
     """GEMVER without B and BATAX: workspace sizes and the argument checks,
     before anything is enqueued."""
