@@ -140,6 +140,10 @@ def dominant(kernel: str, n: int = N, nv: int = NV):
 
 # ---- workloads ------------------------------------------------------------------
 
+# kernels whose suite entry is also timed with inputs that are cold in the
+# last-level cache (every matrix kernel)
+COLD = ("gemver", "bicgk", "atax", "dgemvt", "gemver_contracted", "batax", "dgemv", "gesummv")
+
 class Workload:
     """Device-resident inputs and outputs of one kernel at bench size."""
 
@@ -213,16 +217,26 @@ class Workload:
             b.vadd(self.a, self.b, self.c, form=form, x=self.out, ws=ws)
 
 
-def time_steps(torch, fn, steps: int, warmup: int) -> float:
-    """Seconds per step over `steps` calls after `warmup` untimed ones."""
+def time_stats(torch, fn, steps: int, warmup: int):
+    """(median, min) seconds per call of `fn` over `steps` calls after
+    `warmup` untimed ones: HIP events recorded on torch's current stream (the
+    stream the library launches on) between calls."""
     for _ in range(warmup):
         fn()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    evs[0].record()
+    for i in range(steps):
         fn()
+        evs[i + 1].record()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return float(np.median(ms)) * 1e-3, float(min(ms)) * 1e-3
+
+
+def time_steps(torch, fn, steps: int, warmup: int) -> float:
+    """Median seconds per call (see time_stats)."""
+    return time_stats(torch, fn, steps, warmup)[0]
 
 
 # ---- hardware-counter traffic ------------------------------------------------------
@@ -252,21 +266,45 @@ def counter_traffic(summary: str):
 
 # ---- CPU oracle baseline -------------------------------------------------------------
 
-def cpu_baseline(kernel: str, target_s: float):
-    import numpy as np
+def oracle_bytes(kernel: str, n: int = N) -> int:
+    """Bytes the oracle's loops move for one call at size n: the matrix
+    passes its unfused statements execute (GEMVER: read A, write B, then
+    read B for each product; the others one read of A per product), plus
+    each vector once."""
+    M, v = n * n * 8, n * 8
+    return {"gemver": 4 * M + 10 * v, "bicgk": 2 * M + 4 * v, "atax": 2 * M + 4 * v,
+            "dgemvt": 2 * M + 4 * v}[kernel]
 
+
+def host_cpu() -> dict:
+    """The host CPU's model name and logical CPU count (from /proc/cpuinfo)."""
+    model, count = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    count += 1
+                    model = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": count or (os.cpu_count() or 0)}
+
+
+def cpu_baseline(kernel: str, target_s: float):
+    """The oracle on the host cores, on the same workload (one full call at
+    n = 16384 on host data): with every thread the process may use, and with
+    one thread; the median of 3 calls or more (repeated up to about
+    `target_s` seconds with all threads), in GB/s of the bytes its loops move."""
     import oracle
     from paper_1205_1098_amd import synth
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    oracle.set_threads(threads)
+    threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     seed = synth.SEED
     sid = lambda op: synth.stream_id(2, op)
     A = synth.matrix(seed, sid(0), N, N)
     vs = [synth.uniform(seed, sid(k), N) for k in range(1, 7)]
-    reps, elapsed = 0, 0.0
-    while elapsed < target_s and reps < 20:
-        t0 = time.perf_counter()
+
+    def call():
         if kernel == "gemver":
             oracle.gemver(A, *vs, ALPHA, BETA)
         elif kernel == "bicgk":
@@ -275,17 +313,39 @@ def cpu_baseline(kernel: str, target_s: float):
             oracle.atax(A, vs[0])
         else:
             oracle.dgemvt(A, vs[0], vs[1], ALPHA, BETA)
-        elapsed += time.perf_counter() - t0
-        reps += 1
-    per = elapsed / reps
+
+    def leg(t: int, budget: float, cap: int):
+        oracle.set_threads(t)
+        used = int(oracle.get_threads())
+        times = []
+        while len(times) < 3 or (sum(times) < budget and len(times) < cap):
+            t0 = time.perf_counter()
+            call()
+            times.append(time.perf_counter() - t0)
+        med = float(np.median(times))
+        return {"threads": used, "calls": len(times), "median_ms": round(med * 1e3, 2),
+                "min_ms": round(min(times) * 1e3, 2),
+                "gbs": round(oracle_bytes(kernel) / med / 1e9, 3)}
+
+    full = leg(threads, target_s, 200)
+    one = leg(1, 0.0, 3)
+    oracle.set_threads(1)
     del A
+    cpu = host_cpu()
     return {
-        "value": round(alg_bytes(kernel, "fused") / per / 1e9, 3),
+        "value": full["gbs"],
         "unit": "GB/s",
-        "cores": int(oracle.get_threads()),
+        "cores": full["threads"],
         "kind": "oracle",
-        "sample": f"{reps} full {kernel} n={N} call(s) on host data, {per * 1e3:.1f} ms each; "
-                  f"GB/s on the same algorithmic bytes as the GPU value",
+        "sample": f"{full['calls']} full {kernel} n={N} calls on host data with {full['threads']} "
+                  f"threads (median {full['median_ms']} ms) and 3 with 1 thread (median "
+                  f"{one['median_ms']} ms); GB/s of the {oracle_bytes(kernel)} bytes its "
+                  "unfused loops move per call",
+        "cpu_model": cpu["model"],
+        "logical_cpus": cpu["logical_cpus"],
+        "all_threads": full,
+        "one_thread": one,
+        "bytes_per_call": oracle_bytes(kernel),
     }
 
 
@@ -400,13 +460,37 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
     insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
                                         {"gemver": 0.5, "bicgk": 0.5}, config=4)
     total = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in specs)
+    outs = lambda: [t.clone() for inst in insts for t in inst["out"]]
     plan = bto.BatchPlan(insts, use_graph=graph)
-    sec = time_steps(torch, plan.launch, 10, 2)
+    sec, sec_min = time_stats(torch, plan.launch, 10, 2)
+    # the last timed launch completed every bounded wait (raises otherwise),
+    # so its outputs are those of the batch
+    try:
+        plan.check()
+        checked = True
+    except bto.BtoError as e:
+        print(f"batched: {e}", file=sys.stderr, flush=True)
+        checked = False
+    persistent = outs()
     plan.close()
     # the same instances as short-lived workgroup tiles (four launches in a graph)
+    for inst in insts:
+        for t in inst["out"]:
+            t.fill_(float("nan"))
     tiled = bto.TiledBatch(insts, use_graph=graph)
-    sec_tiled = time_steps(torch, tiled.launch, 10, 2)
+    sec_tiled, sec_tiled_min = time_stats(torch, tiled.launch, 10, 2)
+    torch.cuda.synchronize()
+    tiled_outs = outs()
     tiled.close()
+    # the two forms add in different orders: they agree to the parity
+    # tolerance (each is checked against the oracle by the GPU tests)
+    worst = 0.0
+    for a, b in zip(persistent, tiled_outs):
+        den = float(a.abs().max()) if a.numel() else 0.0
+        num = float((a - b).abs().max()) if a.numel() else 0.0
+        err = num / den if den > 0 else num
+        worst = max(worst, err if err == err else float("inf"))
+    del persistent, tiled_outs
     # the same instances launched one entry-point call at a time
     def loop():
         for inst in insts:
@@ -422,12 +506,18 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         "n_range": [64, 2048],
         "alg_gb": round(total / 1e9, 3),
         "ms_per_batch": round(sec * 1e3, 3),
+        "min_ms": round(sec_min * 1e3, 3),
+        "checked": checked and worst <= 2e-12,
+        "check": "bto_batch_plan_check after the timed launches: every bounded wait of the last "
+                 "launch completed; tiled outputs against persistent ones (normwise, per array)",
+        "tiled_vs_persistent_max_relerr": worst,
         "inst_per_s": round(count / sec, 1),
         "gbs": round(total / sec / 1e9, 1),
         "pct_peak": round(100 * total / sec / 1e9 / PEAK_GBS, 1),
         "traffic": counter_traffic("batch_mixed4096_counters.txt") if count == 4096 else None,
         "tiled": {
             "ms_per_batch": round(sec_tiled * 1e3, 3),
+            "min_ms": round(sec_tiled_min * 1e3, 3),
             "inst_per_s": round(count / sec_tiled, 1),
             "gbs": round(total / sec_tiled / 1e9, 1),
             "pct_peak": round(100 * total / sec_tiled / 1e9 / PEAK_GBS, 1),
@@ -516,21 +606,35 @@ def main() -> int:
     shared = {}
     main_wl = Workload(torch, bto, synth, args.workload, dev, shared)
 
-    # timed region: K fused steps, dominant-kernel events recorded on its stream
+    # timed region: K fused steps and nothing else.  One HIP event is recorded
+    # on torch's current stream (the stream the library launches on) between
+    # steps, so step i's time is the time between events i and i + 1; the
+    # headline is the median of those K times.
     for _ in range(args.warmup):
         main_wl.run("fused")
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record()
+    for i in range(args.steps):
+        main_wl.run("fused")
+        evs[i + 1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    sec = float(np.median(step_ms)) * 1e-3
+
+    # the dominant kernel's launch time, from a separate loop of K steps with
+    # HIP events around that kernel alone (on the stream it is launched on)
     dom_name, dom_bytes = dominant(args.workload)
     if dom_name == "bicgk_fused" and bto.tune_get(bto.tune_slots().index("bicgk_rowres"), N)[0]:
         dom_name = "bicgk_rowres"   # the row-resident sweep serves fused BiCGK at this size
     bto.timing_reset()
-    bto.timing_only(dom_name)     # events around the dominant kernel only
+    bto.timing_only(dom_name)
     bto.timing_enable(True)
-    t0 = time.perf_counter()
     for _ in range(args.steps):
         main_wl.run("fused")
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
     bto.timing_enable(False)
     times = bto.timing_read()
     bto.timing_reset()
@@ -552,6 +656,10 @@ def main() -> int:
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(sec * 1e3, 4),
+        "timing": {"method": "median of K per-step HIP-event intervals on the launching "
+                             "stream; no other events in the timed loop",
+                   "min_ms": round(min(step_ms), 4), "max_ms": round(max(step_ms), 4),
+                   "wall_mean_ms": round(wall * 1e3, 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -579,6 +687,8 @@ def main() -> int:
             "alg_bytes_per_launch": dom_bytes,
             "avg_launch_ms": round(dom_ms, 5),
             "launches_timed": launches,
+            "how": "mean of HIP-event pairs around the kernel on its stream, in a separate "
+                   "loop of K steps after the headline loop",
         },
         "kernel_ms": {k: round(ms / c, 5) for k, (c, ms) in times.items() if c},
         "device": {"name": props.name, "cus": props.multi_processor_count,
@@ -587,15 +697,37 @@ def main() -> int:
 
     if not args.no_suite:
         suite = {}
+        # a second set of matrices (other streams, filled in place): the cold
+        # timings alternate between the two sets, so each step reads 2 GiB
+        # matrices that the 256 MB last-level cache cannot hold from the step
+        # before; the warm timings re-run one set as a plain loop would
+        alt = {"A": torch.empty_like(shared["A"])}
+        bto.synth_fill(alt["A"], synth.stream_state(synth.SEED, synth.stream_id(3, 40)))
         for k in ("gemver", "bicgk", "atax", "dgemvt", "axpydot", "waxpby", "vadd",
                   "gemver_contracted", "batax", "dgemv", "gesummv"):
             wl = main_wl if k == args.workload else Workload(torch, bto, synth, k, dev, shared)
+            wl2 = Workload(torch, bto, synth, k, dev, alt) if k in COLD else None
             ent = {}
             for form in ("fused",) if k == "gemver_contracted" else ("fused", "unfused"):
-                s = time_steps(torch, lambda: wl.run(form), 20, 3)
+                s, smin = time_stats(torch, lambda: wl.run(form), 20, 3)
                 ent[form + "_ms"] = round(s * 1e3, 4)
+                ent[form + "_min_ms"] = round(smin * 1e3, 4)
                 ent[form + "_gbs"] = round(alg_bytes(k, form) / s / 1e9, 1)
+                if wl2 is not None:
+                    flip = [0]
+
+                    def alternate():
+                        (wl if flip[0] == 0 else wl2).run(form)
+                        flip[0] ^= 1
+                    sc = time_steps(torch, alternate, 20, 4)
+                    ent[form + "_cold_ms"] = round(sc * 1e3, 4)
+                    ent[form + "_cold_gbs"] = round(alg_bytes(k, form) / sc / 1e9, 1)
             ent["fused_pct_peak"] = round(100 * ent["fused_gbs"] / PEAK_GBS, 1)
+            if wl2 is not None:
+                ent["fused_cold_pct_peak"] = round(100 * ent["fused_cold_gbs"] / PEAK_GBS, 1)
+                if "unfused_cold_ms" in ent:
+                    ent["speedup_cold"] = round(ent["unfused_cold_ms"] / ent["fused_cold_ms"], 3)
+            del wl2
             if k == "gemver_contracted":
                 # same x and w as GEMVER, without storing B
                 g = suite["gemver"]
@@ -606,6 +738,7 @@ def main() -> int:
             suite[k] = ent
             if wl is not main_wl and k in ("axpydot", "waxpby", "vadd"):
                 del wl
+        alt.clear()
         result["suite"] = suite
         result["generated"] = bench_generated(torch, bto, synth, shared, suite)
 
@@ -618,7 +751,8 @@ def main() -> int:
         st = {}
         s = time_steps(torch, lambda: bto.probe_copy(b, a), 10, 2)
         st["copy_gbs"] = round(2 * n * 8 / s / 1e9, 1)
-        s = time_steps(torch, lambda: bto.probe_read(b, out), 10, 2)
+        rws = torch.empty(bto.probe_read_workspace_bytes(n), dtype=torch.uint8, device=dev)
+        s = time_steps(torch, lambda: bto.probe_read(b, out, rws), 10, 2)
         st["read_gbs"] = round(n * 8 / s / 1e9, 1)
         s = time_steps(torch, lambda: bto.probe_triad(a, b, c, 0.5), 10, 2)
         st["triad_gbs"] = round(3 * n * 8 / s / 1e9, 1)

@@ -549,9 +549,14 @@ def probe_triad(a, b, c, s: float) -> None:
                                     _stream(dev)))
 
 
+def probe_read_workspace_bytes(n: int) -> int:
+    return int(_lib.bto_probe_read_workspace_bytes(int(n)))
+
+
 def probe_read(src, out, ws=None) -> None:
+    """out[0] = sum of src (a streaming read in a fixed order)."""
     dev = src.device
-    need = int(_lib.bto_probe_read_workspace_bytes(src.numel()))
+    need = probe_read_workspace_bytes(src.numel())
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev) if ws is None else ws
     with torch.cuda.device(dev):
         _check(_lib.bto_probe_read(_ptr_of(src), src.numel(), _ptr_of(out), _ptr_of(ws),

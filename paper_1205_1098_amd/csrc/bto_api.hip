@@ -1275,7 +1275,7 @@ bto_status bto_probe_copy(const double *src, double *dst, int64_t n, hipStream_t
 
 size_t bto_probe_read_workspace_bytes(int64_t n)
 {
-    return n < 0 ? 0 : round256((size_t)dot_parts(n) * 8);
+    return n < 0 ? 0 : round256((size_t)read_parts(n) * 8);
 }
 
 bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws, size_t ws_bytes_,
@@ -1290,8 +1290,12 @@ bto_status bto_probe_read(const double *src, int64_t n, double *out, void *ws, s
     BTO_TRY(check_aliases({vspan("src", src, n, false), vspan("out", out, 1, true),
                            wspan(ws, need_ws)},
                           {}));
-    // sum of squares: both operands are the same stream, read once from HBM
-    launch_dot(false, n, 0.0, src, nullptr, src, nullptr, static_cast<double *>(ws), out, st);
+    if (n == 0) {
+        // an empty sum is 0: the finish alone writes it
+        launch_read(0, src, static_cast<double *>(ws), out, st);
+        return check_launch();
+    }
+    launch_read(n, src, static_cast<double *>(ws), out, st);
     return check_launch();
 }
 

@@ -61,6 +61,11 @@ int64_t dot_parts(int64_t n);
 void launch_dot(bool fused_axpy, int64_t n, double alpha, const double *w, const double *v,
                 const double *u, double *z, double *parts, double *r, hipStream_t st);
 
+// Read probe: *out = sum of src[0..n) (fixed order), partials in `parts`
+// (read_parts(n) doubles).
+int64_t read_parts(int64_t n);
+void launch_read(int64_t n, const double *src, double *parts, double *out, hipStream_t st);
+
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t st);
 void launch_triad(int64_t n, double *a, const double *b, const double *c, double s,
                   hipStream_t st);

@@ -277,6 +277,59 @@ __global__ __launch_bounds__(kFinishBlock) void k_dot_finish(int64_t nparts,
         *r = s;
 }
 
+// ---- read probe ------------------------------------------------------------
+//
+// out = sum of n doubles, as a pure streaming read: workgroup b owns elements
+// [kReadChunk b, kReadChunk (b+1)); each of its threads keeps kReadPairs
+// 16-byte loads of the next stretch in flight while it adds the current one,
+// so a workgroup streams 256 KiB before it retires.  Thread t adds pairs t +
+// kReadBlock k of each stretch in stretch order, then the lanes and waves are
+// added in a fixed order and the finish sums the workgroup partials: the
+// result depends on n only.
+
+constexpr int kReadBlock = 256;
+constexpr int kReadPairs = 8;
+constexpr int kReadIters = 8;
+constexpr int64_t kReadChunk = (int64_t)kReadBlock * kReadPairs * 2 * kReadIters;
+
+template <bool VEC>
+__global__ __launch_bounds__(kReadBlock) void k_read_part(int64_t n, const double *src,
+                                                          double *parts)
+{
+    __shared__ double lds[kReadBlock / kWave];
+    const int64_t base = (int64_t)blockIdx.x * kReadChunk;
+    d2 acc{0.0, 0.0};
+    if (VEC && base + kReadChunk <= n) {
+        const double *p = src + base + 2 * threadIdx.x;
+        constexpr int64_t kStretch = 2 * kReadBlock * kReadPairs;   // doubles per stretch
+        d2 cur[kReadPairs], nxt[kReadPairs];
+#pragma unroll
+        for (int k = 0; k < kReadPairs; ++k)
+            cur[k] = ld2_nt(p + 2 * kReadBlock * k);
+#pragma unroll
+        for (int it = 0; it < kReadIters; ++it) {
+            if (it + 1 < kReadIters) {
+#pragma unroll
+                for (int k = 0; k < kReadPairs; ++k)
+                    nxt[k] = ld2_nt(p + (it + 1) * kStretch + 2 * kReadBlock * k);
+            }
+#pragma unroll
+            for (int k = 0; k < kReadPairs; ++k)
+                acc += cur[k];
+#pragma unroll
+            for (int k = 0; k < kReadPairs; ++k)
+                cur[k] = nxt[k];
+        }
+    } else {
+        const int64_t end = base + kReadChunk < n ? base + kReadChunk : n;
+        for (int64_t e = base + threadIdx.x; e < end; e += kReadBlock)
+            acc.x += src[e];
+    }
+    const double s = block_sum(acc.x + acc.y, lds, kReadBlock / kWave);
+    if (threadIdx.x == 0)
+        parts[blockIdx.x] = s;
+}
+
 __global__ __launch_bounds__(kEwBlock) void k_copy(int64_t npair, const double *src, double *dst)
 {
     const int64_t p = (int64_t)blockIdx.x * kEwBlock + threadIdx.x;
@@ -343,6 +396,21 @@ void launch_dot(bool fused_axpy, int64_t n, double alpha, const double *w, const
     }
     launch("dot_finish", k_dot_finish, dim3(1), dim3(kFinishBlock), st, np, (const double *)parts,
            r);
+}
+
+int64_t read_parts(int64_t n) { return n <= 0 ? 0 : ceil_div(n, kReadChunk); }
+
+void launch_read(int64_t n, const double *src, double *parts, double *out, hipStream_t st)
+{
+    const int64_t np = read_parts(n);
+    if (aligned16(src))
+        launch("probe_read", k_read_part<true>, dim3((unsigned)np), dim3(kReadBlock), st, n, src,
+               parts);
+    else
+        launch("probe_read", k_read_part<false>, dim3((unsigned)np), dim3(kReadBlock), st, n, src,
+               parts);
+    launch("dot_finish", k_dot_finish, dim3(1), dim3(kFinishBlock), st, np, (const double *)parts,
+           out);
 }
 
 void launch_copy(int64_t n, const double *src, double *dst, hipStream_t st)
