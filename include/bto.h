@@ -133,6 +133,31 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta,
                       double *B, int64_t ldb, double *x, double *w,
                       void *ws, size_t ws_bytes, bto_form form, hipStream_t stream);
 
+/* GEMVER without a workspace argument and without allocating, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Arguments, results,
+ * forms and errors are those of bto_gemver; the results are bitwise those
+ * of bto_gemver with the same arguments.  The partial sums live in a device
+ * array of bto_gemver_noalloc_max_scratch_bytes() bytes (80 MiB) that the
+ * library owns: one per device, set up by the first call on that device
+ * (the current device, which must be the one `stream` belongs to) and kept
+ * until the process ends.  A call whose scratch need,
+ * bto_workspace_bytes(BTO_K_GEMVER, m, n, form), exceeds it returns
+ * BTO_ERR_WORKSPACE before enqueuing anything (n = m = 16384 fits exactly).
+ * All calls on one device share that array: calls whose kernels overlap
+ * on the device (other streams, other threads) race and give invalid
+ * results; calls enqueued on one stream are ordered and safe.  Nothing in
+ * the array needs clearing between calls.  No hipMalloc, hipFree or other
+ * allocating routine is called. */
+size_t bto_gemver_noalloc_max_scratch_bytes(void);
+bto_status bto_gemver_noalloc(int64_t m, int64_t n, double alpha, double beta,
+                              const double *A, int64_t lda,
+                              const double *u1, const double *v1,
+                              const double *u2, const double *v2,
+                              const double *y, const double *z,
+                              double *B, int64_t ldb, double *x, double *w,
+                              bto_form form, hipStream_t stream);
+
 /* GEMVER with its B contracted away: the same x and w as bto_gemver, for
  * a caller that does not need B.  Contracting a temporary that only feeds
  * the later statements is the heuristic of Section III-E; here it turns

@@ -64,6 +64,9 @@ _SIGS = {
     "bto_bicgk": ([_i64, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_gemver": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr, _ptr,
                     _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
+    "bto_gemver_noalloc_max_scratch_bytes": ([], _sz),
+    "bto_gemver_noalloc": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr,
+                            _ptr, _ptr, _i64, _ptr, _ptr, _int, _ptr], _int),
     "bto_atax": ([_i64, _i64, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_batax": ([_i64, _i64, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _sz, _int, _ptr], _int),
     "bto_gemver_contracted": ([_i64, _i64, _dbl, _dbl, _ptr, _i64, _ptr, _ptr, _ptr, _ptr, _ptr,
@@ -281,6 +284,31 @@ def gemver(A, u1, v1, u2, v2, y, z, alpha, beta, form="fused", B=None, x=None, w
                                _ptr_of(v1), _ptr_of(u2), _ptr_of(v2), _ptr_of(y), _ptr_of(z),
                                _ptr_of(B), ldb, _ptr_of(x), _ptr_of(w), _ptr_of(ws), wsb, f,
                                _stream(dev)))
+    return B, x, w
+
+
+def gemver_noalloc_max_scratch_bytes() -> int:
+    return int(_lib.bto_gemver_noalloc_max_scratch_bytes())
+
+
+def gemver_noalloc(A, u1, v1, u2, v2, y, z, alpha, beta, B, x, w, form="fused"):
+    """GEMVER into caller-given outputs B, x, w on the library's own scratch
+    (bto_gemver_noalloc): neither this wrapper nor the library allocates.
+    Returns (B, x, w)."""
+    lda = _check_mat(A, "A")
+    m, n = A.shape
+    dev = A.device
+    ldb = _check_mat(B, "B")
+    if tuple(B.shape) != (m, n) or B.device != dev:
+        raise ValueError("B must have A's extents and device")
+    for t, nm, k in ((u1, "u1", m), (v1, "v1", n), (u2, "u2", m), (v2, "v2", n), (y, "y", m),
+                     (z, "z", n), (x, "x", n), (w, "w", m)):
+        _check_vec(t, nm, dev, k)
+    with torch.cuda.device(dev):
+        _check(_lib.bto_gemver_noalloc(m, n, float(alpha), float(beta), _ptr_of(A), lda,
+                                       _ptr_of(u1), _ptr_of(v1), _ptr_of(u2), _ptr_of(v2),
+                                       _ptr_of(y), _ptr_of(z), _ptr_of(B), ldb, _ptr_of(x),
+                                       _ptr_of(w), _form(form), _stream(dev)))
     return B, x, w
 
 

@@ -463,13 +463,18 @@ bto_status bto_bicgk(int64_t m, int64_t n, const double *A, int64_t lda, const d
 
 // ---- GEMVER ------------------------------------------------------------------
 
-bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const double *A,
+}  // extern "C"
+
+namespace {
+
+// GEMVER's checks and launches on a given workspace (the caller's, or the
+// library's own scratch for bto_gemver_noalloc).
+bto_status gemver_run(int64_t m, int64_t n, double alpha, double beta, const double *A,
                       int64_t lda, const double *u1, const double *v1, const double *u2,
                       const double *v2, const double *y, const double *z, double *B,
                       int64_t ldb, double *x, double *w, void *ws, size_t ws_bytes_,
                       bto_form form, hipStream_t st)
 {
-    t_error.clear();
     BTO_TRY(check_form(form));
     BTO_TRY(check_matrix(m, n, A, lda, "A"));
     BTO_TRY(check_matrix(m, n, B, ldb, "B"));
@@ -532,6 +537,82 @@ bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const dou
         BTO_TRY(gemv_n(SLOT_GEMV_N, m, n, B, ldb, x, alpha, w, Prow, st));
     }
     return check_launch();
+}
+
+// ---- GEMVER on library-owned scratch -----------------------------------------
+//
+// The column-sum and row-dot partials of bto_gemver_noalloc live in this
+// file-scope device array.  Each device that runs the entry point holds its
+// own copy, at its own address, from the first call on that device until
+// the process ends.  Host code never passes the array's name to a kernel
+// (on the host it is only a stand-in); it passes the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+// Every partial is written before it is read, so nothing needs clearing.
+
+constexpr size_t kNoAllocScratchBytes = size_t(80) << 20;
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+bto_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(BTO_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(BTO_ERR_HIP, std::string("hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return BTO_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+bto_status bto_gemver(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                      int64_t lda, const double *u1, const double *v1, const double *u2,
+                      const double *v2, const double *y, const double *z, double *B,
+                      int64_t ldb, double *x, double *w, void *ws, size_t ws_bytes_,
+                      bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    return gemver_run(m, n, alpha, beta, A, lda, u1, v1, u2, v2, y, z, B, ldb, x, w, ws,
+                      ws_bytes_, form, st);
+}
+
+size_t bto_gemver_noalloc_max_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+bto_status bto_gemver_noalloc(int64_t m, int64_t n, double alpha, double beta, const double *A,
+                              int64_t lda, const double *u1, const double *v1, const double *u2,
+                              const double *v2, const double *y, const double *z, double *B,
+                              int64_t ldb, double *x, double *w, bto_form form, hipStream_t st)
+{
+    t_error.clear();
+    BTO_TRY(check_form(form));
+    BTO_TRY(need(m >= 0 && n >= 0, "negative size"));
+    const size_t need_ws = ws_bytes(BTO_K_GEMVER, m, n, form);
+    if (need_ws > kNoAllocScratchBytes)
+        return fail(BTO_ERR_WORKSPACE, "bto_gemver_noalloc: " + std::to_string(m) + " x " +
+                                           std::to_string(n) + " needs " +
+                                           std::to_string(need_ws) + " bytes of scratch, above "
+                                           "the library's " +
+                                           std::to_string(kNoAllocScratchBytes));
+    void *ws = nullptr;
+    if (need_ws > 0)
+        BTO_TRY(noalloc_scratch(&ws));
+    return gemver_run(m, n, alpha, beta, A, lda, u1, v1, u2, v2, y, z, B, ldb, x, w, ws,
+                      need_ws, form, st);
 }
 
 // ---- ATAX --------------------------------------------------------------------

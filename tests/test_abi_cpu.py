@@ -301,3 +301,24 @@ def test_contracted_gemver_and_batax_checks(bto):
     assert bto._lib.bto_batax(m, k, 2.0, ptr(0), k, ptr(1), ptr(2), ptr(16), wb - 256, 0,
                               None) == 3
     assert bto._lib.bto_batax(m, k, 2.0, ptr(0), k, ptr(1), ptr(2), ptr(16), wb, 7, None) == 1
+
+
+def test_noalloc_refuses_beyond_its_scratch(bto):
+    """bto_gemver_noalloc checks its scratch need before any HIP call:
+    n = m = 16384 fits the 80 MiB exactly, one row more is refused."""
+    assert bto.gemver_noalloc_max_scratch_bytes() == 80 << 20
+    assert bto.workspace_bytes("gemver", 16384, 16384, "fused") == 80 << 20
+    WS = 3
+    v = ctypes.c_void_p
+    for form in (0, 1):
+        st = bto._lib.bto_gemver_noalloc(16385, 16384, 1.5, 0.7, v(FAKE), 16384, v(FAKE),
+                                         v(FAKE), v(FAKE), v(FAKE), v(FAKE), v(FAKE), v(FAKE),
+                                         16384, v(FAKE), v(FAKE), form, None)
+        assert st == WS
+        assert "scratch" in bto._lib.bto_last_error().decode()
+    assert bto._lib.bto_gemver_noalloc(-1, 4, 1.5, 0.7, v(FAKE), 4, v(FAKE), v(FAKE), v(FAKE),
+                                       v(FAKE), v(FAKE), v(FAKE), v(FAKE), 4, v(FAKE), v(FAKE),
+                                       0, None) == 1
+    assert bto._lib.bto_gemver_noalloc(4, 4, 1.5, 0.7, v(FAKE), 4, v(FAKE), v(FAKE), v(FAKE),
+                                       v(FAKE), v(FAKE), v(FAKE), v(FAKE), 4, v(FAKE), v(FAKE),
+                                       9, None) == 1
