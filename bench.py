@@ -20,9 +20,12 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
   stream      measured copy / read / triad ceilings at 2 GiB per array
   batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
               one persistent graph-captured launch, and the same instances as
-              a tiled batch (four graph-captured launches of short-lived tiles)
+              a tiled batch (one graph of launches of short-lived tiles: both
+              kinds' first sweeps, their sums, GEMVER's second sweeps, sums)
   serving     Poisson and saturated request streams through the server
-              (req/s, p50 / p99 latency), continuous batching against FIFO
+              (req/s, p50 / p99 latency): continuous batching with tiled
+              batches, with the entry points only, with persistent plans,
+              and a one-at-a-time FIFO server
   cpu_baseline  the CPU oracle timed on the host cores on the same workload
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload gemver|bicgk|...]
@@ -473,11 +476,13 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         checked = False
     persistent = outs()
     plan.close()
-    # the same instances as short-lived workgroup tiles (four launches in a graph)
+    # the same instances as short-lived workgroup tiles: GEMVER's chain and
+    # BiCGK's as two branches of one graph, under the tuned configuration
     for inst in insts:
         for t in inst["out"]:
             t.fill_(float("nan"))
-    tiled = bto.TiledBatch(insts, use_graph=graph)
+    tiled_cfg = bto.TiledConfig.default(use_graph=1 if graph else 0)
+    tiled = bto.TiledBatch(insts, config=tiled_cfg)
     sec_tiled, sec_tiled_min = time_stats(torch, tiled.launch, 10, 2)
     torch.cuda.synchronize()
     tiled_outs = outs()
@@ -522,6 +527,7 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
             "gbs": round(total / sec_tiled / 1e9, 1),
             "pct_peak": round(100 * total / sec_tiled / 1e9 / PEAK_GBS, 1),
             "speedup_vs_persistent": round(sec / sec_tiled, 3),
+            "config": tiled_cfg.as_dict(),
         },
         "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
         "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,
@@ -530,9 +536,11 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
 
 def bench_serving(torch, bto, count: int, warmup: int) -> dict:
     """Requests for BiCGK / GEMVER / ATAX (weights .4/.4/.2) over a pool of 64
-    device-resident matrices with n log-uniform on [256, 16384]: first all at
-    once (saturated throughput), then Poisson arrivals at 0.7 of it, served
-    with continuous batching and then by a one-at-a-time FIFO server."""
+    device-resident matrices with n log-uniform on [256, 16384]: all at once
+    (saturated throughput), then Poisson arrivals at 0.7 of what the entry
+    points alone sustain, served with continuous batching by three routes
+    (tiled batches for small GEMVER/BiCGK, the default; entry points only;
+    persistent batch plans) and by a one-at-a-time FIFO server."""
     from paper_1205_1098_amd import serve
 
     GiB = 1 << 30
@@ -556,16 +564,29 @@ def bench_serving(torch, bto, count: int, warmup: int) -> dict:
 
     # continuous batching over the single-instance entry points on two lanes
     ex = serve.GpuExecutor(torch, bto, pool, batch_n=0)
-    print("serving: saturated run", file=sys.stderr, flush=True)
+    print("serving: saturated run, entry points only", file=sys.stderr, flush=True)
     once(ex, serve.make_requests(min(total, 2000), sizes, rate=None, first_rid=900000), 64, 2)
-    sat = once(ex, serve.make_requests(total, sizes, rate=None), 64, 2)
-    lam = 0.7 * sat["req_per_s"]
-    print(f"serving: Poisson run at {lam:.0f} req/s", file=sys.stderr, flush=True)
-    poisson = once(ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
+    direct_sat = once(ex, serve.make_requests(total, sizes, rate=None), 64, 2)
+    # one offered load for every route: 0.7 of what the entry points alone sustain
+    lam = 0.7 * direct_sat["req_per_s"]
+    print(f"serving: Poisson runs at {lam:.0f} req/s", file=sys.stderr, flush=True)
+    direct_poisson = once(ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
     ex.close()
-    # the same, with requests of n <= 2048 through the batch plans
-    plan_ex = serve.GpuExecutor(torch, bto, pool)
-    print("serving: runs with batch plans", file=sys.stderr, flush=True)
+    # the default: GEMVER and BiCGK requests of n <= 2048 in refillable tiled
+    # batches (one graph launch per step), the rest through the entry points
+    tiled_ex = serve.GpuExecutor(torch, bto, pool)
+    print("serving: runs with tiled batches", file=sys.stderr, flush=True)
+    once(tiled_ex, serve.make_requests(min(total, 2000), sizes, rate=None, first_rid=800000),
+         64, 2)
+    sat = once(tiled_ex, serve.make_requests(total, sizes, rate=None), 64, 2)
+    poisson = once(tiled_ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
+    lam_own = 0.7 * sat["req_per_s"]
+    poisson_own = once(tiled_ex, serve.make_requests(total, sizes, rate=lam_own,
+                                                     first_rid=2 * total), 64, 2)
+    tiled_ex.close()
+    # requests of n <= 2048 through refillable persistent plans instead
+    plan_ex = serve.GpuExecutor(torch, bto, pool, batch_form="persistent")
+    print("serving: runs with persistent batch plans", file=sys.stderr, flush=True)
     plan_sat = once(plan_ex, serve.make_requests(total, sizes, rate=None), 64, 2)
     plan_poisson = once(plan_ex, serve.make_requests(total, sizes, rate=lam, first_rid=total),
                         64, 2)
@@ -579,8 +600,12 @@ def bench_serving(torch, bto, count: int, warmup: int) -> dict:
         "pool": len(sizes), "pool_gb": round(pool.bytes / 1e9, 2), "n_range": [256, 16384],
         "weights": serve.WEIGHTS, "budget_gib": 32, "slots": 64, "lanes": 2,
         "requests": count, "warmup": warmup, "seed": serve.synth.SEED,
+        "route": f"GEMVER/BiCGK with n <= {int(bto.batch_max_n())} in refillable tiled "
+                 "batches, the rest through the fused entry points",
         "saturated": sat, "poisson_rate": round(lam, 1), "poisson": poisson,
-        "with_batch_plans": {"batch_n": int(bto.batch_max_n()), "saturated": plan_sat,
+        "poisson_own_rate": {"rate": round(lam_own, 1), "result": poisson_own},
+        "entry_points_only": {"saturated": direct_sat, "poisson": direct_poisson},
+        "persistent_plans": {"batch_n": int(bto.batch_max_n()), "saturated": plan_sat,
                              "poisson": plan_poisson},
         "fifo": fifo,
     }

@@ -26,8 +26,10 @@
  *   - Matrices are m x n, row-major: element (i, j) at A[i*lda + j],
  *     lda >= max(1, n).
  *   - Every array pointer is a DEVICE pointer on the current HIP device,
- *     allocated and owned by the caller.  The library never allocates,
- *     frees or keeps device memory between calls.
+ *     allocated and owned by the caller.  The kernel entry points never
+ *     allocate or free device memory; plans (batch and tiled batch) own
+ *     what their create calls allocate, and bto_gemver_noalloc uses a
+ *     static array the library keeps per device.
  *   - Work is enqueued on `stream` (NULL = the default stream) and the call
  *     returns without synchronizing.  Inputs must stay valid, and outputs
  *     untouched by others, until the stream reaches the end of the call.
@@ -408,34 +410,103 @@ bto_status bto_batch_plan_launch(bto_batch_plan *plan, hipStream_t stream);
  * first sweep, and BTO_ERR_HIP here means one gave up (the launch's results
  * are then not valid).  Synchronizes; for tests and diagnostics. */
 bto_status bto_batch_plan_check(bto_batch_plan *plan, hipStream_t stream);
+
+/* The same check without waiting: enqueue on `stream` a copy of the plan's
+ * error word (nonzero when a bounded wait of the launch before it gave up)
+ * into `dst`, one int of caller-owned memory (pinned host memory from
+ * hipHostMalloc, or device memory).  The value is there once the stream has
+ * passed the copy, e.g. when an event recorded after it completes.  For
+ * servers that check every launch without synchronizing. */
+bto_status bto_batch_plan_error_async(bto_batch_plan *plan, int *dst, hipStream_t stream);
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
 
 /* ---- tiled batches ---------------------------------------------------------
  * The same fused GEMVER and BiCGK instances (descriptors as above; ATAX and
  * the unfused form are refused with BTO_ERR_UNSUPPORTED) cut into
- * short-lived workgroup tiles instead of one workgroup per instance: every
- * instance's first sweep runs as tiles of 32 rows by 128 columns in one
- * launch, a second launch adds each instance's partial sums (BiCGK's q and
- * s, GEMVER's x = beta B^T y + z) in a fixed order, and GEMVER's second
- * sweep (w = alpha B x) follows as a third launch of tiles and a fourth of
- * sums.  The kernel boundaries order the phases, so no tile waits for
- * another.  Each result depends only on its own instance (a fixed tile and
+ * short-lived workgroup tiles instead of one workgroup per instance: a tile
+ * is one sweep of one instance over a band of rows and a block of columns.
+ * Tiles of one kind form a group launched by a kernel specialised for the
+ * group's tile shape: GEMVER's first sweeps (B = A + u1 v1^T + u2 v2^T
+ * stored, partial column sums of B^T y), BiCGK's sweeps (row dots and
+ * column sums in one pass) of narrow and of wide matrices, a launch that
+ * adds each instance's partial sums in a fixed order (BiCGK's q and s,
+ * GEMVER's x = beta B^T y + z), GEMVER's second sweeps (w = alpha B x) of
+ * narrow and of wide matrices, and the sums of w.  The kernel boundaries
+ * order the phases, so no tile waits for another.  Each result depends only
+ * on its own instance and the plan's configuration (a fixed tile and
  * summation order), not on the other instances or the launch; it rounds
  * differently from the persistent plan's.  This is the loop partition of
  * Section III-C (row bands across workgroups, columns across lanes)
- * applied to many instances at once.
- *
- * bto_tiled_batch_create validates the instances as bto_batch_plan_create
- * does, then allocates and fills the plan's device tables and partial-sum
- * scratch (about 1/32 of each matrix for the column sums and 1/128 for the
- * row dots), which the plan owns until it is destroyed.  With use_graph set
- * the four launches are captured once in a HIP graph.
- * bto_tiled_batch_launch enqueues them on `stream` and allocates nothing;
- * launches of one plan must not overlap (they share its scratch). */
+ * applied to many instances at once; the configuration holds the
+ * partition's parameters that the search of Section IV tunes here. */
+typedef struct {
+    int store_shape;   /* tile shape (bto_tiled_shape) of GEMVER's first sweeps */
+    int narrow_shape;  /* of the read-only sweeps of matrices at most narrow_n wide */
+    int wide_shape;    /* of the read-only sweeps of wider matrices */
+    int narrow_n;      /* column count up to which narrow_shape is used (>= 0) */
+    int store_rb;      /* rows per band of GEMVER's first sweeps */
+    int read_rb;       /* rows per band of the read-only sweeps (at most 64 rows per
+                          wave: read_rb / waves_down <= 64) */
+    int wgs_per_cu;    /* 0: one workgroup per tile; 1..16: that many persistent
+                          workgroups per compute unit in each launch, stepping
+                          through the group's tiles */
+    int use_graph;     /* capture the launches in a HIP graph (0 or 1) */
+} bto_tiled_config;
+
 typedef struct bto_tiled_batch bto_tiled_batch;
 
+/* The default configuration (the tuned one), for callers to adjust. */
+void bto_tiled_config_default(bto_tiled_config *config);
+/* The tile shapes a configuration may name: a workgroup of waves_across x
+ * waves_down waves, kv 16-byte pairs per lane (a block of
+ * 128 * kv * waves_across columns), depth rows of loads in flight per wave.
+ * Band heights must be multiples of waves_down. */
+int bto_tiled_shape_count(void);
+bto_status bto_tiled_shape(int shape, int *kv, int *depth, int *waves_across, int *waves_down);
+
+/* bto_tiled_batch_create validates the instances as bto_batch_plan_create
+ * does, then allocates and fills the plan's device tables and partial-sum
+ * scratch (for the defaults about 1/32 of each matrix for the column sums
+ * and 1/128 for the row dots), which the plan owns until it is destroyed.
+ * With use_graph set the launches are captured once in a HIP graph.
+ * bto_tiled_batch_create_config does the same under `config` (NULL: the
+ * defaults; an invalid configuration gives BTO_ERR_INVALID_ARG).
+ * bto_tiled_batch_launch enqueues the batch on `stream` and allocates
+ * nothing; launches of one plan must not overlap (they share its scratch). */
 bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int use_graph,
                                   bto_tiled_batch **plan);
+bto_status bto_tiled_batch_create_config(const bto_batch_desc *descs, int count,
+                                         const bto_tiled_config *config,
+                                         bto_tiled_batch **plan);
+
+/* A tiled plan that is filled later, for loops that run a different set of
+ * instances each step (continuous batching in a server).  It holds tables
+ * and scratch for `capacity` instances of either kind of at most max_m rows
+ * and max_n columns (max_n <= bto_batch_max_n()).  With use_graph the graph
+ * is captured once and replayed after every refill: its launches have a
+ * fixed number of persistent workgroups that read each group's tile count
+ * from the device, so config->wgs_per_cu must then be 1..16 (0 is refused).
+ * Without a graph, each launch is sized from the last refill's tiles and
+ * launches of empty groups are skipped.  NULL takes the defaults, with 2
+ * workgroups per compute unit if the defaults have one per tile.  The plan
+ * starts with no instances. */
+bto_status bto_tiled_batch_create_empty(int capacity, int64_t max_m, int64_t max_n,
+                                        const bto_tiled_config *config,
+                                        bto_tiled_batch **plan);
+
+/* Replace a refillable plan's instances.  They are validated as in
+ * bto_tiled_batch_create (BTO_ERR_INVALID_ARG / BTO_ERR_ALIAS /
+ * BTO_ERR_UNSUPPORTED, BTO_ERR_INVALID_ARG for more than `capacity`
+ * instances or a plan not made by _create_empty, BTO_ERR_WORKSPACE for more
+ * tiles or scratch than the plan holds); on error the plan keeps its
+ * previous instances.  The tables are copied to the device asynchronously
+ * on `stream` through pinned memory the plan owns, so they take effect for
+ * launches enqueued on the same stream afterwards; the host call waits only
+ * until the previous refill's copy has been read.  Refills and launches of
+ * one plan must all be issued on one stream.  No device memory is
+ * allocated. */
+bto_status bto_tiled_batch_reset(bto_tiled_batch *plan, const bto_batch_desc *descs, int count,
+                                 hipStream_t stream);
 bto_status bto_tiled_batch_launch(bto_tiled_batch *plan, hipStream_t stream);
 bto_status bto_tiled_batch_destroy(bto_tiled_batch *plan);
 

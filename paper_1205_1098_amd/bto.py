@@ -116,10 +116,18 @@ _SIGS = {
     "bto_batch_plan_create_empty": ([_int, _i64, _ptr, _ptr], _int),
     "bto_batch_scratch_doubles": ([_ptr, _int, _ptr], _i64),
     "bto_batch_plan_check": ([_ptr, _ptr], _int),
+    "bto_batch_plan_error_async": ([_ptr, _ptr, _ptr], _int),
     "bto_batch_plan_reset": ([_ptr, _ptr, _int, _ptr], _int),
     "bto_batch_plan_launch": ([_ptr, _ptr], _int),
     "bto_batch_plan_destroy": ([_ptr], _int),
+    "bto_tiled_config_default": ([_ptr], None),
+    "bto_tiled_shape_count": ([], _int),
+    "bto_tiled_shape": ([_int, ctypes.POINTER(_int), ctypes.POINTER(_int), ctypes.POINTER(_int),
+                         ctypes.POINTER(_int)], _int),
     "bto_tiled_batch_create": ([_ptr, _int, _int, _ptr], _int),
+    "bto_tiled_batch_create_config": ([_ptr, _int, _ptr, _ptr], _int),
+    "bto_tiled_batch_create_empty": ([_int, _i64, _i64, _ptr, _ptr], _int),
+    "bto_tiled_batch_reset": ([_ptr, _ptr, _int, _ptr], _int),
     "bto_tiled_batch_launch": ([_ptr, _ptr], _int),
     "bto_tiled_batch_destroy": ([_ptr], _int),
 }
@@ -775,6 +783,13 @@ class BatchPlan:
         with torch.cuda.device(self.device):
             _check(_lib.bto_batch_plan_check(self._plan, _stream(self.device)))
 
+    def error_async(self, dst: int, stream: int) -> None:
+        """Enqueue on the raw `stream` handle a copy of the plan's error word
+        into the int at address `dst` (pinned host or device memory)."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        _check(_lib.bto_batch_plan_error_async(self._plan, dst, stream))
+
     def reset(self, instances) -> None:
         """Replace the instances (copied on the current stream; no allocation)."""
         if not self._plan:
@@ -819,21 +834,109 @@ class BatchPlan:
             pass
 
 
+class TiledConfig(ctypes.Structure):
+    """bto_tiled_config: the tiled batch's partition parameters."""
+    _fields_ = [("store_shape", ctypes.c_int), ("narrow_shape", ctypes.c_int),
+                ("wide_shape", ctypes.c_int), ("narrow_n", ctypes.c_int),
+                ("store_rb", ctypes.c_int), ("read_rb", ctypes.c_int),
+                ("wgs_per_cu", ctypes.c_int), ("use_graph", ctypes.c_int)]
+
+    @classmethod
+    def default(cls, **changes) -> "TiledConfig":
+        c = cls()
+        _lib.bto_tiled_config_default(ctypes.byref(c))
+        for k, v in changes.items():
+            if k not in {f for f, _ in cls._fields_}:
+                raise KeyError(k)
+            setattr(c, k, int(v))
+        return c
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+def tiled_shapes() -> list:
+    """The tiled batches' tile shapes: dicts of kv, depth, waves_across,
+    waves_down (and the block's column count)."""
+    out = []
+    for s in range(int(_lib.bto_tiled_shape_count())):
+        v = [_int() for _ in range(4)]
+        _check(_lib.bto_tiled_shape(s, *[ctypes.byref(x) for x in v]))
+        kv, d, wc, wr = (x.value for x in v)
+        out.append({"kv": kv, "depth": d, "waves_across": wc, "waves_down": wr,
+                    "cols": 128 * kv * wc, "threads": 64 * wc * wr})
+    return out
+
+
 class TiledBatch:
     """Fused GEMVER / BiCGK instances (the dicts BatchPlan takes) run as
-    short-lived workgroup tiles: four launches (first sweeps, their sums,
-    GEMVER's second sweeps, their sums), captured in a HIP graph with
-    `use_graph`.  launch() enqueues them on the current stream and
-    allocates nothing."""
+    short-lived workgroup tiles, launched per group of tiles (first sweeps,
+    their sums, GEMVER's second sweeps, their sums), captured in a HIP graph
+    with `use_graph`.  `config` (a TiledConfig) sets the partition; None
+    takes the library's defaults (with `use_graph` applied).  launch()
+    enqueues the batch on the current stream and allocates nothing.  A plan
+    made with `TiledBatch.empty` is refilled with `reset` (or `reset_descs`)
+    before each launch."""
 
-    def __init__(self, instances, use_graph: bool = True):
+    def __init__(self, instances, use_graph: bool = True, config: TiledConfig | None = None, *,
+                 _capacity=None, _max_m=0, _max_n=0, _device=None):
         self._plan = ctypes.c_void_p()
+        if config is None:
+            config = TiledConfig.default(use_graph=1 if use_graph else 0)
+        self.config = config
+        if _capacity is not None:
+            self.device = torch.device(_device if _device is not None else "cuda:0")
+            self._keep = []
+            with torch.cuda.device(self.device):
+                _check(_lib.bto_tiled_batch_create_empty(int(_capacity), int(_max_m), int(_max_n),
+                                                         ctypes.byref(config),
+                                                         ctypes.byref(self._plan)))
+            self.capacity, self.count = int(_capacity), 0
+            return
         descs, self._keep, dev = _batch_descs(instances)
         self.device = dev if dev is not None else torch.device("cuda", torch.cuda.current_device())
         with torch.cuda.device(self.device):
-            _check(_lib.bto_tiled_batch_create(ctypes.byref(descs), len(instances),
-                                               1 if use_graph else 0, ctypes.byref(self._plan)))
-        self.count = len(instances)
+            _check(_lib.bto_tiled_batch_create_config(ctypes.byref(descs), len(instances),
+                                                      ctypes.byref(config),
+                                                      ctypes.byref(self._plan)))
+        self.capacity = self.count = len(instances)
+
+    @classmethod
+    def empty(cls, capacity: int, max_m: int, max_n: int, config: TiledConfig | None = None,
+              device="cuda:0") -> "TiledBatch":
+        """A refillable plan for up to `capacity` instances of at most
+        max_m x max_n (config.wgs_per_cu must be nonzero)."""
+        if config is None:
+            config = TiledConfig.default()
+            if config.wgs_per_cu == 0:
+                config.wgs_per_cu = 2
+        return cls(None, config=config, _capacity=capacity, _max_m=max_m, _max_n=max_n,
+                   _device=device)
+
+    def reset(self, instances) -> None:
+        """Replace the instances (copied on the current stream; no allocation)."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        descs, keep, _ = _batch_descs(instances)
+        with torch.cuda.device(self.device):
+            _check(_lib.bto_tiled_batch_reset(self._plan, ctypes.byref(descs), len(instances),
+                                              _stream(self.device)))
+        self._keep, self.count = keep, len(instances)
+
+    def reset_descs(self, descs, count: int, stream: int, keep=None) -> None:
+        """Replace the instances from a filled `Desc` array (device addresses
+        as integers) with the copy enqueued on the raw `stream` handle; the
+        caller keeps the buffers alive."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        _check(_lib.bto_tiled_batch_reset(self._plan, ctypes.byref(descs), count, stream))
+        self._keep, self.count = keep or [], count
+
+    def launch_on(self, stream: int) -> None:
+        """launch() on a raw HIP stream handle."""
+        if not self._plan:
+            raise RuntimeError("plan is closed")
+        _check(_lib.bto_tiled_batch_launch(self._plan, stream))
 
     def launch(self) -> None:
         if not self._plan:

@@ -1905,6 +1905,18 @@ bto_status bto_batch_plan_check(bto_batch_plan *plan, hipStream_t stream)
     return BTO_SUCCESS;
 }
 
+bto_status bto_batch_plan_error_async(bto_batch_plan *plan, int *dst, hipStream_t stream)
+{
+    t_error.clear();
+    if (!plan || !dst)
+        return fail(BTO_ERR_INVALID_ARG, "plan or dst is NULL");
+    const hipError_t e = hipMemcpyAsync(dst, plan->d_meta + kMetaError, sizeof(int),
+                                        hipMemcpyDefault, stream);
+    if (e != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("error copy: ") + hipGetErrorString(e));
+    return BTO_SUCCESS;
+}
+
 bto_status bto_batch_plan_destroy(bto_batch_plan *plan)
 {
     t_error.clear();
@@ -1916,21 +1928,34 @@ bto_status bto_batch_plan_destroy(bto_batch_plan *plan)
 
 // ---- tiled batches ---------------------------------------------------------------
 //
-// Fused GEMVER and BiCGK instances cut into short-lived workgroup tiles:
-// every instance's first sweep in one launch (a unit per row band and
-// column block), its partial sums reduced by a second launch, GEMVER's
-// second sweep in a third and its row dots reduced by a fourth.  Kernel
-// boundaries order the phases, so no tile waits for another and no
-// device-scope fence is issued.
+// Fused GEMVER and BiCGK instances cut into workgroup tiles, grouped by kind
+// (GEMVER's first sweeps, which store B; the read-only sweeps of narrow and
+// of wide matrices) and launched group by group, with launches of finish
+// units between the sweeps: first sweeps, their sums, GEMVER's second
+// sweeps, their sums.  Kernel boundaries order the phases, so no tile waits
+// for another and no device-scope fence is issued.  The device header
+// gives each group's first tile and tile count, so a refillable plan keeps
+// its launches (and its captured graph) and only its tables change.
 
 struct bto_tiled_batch {
+    bto_tiled_config cfg{};
+    bool refillable = false;
+    int capacity = 0;                   // instances per refill
+    int64_t cap_entries = 0, cap_units = 0, cap_jobs = 0, cap_funits = 0, cap_scratch = 0;
     BTileEntry *d_entries = nullptr;
-    BTileUnit *d_units = nullptr;       // first-sweep units, then second-sweep units
-    FinishJob *d_jobs = nullptr;        // jobs after the first sweep, then after the second
+    BTileUnit *d_units = nullptr;       // tile groups, in group order
+    FinishJob *d_jobs = nullptr;        // jobs after the first sweeps, then after the second
     BFinishUnit *d_funits = nullptr;
-    double *d_scratch = nullptr;
-    int64_t units[2] = {0, 0};          // per sweep
-    int64_t fin1 = 0, fin2 = 0;
+    int *d_hdr = nullptr;               // kBtHdrInts: first tile and count per group
+    double *d_scratch = nullptr;        // partial sums
+    int grid[BG_COUNT] = {};            // workgroups per launch (0: nothing to launch)
+    int cus = 0;                        // compute units of the plan's device
+    int count = 0;
+    // pinned staging of the tables for asynchronous refills, and the event
+    // that marks when the last refill has been read
+    char *h_stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t staged = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
@@ -1938,31 +1963,107 @@ struct bto_tiled_batch {
 
 namespace {
 
+// Defaults from the tiled-batch search (4096 mixed GEMVER/BiCGK instances,
+// n log-uniform on [64, 2048], MI355X): GEMVER's first sweeps in tiles of
+// 64 rows by 256 columns (8 waves, two 16-byte pairs per lane, two rows in
+// flight per wave), the read-only sweeps in 64-row tiles of 256 columns for
+// matrices up to 512 columns wide and of 1024 columns (16 waves) above,
+// one workgroup per tile.  The best dozen configurations were within 1.5%.
+constexpr bto_tiled_config kTiledDefaults = {
+    /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 1, /*narrow_n*/ 512,
+    /*store_rb*/ 64, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
+constexpr int kTiledFinishWgsPerCu = 8;
+constexpr int kTiledRefillWgsPerCu = 2;   // refillable plans made with the defaults
+
+
+bto_status tiled_check_config(const bto_tiled_config &c)
+{
+    if (!btile_shape_ok(c.store_shape, kBtFirstOps, c.store_rb))
+        return fail(BTO_ERR_INVALID_ARG, "store_shape / store_rb: not an instantiated tile shape "
+                                         "for the first sweeps with that band height");
+    for (int sh : {c.narrow_shape, c.wide_shape})
+        if (!btile_shape_ok(sh, OP_ROWDOT, c.read_rb))
+            return fail(BTO_ERR_INVALID_ARG, "narrow_shape / wide_shape / read_rb: not an "
+                                             "instantiated tile shape for GEMVER's second sweeps "
+                                             "with that band height");
+    if (c.narrow_n < 0)
+        return fail(BTO_ERR_INVALID_ARG, "narrow_n must not be negative");
+    if (c.wgs_per_cu < 0 || c.wgs_per_cu > 16)
+        return fail(BTO_ERR_INVALID_ARG, "wgs_per_cu must be 0 (a workgroup per tile) to 16");
+    if (c.use_graph != 0 && c.use_graph != 1)
+        return fail(BTO_ERR_INVALID_ARG, "use_graph must be 0 or 1");
+    return BTO_SUCCESS;
+}
+
+// What one instance adds to each table.
+struct TiledNeeds {
+    int64_t entries = 0, units = 0, jobs = 0, funits = 0, scratch = 0;
+};
+
+int64_t round32(int64_t d) { return ceil_div(d > 0 ? d : 1, (int64_t)32) * 32; }
+
+int read_shape_of(const bto_tiled_config &c, int64_t n)
+{
+    return n <= c.narrow_n ? c.narrow_shape : c.wide_shape;
+}
+
+TiledNeeds tiled_needs(const bto_tiled_config &c, int kind, int64_t m, int64_t n)
+{
+    TiledNeeds t;
+    const bool some = m > 0 && n > 0;
+    // the first sweeps (GEMVER's and BiCGK's) in store_shape tiles of store_rb rows
+    const int64_t fbands = some ? ceil_div(m, (int64_t)c.store_rb) : 0;
+    const int64_t ftiles = fbands * (some ? ceil_div(n, btile_cols(c.store_shape)) : 0);
+    t.jobs = 2;
+    t.funits = ceil_div(m, (int64_t)64) + ceil_div(n, (int64_t)64);
+    if (kind == BTO_K_GEMVER) {
+        const int rs = read_shape_of(c, n);
+        const int64_t rbands = some ? ceil_div(m, (int64_t)c.read_rb) : 0;
+        const int64_t nwt = some ? ceil_div(n, btile_wave_cols(rs)) : 0;
+        t.entries = some ? 2 : 0;
+        t.units = ftiles + rbands * (some ? ceil_div(n, btile_cols(rs)) : 0);
+        t.scratch = round32(fbands * n) + round32(nwt * m);
+    } else {
+        const int64_t nwt = some ? ceil_div(n, btile_wave_cols(c.store_shape)) : 0;
+        t.entries = some ? 1 : 0;
+        t.units = ftiles;
+        t.scratch = round32(nwt * m) + round32(fbands * n);
+    }
+    return t;
+}
+
 struct TiledImage {
     std::vector<BTileEntry> entries;
-    std::vector<BTileUnit> units[2];      // per sweep
-    std::vector<FinishJob> jobs1, jobs2;
+    std::vector<BTileUnit> units[BG_COUNT];   // tile groups
+    std::vector<FinishJob> jobs[BG_COUNT];    // finish groups
+
+    int64_t njobs() const
+    {
+        int64_t k = 0;
+        for (const auto &j : jobs) k += (int64_t)j.size();
+        return k;
+    }
+    int64_t nunits() const
+    {
+        int64_t k = 0;
+        for (const auto &u : units) k += (int64_t)u.size();
+        return k;
+    }
+    int64_t nfinish_units() const
+    {
+        int64_t k = 0;
+        for (const auto &js : jobs)
+            for (const FinishJob &j : js) k += ceil_div(j.len, (int64_t)64);
+        return k;
+    }
     int64_t scratch = 32;   // doubles; offset 0 is left unused, so no area is at "null"
 };
 
-void tiled_free(bto_tiled_batch *p)
-{
-    if (!p) return;
-    if (p->exec) (void)hipGraphExecDestroy(p->exec);
-    if (p->graph) (void)hipGraphDestroy(p->graph);
-    if (p->cap) (void)hipStreamDestroy(p->cap);
-    if (p->d_entries) (void)hipFree(p->d_entries);
-    if (p->d_units) (void)hipFree(p->d_units);
-    if (p->d_jobs) (void)hipFree(p->d_jobs);
-    if (p->d_funits) (void)hipFree(p->d_funits);
-    if (p->d_scratch) (void)hipFree(p->d_scratch);
-    delete p;
-}
-
-// Validate the instances and lay out entries, units, finish jobs and the
-// partial-sum areas (offsets into a scratch area starting at 0; pointers are
-// rebased once it is allocated).
-bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
+// Validate the instances and lay out entries, tiles, finish jobs and the
+// partial-sum areas (offsets into a scratch area starting at 0, kept as
+// fake pointers until they are rebased onto the plan's scratch).
+bto_status tiled_image(const bto_tiled_config &c, const bto_batch_desc *descs, int count,
+                       TiledImage &img)
 {
     if (count < 0 || (count > 0 && !descs))
         return fail(BTO_ERR_INVALID_ARG, "bad instance list");
@@ -1984,39 +2085,28 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
     });
     auto take = [&](int64_t doubles) {   // an offset, as a fake pointer until rebased
         const int64_t off = img.scratch;
-        img.scratch += ceil_div(doubles > 0 ? doubles : 1, (int64_t)32) * 32;
+        img.scratch += round32(doubles);
         return reinterpret_cast<double *>((uintptr_t)(off * 8));
     };
-    // the rows of the instance in bands, each band's column blocks side by
-    // side, so that neighbouring workgroups read neighbouring memory
-    auto tiles = [&](std::vector<BTileUnit> &units, int entry, int64_t nb, int64_t nc) {
+    // the bands of the instance one after another, each band's column blocks
+    // side by side, so that neighbouring tiles read neighbouring memory
+    auto tiles = [&](int group, int entry, int64_t nb, int64_t nc) {
+        if ((int64_t)img.units[group].size() + nb * nc > INT_MAX)
+            return false;
         for (int64_t b = 0; b < nb; ++b)
-            for (int64_t c = 0; c < nc; ++c)
-                units.push_back({entry, (int32_t)b, (int32_t)c, 0});
+            for (int64_t k = 0; k < nc; ++k)
+                img.units[group].push_back({entry, (int32_t)b, (int32_t)k, 0});
+        return true;
     };
-    // read-only sweeps of wider matrices take the wide blocks
-    auto read_shape = [](int64_t n) { return n > 512 ? BT_WIDE : BT_NARROW; };
-    int64_t fin_blocks = 0;   // an upper bound on the finish units of both sweeps
+    const auto too_many = [] { return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch"); };
+    int64_t fin_blocks = 0;
     for (int i : order) {
         const BatchItem &it = items[i];
         const int64_t m = it.m, n = it.n;
         const bool some = m > 0 && n > 0;
-        const int64_t nb = some ? ceil_div(m, (int64_t)kBTileRows) : 0;
-        const int rs = read_shape(n);
-        const int64_t nc = some ? ceil_div(n, (int64_t)kBTileCols[rs]) : 0;   // read sweeps
-        const int64_t nwt = some ? ceil_div(n, (int64_t)kBTileWaveCols[rs]) : 0;   // their row-dot parts
-        const int64_t ncw = some ? ceil_div(n, (int64_t)kBTileCols[BT_NARROW]) : 0;
-        // every launch indexes its units, and every finish its 64-output
-        // blocks, with an int: refuse before building lists that large
-        const int64_t first = nb * (it.kind == BTO_K_GEMVER ? ncw : nc);
-        const int64_t second = it.kind == BTO_K_GEMVER ? nb * nc : 0;
-        if ((int64_t)img.units[0].size() + first > INT_MAX ||
-            (int64_t)img.units[1].size() + second > INT_MAX)
-            return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch");
-        const int64_t blocks = 2 * ceil_div(m > n ? m : n, (int64_t)64);
-        fin_blocks += blocks;
-        if (fin_blocks > INT_MAX)
-            return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
+        // the first sweeps: store_shape tiles of store_rb rows
+        const int64_t fbands = some ? ceil_div(m, (int64_t)c.store_rb) : 0;
+        const int64_t fcols = some ? ceil_div(n, btile_cols(c.store_shape)) : 0;
         const bool rows16 = it.lda % 2 == 0 || m <= 1;
         BTileEntry e{};
         e.a.m = m;
@@ -2025,24 +2115,29 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
         e.a.ldb = it.ldb;
         e.a.A = it.A;
         if (it.kind == BTO_K_BICGK) {
-            // q = A p, s = A^T r: row dots per column block, column sums per band
-            double *prow = take(nwt * m), *pcol = take(nb * n);
+            // q = A p, s = A^T r: row dots per wave tile, column sums per band
+            const int64_t nwt = some ? ceil_div(n, btile_wave_cols(c.store_shape)) : 0;
+            double *prow = take(nwt * m), *pcol = take(fbands * n);
             e.a.xr = it.vec[0];
             e.a.yc = it.vec[1];
             e.a.Prow = prow;
             e.a.Pcol = pcol;
-            e.ops = OP_ROWDOT | OP_COLSUM;
             e.vec = aligned16(it.A) && rows16;
-            e.shape = (int16_t)rs;
+            e.ops = OP_ROWDOT | OP_COLSUM;
             if (some) {
                 img.entries.push_back(e);
-                tiles(img.units[0], (int)img.entries.size() - 1, nb, nc);
+                if (!tiles(BG_FIRST, (int)img.entries.size() - 1, fbands, fcols))
+                    return too_many();
             }
-            img.jobs1.push_back({prow, nwt, m, 1.0, nullptr, it.out[0]});
-            img.jobs1.push_back({pcol, nb, n, 1.0, nullptr, it.out[1]});
+            img.jobs[BG_FIN1].push_back({prow, nwt, m, 1.0, nullptr, it.out[0]});
+            img.jobs[BG_FIN1].push_back({pcol, fbands, n, 1.0, nullptr, it.out[1]});
         } else {
             // B = A + u1 v1^T + u2 v2^T and x = beta B^T y + z, then w = alpha B x
-            double *pcol = take(nb * n), *prow = take(nwt * m);
+            const int rs = read_shape_of(c, n);
+            const int64_t rbands = some ? ceil_div(m, (int64_t)c.read_rb) : 0;
+            const int64_t rcols = some ? ceil_div(n, btile_cols(rs)) : 0;
+            const int64_t nwt = some ? ceil_div(n, btile_wave_cols(rs)) : 0;
+            double *pcol = take(fbands * n), *prow = take(nwt * m);
             e.a.B = it.B;
             e.a.u1 = it.vec[0];
             e.a.v1 = it.vec[1];
@@ -2050,9 +2145,8 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
             e.a.v2 = it.vec[3];
             e.a.yc = it.vec[4];
             e.a.Pcol = pcol;
-            e.ops = OP_UPD1 | OP_UPD2 | OP_COLSUM;
             e.vec = aligned16(it.A) && aligned16(it.B) && rows16 && (it.ldb % 2 == 0 || m <= 1);
-            e.shape = BT_NARROW;
+            e.ops = OP_UPD1 | OP_UPD2 | OP_COLSUM;
             BTileEntry e2{};
             e2.a.m = m;
             e2.a.n = n;
@@ -2061,59 +2155,292 @@ bto_status tiled_image(const bto_batch_desc *descs, int count, TiledImage &img)
             e2.a.A = it.B;
             e2.a.xr = it.out[0];
             e2.a.Prow = prow;
-            e2.ops = OP_ROWDOT;
             e2.vec = aligned16(it.B) && (it.ldb % 2 == 0 || m <= 1);
-            e2.shape = (int16_t)rs;
+            e2.ops = OP_ROWDOT;
             if (some) {
                 img.entries.push_back(e);
-                tiles(img.units[0], (int)img.entries.size() - 1, nb, ncw);
+                if (!tiles(BG_FIRST, (int)img.entries.size() - 1, fbands, fcols))
+                    return too_many();
                 img.entries.push_back(e2);
-                tiles(img.units[1], (int)img.entries.size() - 1, nb, nc);
+                if (!tiles(n <= c.narrow_n ? BG_ROW_NARROW : BG_ROW_WIDE,
+                           (int)img.entries.size() - 1, rbands, rcols))
+                    return too_many();
             }
-            img.jobs1.push_back({pcol, nb, n, it.beta, it.vec[5], it.out[0]});
-            img.jobs2.push_back({prow, nwt, m, it.alpha, nullptr, it.out[1]});
+            img.jobs[BG_FIN1].push_back({pcol, fbands, n, it.beta, it.vec[5], it.out[0]});
+            img.jobs[BG_FIN_W].push_back({prow, nwt, m, it.alpha, nullptr, it.out[1]});
         }
         if ((int64_t)img.entries.size() > INT_MAX)
             return fail(BTO_ERR_UNSUPPORTED, "too many instances for one launch");
+        // every finish indexes its 64-output blocks with an int
+        fin_blocks += ceil_div(m, (int64_t)64) + ceil_div(n, (int64_t)64);
+        if (fin_blocks > INT_MAX)
+            return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
     }
     return BTO_SUCCESS;
 }
 
-std::vector<BFinishUnit> finish_units(const std::vector<FinishJob> &jobs, int first_job)
+void finish_units(const std::vector<FinishJob> &jobs, int first_job, std::vector<BFinishUnit> &u)
 {
-    std::vector<BFinishUnit> u;
     for (size_t j = 0; j < jobs.size(); ++j)
         for (int64_t b = 0; b < ceil_div(jobs[j].len, (int64_t)64); ++b)
             u.push_back({first_job + (int32_t)j, (int32_t)b});
-    return u;
+}
+
+// The flat tables of an image, with its partial-sum offsets rebased onto
+// `base` (the plan's scratch).
+struct TiledTables {
+    std::vector<BTileEntry> entries;
+    std::vector<BTileUnit> units;
+    std::vector<FinishJob> jobs;
+    std::vector<BFinishUnit> funits;
+    int hdr[kBtHdrInts] = {};
+};
+
+void tiled_tables(TiledImage &img, uintptr_t base, TiledTables &t)
+{
+    auto rebase = [&](double *&q) {
+        if (q) q = reinterpret_cast<double *>(base + reinterpret_cast<uintptr_t>(q));
+    };
+    for (BTileEntry &e : img.entries) {
+        rebase(e.a.Prow);
+        rebase(e.a.Pcol);
+    }
+    for (auto &jobs : img.jobs)
+        for (FinishJob &j : jobs)
+            j.P = reinterpret_cast<const double *>(base + reinterpret_cast<uintptr_t>(j.P));
+    t.entries.swap(img.entries);
+    for (int g = 0; g < BG_COUNT; ++g) {
+        if (bt_is_finish(g)) {
+            t.hdr[2 * g] = (int)t.funits.size();
+            finish_units(img.jobs[g], (int)t.jobs.size(), t.funits);
+            t.hdr[2 * g + 1] = (int)t.funits.size() - t.hdr[2 * g];
+            t.jobs.insert(t.jobs.end(), img.jobs[g].begin(), img.jobs[g].end());
+        } else {
+            t.hdr[2 * g] = (int)t.units.size();
+            t.hdr[2 * g + 1] = (int)img.units[g].size();
+            t.units.insert(t.units.end(), img.units[g].begin(), img.units[g].end());
+        }
+    }
+}
+
+void tiled_free(bto_tiled_batch *p)
+{
+    if (!p) return;
+    if (p->staged) (void)hipEventSynchronize(p->staged);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d_entries) (void)hipFree(p->d_entries);
+    if (p->d_units) (void)hipFree(p->d_units);
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_funits) (void)hipFree(p->d_funits);
+    if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->d_scratch) (void)hipFree(p->d_scratch);
+    if (p->h_stage) (void)hipHostFree(p->h_stage);
+    if (p->staged) (void)hipEventDestroy(p->staged);
+    delete p;
+}
+
+void tiled_group(const bto_tiled_batch *p, int g, hipStream_t st)
+{
+    const bto_tiled_config &c = p->cfg;
+    switch (g) {
+    case BG_FIRST:
+        launch_btile(c.store_shape, kBtFirstOps, c.store_rb, p->d_entries, p->d_units, p->d_hdr,
+                     g, p->grid[g], st);
+        break;
+    case BG_ROW_NARROW:
+    case BG_ROW_WIDE:
+        launch_btile(g == BG_ROW_NARROW ? c.narrow_shape : c.wide_shape, OP_ROWDOT, c.read_rb,
+                     p->d_entries, p->d_units, p->d_hdr, g, p->grid[g], st);
+        break;
+    default:
+        launch_btile_finish(p->d_jobs, p->d_funits, p->d_hdr, g, p->grid[g], st);
+        break;
+    }
 }
 
 void tiled_enqueue(const bto_tiled_batch *p, hipStream_t st)
 {
-    launch_btile(p->d_entries, p->d_units, p->units[0], st);
-    launch_bfinish(p->d_jobs, p->d_funits, p->fin1, st);
-    launch_btile(p->d_entries, p->d_units + p->units[0], p->units[1], st);
-    launch_bfinish(p->d_jobs, p->d_funits + p->fin1, p->fin2, st);
+    for (int g = 0; g < BG_COUNT; ++g)
+        tiled_group(p, g, st);
 }
 
-template <typename T>
-bool upload(T **dst, const std::vector<T> &a, const std::vector<T> &b)
+size_t tiled_stage_layout(const bto_tiled_batch *p, size_t off[5])
 {
-    const size_t n = a.size() + b.size();
-    if (hipMalloc(dst, sizeof(T) * (n > 0 ? n : 1)) != hipSuccess)
-        return false;
-    if (!a.empty() && hipMemcpy(*dst, a.data(), sizeof(T) * a.size(), hipMemcpyHostToDevice) !=
-                          hipSuccess)
-        return false;
-    if (!b.empty() && hipMemcpy(*dst + a.size(), b.data(), sizeof(T) * b.size(),
-                                hipMemcpyHostToDevice) != hipSuccess)
-        return false;
-    return true;
+    size_t o = 0;
+    off[0] = o; o += round256(sizeof(BTileEntry) * (size_t)p->cap_entries);
+    off[1] = o; o += round256(sizeof(BTileUnit) * (size_t)p->cap_units);
+    off[2] = o; o += round256(sizeof(FinishJob) * (size_t)p->cap_jobs);
+    off[3] = o; o += round256(sizeof(BFinishUnit) * (size_t)p->cap_funits);
+    off[4] = o; o += round256(sizeof(int) * kBtHdrInts);
+    return o;
+}
+
+// Allocate a plan's device tables (capacities set), its staging and event.
+bto_status tiled_alloc(bto_tiled_batch *p)
+{
+    auto bytes = [](size_t each, int64_t n) { return each * (size_t)(n > 0 ? n : 1); };
+    if (hipMalloc(&p->d_entries, bytes(sizeof(BTileEntry), p->cap_entries)) != hipSuccess ||
+        hipMalloc(&p->d_units, bytes(sizeof(BTileUnit), p->cap_units)) != hipSuccess ||
+        hipMalloc(&p->d_jobs, bytes(sizeof(FinishJob), p->cap_jobs)) != hipSuccess ||
+        hipMalloc(&p->d_funits, bytes(sizeof(BFinishUnit), p->cap_funits)) != hipSuccess ||
+        hipMalloc(&p->d_hdr, sizeof(int) * kBtHdrInts) != hipSuccess ||
+        hipMemset(p->d_hdr, 0, sizeof(int) * kBtHdrInts) != hipSuccess ||
+        hipMalloc(&p->d_scratch, bytes(sizeof(double), p->cap_scratch)) != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(hipGetLastError()));
+    size_t off[5];
+    p->stage_bytes = tiled_stage_layout(p, off);
+    if (hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipHostMalloc");
+    if (hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipEventCreate");
+    return BTO_SUCCESS;
+}
+
+// Copy validated tables into the plan on `stream` (asynchronously, through
+// the pinned staging, after the previous refill has been read).
+bto_status tiled_store(bto_tiled_batch *p, const TiledTables &t, hipStream_t stream)
+{
+    if (hipEventSynchronize(p->staged) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipEventSynchronize");
+    size_t off[5];
+    tiled_stage_layout(p, off);
+    char *st = p->h_stage;
+    struct Part {
+        void *dst;
+        const void *src;
+        size_t bytes;
+        size_t off;
+    } parts[5] = {
+        {p->d_entries, t.entries.data(), sizeof(BTileEntry) * t.entries.size(), off[0]},
+        {p->d_units, t.units.data(), sizeof(BTileUnit) * t.units.size(), off[1]},
+        {p->d_jobs, t.jobs.data(), sizeof(FinishJob) * t.jobs.size(), off[2]},
+        {p->d_funits, t.funits.data(), sizeof(BFinishUnit) * t.funits.size(), off[3]},
+        {p->d_hdr, t.hdr, sizeof(int) * kBtHdrInts, off[4]},
+    };
+    for (const Part &q : parts) {
+        if (q.bytes == 0)
+            continue;
+        std::memcpy(st + q.off, q.src, q.bytes);
+        if (hipMemcpyAsync(q.dst, st + q.off, q.bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+            return fail(BTO_ERR_HIP, std::string("refill: ") + hipGetErrorString(hipGetLastError()));
+    }
+    if (hipEventRecord(p->staged, stream) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipEventRecord");
+    return BTO_SUCCESS;
+}
+
+bto_status tiled_capture(bto_tiled_batch *p)
+{
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipStreamCreate");
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipStreamBeginCapture");
+    t_capturing = true;
+    tiled_enqueue(p, p->cap);
+    t_capturing = false;
+    if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipStreamEndCapture");
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipGraphInstantiate");
+    return BTO_SUCCESS;
+}
+
+bto_status device_cus(int &cus)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return fail(BTO_ERR_HIP, "no device");
+    return BTO_SUCCESS;
+}
+
+bto_status resolve_config(const bto_tiled_config *config, bto_tiled_config &c)
+{
+    c = config ? *config : kTiledDefaults;
+    return tiled_check_config(c);
+}
+
+// Workgroups per launch for a set of tiles: one per tile, or persistent
+// workgroups (never more than tiles); none for an empty group.
+void set_grids(bto_tiled_batch *p, const int *hdr)
+{
+    for (int g = 0; g < BG_COUNT; ++g) {
+        const int64_t n = hdr[2 * g + 1];
+        const int64_t per = bt_is_finish(g) ? kTiledFinishWgsPerCu : p->cfg.wgs_per_cu;
+        const int64_t cap = per > 0 ? (int64_t)p->cus * per : n;
+        p->grid[g] = (int)(n < cap ? n : cap);
+    }
+}
+
+bto_status tiled_create(const bto_batch_desc *descs, int count, const bto_tiled_config &c,
+                        bto_tiled_batch **plan)
+{
+    TiledImage img;
+    BTO_TRY(tiled_image(c, descs, count, img));
+    int cus = 0;
+    BTO_TRY(device_cus(cus));
+    bto_tiled_batch *p = new bto_tiled_batch();
+    p->cfg = c;
+    p->count = count;
+    p->capacity = count;
+    p->cap_entries = (int64_t)img.entries.size();
+    p->cap_units = img.nunits();
+    p->cap_jobs = img.njobs();
+    p->cap_scratch = img.scratch;
+    p->cap_funits = img.nfinish_units();
+    bto_status s = tiled_alloc(p);
+    TiledTables t;
+    if (s == BTO_SUCCESS) {
+        tiled_tables(img, reinterpret_cast<uintptr_t>(p->d_scratch), t);
+        s = tiled_store(p, t, nullptr);
+    }
+    if (s == BTO_SUCCESS && hipEventSynchronize(p->staged) != hipSuccess)
+        s = fail(BTO_ERR_HIP, "hipEventSynchronize");
+    if (s != BTO_SUCCESS) {
+        tiled_free(p);
+        return s;
+    }
+    p->cus = cus;
+    set_grids(p, t.hdr);
+    if (c.use_graph) {
+        s = tiled_capture(p);
+        if (s != BTO_SUCCESS) {
+            tiled_free(p);
+            return s;
+        }
+    }
+    *plan = p;
+    return BTO_SUCCESS;
 }
 
 }  // namespace
 
 extern "C" {
+
+void bto_tiled_config_default(bto_tiled_config *config)
+{
+    if (config)
+        *config = kTiledDefaults;
+}
+
+int bto_tiled_shape_count(void) { return kBtShapeCount; }
+
+bto_status bto_tiled_shape(int shape, int *kv, int *depth, int *waves_across, int *waves_down)
+{
+    t_error.clear();
+    if (shape < 0 || shape >= kBtShapeCount)
+        return fail(BTO_ERR_INVALID_ARG, "no such tile shape");
+    int v[4];
+    btile_shape_info(shape, v);
+    if (kv) *kv = v[0];
+    if (depth) *depth = v[1];
+    if (waves_across) *waves_across = v[2];
+    if (waves_down) *waves_down = v[3];
+    return BTO_SUCCESS;
+}
 
 bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int use_graph,
                                   bto_tiled_batch **plan)
@@ -2123,58 +2450,112 @@ bto_status bto_tiled_batch_create(const bto_batch_desc *descs, int count, int us
         if (!plan)
             return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
         *plan = nullptr;
-        TiledImage img;
-        BTO_TRY(tiled_image(descs, count, img));
-        // every host list is built before the plan owns device memory
-        std::vector<BFinishUnit> f1 = finish_units(img.jobs1, 0);
-        std::vector<BFinishUnit> f2 = finish_units(img.jobs2, (int)img.jobs1.size());
+        bto_tiled_config c = kTiledDefaults;
+        c.use_graph = use_graph ? 1 : 0;
+        return tiled_create(descs, count, c, plan);
+    });
+}
+
+bto_status bto_tiled_batch_create_config(const bto_batch_desc *descs, int count,
+                                         const bto_tiled_config *config, bto_tiled_batch **plan)
+{
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        *plan = nullptr;
+        bto_tiled_config c;
+        BTO_TRY(resolve_config(config, c));
+        return tiled_create(descs, count, c, plan);
+    });
+}
+
+bto_status bto_tiled_batch_create_empty(int capacity, int64_t max_m, int64_t max_n,
+                                        const bto_tiled_config *config, bto_tiled_batch **plan)
+{
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        *plan = nullptr;
+        bto_tiled_config c;
+        BTO_TRY(resolve_config(config, c));
+        if (!config && c.wgs_per_cu == 0)
+            c.wgs_per_cu = kTiledRefillWgsPerCu;
+        if (c.wgs_per_cu == 0 && c.use_graph)
+            return fail(BTO_ERR_INVALID_ARG, "a refillable plan in a graph needs persistent "
+                                             "workgroups (wgs_per_cu 1 to 16)");
+        if (capacity < 0 || max_m < 0 || max_n < 0)
+            return fail(BTO_ERR_INVALID_ARG, "negative capacity or size");
+        if (max_n > batch_max_n())
+            return fail(BTO_ERR_UNSUPPORTED, "more columns than a batched instance may have");
+        // the most any one instance within the bounds can need, per table:
+        // each count grows with m and n within one read shape
+        TiledNeeds worst;
+        for (int kind : {BTO_K_GEMVER, BTO_K_BICGK})
+            for (int64_t n : {max_n, max_n < c.narrow_n ? max_n : (int64_t)c.narrow_n}) {
+                const TiledNeeds t = tiled_needs(c, kind, max_m, n);
+                worst.entries = std::max(worst.entries, t.entries);
+                worst.units = std::max(worst.units, t.units);
+                worst.jobs = std::max(worst.jobs, t.jobs);
+                worst.funits = std::max(worst.funits, t.funits);
+                worst.scratch = std::max(worst.scratch, t.scratch);
+            }
+        const double cap = capacity;
+        if (cap * (double)worst.units > INT_MAX || cap * (double)worst.funits > INT_MAX)
+            return fail(BTO_ERR_UNSUPPORTED, "too many tiles for one launch");
+        int cus = 0;
+        BTO_TRY(device_cus(cus));
         bto_tiled_batch *p = new bto_tiled_batch();
-        auto hip_fail = [&](const char *what) {
+        p->cfg = c;
+        p->refillable = true;
+        p->capacity = capacity;
+        p->cap_entries = capacity * worst.entries;
+        p->cap_units = capacity * worst.units;
+        p->cap_jobs = capacity * worst.jobs;
+        p->cap_funits = capacity * worst.funits;
+        p->cap_scratch = 32 + capacity * worst.scratch;
+        p->cus = cus;
+        // a graph replays fixed launches that read their tile counts from the
+        // device header; without one, each refill sizes the launches itself
+        for (int g = 0; g < BG_COUNT && c.use_graph; ++g)
+            p->grid[g] = cus * (bt_is_finish(g) ? kTiledFinishWgsPerCu : c.wgs_per_cu);
+        bto_status s = tiled_alloc(p);
+        if (s == BTO_SUCCESS && c.use_graph)
+            s = tiled_capture(p);
+        if (s != BTO_SUCCESS) {
             tiled_free(p);
-            return fail(BTO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(hipGetLastError()));
-        };
-        if (hipMalloc(&p->d_scratch, sizeof(double) * (size_t)(img.scratch > 0 ? img.scratch : 1)) !=
-            hipSuccess)
-            return hip_fail("hipMalloc");
-        // rebase the partial-sum offsets onto the scratch area
-        const uintptr_t base = reinterpret_cast<uintptr_t>(p->d_scratch);
-        auto rebase = [&](double *&q) {
-            if (q) q = reinterpret_cast<double *>(base + reinterpret_cast<uintptr_t>(q));
-        };
-        for (BTileEntry &e : img.entries) {
-            rebase(e.a.Prow);
-            rebase(e.a.Pcol);
-        }
-        for (auto *jobs : {&img.jobs1, &img.jobs2})
-            for (FinishJob &j : *jobs)
-                j.P = reinterpret_cast<const double *>(base + reinterpret_cast<uintptr_t>(j.P));
-        p->units[0] = (int64_t)img.units[0].size();
-        p->units[1] = (int64_t)img.units[1].size();
-        p->fin1 = (int64_t)f1.size();
-        p->fin2 = (int64_t)f2.size();
-        if (p->fin1 > INT_MAX || p->fin2 > INT_MAX) {
-            tiled_free(p);
-            return fail(BTO_ERR_UNSUPPORTED, "too many outputs for one launch");
-        }
-        const std::vector<BTileEntry> none_e;
-        if (!upload(&p->d_entries, img.entries, none_e) ||
-            !upload(&p->d_units, img.units[0], img.units[1]) ||
-            !upload(&p->d_jobs, img.jobs1, img.jobs2) || !upload(&p->d_funits, f1, f2))
-            return hip_fail("device table");
-        if (use_graph && p->units[0] + p->units[1] + p->fin1 + p->fin2 > 0) {
-            if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
-                return hip_fail("hipStreamCreate");
-            if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-                return hip_fail("hipStreamBeginCapture");
-            t_capturing = true;
-            tiled_enqueue(p, p->cap);
-            t_capturing = false;
-            if (hipStreamEndCapture(p->cap, &p->graph) != hipSuccess)
-                return hip_fail("hipStreamEndCapture");
-            if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-                return hip_fail("hipGraphInstantiate");
+            return s;
         }
         *plan = p;
+        return BTO_SUCCESS;
+    });
+}
+
+bto_status bto_tiled_batch_reset(bto_tiled_batch *plan, const bto_batch_desc *descs, int count,
+                                 hipStream_t stream)
+{
+    return host_guard([&]() -> bto_status {
+        t_error.clear();
+        if (!plan)
+            return fail(BTO_ERR_INVALID_ARG, "plan is NULL");
+        if (!plan->refillable)
+            return fail(BTO_ERR_INVALID_ARG, "the plan was not made by bto_tiled_batch_create_empty");
+        if (count > plan->capacity)
+            return fail(BTO_ERR_INVALID_ARG, "more instances than the plan's capacity");
+        TiledImage img;
+        BTO_TRY(tiled_image(plan->cfg, descs, count, img));
+        if ((int64_t)img.entries.size() > plan->cap_entries || img.nunits() > plan->cap_units ||
+            img.njobs() > plan->cap_jobs || img.nfinish_units() > plan->cap_funits ||
+            img.scratch > plan->cap_scratch)
+            return fail(BTO_ERR_WORKSPACE, "the instances need more tiles or scratch than the "
+                                           "plan was made for");
+        TiledTables t;
+        tiled_tables(img, reinterpret_cast<uintptr_t>(plan->d_scratch), t);
+        BTO_TRY(tiled_store(plan, t, stream));
+        if (!plan->exec)
+            set_grids(plan, t.hdr);
+        plan->count = count;
         return BTO_SUCCESS;
     });
 }

@@ -143,33 +143,53 @@ struct FinishAux {
 };
 void launch_finish_aux(const char *name, const FinishAux &f, hipStream_t st);
 
-// Tiled batches: many instances' tile sweeps in one launch, one workgroup
-// per (sweep, row band, column block) unit, then their partial sums reduced
-// by one launch of finish units.  Bands are kBTileRows rows.  Two workgroup
-// shapes (16 waves each): narrow blocks of 128 columns (1 KiB wave rows, two
-// rows per wave) for the sweeps that store B and for narrow matrices, wide
-// blocks of 1024 columns (four 2 KiB wave rows side by side, eight rows per
-// wave) for read-only sweeps of wider ones.
-constexpr int kBTileRows = 32;
-enum BTileShape { BT_NARROW = 0, BT_WIDE = 1 };
-constexpr int kBTileCols[2] = {128, 1024};      // columns per workgroup block
-constexpr int kBTileWaveCols[2] = {128, 256};   // per wave tile: one row-dot partial each
+// Tiled batches (bto_btile.hip): the sweeps of many instances cut into
+// workgroup tiles (one sweep of one instance, a band of rows, a block of
+// columns), launched per group of tiles of one kind with a kernel
+// specialised for the group's tile shape and operations, then their
+// partial sums reduced by finish launches.
 struct BTileEntry {     // one sweep of one instance
     TileArgs a;
-    int32_t ops;        // OP_ROWDOT | OP_COLSUM, OP_UPD1 | OP_UPD2 | OP_COLSUM or OP_ROWDOT
-    int16_t vec;        // A (and B) 16-byte aligned with even leading dimensions
-    int16_t shape;      // BT_NARROW or BT_WIDE
+    int32_t vec;        // A (and B) 16-byte aligned with even leading dimensions
+    int32_t ops;        // the sweep's operations (OP_* flags)
 };
-struct BTileUnit {      // one workgroup of a tiled launch
+struct BTileUnit {      // one tile
     int32_t entry, band, cblk, pad;
 };
 struct BFinishUnit {    // 64 outputs of one finish job
     int32_t job, block;
 };
-void launch_btile(const BTileEntry *entries, const BTileUnit *units, int64_t nunits,
-                  hipStream_t st);
-void launch_bfinish(const FinishJob *jobs, const BFinishUnit *units, int64_t nunits,
-                    hipStream_t st);
+// The groups of a tiled batch, in launch order.  The first launch runs
+// GEMVER's first sweeps and BiCGK's sweeps together (a tile of either kind
+// per workgroup, the entry's ops telling which), so that tiles that read and
+// write interleave with tiles that only read.  The device header holds, for
+// group g, the index of its first tile (or finish unit) at [2g] and their
+// count at [2g + 1].
+enum BtGroup {
+    BG_FIRST = 0,       // GEMVER: B = A + u1 v1^T + u2 v2^T and column sums; BiCGK sweeps
+    BG_FIN1,            // sums of GEMVER's x and BiCGK's q and s
+    BG_ROW_NARROW,      // GEMVER second sweeps (w = alpha B x), matrices at most narrow_n wide
+    BG_ROW_WIDE,        // ... wider ones
+    BG_FIN_W,           // sums of GEMVER's w
+    BG_COUNT
+};
+inline bool bt_is_finish(int g) { return g == BG_FIN1 || g == BG_FIN_W; }
+constexpr int kBtHdrInts = 2 * BG_COUNT;
+constexpr int kBtShapeCount = 12;
+// a tile shape that is instantiated for `ops` and can take bands of rb rows
+bool btile_shape_ok(int shape, int ops, int rb);
+int64_t btile_cols(int shape);        // columns per workgroup block
+int64_t btile_wave_cols(int shape);   // columns per wave tile (one row-dot partial each)
+int btile_threads(int shape);
+void btile_shape_info(int shape, int out[4]);   // kv, depth, waves across, waves down
+// `grid` workgroups; with fewer than the group's tiles they step through them.
+// ops is OP_ROWDOT for GEMVER's second sweeps, or kBtFirstOps for the first
+// launch, whose tiles take their operations from their entries.
+constexpr int kBtFirstOps = -1;
+void launch_btile(int shape, int ops, int rb, const BTileEntry *entries, const BTileUnit *units,
+                  const int *hdr, int group, int grid, hipStream_t st);
+void launch_btile_finish(const FinishJob *jobs, const BFinishUnit *units, const int *hdr,
+                         int group, int grid, hipStream_t st);
 
 // Row-resident ATAX: each workgroup keeps one row of A on chip at a time.
 // Row-resident sweeps: the number of workgroups (partial column-sum

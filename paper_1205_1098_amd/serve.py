@@ -10,11 +10,12 @@ brings fresh input vectors.  The scheduler:
   request larger than the whole budget is rejected at once, and one that has
   waited longer than the time-out is failed without running;
 * at every step launches all admitted requests that have not been launched
-  yet: those with at most `batch_max_n` columns together, in one persistent
-  batched launch (one workgroup per instance), the others each through its
-  single-instance entry point, which spreads one instance over the whole
-  GPU.  Steps alternate between streams (lanes), so a step's work overlaps
-  the previous step's;
+  yet: those with at most `batch_max_n` columns together, as one batch (by
+  default a tiled batch: every instance cut into workgroup tiles that spread
+  over the whole GPU, in one graph launch; or a persistent batched launch
+  with one workgroup per instance), the others each through its
+  single-instance entry point.  Steps alternate between streams (lanes), so
+  a step's work overlaps the previous step's;
 * takes a request's completion from an event recorded after its launch
   group: the request's latency is that event's time minus its arrival, and
   its memory and slot are released.
@@ -153,7 +154,10 @@ class Server:
             (token, [requests], queue) triples, `failed` (request, message)
             pairs.  Tokens of one queue complete in launch order (a queue is
             a device stream), so only the oldest of each queue is polled
-        poll(token) -> float | None           completion time, None if running
+        poll(token) -> float | (float, str | None) | None
+                                              completion time (and an error
+                                              that fails the token's requests),
+                                              None if running
         release(req)                          free the request's device memory
         idle(until)                           wait (or advance a virtual clock)
                                               until `until`, a completion, or a
@@ -227,14 +231,18 @@ class Server:
             for dq in self.inflight.values():
                 while dq:
                     token, reqs = dq[0]
-                    t = self.ex.poll(token)
-                    if t is None:
+                    res = self.ex.poll(token)
+                    if res is None:
                         break
+                    t, err = res if isinstance(res, tuple) else (res, None)
                     dq.popleft()
                     self.ninflight -= 1
                     changed = True
                     for r in reqs:
-                        self._finish(r, "cancelled" if r.cancel_requested else "done", t)
+                        if err is not None:
+                            self._finish(r, "failed", t, err)
+                        else:
+                            self._finish(r, "cancelled" if r.cancel_requested else "done", t)
                         self._release(r)
         # queue time-outs, oldest first (requests are submitted in arrival
         # order); only requests that have not started can time out
@@ -371,28 +379,40 @@ class GpuExecutor:
 
     Per request: one allocation for its vectors (plus B for GEMVER) and one
     generator launch for its inputs; then the requests of a step with at
-    most `batch_max_n` columns go into a reusable batch plan (a ring of them
-    per lane, so refilling one never waits for the step just launched) on
-    the lane's batch stream, and the others through the fused entry points
-    on the lane's direct stream, so a long batch never holds up a large
-    request or the reverse.  Calls take device addresses directly (no tensor
-    views per call).  Completion comes from pooled timing events: a
+    most `batch_max_n` columns go into a refillable batch plan (a ring of
+    them per lane, so refilling one never waits for the step just launched)
+    on the lane's batch stream, and the others through the fused entry
+    points on the lane's direct stream, so a long batch never holds up a
+    large request or the reverse.  Tiled batches (the default) take GEMVER
+    and BiCGK; ATAX requests then take their entry point.  A persistent
+    plan's launch is followed by an asynchronous copy of its error word, so
+    a request whose batched launch gave up a bounded wait fails instead of
+    returning invalid results.  Calls take device addresses directly (no
+    tensor views per call).  Completion comes from pooled timing events: a
     request's finish time is the device's, not the moment the host noticed.
     """
 
     def __init__(self, torch, bto, pool: MatrixPool, lanes: int = 2, capacity: int = 64,
                  plans_per_lane: int = 4, batch_n: int | None = None, threads: int = 0,
                  wgs_per_cu: int = 0, seed: int = synth.SEED, keep_outputs: bool = False,
-                 device="cuda:0"):
+                 device="cuda:0", batch_form: str = "tiled", tiled_config=None):
         """`batch_n`: requests with at most this many columns go through the
-        batch plans (None: the library's limit; 0: none)."""
+        batch plans (None: the library's limit; 0: none).  `batch_form`:
+        "tiled" (refillable tiled batches, for GEMVER and BiCGK; ATAX
+        requests take their entry point) or "persistent" (refillable
+        persistent plans, every kind; `threads` and `wgs_per_cu` are their
+        knobs).  `tiled_config`: a TiledConfig for the tiled batches (None:
+        the library's defaults, launched without a graph)."""
         self.torch, self.bto, self.pool = torch, bto, pool
         self.dev = torch.device(device)
         if self.dev.index not in (None, torch.cuda.current_device()):
             raise ValueError("the executor runs on the current device")
+        if batch_form not in ("tiled", "persistent"):
+            raise ValueError("batch_form must be 'tiled' or 'persistent'")
         self.seed = seed
         self.keep = keep_outputs
         self.capacity = capacity
+        self.batch_form = batch_form
         limit = int(bto.batch_max_n())
         self.batch_max = limit if batch_n is None else int(batch_n)
         if not 0 <= self.batch_max <= limit:
@@ -400,17 +420,34 @@ class GpuExecutor:
         batch = self.batch_max > 0
         self.direct = [torch.cuda.Stream(self.dev) for _ in range(lanes)]
         self.hdirect = [bto.stream_handle(st) for st in self.direct]
+        self.errs = None
         if batch:
             self.bstreams = [torch.cuda.Stream(self.dev) for _ in range(lanes)]
             self.hbatch = [bto.stream_handle(st) for st in self.bstreams]
-            # scratch for the tile partials of a full plan of the largest
-            # batched requests
-            small = [n for n in set(pool.sizes) if n <= self.batch_max]
-            per = max((bto.batch_scratch_doubles([{"kind": k, "m": n, "n": n}])
-                       for k in KINDS for n in small), default=0)
-            self.plans = [[bto.BatchPlan.empty(capacity, capacity * per, threads, wgs_per_cu,
-                                               True, self.dev)
-                           for _ in range(plans_per_lane)] for _ in range(lanes)]
+            if batch_form == "tiled":
+                # launched without a graph, each refill sizes its launches and
+                # skips empty groups: a step with one small request costs the
+                # launches its entry point would
+                cfg = tiled_config if tiled_config is not None else \
+                    bto.TiledConfig.default(use_graph=0)
+                self.plans = [[bto.TiledBatch.empty(capacity, self.batch_max, self.batch_max,
+                                                    config=cfg, device=self.dev)
+                               for _ in range(plans_per_lane)] for _ in range(lanes)]
+            else:
+                # scratch for the tile partials of a full plan of the largest
+                # batched requests
+                small = [n for n in set(pool.sizes) if n <= self.batch_max]
+                per = max((bto.batch_scratch_doubles([{"kind": k, "m": n, "n": n}])
+                           for k in KINDS for n in small), default=0)
+                self.plans = [[bto.BatchPlan.empty(capacity, capacity * per, threads, wgs_per_cu,
+                                                   True, self.dev)
+                               for _ in range(plans_per_lane)] for _ in range(lanes)]
+                # each launch's error word lands in its own slot of pinned
+                # memory, read when the launch's event has completed
+                nslots = 4096
+                self.errs = torch.zeros(nslots, dtype=torch.int32, pin_memory=True)
+                self.errs_np = self.errs.numpy()
+                self.free_errs = list(range(nslots))
             self.descs = [[(bto.Desc * capacity)() for _ in range(plans_per_lane)]
                           for _ in range(lanes)]
         self.ring = [0] * lanes
@@ -510,7 +547,8 @@ class GpuExecutor:
         tokens, failed, small = [], [], []
         bst = self.bstreams[lane] if self.batch_max else None
         for r in reqs:
-            is_small = r.n <= self.batch_max
+            is_small = r.n <= self.batch_max and (self.batch_form == "persistent" or
+                                                  r.kind != "atax")
             stream = bst if is_small else self.direct[lane]
             try:
                 r.bufs = self._alloc(r, self.hbatch[lane] if is_small else self.hdirect[lane])
@@ -532,27 +570,43 @@ class GpuExecutor:
             k = self.ring[lane]
             self.ring[lane] = (k + 1) % len(self.plans[lane])
             plan, descs = self.plans[lane][k], self.descs[lane][k]
+            slot = None
             try:
                 for i, r in enumerate(small):
                     self._desc(descs[i], r)
                 plan.reset_descs(descs, len(small), self.hbatch[lane])
                 plan.launch_on(self.hbatch[lane])
+                if self.errs is not None:
+                    # a persistent plan's bounded waits: its error word
+                    # after this launch, checked when the launch completes
+                    slot = self.free_errs.pop()
+                    plan.error_async(self.errs.data_ptr() + 4 * slot, self.hbatch[lane])
             except Exception as e:
+                if slot is not None:
+                    self.free_errs.append(slot)
                 for r in small:
                     failed.append((r, f"{type(e).__name__}: {e}"))
                     self._bury(r, bst)
             else:
                 for r in small:
                     r.batched = True
-                tokens.append((self._event(bst), small, ("batch", lane)))
+                ev = self._event(bst)
+                tokens.append((ev if slot is None else (ev, slot), small, ("batch", lane)))
         return tokens, failed
 
     def poll(self, token):
-        if not token.query():
+        ev, slot = token if isinstance(token, tuple) else (token, None)
+        if not ev.query():
             return None
-        t = self.ref.elapsed_time(token) * 1e-3
-        self.events.append(token)
-        return t
+        t = self.ref.elapsed_time(ev) * 1e-3
+        self.events.append(ev)
+        if slot is None:
+            return t
+        bad = int(self.errs_np[slot]) != 0
+        self.free_errs.append(slot)
+        if bad:
+            return t, "a tile of the batched launch gave up waiting; its results are not valid"
+        return t, None
 
     def release(self, req: Request) -> None:
         b = req.bufs

@@ -297,20 +297,39 @@ def bucket_evaluator(single, groups: dict):
 #: the batch plan's knobs and the values searched (the first is the library default)
 BATCH_SPACE = {
     # fuse-or-split of every instance; "tiled": fused, as short-lived tiles
-    # (bto_tiled_batch), to which the persistent plan's knobs below do not apply
+    # (bto_tiled_batch), to which the persistent plan's knobs do not apply
     "form": ["fused", "unfused", "tiled"],
+    # the persistent plan (bto_batch_plan)
     "threads": [256, 512],                      # workgroup size
     "wgs_per_cu": [2, 1, 3, 4],                 # persistent workgroups per CU ("threads")
     "split_bytes": [16 << 20, -1, 8 << 20, 32 << 20, 4 << 20],   # row tiles of large instances
+    # the tiled form (bto_tiled_config): tile shapes (the partition axis and
+    # the per-partition parallelism), band heights (how many partitions) and
+    # persistent workgroups (0: one per tile)
+    "t_store_shape": [2, 3, 11, 7, 1, 0, 4, 5, 6, 8, 9, 10],
+    "t_store_rb": [64, 32, 16, 128],
+    "t_wide_shape": [1, 2, 3, 8, 11, 7, 0],
+    "t_narrow_shape": [2, 3, 5, 1, 0],
+    "t_read_rb": [64, 32, 128],
+    "t_wgs_per_cu": [0, 1, 2, 4],
 }
+PLAN_KNOBS = ("threads", "wgs_per_cu", "split_bytes")
+TILED_KNOBS = ("t_store_shape", "t_store_rb", "t_wide_shape", "t_narrow_shape", "t_read_rb",
+               "t_wgs_per_cu")
+
+
+def tiled_config_of(cfg: dict) -> dict:
+    """The bto_tiled_config fields of a batch configuration's tiled knobs."""
+    return {k[2:]: v for k, v in cfg.items() if k in TILED_KNOBS}
 
 
 def tune_batch(evaluate, space: dict | None = None, cache: dict | None = None) -> tuple:
-    """Orthogonal search over the batch plan's knobs: fusion first, then each
-    knob in turn over its values, keeping the best so far (the paper's
-    orthogonal strategy, Section V-D1).  `evaluate(cfg) -> seconds` for a
-    dict cfg; results are cached by the configuration.  Returns (best cfg,
-    its time, evaluations)."""
+    """Orthogonal search over the batch knobs: fusion first, then each knob of
+    the winning form in turn over its values, keeping the best so far (the
+    paper's orthogonal strategy, Section V-D1).  `evaluate(cfg) -> seconds`
+    for a dict cfg (infinity for a configuration that cannot run or gives
+    wrong results); results are cached by the configuration.  Returns (best
+    cfg, its time, evaluations)."""
     space = BATCH_SPACE if space is None else space
     cache = {} if cache is None else cache
 
@@ -322,8 +341,9 @@ def tune_batch(evaluate, space: dict | None = None, cache: dict | None = None) -
 
     best = {k: v[0] for k, v in space.items()}
     for knob in space:                        # "form" first: fusion before geometry
-        if knob != "form" and best.get("form") == "tiled":
-            continue                          # the persistent plan's knobs
+        tiled = best.get("form") == "tiled"
+        if (tiled and knob in PLAN_KNOBS) or (not tiled and knob in TILED_KNOBS):
+            continue                          # knobs of the form not chosen
         for val in space[knob]:
             trial = {**best, knob: val}
             if fit(trial) < fit(best):
@@ -547,11 +567,16 @@ def _tune_batch_main(torch, bto, args) -> int:
                                               {"gemver": 0.5, "bicgk": 0.5},
                                               form="fused" if form == "tiled" else form)
         insts, _ = sets[form]
-        if form == "tiled":
-            plan = bto.TiledBatch(insts)
-        else:
-            plan = bto.BatchPlan(insts, threads=cfg["threads"], wgs_per_cu=cfg["wgs_per_cu"],
-                                 split_bytes=cfg["split_bytes"])
+        try:
+            if form == "tiled":
+                plan = bto.TiledBatch(insts, config=bto.TiledConfig.default(
+                    **tiled_config_of(cfg)))
+            else:
+                plan = bto.BatchPlan(insts, threads=cfg["threads"], wgs_per_cu=cfg["wgs_per_cu"],
+                                     split_bytes=cfg["split_bytes"])
+        except bto.BtoError as e:          # a configuration the library refuses
+            print(json.dumps({"cfg": cfg, "refused": str(e)}), flush=True)
+            return float("inf")
         for _ in range(2):
             plan.launch()
         torch.cuda.synchronize()

@@ -25,13 +25,16 @@ class Token:
 
 class FakeExecutor:
     def __init__(self, bandwidth=6.4e12, overhead=10e-6, batch_max=2048, fail_rids=(),
-                 compute=False, launch_cost=0.0):
+                 compute=False, launch_cost=0.0, device_fail_rids=()):
         self.t = 0.0
         self.device_free = 0.0
         self.bw = bandwidth
         self.overhead = overhead
         self.batch_max = batch_max
         self.fail = set(fail_rids)
+        # requests whose launch completes with an error (a batched launch
+        # whose error word is set): every request of that launch fails
+        self.device_fail = set(device_fail_rids)
         self.compute = compute
         self.launch_cost = launch_cost
         self.open = set()
@@ -91,6 +94,8 @@ class FakeExecutor:
     def poll(self, tok):
         if self.t >= tok.done:
             self.open.discard(tok)
+            if any(r.rid in self.device_fail for r in tok.reqs):
+                return tok.done, "a tile of the batched launch gave up waiting"
             return tok.done
         return None
 

@@ -175,3 +175,43 @@ def test_tiled_batch_refuses_more_tiles_than_a_launch_indexes(bto):
         d.out[k] = (1 << 58) + k * (1 << 45)
     assert create_tiled(bto, [d]) == 5
     assert "tiles" in bto._lib.bto_last_error().decode()
+
+
+def test_tiled_config_validation(bto):
+    """Configurations are checked before any device work: shapes, band
+    heights against the shapes' row groups (and at most 64 rows per wave in
+    the read-only sweeps), workgroups per compute unit, the graph flag."""
+    shapes = bto.tiled_shapes()
+    assert len(shapes) == bto._lib.bto_tiled_shape_count() >= 4
+    d = bto.TiledConfig.default()
+    assert 0 <= d.store_shape < len(shapes) and d.use_graph == 1
+    arr = (bto.Desc * 1)()
+    plan = ctypes.c_void_p()
+    bad = [dict(store_shape=len(shapes)), dict(wide_shape=-1), dict(narrow_shape=99),
+           dict(store_rb=0), dict(read_rb=-4), dict(narrow_n=-1), dict(wgs_per_cu=17),
+           dict(wgs_per_cu=-1), dict(use_graph=2)]
+    for s, sh in enumerate(shapes):
+        wr = sh["waves_down"]
+        if wr > 1:
+            bad.append(dict(store_shape=s, store_rb=wr + 1))
+        bad.append(dict(wide_shape=s, read_rb=65 * wr))       # 65 rows per wave
+    for ch in bad:
+        c = bto.TiledConfig.default(**ch)
+        assert bto._lib.bto_tiled_batch_create_config(ctypes.byref(arr), 0, ctypes.byref(c),
+                                                      ctypes.byref(plan)) == 1, ch
+        assert bto._lib.bto_tiled_batch_create_empty(4, 64, 64, ctypes.byref(c),
+                                                     ctypes.byref(plan)) == 1, ch
+    c = bto.TiledConfig.default(wgs_per_cu=0)
+    assert bto._lib.bto_tiled_batch_create_empty(4, 64, 64, ctypes.byref(c),
+                                                 ctypes.byref(plan)) == 1
+    assert "persistent" in bto._lib.bto_last_error().decode()
+    c = bto.TiledConfig.default(wgs_per_cu=0, use_graph=0)     # sized per refill: accepted
+    assert bto._lib.bto_tiled_batch_create_empty(4, 64, 64, ctypes.byref(c),
+                                                 ctypes.byref(plan)) == 4   # no device here
+    c = bto.TiledConfig.default(wgs_per_cu=2)
+    assert bto._lib.bto_tiled_batch_create_empty(-1, 64, 64, ctypes.byref(c),
+                                                 ctypes.byref(plan)) == 1
+    assert bto._lib.bto_tiled_batch_create_empty(4, 64, 2049, ctypes.byref(c),
+                                                 ctypes.byref(plan)) == 5
+    assert bto._lib.bto_tiled_batch_reset(None, None, 0, None) == 1
+    assert bto._lib.bto_tiled_shape(len(shapes), None, None, None, None) == 1

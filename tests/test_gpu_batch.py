@@ -384,3 +384,125 @@ def test_tiled_batch_refuses_other_work(env):
     with pytest.raises(bto.BtoError) as e:
         bto.TiledBatch(ov)
     assert e.value.status == 2
+
+
+# ---- tiled batch configurations and refillable plans ------------------------------
+
+# every tile shape in each role at least once, band heights at the shapes'
+# limits, one workgroup per tile and persistent workgroups, graph or not
+TILED_CONFIGS = [
+    dict(),
+    dict(wgs_per_cu=1),
+    dict(store_shape=1, narrow_shape=2, wide_shape=8, store_rb=64, read_rb=64, wgs_per_cu=2),
+    dict(store_shape=2, narrow_shape=3, wide_shape=9, store_rb=8, read_rb=64, wgs_per_cu=3,
+         use_graph=0),
+    dict(store_shape=3, narrow_shape=4, wide_shape=6, store_rb=128, read_rb=8, narrow_n=0,
+         wgs_per_cu=0, use_graph=0),
+    dict(store_shape=4, narrow_shape=5, wide_shape=7, store_rb=8, read_rb=64, wgs_per_cu=16),
+    dict(store_shape=5, narrow_shape=6, wide_shape=1, store_rb=36, read_rb=8, narrow_n=2048,
+         wgs_per_cu=4),
+    dict(store_shape=6, narrow_shape=7, wide_shape=0, store_rb=4, read_rb=16, narrow_n=1000),
+    dict(store_shape=7, narrow_shape=8, wide_shape=2, store_rb=32, read_rb=32, wgs_per_cu=1),
+    dict(store_shape=8, narrow_shape=9, wide_shape=3, store_rb=12, read_rb=12, wgs_per_cu=2),
+    dict(store_shape=9, narrow_shape=1, wide_shape=5, store_rb=1, read_rb=40, wgs_per_cu=8),
+    dict(store_shape=10, narrow_shape=10, wide_shape=11, store_rb=64, read_rb=48, wgs_per_cu=2),
+    dict(store_shape=11, narrow_shape=11, wide_shape=10, store_rb=7, read_rb=5),
+    dict(store_shape=0, store_rb=16, wgs_per_cu=2),
+]
+
+
+def _tiled_set(torch, bto, data, seed, config):
+    """Random sizes plus the shapes around every tile edge."""
+    insts, specs = batch.make_instances(torch, bto, 40, 64, 2048, TILED_WEIGHTS, seed=seed,
+                                        data=data, config=config)
+    shapes = [(1, 1), (1, 2048), (2, 2), (31, 127), (33, 129), (65, 257), (300, 130),
+              (4097, 1), (129, 2047), (2048, 2048), (3, 1025), (257, 513), (17, 512)]
+    for k, kind in enumerate(TILED_WEIGHTS):
+        i, sp = batch.make_instances(torch, bto, len(shapes), 1, 2, {kind: 1.0}, seed=seed + 1,
+                                     config=config + 1 + k, data=data, shapes=shapes)
+        insts += i
+        specs += sp
+    return insts, specs
+
+
+@pytest.mark.parametrize("k", range(len(TILED_CONFIGS)))
+def test_tiled_configs_match_oracle(env, k):
+    """Each configuration against the oracle (1e-12, and bitwise on integer
+    data); one workgroup per tile and persistent workgroups give the same
+    bits for the same shapes and bands."""
+    torch, bto = env
+    ch = TILED_CONFIGS[k]
+    for data in ("uniform", "int"):
+        insts, specs = _tiled_set(torch, bto, data, 40 + k, 40 + 3 * k)
+        _poison(insts)
+        plan = bto.TiledBatch(insts, config=bto.TiledConfig.default(**ch))
+        plan.launch()
+        torch.cuda.synchronize()
+        check_all(torch, insts, specs, exact=(data == "int"))
+        first = _outputs(insts)
+        plan.close()
+        other = dict(ch, wgs_per_cu=0 if ch.get("wgs_per_cu", 0) else 2)
+        _poison(insts)
+        plan = bto.TiledBatch(insts, config=bto.TiledConfig.default(**other))
+        plan.launch()
+        torch.cuda.synchronize()
+        assert all(torch.equal(a, b) for a, b in zip(first, _outputs(insts)))
+        plan.close()
+
+
+@pytest.mark.parametrize("graph,wgs", [(1, 2), (0, 2), (0, 0)])
+def test_tiled_refills(env, graph, wgs):
+    """A refillable plan run on three different sets in a row (the second
+    smaller, the third empty, then the first again): every instance against
+    the oracle, and bitwise equal to a plan built for that set with the same
+    configuration.  In a graph the launches are fixed; without one they are
+    sized from each refill (with one workgroup per tile, or persistent)."""
+    torch, bto = env
+    cfg = bto.TiledConfig.default(wgs_per_cu=wgs, use_graph=graph)
+    a, sa = batch.make_instances(torch, bto, 70, 64, 2048, TILED_WEIGHTS, seed=60, config=60)
+    b, sb = batch.make_instances(torch, bto, 9, 64, 700, TILED_WEIGHTS, seed=61, config=61)
+    plan = bto.TiledBatch.empty(80, 2048, 2048, config=cfg)
+    for insts, specs in ((a, sa), (b, sb), ([], []), (a, sa)):
+        _poison(insts)
+        plan.reset(insts)
+        plan.launch()
+        torch.cuda.synchronize()
+        check_all(torch, insts, specs, exact=False)
+        got = _outputs(insts)
+        if insts:
+            static = bto.TiledBatch(insts, config=cfg)
+            _poison(insts)
+            static.launch()
+            torch.cuda.synchronize()
+            assert all(torch.equal(x, y) for x, y in zip(got, _outputs(insts)))
+            static.close()
+    plan.close()
+
+
+def test_tiled_refill_limits(env):
+    torch, bto = env
+    cfg = bto.TiledConfig.default(wgs_per_cu=2)
+    insts, _ = batch.make_instances(torch, bto, 5, 64, 300, TILED_WEIGHTS, seed=62, config=62)
+    plan = bto.TiledBatch.empty(4, 300, 300, config=cfg)
+    with pytest.raises(bto.BtoError) as e:
+        plan.reset(insts)                               # five instances, room for four
+    assert e.value.status == 1
+    # the tables are sized for four instances of 300 x 300 in all: two of
+    # 1000 x 1000 need more tiles and scratch than that
+    big, _ = batch.make_instances(torch, bto, 2, 1000, 1001, {"gemver": 1.0}, seed=63,
+                                  config=63)
+    with pytest.raises(bto.BtoError) as e:
+        plan.reset(big)
+    assert e.value.status == 3
+    plan.reset(insts[:4])                               # the plan still works
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.close()
+    static = bto.TiledBatch(insts[:2])
+    with pytest.raises(bto.BtoError) as e:
+        static.reset(insts[:1])                         # not refillable
+    assert e.value.status == 1
+    static.close()
+    with pytest.raises(bto.BtoError) as e:
+        bto.TiledBatch.empty(4, 300, 300, config=bto.TiledConfig.default(wgs_per_cu=0))
+    assert e.value.status == 1

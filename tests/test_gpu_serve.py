@@ -26,15 +26,22 @@ def pool():
     return torch, bto, serve.MatrixPool(torch, bto, SIZES)
 
 
-@pytest.fixture(scope="module", params=["direct", "plans"])
+@pytest.fixture(scope="module", params=["direct", "tiled", "persistent"])
 def env(pool, request):
     """Small requests through the single-instance entry points, or through
-    the batch plans (n <= 2048)."""
+    refillable batches (n <= 2048): tiled (GEMVER and BiCGK; ATAX takes its
+    entry point) or persistent plans (every kind)."""
     torch, bto, mats = pool
+    route = request.param
     ex = serve.GpuExecutor(torch, bto, mats, keep_outputs=True,
-                           batch_n=0 if request.param == "direct" else None)
+                           batch_n=0 if route == "direct" else None,
+                           batch_form="persistent" if route == "persistent" else "tiled")
     yield torch, bto, mats, ex
     ex.close()
+
+
+def batched(ex, r):
+    return r.n <= ex.batch_max and (ex.batch_form == "persistent" or r.kind != "atax")
 
 
 def relerr(got, ref):
@@ -79,7 +86,7 @@ def test_mix_matches_oracle_and_alone(env, rate):
     for r in reqs:
         steps.setdefault((r.step, r.batched), []).append(r)
     assert any(len(g) > 1 for g in steps.values())
-    assert all(r.batched == (r.n <= ex.batch_max) for r in reqs)
+    assert all(r.batched == batched(ex, r) for r in reqs)
     if ex.batch_max:
         assert any(len(g) > 1 for (_, b), g in steps.items() if b)
     assert all(r.latency > 0 for r in reqs)
@@ -106,3 +113,23 @@ def test_budget_limits_inflight(env):
     assert srv.used_bytes == 0 and srv.used_slots == 0
     # completion times never precede arrival or launch order within a lane
     assert all(r.done >= r.launched - 1e-3 for r in reqs)
+
+
+def test_persistent_error_words_read_per_launch(pool):
+    """The persistent route checks each batched launch's error word without
+    synchronizing: a good launch leaves 0 in its slot, and its requests
+    finish as done; every slot is returned."""
+    torch, bto, mats = pool
+    ex = serve.GpuExecutor(torch, bto, mats, batch_form="persistent")
+    try:
+        free = len(ex.free_errs)
+        ex.errs.fill_(7)
+        reqs = serve.make_requests(24, SIZES, rate=None, first_rid=7000)
+        serve_all(torch, ex, reqs, slots=16)
+        assert all(r.state == "done" for r in reqs)
+        assert any(r.batched for r in reqs)
+        assert len(ex.free_errs) == free
+        used = [k for k in range(len(ex.errs_np)) if ex.errs_np[k] != 7]
+        assert used and all(ex.errs_np[k] == 0 for k in used)
+    finally:
+        ex.close()

@@ -208,3 +208,23 @@ def test_summary_statistics():
     assert s["p99_ms"] == pytest.approx(np.percentile(lat, 99))
     ends = sorted(r.done for r in reqs)
     assert s["req_per_s"] == pytest.approx(90 / (ends[-1] - ends[9]))
+
+
+def test_device_error_fails_its_launch_group():
+    """A launch that completes with an error (a batched launch whose bounded
+    wait gave up) fails every request of that launch, never marks them done,
+    and releases their memory and slots; other launches are unaffected."""
+    sizes = [300, 500, 9000]
+    reqs = serve.make_requests(60, sizes, rate=None)
+    bad = {r.rid for r in reqs if r.n <= 2048}
+    victim = min(bad)
+    ex = FakeExecutor(device_fail_rids={victim})
+    srv, ex = run(reqs, ex, budget_bytes=64 * GiB, slots=8)
+    failed = [r for r in reqs if r.state == "failed"]
+    assert failed and all("gave up" in r.error for r in failed)
+    assert any(r.rid == victim for r in failed)
+    # exactly the requests launched together with the victim failed
+    group = next(g for _, g in ex.launched if victim in g)
+    assert {r.rid for r in failed} == set(group)
+    assert all(r.state == "done" for r in reqs if r.rid not in group)
+    assert srv.used_bytes == 0 and srv.used_slots == 0 and ex.live_bytes == 0

@@ -239,7 +239,10 @@ def test_batch_knobs_orthogonal_search():
 
     cache = {}
     best, sec, evals = tune.tune_batch(ev, cache=cache)
-    assert best == {"form": "fused", "threads": 256, "wgs_per_cu": 2, "split_bytes": 8 << 20}
+    defaults = {k: v[0] for k, v in tune.BATCH_SPACE.items()}
+    assert best == {**defaults, "form": "fused", "threads": 256, "wgs_per_cu": 2,
+                    "split_bytes": 8 << 20}
+    assert all(c[k] == defaults[k] for c in calls for k in tune.TILED_KNOBS)
     assert sec == pytest.approx(1.0)
     keys = [json.dumps(c, sort_keys=True) for c in calls]
     assert len(keys) == len(set(keys)) == evals           # no configuration measured twice
@@ -310,4 +313,28 @@ def test_batch_knobs_tiled_form_skips_plan_knobs():
 
     best, sec, evals = tune.tune_batch(ev)
     assert best["form"] == "tiled" and sec == pytest.approx(0.9)
-    assert evals == len(tune.BATCH_SPACE["form"])
+    assert all(c["threads"] == tune.BATCH_SPACE["threads"][0] and
+               c["split_bytes"] == tune.BATCH_SPACE["split_bytes"][0] for c in calls)
+
+
+def test_batch_knobs_search_the_winning_forms_knobs():
+    """With the tiled form best, its partition knobs are searched one after
+    another (and the plan's are not); a refused configuration (infinite
+    time) is never chosen."""
+    seen = []
+
+    def ev(cfg):
+        seen.append(cfg)
+        if cfg["form"] != "tiled":
+            return 2.0
+        if cfg["t_store_rb"] == 16:
+            return float("inf")            # e.g. refused by the library
+        return 1.0 - 0.01 * (cfg["t_store_shape"] == 3) - 0.02 * (cfg["t_read_rb"] == 32)
+
+    best, sec, evals = tune.tune_batch(ev)
+    assert best["form"] == "tiled"
+    assert best["t_store_shape"] == 3 and best["t_read_rb"] == 32 and best["t_store_rb"] != 16
+    assert sec == pytest.approx(0.97)
+    assert all(c["threads"] == tune.BATCH_SPACE["threads"][0] for c in seen)
+    assert tune.tiled_config_of(best)["store_shape"] == 3
+    assert set(tune.tiled_config_of(best)) == {k[2:] for k in tune.TILED_KNOBS}
