@@ -86,3 +86,58 @@ out: x : vector(column), w : vector(column)
   x = beta * B' * y + z
   w = alpha * B * x
 }"""
+
+# Programs whose fused passes the library's sweeps cannot run (an update of
+# rank three; several row dots and column sums over one matrix): the
+# compiler emits their passes as HIP (btoc_gen), built with the package.
+GENERATED = {
+    "gemver3": """GEMVER3
+in:  A : matrix(row), u1 : vector(column), v1 : vector(column), u2 : vector(column),
+     v2 : vector(column), u3 : vector(column), v3 : vector(column), y : vector(column),
+     z : vector(column), alpha : scalar, beta : scalar
+out: B : matrix(row), x : vector(column), w : vector(column)
+{
+  B = A + u1 * v1' + u2 * v2' + u3 * v3'
+  x = beta * B' * y + z
+  w = alpha * B * x
+}""",
+    "gemver3c": """GEMVER3C
+in:  A : matrix(row), u1 : vector(column), v1 : vector(column), u2 : vector(column),
+     v2 : vector(column), u3 : vector(column), v3 : vector(column), y : vector(column),
+     z : vector(column), alpha : scalar, beta : scalar
+out: x : vector(column), w : vector(column)
+{
+  B = A + u1 * v1' + u2 * v2' + u3 * v3'
+  x = beta * B' * y + z
+  w = alpha * B * x
+}""",
+    "bicgk2": """BICGK2
+in:  A : matrix(row), p1 : vector(column), p2 : vector(column), r1 : vector(column),
+     r2 : vector(column)
+out: q1 : vector(column), q2 : vector(column), s1 : vector(column), s2 : vector(column)
+{
+  q1 = A * p1
+  q2 = A * p2
+  s1 = A' * r1
+  s2 = A' * r2
+}""",
+    "multimv": """MULTIMV
+in:  A : matrix(row), x1 : vector(column), x2 : vector(column), x3 : vector(column),
+     y : vector(column), alpha : scalar, beta : scalar
+out: z1 : vector(column), z2 : vector(column), z3 : vector(column)
+{
+  z1 = alpha * A * x1 + beta * y
+  z2 = A * x2 - y
+  z3 = beta * alpha * A * x3
+}""",
+    "bicgk2c": """BICGK2C
+in:  A : matrix(column), p1 : vector(column), p2 : vector(column), r1 : vector(column),
+     r2 : vector(column)
+out: q1 : vector(column), q2 : vector(column), s1 : vector(column), s2 : vector(column)
+{
+  q1 = A * p1
+  q2 = A * p2
+  s1 = A' * r1
+  s2 = A' * r2
+}""",
+}

@@ -393,8 +393,6 @@ class _Typer:
             raise SpecError("only vectors add to vectors, and outer products to a matrix")
         if a.trans or a.coef != ONE:
             raise SpecError("an update applies to an untransposed, unscaled matrix")
-        if len(a.terms) == 2:
-            raise SpecError("at most two rank-1 terms per update")
         return Mat(a.base, a.terms + ((b.u, b.v),))
 
     def mul(self, a, b):
@@ -433,7 +431,9 @@ class _Typer:
 
 @dataclass
 class Pass:
-    """One sweep of `base` (bto_pass)."""
+    """One sweep of `base`: a bto_pass call (target "library"), or an
+    emitted loop nest (target "generated", whose reductions are the lists
+    `rows` and `cols`, any number of each)."""
     level: int
     base: str
     terms: tuple                 # the update, when stored or contracted
@@ -442,6 +442,8 @@ class Pass:
     chain: bool = False
     row: dict | None = None      # {"x", "out", "scale", "add", "add_scale"}
     col: dict | None = None      # {"y", "out", "scale", "add", "add_scale"}
+    rows: list = field(default_factory=list)    # generated: row dots
+    cols: list = field(default_factory=list)    # generated: column sums
 
 
 @dataclass
@@ -505,6 +507,7 @@ class Program:
     temps: list                   # vector temporaries
     temp_mats: dict               # stored updates that are not outputs: name -> source
     colmajor: set = field(default_factory=set)   # matrices stored by columns
+    target: str = "library"       # "library" (bto_pass) or "generated" (emitted passes)
 
     def describe(self):
         lines = []
@@ -513,6 +516,12 @@ class Program:
                 ops = [k for k, on in (("STORE", s.store), ("CONTRACT", s.contract),
                                        ("CHAIN", s.chain), ("ROWDOT", s.row),
                                        ("COLSUM", s.col)) if on]
+                if s.rows:
+                    ops.append("ROWDOT" + (f"x{len(s.rows)}" if len(s.rows) > 1 else ""))
+                if s.cols:
+                    ops.append("COLSUM" + (f"x{len(s.cols)}" if len(s.cols) > 1 else ""))
+                if s.terms and (s.store or s.contract) and len(s.terms) > 2:
+                    ops.append(f"RANK{len(s.terms)}")
                 lines.append(f"pass {s.level}: {s.base} {'|'.join(ops)}")
             elif isinstance(s, VecOp):
                 lines.append(f"vec {s.level}: {s.out} = a*{s.x} + b*{s.y}")
@@ -569,11 +578,24 @@ def _uses(defs, name):
 DECISIONS = ("share", "contract", "chain", "vector")
 
 
-def compile_spec(text: str, form: str = "fused", off=()) -> Program:
+#: most rank-1 terms one library pass applies (bto_pass stores or contracts two)
+LIBRARY_MAX_TERMS = 2
+
+
+def compile_spec(text: str, form: str = "fused", off=(), target: str = "library") -> Program:
     """Parse, type and schedule a specification (see the module text).
-    `off` names fusion decisions (DECISIONS) not to take in the fused form."""
+    `off` names fusion decisions (DECISIONS) not to take in the fused form.
+    `target` "library" lowers onto the library's passes (one row dot and one
+    column sum per sweep, updates of rank two at most); "generated" plans
+    for emitted passes (btoc_gen): products of one matrix at one point of
+    the schedule all share a sweep, and an update of any rank is stored or
+    formed in registers (contracted) by the sweep that reads it."""
     if form not in ("fused", "unfused"):
         raise SpecError("form must be 'fused' or 'unfused'")
+    if target not in ("library", "generated"):
+        raise SpecError("target must be 'library' or 'generated'")
+    if target == "generated" and form != "fused":
+        raise SpecError("generated passes are the fused form")
     if any(d not in DECISIONS for d in off):
         raise SpecError(f"unknown fusion decision in {tuple(off)}")
     spec = parse(text)
@@ -586,7 +608,10 @@ def compile_spec(text: str, form: str = "fused", off=()) -> Program:
     fused = form == "fused"
     outputs = set(ty.outputs)
     on = {d: fused and d not in off for d in DECISIONS}
-    sched = _Scheduler(fused, ty.colmajor, on)
+    gen = target == "generated"
+    if gen:
+        on["chain"] = False        # the row-resident chain is the library's own sweep
+    sched = _Scheduler(fused, ty.colmajor, on, generated=gen)
     sched.temps = [n for n, v in ty.defs if isinstance(v, Lin) and n not in outputs]
     for name in ty.inputs:
         sched.avail[name] = 0
@@ -594,6 +619,10 @@ def compile_spec(text: str, form: str = "fused", off=()) -> Program:
     for name, val in ty.defs:
         if name in outputs and isinstance(val, Mat) and not val.terms:
             raise SpecError(f"{name}: a matrix output must update a matrix input")
+        if (isinstance(val, Mat) and fused and not gen
+                and len(val.terms) > LIBRARY_MAX_TERMS):
+            raise SpecError(f"{name}: an update of rank {len(val.terms)} needs generated "
+                            f"passes (the library's sweeps apply {LIBRARY_MAX_TERMS} terms)")
     # matrix updates: stored when an output (or always, unfused), else contracted
     for name, val in ty.defs:
         if isinstance(val, Mat) and val.terms and (name in outputs or not on["contract"]):
@@ -606,7 +635,8 @@ def compile_spec(text: str, form: str = "fused", off=()) -> Program:
             sched.dot(name, val)
 
     return Program(spec.name, form, [d.name for d in spec.inputs], ty.outputs, ty.kinds,
-                   _ordered(sched.steps), sched.temps, sched.temp_mats, set(ty.colmajor))
+                   _ordered(sched.steps), sched.temps, sched.temp_mats, set(ty.colmajor),
+                   target)
 
 
 class _Scheduler:
@@ -614,8 +644,9 @@ class _Scheduler:
     by columns is the row-major n x m matrix of its transpose, so its
     products swap row dots and column sums and its updates swap u and v."""
 
-    def __init__(self, fused: bool, colmajor=(), on=None):
+    def __init__(self, fused: bool, colmajor=(), on=None, generated: bool = False):
         self.fused = fused
+        self.generated = generated
         self.on = on if on is not None else {d: fused for d in DECISIONS}
         self.colmajor = set(colmajor)
         self.avail = {}          # vector or matrix -> first level that may read it
@@ -701,7 +732,7 @@ class _Scheduler:
                 if t.vec in self.temps:
                     self.temps.remove(t.vec)
                 return src.level + 1
-        if terms and add is not None and add_scale != ONE:
+        if terms and add is not None and add_scale != ONE and not self.generated:
             # a contracted sweep adds its vector unscaled: scale it first
             tmp = self.temp()
             self.vec_sum(tmp, [(add_scale, add)], add_level)
@@ -778,7 +809,21 @@ class _Scheduler:
 
     def place(self, lvl, base, terms, kind, spec_):
         """Fuse into a pass over the same matrix at the same level that has
-        this kind of reduction free; otherwise open a pass."""
+        this kind of reduction free (generated passes: any pass over the same
+        matrix at that level); otherwise open a pass."""
+        if self.generated:
+            for s in self.steps:
+                if not isinstance(s, Pass) or s.level != lvl:
+                    continue
+                same = ((s.store is not None and s.store == base and not terms)
+                        or (s.store is None and s.base == base and s.terms == terms))
+                if same and self.on["share"]:
+                    getattr(s, kind + "s").append(spec_)
+                    return s
+            p = Pass(lvl, base, terms, contract=bool(terms))
+            getattr(p, kind + "s").append(spec_)
+            self.steps.append(p)
+            return p
         if self.on["share"]:
             for s in self.steps:
                 if not isinstance(s, Pass) or s.level != lvl or s.chain:

@@ -9,6 +9,8 @@ scalars and literals) on the host.
 
 from __future__ import annotations
 
+import ctypes
+
 import torch
 
 from . import bto
@@ -22,7 +24,7 @@ def _coef(c, scalars):
     return v
 
 
-def run(prog, bound: dict, ws=None) -> dict:
+def run(prog, bound: dict, ws=None, gen=None) -> dict:
     """Enqueue the program.  `bound` maps every input to a tensor (matrices
     (m, n) float64, row-major, or column-major where the specification says
     matrix(column), i.e. unit stride down a column; vectors 1-D float64) or
@@ -31,7 +33,12 @@ def run(prog, bound: dict, ws=None) -> dict:
     column-major matrix is returned as an (m, n) view of its storage.
 
     Passes run on matrices as stored: a column-major matrix is handed to the
-    library as the row-major matrix of its transpose."""
+    library as the row-major matrix of its transpose.  `gen` = (generated
+    library, its passes, genome) runs the matrix passes in a library emitted
+    by btoc_gen instead of bto_pass.
+
+    A bound output may not share memory with any bound input (an output is
+    written while inputs are still read)."""
     env, scalars = {}, {}
     dev = None
     for name in prog.inputs:
@@ -51,6 +58,7 @@ def run(prog, bound: dict, ws=None) -> dict:
     if dev is None:
         raise SpecError("the program has no tensor input")
     given = {o: bound[o] for o in prog.outputs if o in bound}
+    _check_overlaps(prog, bound, given)
     zeros = {}
 
     def zero(k):
@@ -86,8 +94,21 @@ def run(prog, bound: dict, ws=None) -> dict:
             raise SpecError(f"{name} is read before it is written")
         return env[name]
 
-    need = max([bto.pass_workspace_bytes(_ops(s), *_shape(s, env)) for s in prog.steps
-                if isinstance(s, Pass) and s.base in env] + [1])
+    if gen is not None:
+        lib, gpasses, genome = gen
+        gindex = {id(p): k for k, p in enumerate(gpasses)}
+        scal = [scalars[n] for n in prog.inputs if prog.kinds[n] == "scalar"]
+        scal_c = (ctypes.c_double * max(len(scal), 1))(*scal)
+
+        def gen_ws(s, m, n):
+            k = gindex[id(s)]
+            return lib.workspace_bytes(k, m, n, *genome[k])
+
+        need = max([gen_ws(s, *_shape(s, env)) for s in prog.steps
+                    if isinstance(s, Pass) and s.base in env] + [1])
+    else:
+        need = max([bto.pass_workspace_bytes(_ops(s), *_shape(s, env)) for s in prog.steps
+                    if isinstance(s, Pass) and s.base in env] + [1])
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
 
@@ -116,6 +137,15 @@ def run(prog, bound: dict, ws=None) -> dict:
             continue
         A = get(s.base)
         m, n = A.shape
+        if gen is not None:
+            k = gindex[id(s)]
+            shape, rb = genome[k]
+            need = gen_ws(s, m, n)
+            if ws.numel() < need:
+                ws = torch.empty(need, dtype=torch.uint8, device=dev)
+            _gen_pass(lib, k, s, A, m, n, shape, rb, get, vec_out, mat_out, scal_c, len(scal),
+                      ws, dev)
+            continue
         kw = {}
         if s.store or s.contract:
             us = [get(u) for u, _ in s.terms] + [zero(m)] * (2 - len(s.terms))
@@ -147,6 +177,89 @@ def run(prog, bound: dict, ws=None) -> dict:
             ws = torch.empty(k, dtype=torch.uint8, device=dev)
         bto.fused_pass(_ops(s), A, ws=ws, **kw)
     return {o: (env[o].t() if o in prog.colmajor else env[o]) for o in prog.outputs}
+
+
+def _gen_pass(lib, k, s, A, m, n, shape, rb, get, vec_out, mat_out, scal_c, nscal, ws, dev):
+    """One pass in a generated library (btog_run_pass), operands bound by
+    the pass's structure: update terms, row dots, column sums."""
+    from .btoc_gen import PassArgs
+
+    a = PassArgs()
+    a.m, a.n = m, n
+    a.lda = bto._check_mat(A, "A")
+    a.A = A.data_ptr()
+    keep = [A]
+    if s.store or s.contract:
+        for r, (u, v) in enumerate(s.terms):
+            tu, tv = get(u), get(v)
+            bto._check_vec(tu, u, dev, m)
+            bto._check_vec(tv, v, dev, n)
+            a.u[r], a.v[r] = tu.data_ptr(), tv.data_ptr()
+            keep += [tu, tv]
+    if s.store:
+        B = mat_out(s.store, m, n)
+        a.ldb = bto._check_mat(B, "B")
+        a.B = B.data_ptr()
+        keep.append(B)
+    else:
+        a.ldb = a.lda
+    for q, r in enumerate(s.rows):
+        x = get(r["x"])
+        bto._check_vec(x, r["x"], dev, n)
+        out = vec_out(r["out"], m)
+        a.x[q], a.row_out[q] = x.data_ptr(), out.data_ptr()
+        if r["add"] is not None:
+            add = get(r["add"])
+            bto._check_vec(add, r["add"], dev, m)
+            a.row_add[q] = add.data_ptr()
+    for q, c in enumerate(s.cols):
+        y = get(c["y"])
+        bto._check_vec(y, c["y"], dev, m)
+        out = vec_out(c["out"], n)
+        a.y[q], a.col_out[q] = y.data_ptr(), out.data_ptr()
+        if c["add"] is not None:
+            add = get(c["add"])
+            bto._check_vec(add, c["add"], dev, n)
+            a.col_add[q] = add.data_ptr()
+    a.scalars = scal_c
+    a.nscalars = nscal
+    with torch.cuda.device(dev):
+        st = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+        lib._check(lib.lib.btog_run_pass(k, ctypes.byref(a), shape, rb,
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), st))
+
+
+def _span(t):
+    """[lo, hi) bytes of a tensor's storage that it can touch."""
+    if t.numel() == 0:
+        return None
+    lo = t.data_ptr()
+    hi = lo + 8 * (1 + sum((d - 1) * st for d, st in zip(t.shape, t.stride())))
+    return lo, hi
+
+
+def _check_overlaps(prog, bound, given):
+    """Refuse an output bound to memory that a bound input also uses, except
+    a matrix update bound to exactly the matrix it updates (in place, as
+    the library's GEMVER allows B == A)."""
+    in_place = {(s.store, s.base) for s in prog.steps if isinstance(s, Pass) and s.store}
+    ins = [(n, _span(bound[n])) for n in prog.inputs
+           if prog.kinds[n] != "scalar" and isinstance(bound.get(n), torch.Tensor)]
+    for o, t in given.items():
+        if not isinstance(t, torch.Tensor):
+            continue
+        so = _span(t)
+        if so is None:
+            continue
+        for n, si in ins:
+            if si is None or not (si[0] < so[1] and so[0] < si[1]):
+                continue
+            u = bound[n]
+            exact = (t.data_ptr() == u.data_ptr() and t.shape == u.shape
+                     and t.stride() == u.stride())
+            if (o, n) in in_place and exact:
+                continue
+            raise SpecError(f"output {o} shares memory with input {n}")
 
 
 def _stored(name, t, prog):

@@ -2,7 +2,9 @@
 
 Run as ``python -m paper_1205_1098_amd.build_lib``; ``__graft_entry__.build``
 calls :func:`build`.  Sources are compiled in parallel into ``_build/`` and
-linked into ``paper_1205_1098_amd/libbto.so`` in the source tree.
+linked into ``paper_1205_1098_amd/libbto.so`` in the source tree; then the
+spec compiler's generated programs are emitted and compiled into
+``paper_1205_1098_amd/gen/``.
 """
 
 from __future__ import annotations
@@ -57,6 +59,10 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    # the libraries the spec compiler generates for its shipped programs
+    from . import btoc_gen
+
+    btoc_gen.build_all(verbose=verbose)
     return LIB
 
 

@@ -183,7 +183,7 @@ out: r : scalar, y : vector(column)
     ("K\nin: A : matrix(row), x : vector(column)\nout: y : vector(column)\n{ x = A * x }",
      "input"),
     ("K\nin: A : matrix(row), u : vector(column)\nout: B : matrix(row)\n"
-     "{ B = A + u * u' + u * u' + u * u' }", "at most two"),
+     "{ B = A + u * u' + u * u' + u * u' }", "needs generated"),
     ("K\nin: A : matrix(row), x : vector(column)\nout: y : vector(column), w : vector(column)\n"
      "{ y = A * x }", "never assigned"),
     ("K\nin: A : matrix(row)\nout: B : matrix(row)\n{ B = A }", "must update"),
