@@ -17,6 +17,9 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
               (against GEMVER's two forms) and BATAX (y = beta A^T A x)
   generated   the same kernels compiled from their specifications (btoc),
               against the hand-written fused entry points
+  generated_passes  programs whose fused passes the compiler emits as HIP
+              (a rank-3 update, several row dots and column sums per sweep)
+              at n = 16384, against their unfused and library lowerings
   stream      measured copy / read / triad ceilings at 2 GiB per array
   batched     4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048]) in
               one persistent graph-captured launch, and the same instances as
@@ -455,6 +458,55 @@ def bench_generated(torch, bto, synth, shared, suite) -> dict:
     return out
 
 
+def bench_generated_passes(torch, bto, n: int = N) -> dict:
+    """The programs whose fused passes the compiler generates as HIP
+    (bto_specs.GENERATED) at n x n: the generated library under its searched
+    genome (and under the structural one), against the same program lowered
+    unfused onto the library's passes and, where the library can run it
+    fused, against that lowering (more sweeps)."""
+    from paper_1205_1098_amd import bto_specs, btoc, btoc_gen
+
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, text in bto_specs.GENERATED.items():
+        prog = btoc.compile_spec(text, target="generated")
+        bound = btoc_gen.synthetic_bound(prog, n, dev)
+        first = btoc_gen.run(prog, bound)
+        bound.update(first)                  # outputs preallocated for the timed loops
+        genome = btoc_gen.default_genome(prog)
+        heur = btoc_gen.heuristic_genome(prog)
+        sec = time_steps(torch, lambda: btoc_gen.run(prog, bound, genome), 20, 3)
+        sec_h = sec if heur == genome else time_steps(
+            torch, lambda: btoc_gen.run(prog, bound, heur), 20, 3)
+        nbytes = btoc_gen.alg_bytes(prog, n, n)
+        ent = {"passes": len(prog.passes()), "schedule": prog.describe(),
+               "genome": [list(g) for g in genome],
+               "tuned": btoc_gen.tuned_genome(prog) is not None,
+               "alg_gb": round(nbytes / 1e9, 3), "ms": round(sec * 1e3, 4),
+               "gbs": round(nbytes / sec / 1e9, 1),
+               "pct_peak": round(100 * nbytes / sec / 1e9 / PEAK_GBS, 1),
+               "structural_genome_ms": round(sec_h * 1e3, 4)}
+        unf = btoc.compile_spec(text, "unfused")
+        sec_u = time_steps(torch, lambda: unf.run(**bound), 10, 2)
+        ent["unfused"] = {"passes": len(unf.passes()), "ms": round(sec_u * 1e3, 4),
+                          "speedup": round(sec_u / sec, 3)}
+        try:
+            lib_prog = btoc.compile_spec(text)
+        except btoc.SpecError as e:
+            ent["library_fused"] = {"refused": str(e)}
+        else:
+            sec_l = time_steps(torch, lambda: lib_prog.run(**bound), 10, 2)
+            ent["library_fused"] = {"passes": len(lib_prog.passes()),
+                                    "ms": round(sec_l * 1e3, 4),
+                                    "speedup": round(sec_l / sec, 3)}
+        out[name] = ent
+        print(f"generated {name}: {ent['ms']} ms, {ent['gbs']} GB/s", file=sys.stderr,
+              flush=True)
+        del bound, first
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
     fair seeded coin) in one graph-captured persistent launch."""
@@ -787,6 +839,9 @@ def main() -> int:
     shared.clear()
     del main_wl
     torch.cuda.empty_cache()
+    if not args.no_suite:
+        result["generated_passes"] = bench_generated_passes(torch, bto)
+        torch.cuda.empty_cache()
     if not args.no_batch:
         result["batched"] = bench_batched(torch, bto, args.batch_count, not args.no_batch_loop,
                                           not args.batch_direct)

@@ -638,7 +638,14 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description="HIP source of a BTO specification's passes")
     ap.add_argument("spec", nargs="?")
     ap.add_argument("--build", action="store_true")
+    ap.add_argument("--tune", nargs="*", default=None, metavar="NAME",
+                    help="search the genomes of these programs of bto_specs.GENERATED (all "
+                         "when none is named) on the device at --n and write the tuned table")
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--table", default=TUNED_TABLE)
     args = ap.parse_args(argv)
+    if args.tune is not None:
+        return _tune_main(args.tune or sorted(bto_specs.GENERATED), args.n, args.table)
     if args.spec is None:
         if args.build:
             for p in build_all(verbose=True):
@@ -731,15 +738,50 @@ def load(prog: Program) -> Library:
     return _loaded[path]
 
 
+#: genomes found by the search (``tune``) on MI355X, keyed by program name,
+#: used while the program's emitted source is unchanged.  BTO_GEN_TUNING
+#: names another table of the same form.
+TUNED_TABLE = os.path.join(PKG, "gen_tuned.json")
+
+
+def tuned_table() -> dict:
+    import json
+
+    path = os.environ.get("BTO_GEN_TUNING") or TUNED_TABLE
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def tuned_genome(prog: Program) -> list | None:
+    """The searched genome of `prog` when the table has one for its current
+    source (same digest), else None."""
+    ent = tuned_table().get(prog.name)
+    if not ent or ent.get("digest") != digest(emit(prog)):
+        return None
+    return [tuple(g) for g in ent["genome"]]
+
+
 def default_genome(prog: Program) -> list:
-    """(shape, rb) per pass: the sweep that stores an update in narrow
-    tiles of short bands (as GEMVER's first pass in the library), read-only
-    sweeps with column sums in wide 4 x 4-wave tiles of 128 rows, and
-    sweeps of row dots only in 2048-column tiles of 4 rows."""
+    """(shape, rb) per pass: the searched genome when the tuned table has
+    one for this source; otherwise the sweep that stores an update in
+    narrow tiles of short bands (as GEMVER's first pass in the library),
+    sweeps that only read (contracted updates formed in registers included)
+    with column sums in wide 4 x 4-wave tiles of 128 rows, and with row dots
+    only in 2048-column tiles of 4 rows."""
+    tuned = tuned_genome(prog)
+    if tuned is not None and len(tuned) == len(gen_passes(prog)):
+        return tuned
+    return heuristic_genome(prog)
+
+
+def heuristic_genome(prog: Program) -> list:
+    """The genome chosen from each pass's structure alone."""
     out = []
     for p in gen_passes(prog):
         R, store, P, Q = layout(p)
-        if store or R:
+        if store:
             out.append((0, 32))
         elif Q:
             out.append((6, 128))
@@ -763,6 +805,54 @@ def genome_choices(prog: Program, lib: Library | None = None) -> list:
     return out
 
 
+def tune(prog: Program, bound: dict, reps: int = 5, warmup: int = 2, population: int = 20,
+         generations: int = 6, seed: int = 0, log=None) -> dict:
+    """Search the genome of `prog` on the bound inputs with the MFGA of
+    Section IV (tune.mfga_genes), starting from the structural genome.  The
+    fitness of a genome is the program's time on the device (HIP events on
+    the current stream, `reps` runs after `warmup`); a genome whose outputs
+    differ from the structural genome's by more than 1e-12 (normwise per
+    output), or that the library refuses, scores infinity.  Returns the
+    best genome, its time, the start's time and the number measured."""
+    import torch
+
+    from . import bto, tune as tuner
+
+    start = heuristic_genome(prog)
+    bound = dict(bound)
+    first = run(prog, bound, start)
+    torch.cuda.synchronize()
+    bound.update(first)                      # later runs write the same tensors
+    ref = [first[o].clone() for o in prog.outputs]
+    choices = genome_choices(prog)
+
+    def fitness(genome):
+        try:
+            for o in prog.outputs:
+                bound[o].fill_(float("nan"))
+            for _ in range(warmup):
+                run(prog, bound, genome)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                run(prog, bound, genome)
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b) / reps
+        except (bto.BtoError, SpecError):
+            return float("inf")
+        ok = tuner.outputs_agree([bound[o] for o in prog.outputs], ref)
+        if log:
+            log({"genome": [list(g) for g in genome], "ms": round(ms, 4), "checked": ok})
+        return ms if ok else float("inf")
+
+    t0 = fitness(tuple(start))
+    best, ms, evals = tuner.mfga_genes(choices, fitness, start=start, population=population,
+                                       generations=generations, seed=seed)
+    return {"genome": [list(g) for g in best], "ms": ms, "start_ms": t0, "evaluations": evals}
+
+
 def run(prog: Program, bound: dict, genome=None, ws=None) -> dict:
     """Enqueue the program on the current stream: its matrix passes in the
     generated library, its vector statements through libbto (see
@@ -778,5 +868,80 @@ def run(prog: Program, bound: dict, genome=None, ws=None) -> dict:
     return btoc_run.run(prog, bound, ws, gen=(lib, passes, genome))
 
 
+def synthetic_bound(prog: Program, n: int, dev, seed_base: int = 970) -> dict:
+    """Seeded uniform[-1, 1) inputs of an n x n instance of `prog` on `dev`
+    (scalars 1.5, 0.7, ... in declaration order); column-major matrices as
+    transposed views of row-major storage."""
+    import torch
+
+    from . import bto, synth
+
+    bound = {}
+    scal = iter((1.5, 0.7, 1.25, 0.5, 2.0, 0.3, 1.1, 0.9))
+    for j, name in enumerate(prog.inputs):
+        kind = prog.kinds[name]
+        sid = synth.stream_id(13, seed_base + j)
+        if kind == "scalar":
+            bound[name] = next(scal)
+        elif kind == "matrix":
+            A = torch.empty((n, n), dtype=torch.float64, device=dev)
+            bto.synth_fill(A, synth.stream_state(synth.SEED, sid))
+            bound[name] = A.t() if name in prog.colmajor else A
+        else:
+            v = torch.empty(n, dtype=torch.float64, device=dev)
+            bto.synth_fill(v, synth.stream_state(synth.SEED, sid))
+            bound[name] = v
+    return bound
+
+
+def alg_bytes(prog: Program, m: int, n: int) -> int:
+    """Algorithmic HBM bytes of the program's generated schedule: each pass
+    reads its matrix once and writes a stored update once; each vector a
+    pass reads or writes counts once per pass."""
+    total = 0
+    for p in gen_passes(prog):
+        R, store, P, Q = layout(p)
+        total += m * n * 8 * (2 if store else 1)
+        vec = R * (m + n) + P * (n + m) + Q * (m + n)
+        vec += sum(m for r in p.rows if r.get("add") is not None)
+        vec += sum(n for c in p.cols if c.get("add") is not None)
+        total += 8 * vec
+    return total
+
+
+def _tune_main(names, n, table_path) -> int:
+    import json
+    import time
+
+    import torch
+
+    from . import bto_specs, tune as tuner
+
+    dev = torch.device("cuda:0")
+    table = {}
+    if os.path.exists(table_path):
+        with open(table_path) as f:
+            table = json.load(f)
+    for name in names:
+        prog = compile_spec(bto_specs.GENERATED[name], target="generated")
+        bound = synthetic_bound(prog, n, dev)
+        t0 = time.perf_counter()
+        res = tune(prog, bound, log=lambda r: print(json.dumps({name: r}), flush=True))
+        res.update({"digest": digest(emit(prog)), "n": n,
+                    "environment": tuner.environment_key(digest=digest(emit(prog))),
+                    "search_s": round(time.perf_counter() - t0, 1)})
+        table[prog.name] = res
+        print(json.dumps({prog.name: res}), flush=True)
+        del bound
+        torch.cuda.empty_cache()
+    with open(table_path, "w") as f:
+        json.dump(table, f, indent=1, sort_keys=True)
+    return 0
+
+
 if __name__ == "__main__":
-    raise SystemExit(main())
+    # run as the package's module, so that its ctypes types are the ones
+    # the runtime (btoc_run) builds
+    from paper_1205_1098_amd.btoc_gen import main as _main
+
+    raise SystemExit(_main())

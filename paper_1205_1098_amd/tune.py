@@ -144,7 +144,7 @@ class Tuner:
     the measurement; results are cached by organism key."""
 
     def __init__(self, space: Space, evaluate, cache_path: str | None = None, seed: int = 0,
-                 prune: float = 0.25):
+                 prune: float = 0.25, env_key: str = ""):
         self.space = space
         self.prune = prune
         self._kernel, self._m, self._n = None, 1024, 1024   # the GA's current problem
@@ -153,9 +153,14 @@ class Tuner:
         self.cache: dict = {}
         self.rng = random.Random(seed)
         self.evaluations = 0
+        # a cache measured on another device, ROCm or build of the library
+        # is not reused: its fitness values describe other code
+        self.env_key = env_key
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
-                self.cache = json.load(f).get("fitness", {})
+                data = json.load(f)
+            if data.get("environment", "") == env_key:
+                self.cache = data.get("fitness", {})
 
     # ---- bookkeeping -------------------------------------------------------
     def fitness(self, kernel: str, m: int, n: int, org: Organism) -> float:
@@ -168,7 +173,7 @@ class Tuner:
     def save(self, extra: dict | None = None) -> None:
         if not self.cache_path:
             return
-        data = {"fitness": self.cache}
+        data = {"fitness": self.cache, "environment": self.env_key}
         if extra:
             data.update(extra)
         tmp = self.cache_path + ".tmp"
@@ -283,6 +288,104 @@ class Tuner:
         return best
 
 
+# ---- genomes of generated programs ----------------------------------------------------
+
+def mfga_genes(choices: list, fitness, start=None, population: int = 20, generations: int = 6,
+               k: int = 2, mutation_rate: float = 0.3, seed: int = 0) -> tuple:
+    """The MFGA of Section IV over a genome of independent genes, gene i
+    taking values in choices[i] (for generated programs: one (tile shape,
+    band height) per pass).  Starts from `start` (the max-fuse organism's
+    default geometry), seeds the population with its mutations, evolves it
+    by tournaments of k and per-gene crossover (the best so far kept), then
+    refines the winner one gene at a time over all its values.
+    `fitness(genome) -> seconds` (infinity for a genome that cannot run or
+    gives wrong results); each genome is measured once.  Returns (best
+    genome, its fitness, genomes measured)."""
+    rng = random.Random(seed)
+    cache: dict = {}
+
+    def fit(g):
+        g = tuple(g)
+        if g not in cache:
+            cache[g] = float(fitness(g))
+        return cache[g]
+
+    def mutate(g):
+        g = list(g)
+        i = rng.randrange(len(g))
+        shape, rb = g[i]
+        kind = rng.randrange(3)
+        opts = choices[i]
+        if kind == 0:                                   # the partition level (band height)
+            pool = [c for c in opts if c[0] == shape and c[1] != rb]
+        elif kind == 1:                                 # the partition axis (tile shape)
+            same = [c for c in opts if c[0] != shape and c[1] == rb]
+            pool = same or [c for c in opts if c[0] != shape]
+        else:                                           # anything else
+            pool = [c for c in opts if c != (shape, rb)]
+        if pool:
+            g[i] = rng.choice(pool)
+        return tuple(g)
+
+    def crossover(a, b):
+        return tuple(rng.choice((x, y)) for x, y in zip(a, b))
+
+    start = tuple(start) if start is not None else tuple(c[0] for c in choices)
+    pop = [start] + [mutate(start) for _ in range(population - 1)]
+    best = min(pop, key=fit)
+    for _ in range(generations):
+        parents = [min((rng.choice(pop) for _ in range(k)), key=fit)
+                   for _ in range(2 * population)]
+        pop = [best]                                    # the best so far survives
+        for i in range(population - 1):
+            child = crossover(parents[2 * i], parents[2 * i + 1])
+            if rng.random() < mutation_rate:
+                child = mutate(child)
+            pop.append(child)
+        best = min(pop, key=fit)
+    # refinement: each gene in turn over all its values, the others fixed
+    # (the orthogonal search of Section V-D1), until nothing improves; the
+    # paper's final sweep of the thread count is the band heights' share
+    improved = True
+    while improved:
+        improved = False
+        for i in range(len(best)):
+            for c in choices[i]:
+                trial = best[:i] + (c,) + best[i + 1:]
+                if fit(trial) < fit(best):
+                    best, improved = trial, True
+    return best, fit(best), len(cache)
+
+
+def environment_key(bto=None, digest: str = "") -> str:
+    """What a measured fitness depends on besides the configuration: the
+    device architecture, the ROCm version and a digest of the code timed.
+    Caches keyed with it are not reused on another box or build."""
+    arch, rocm = "cpu", "none"
+    try:
+        import torch
+        if torch.cuda.is_available():
+            arch = torch.cuda.get_device_properties(0).gcnArchName
+        rocm = str(getattr(torch.version, "hip", None) or "none")
+    except Exception:
+        pass
+    if not digest and bto is not None:
+        digest = library_digest(bto)
+    return f"{arch}|rocm {rocm}|{digest}"
+
+
+def library_digest(bto) -> str:
+    """Digest of the library's kernel sources (what a timing depends on)."""
+    import hashlib
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
 def bucket_evaluator(single, groups: dict):
     """Fitness for a size bucket: the summed time over the bucket's sample
     sizes (groups maps the bucket's largest sample to all of them), so a
@@ -360,24 +463,51 @@ def apply(bto, org: Organism, size: int = 0) -> None:
         bto.tune_set(slot, *c, size=size)
 
 
+def outputs_agree(got: list, ref: list, tol: float = 1e-12) -> bool:
+    """Every output within `tol` normwise relative error of the reference
+    (absolute where the reference is all zero); NaN never agrees."""
+    for g, r in zip(got, ref):
+        if g.numel() == 0:
+            continue
+        den = float(r.abs().max())
+        num = float((g - r).abs().max())
+        err = num / den if den > 0 else num
+        if not err <= tol:
+            return False
+    return True
+
+
 def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3, keep: int = 4):
     """An evaluate() that times one call of a kernel on the current device.
-    `make_workload(kernel, m, n)` returns an object with run(form); the last
-    `keep` workloads stay resident."""
+    `make_workload(kernel, m, n)` returns an object with run(form) and
+    outputs(); the last `keep` workloads stay resident.  Every timed
+    variant's outputs are compared with those of the library's default
+    configuration (fused form) on the same inputs: a variant that disagrees
+    beyond 1e-12, or that the library refuses or that fails, scores
+    infinity and is never chosen."""
     cache = {}
+    refs = {}
 
     def evaluate(kernel, m, n, org):
         key = (kernel, m, n)
         if key not in cache:
             if len(cache) >= keep:
-                cache.pop(next(iter(cache)))
+                old = next(iter(cache))
+                cache.pop(old)
+                refs.pop(old, None)
                 torch.cuda.empty_cache()
             cache[key] = make_workload(kernel, m, n)
         wl = cache[key]
+        if key not in refs:
+            wl.run("fused")
+            torch.cuda.synchronize()
+            refs[key] = [t.clone() for t in wl.outputs()]
         size = max(m, n)
         saved = {s: bto.tune_get(s, size) for s, _ in org.slots}
         try:
             apply(bto, org, size)
+            for t in wl.outputs():
+                t.fill_(float("nan"))
             for _ in range(warmup):
                 wl.run(org.form)
             start = torch.cuda.Event(enable_timing=True)
@@ -387,7 +517,11 @@ def gpu_evaluator(bto, torch, make_workload, reps: int = 10, warmup: int = 3, ke
                 wl.run(org.form)
             stop.record()
             stop.synchronize()
+            if not outputs_agree(wl.outputs(), refs[key]):
+                return float("inf")
             return start.elapsed_time(stop) / reps * 1e-3
+        except (bto.BtoError, RuntimeError):
+            return float("inf")
         finally:
             for s, c in saved.items():
                 bto.tune_set(s, *c, size=size)
@@ -419,6 +553,15 @@ class _MatrixWorkload:
             self.y, self.z, self.x, self.w = vm(1), vn(2), vn(3), vm(4)
         self.ws = {f: torch.empty(max(1, bto.workspace_bytes(kernel, m, n, f)),
                                   dtype=torch.uint8, device=dev) for f in FORMS}
+
+    def outputs(self):
+        if self.kernel == "gemver":
+            return [self.B, self.x, self.w]
+        if self.kernel == "bicgk":
+            return [self.q, self.s]
+        if self.kernel == "atax":
+            return [self.y]
+        return [self.x, self.w]
 
     def run(self, form):
         b, ws = self.bto, self.ws[form]
@@ -520,7 +663,8 @@ def main(argv=None) -> int:
         shapes = [(n, n) for n in groups]
     else:
         shapes = [(args.m, args.n)]
-    tuner = Tuner(space, ev, args.cache, args.seed, args.prune)
+    tuner = Tuner(space, ev, args.cache, args.seed, args.prune,
+                  env_key=environment_key(bto))
     best = {}
     for m, n in shapes:
         for k in args.kernels:
@@ -557,6 +701,10 @@ def _tune_batch_main(torch, bto, args) -> int:
     from paper_1205_1098_amd import batch
 
     sets = {}
+    refs = {}
+
+    def outs(insts):
+        return [t for inst in insts for t in inst["out"]]
 
     def evaluate(cfg):
         form = cfg["form"]
@@ -566,7 +714,17 @@ def _tune_batch_main(torch, bto, args) -> int:
             sets[form] = batch.make_instances(torch, bto, 4096, 64, 2048,
                                               {"gemver": 0.5, "bicgk": 0.5},
                                               form="fused" if form == "tiled" else form)
+            if "ref" not in refs:
+                # the reference outputs: the persistent plan's defaults
+                # (the instances of every form are generated alike)
+                ref_plan = bto.BatchPlan(sets[form][0])
+                ref_plan.launch()
+                ref_plan.check()
+                refs["ref"] = [t.clone() for t in outs(sets[form][0])]
+                ref_plan.close()
         insts, _ = sets[form]
+        for t in outs(insts):
+            t.fill_(float("nan"))
         try:
             if form == "tiled":
                 plan = bto.TiledBatch(insts, config=bto.TiledConfig.default(
@@ -586,21 +744,31 @@ def _tune_batch_main(torch, bto, args) -> int:
             plan.launch()
         b.record()
         b.synchronize()
+        ok = outputs_agree(outs(insts), refs["ref"])
+        if form != "tiled":
+            try:
+                plan.check()
+            except bto.BtoError:
+                ok = False
         plan.close()
-        sec = a.elapsed_time(b) / 5 * 1e-3
-        print(json.dumps({"cfg": cfg, "ms": round(sec * 1e3, 3)}), flush=True)
+        sec = a.elapsed_time(b) / 5 * 1e-3 if ok else float("inf")
+        print(json.dumps({"cfg": cfg, "ms": round(sec * 1e3, 3), "checked": ok}), flush=True)
         return sec
 
+    env = environment_key(bto)
     cache = {}
     if args.cache and os.path.exists(args.cache):
         with open(args.cache) as f:
-            cache = json.load(f).get("batch_fitness", {})
+            data = json.load(f)
+        if data.get("environment") == env:
+            cache = data.get("batch_fitness", {})
     best, sec, evals = tune_batch(evaluate, cache=cache)
     out = {"best": best, "ms": round(sec * 1e3, 3), "evaluations": evals}
     print(json.dumps(out), flush=True)
     if args.cache:
         with open(args.cache, "w") as f:
-            json.dump({"batch_fitness": cache, "batch_best": out}, f, indent=1, sort_keys=True)
+            json.dump({"batch_fitness": cache, "batch_best": out, "environment": env}, f,
+                      indent=1, sort_keys=True)
     return 0
 
 

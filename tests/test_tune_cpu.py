@@ -338,3 +338,56 @@ def test_batch_knobs_search_the_winning_forms_knobs():
     assert all(c["threads"] == tune.BATCH_SPACE["threads"][0] for c in seen)
     assert tune.tiled_config_of(best)["store_shape"] == 3
     assert set(tune.tiled_config_of(best)) == {k[2:] for k in tune.TILED_KNOBS}
+
+
+def test_mfga_genes_finds_the_optimum_and_skips_failures():
+    """The genome search over per-pass (shape, band height) genes: from the
+    start genome it reaches the optimum of a separable cost, never keeps a
+    genome scored infinite (refused or wrong), and measures each genome
+    once."""
+    choices = [[(s, rb) for s in range(4) for rb in (8, 16, 32, 64)] for _ in range(3)]
+    target = ((2, 32), (1, 8), (3, 64))
+    seen = []
+
+    def cost(g):
+        seen.append(g)
+        if g[0] == (0, 64):
+            return float("inf")
+        return sum(abs(a[0] - b[0]) + abs(a[1] - b[1]) / 8 for a, b in zip(g, target)) + 1.0
+
+    best, fit, evals = tune.mfga_genes(choices, cost, start=((0, 8),) * 3, population=20,
+                                       generations=8, seed=5)
+    assert best == target and fit == pytest.approx(1.0)
+    assert len(seen) == len(set(seen)) == evals
+    assert seen[0] == ((0, 8),) * 3
+    again, _, _ = tune.mfga_genes(choices, cost, start=((0, 8),) * 3, population=20,
+                                  generations=8, seed=5)
+    assert again == best                                   # seeded: reproducible
+
+
+def test_outputs_agree():
+    torch = pytest.importorskip("torch")
+    ref = [torch.tensor([1.0, -2.0, 4.0], dtype=torch.float64),
+           torch.zeros(2, dtype=torch.float64)]
+    assert tune.outputs_agree([r.clone() for r in ref], ref)
+    near = [ref[0] * (1 + 1e-14), ref[1] + 1e-13]
+    assert tune.outputs_agree(near, ref)
+    assert not tune.outputs_agree([ref[0] * (1 + 1e-10), ref[1]], ref)
+    assert not tune.outputs_agree([torch.tensor([1.0, float("nan"), 4.0], dtype=torch.float64),
+                                   ref[1]], ref)
+
+
+def test_cache_is_keyed_by_environment(tmp_path):
+    """A fitness cache written under one device/ROCm/library key is reused
+    under the same key and ignored under another."""
+    sp = fake_space()
+    path = str(tmp_path / "cache.json")
+    t = tune.Tuner(sp, Counter(), cache_path=path, env_key="gfx950|rocm 7|abc")
+    org = t.max_fuse("bicgk")
+    t.fitness("bicgk", 64, 64, org)
+    t.save()
+    same = tune.Tuner(sp, Counter(), cache_path=path, env_key="gfx950|rocm 7|abc")
+    assert same.cache
+    other = tune.Tuner(sp, Counter(), cache_path=path, env_key="gfx950|rocm 7|def")
+    assert not other.cache
+    assert "|" in tune.environment_key(digest="x") and tune.library_digest(None)
