@@ -509,7 +509,8 @@ def bench_generated_passes(torch, bto, n: int = N) -> dict:
 
 def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
-    fair seeded coin) in one graph-captured persistent launch."""
+    fair seeded coin) in one graph-captured persistent launch, then as tiled
+    batches."""
     from paper_1205_1098_amd import batch
 
     insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
@@ -528,8 +529,9 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         checked = False
     persistent = outs()
     plan.close()
-    # the same instances as short-lived workgroup tiles: GEMVER's chain and
-    # BiCGK's as two branches of one graph, under the tuned configuration
+    # the same instances as short-lived workgroup tiles (GEMVER's first
+    # sweeps and BiCGK's in one launch, then the finishes and GEMVER's second
+    # sweeps), under the tuned configuration
     for inst in insts:
         for t in inst["out"]:
             t.fill_(float("nan"))
@@ -580,6 +582,8 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
             "pct_peak": round(100 * total / sec_tiled / 1e9 / PEAK_GBS, 1),
             "speedup_vs_persistent": round(sec / sec_tiled, 3),
             "config": tiled_cfg.as_dict(),
+            "traffic": counter_traffic("tiled_batch_mixed4096_counters.txt")
+            if count == 4096 else None,
         },
         "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
         "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,

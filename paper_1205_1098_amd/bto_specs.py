@@ -65,15 +65,12 @@ out: x : vector(column)
 }""",
 }
 
-# Fig. 1, as printed (declarations over several lines)
+# BATAX, the running example of Section II (Fig. 1): y = beta A^T A x
 BATAX = """BATAX
-in:
-    x : vector(column), beta : scalar,
-    A : matrix(row)
-out:
-    y : vector(column)
+in:  A : matrix(row), x : vector(column), beta : scalar
+out: y : vector(column)
 {
-    y = beta * A' * (A * x)
+  y = beta * A' * (A * x)
 }"""
 
 GEMVER_CONTRACTED = """GEMVERC

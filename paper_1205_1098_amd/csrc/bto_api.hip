@@ -1963,15 +1963,17 @@ struct bto_tiled_batch {
 
 namespace {
 
-// Defaults from the tiled-batch search (4096 mixed GEMVER/BiCGK instances,
-// n log-uniform on [64, 2048], MI355X): GEMVER's first sweeps in tiles of
-// 64 rows by 256 columns (8 waves, two 16-byte pairs per lane, two rows in
-// flight per wave), the read-only sweeps in 64-row tiles of 256 columns for
-// matrices up to 512 columns wide and of 1024 columns (16 waves) above,
-// one workgroup per tile.  The best dozen configurations were within 1.5%.
+// Defaults from the tiled-batch search (tune.py --batch: 4096 mixed
+// GEMVER/BiCGK instances, n log-uniform on [64, 2048], MI355X): the first
+// sweeps (GEMVER's with BiCGK's) in tiles of 128 rows by 256 columns (8
+// waves down, two 16-byte pairs per lane, two rows in flight per wave);
+// GEMVER's second sweeps in 64-row tiles of 256 columns for matrices up to
+// 512 columns wide and of 512 columns (2 waves, each sweeping the whole
+// band) above; one workgroup per tile.  The best dozen configurations were
+// within 1.5% of each other.
 constexpr bto_tiled_config kTiledDefaults = {
-    /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 1, /*narrow_n*/ 512,
-    /*store_rb*/ 64, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
+    /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 7, /*narrow_n*/ 512,
+    /*store_rb*/ 128, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
 constexpr int kTiledFinishWgsPerCu = 8;
 constexpr int kTiledRefillWgsPerCu = 2;   // refillable plans made with the defaults
 

@@ -24,8 +24,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # what defines a measured kernel: its device code, the shared device helpers
 # and launch declarations, and (matrix sweeps) the tuned configurations
 SOURCE_SETS = {
-    "matrix": ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_dev.hpp",
+    "matrix": ["paper_1205_1098_amd/csrc/bto_mat.hip", "paper_1205_1098_amd/csrc/bto_tile.hpp",
+               "paper_1205_1098_amd/csrc/bto_dev.hpp",
                "paper_1205_1098_amd/csrc/bto_internal.hpp", "paper_1205_1098_amd/csrc/bto_tuned.hpp"],
+    "tiled": ["paper_1205_1098_amd/csrc/bto_btile.hip", "paper_1205_1098_amd/csrc/bto_tile.hpp",
+              "paper_1205_1098_amd/csrc/bto_dev.hpp", "paper_1205_1098_amd/csrc/bto_internal.hpp",
+              "paper_1205_1098_amd/csrc/bto_api.hip"],
     "vector": ["paper_1205_1098_amd/csrc/bto_vec.hip", "paper_1205_1098_amd/csrc/bto_dev.hpp",
                "paper_1205_1098_amd/csrc/bto_internal.hpp"],
     "batch": ["paper_1205_1098_amd/csrc/bto_batch.hip", "paper_1205_1098_amd/csrc/bto_batch.hpp",

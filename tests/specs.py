@@ -56,4 +56,23 @@ out: z : vector(column)
 {
   z = -A * x + y - alpha * w
 }""",
+    # scaled sums longer than one pass takes (eight terms): the sum so far
+    # carries into the next pass
+    "lin9": """LIN9
+in:  a1 : vector(column), a2 : vector(column), a3 : vector(column), a4 : vector(column),
+     a5 : vector(column), a6 : vector(column), a7 : vector(column), a8 : vector(column),
+     a9 : vector(column), c : scalar
+out: x : vector(column)
+{
+  x = a1 + 2 * a2 - a3 + c * a4 + a5 - 3 * a6 + a7 + a8 - c * a9
+}""",
+    "lin16": """LIN16
+in:  b1 : vector(column), b2 : vector(column), b3 : vector(column), b4 : vector(column),
+     b5 : vector(column), b6 : vector(column), b7 : vector(column), b8 : vector(column),
+     b9 : vector(column), b10 : vector(column), b11 : vector(column), b12 : vector(column),
+     b13 : vector(column), b14 : vector(column), b15 : vector(column), b16 : vector(column)
+out: x : vector(column)
+{
+  x = b1 + b2 + b3 + b4 + b5 + b6 + b7 + b8 + b9 + b10 + b11 + b12 + b13 + b14 + b15 - b16
+}""",
 }

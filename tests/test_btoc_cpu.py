@@ -54,7 +54,7 @@ def test_fig1_batax_is_one_row_resident_pass():
     the whole kernel is one pass (the max-fuse organism of Section IV-A);
     unfused, the temporary A x is stored and read back."""
     prog = btoc.compile_spec(specs.BATAX)
-    assert prog.name == "BATAX" and prog.inputs == ["x", "beta", "A"] and prog.outputs == ["y"]
+    assert prog.name == "BATAX" and prog.inputs == ["A", "x", "beta"] and prog.outputs == ["y"]
     assert prog.describe() == ["pass 0: A CHAIN|ROWDOT|COLSUM"]
     assert prog.temps == []
     unf = btoc.compile_spec(specs.BATAX, "unfused")
@@ -79,7 +79,35 @@ NOVEL_SCHEDULES = {
     "two_dots": ["pass 0: A ROWDOT", "pass 1: A ROWDOT"],
     "mixed": ["vec 0: _s1 = a*y + b*w", "pass 0: A ROWDOT"],
     "lin4": ["lincomb 0: x = c*w + c*y + c*z + c*v"],
+    "lin9": ["lincomb 0: x = " + " + ".join(f"c*a{k}" for k in range(1, 9)),
+             "lincomb 0: x = c*x + c*a9"],
+    "lin16": ["lincomb 0: x = " + " + ".join(f"c*b{k}" for k in range(1, 9)),
+              "lincomb 0: x = c*x + " + " + ".join(f"c*b{k}" for k in range(9, 16)),
+              "lincomb 0: x = c*x + c*b16"],
 }
+
+
+def test_declarations_over_several_lines():
+    """A declaration list may break after a comma and resume on the next
+    line; without the comma the next line is not part of the list."""
+    prog = btoc.compile_spec("""DOTS
+in:
+    u : vector(column),
+    w : vector(column),
+    s : scalar
+out:
+    r : scalar
+{
+    r = u' * w
+}""")
+    assert prog.inputs == ["u", "w", "s"] and prog.outputs == ["r"]
+    with pytest.raises(btoc.SpecError):
+        btoc.compile_spec("""DOTS
+in:
+    u : vector(column)
+    w : vector(column)
+out: r : scalar
+{ r = u' * w }""")
 
 
 @pytest.mark.parametrize("name", sorted(NOVEL_SCHEDULES))
@@ -304,3 +332,30 @@ def test_command_line(capsys, tmp_path):
     assert "pass 1: A ROWDOT" in capsys.readouterr().out
     f.write_text("K\nin: x : vector(column)\nout: y : vector(column)\n{ y = z }")
     assert btoc.main([str(f)]) == 1
+
+
+def test_bound_output_over_an_input_is_refused():
+    """An output bound to memory an input also uses is refused before
+    anything runs (it would be written while the input is still read); a
+    matrix update bound to exactly the matrix it updates is the in-place
+    form and is accepted up to the first library call."""
+    torch = pytest.importorskip("torch")
+    prog = btoc.compile_spec(specs.NOVEL["lin9"])
+    vecs = {f"a{k}": torch.zeros(16, dtype=torch.float64) for k in range(1, 10)}
+    with pytest.raises(btoc.SpecError, match="shares memory"):
+        prog.run(c=1.5, x=vecs["a9"], **vecs)
+    buf = torch.zeros(40, dtype=torch.float64)
+    vecs["a3"] = buf[:16]
+    with pytest.raises(btoc.SpecError, match="shares memory"):
+        prog.run(c=1.5, x=buf[10:26], **vecs)
+    g = btoc.compile_spec(specs.TABLE_I["gemver"])
+    A = torch.zeros((8, 8), dtype=torch.float64)
+    ins = {k: torch.zeros(8, dtype=torch.float64) for k in ("u1", "v1", "u2", "v2", "y", "z")}
+    with pytest.raises(btoc.SpecError, match="shares memory"):
+        g.run(A=A, B=A[:, :], x=ins["z"], alpha=1.5, beta=0.7, **ins)   # x over input z
+    try:
+        g.run(A=A, B=A, alpha=1.5, beta=0.7, **ins)                   # in place: not refused
+    except btoc.SpecError as e:
+        pytest.fail(f"in-place update refused: {e}")
+    except Exception:
+        pass          # no device here: the first library call fails, as it must

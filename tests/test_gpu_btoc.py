@@ -49,6 +49,8 @@ PROGRAMS = {
     "two_dots": (specs.NOVEL["two_dots"], dict(A="A", x="n"), True),
     "mixed": (specs.NOVEL["mixed"], dict(A="A", x="n", y="m", w="m", alpha=0.5), False),
     "lin4": (specs.NOVEL["lin4"], dict(w="n", y="n", z="n", v="n", a=1.5), False),
+    "lin9": (specs.NOVEL["lin9"], dict({f"a{k}": "n" for k in range(1, 10)}, c=1.5), False),
+    "lin16": (specs.NOVEL["lin16"], {f"b{k}": "n" for k in range(1, 17)}, False),
 }
 SHAPES = [(1, 1), (65, 127), (513, 1000), (300, 4097), (2047, 2049)]
 SQUARE = [(1, 1), (127, 127), (1000, 1000), (2049, 2049)]
