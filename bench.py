@@ -33,7 +33,7 @@ step, in GB/s.  Rank 0 prints one JSON line with, besides the headline:
 
 Usage: python bench.py [--steps K] [--warmup W] [--workload gemver|bicgk|...]
        [--no-suite] [--no-cpu] [--no-stream] [--no-batch] [--no-serve]
-       [--batch-direct] [--no-batch-loop] [--copy-probe]
+       [--batch-direct] [--no-batch-loop] [--copy-probe] [--row-lengths]
 """
 
 from __future__ import annotations
@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=1000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 2 GiB copy probe (calibrates hardware byte counters)")
+    ap.add_argument("--row-lengths", action="store_true",
+                    help="only time the first sweeps per row length: tiled batches of one size "
+                         "and one kind, and single tall matrices of the same row length")
     return ap.parse_args()
 
 
@@ -95,6 +98,93 @@ def copy_probe(torch, bto, reps: int = 3) -> int:
     torch.cuda.synchronize()
     print(json.dumps({"probe": "copy", "doubles": n, "read_bytes": n * 8, "write_bytes": n * 8,
                       "launches": reps}), flush=True)
+    return 0
+
+
+def tiled_group_ms(torch, bto, insts, cfg, steps: int = 5) -> dict:
+    """Mean time per launch of each group of a tiled batch (first sweeps,
+    their sums, second sweeps, their sums), from HIP events around each
+    launch on its stream; the plan runs without its graph here so that every
+    launch is seen."""
+    conf = bto.TiledConfig.default(**{**cfg.as_dict(), "use_graph": 0})
+    t = bto.TiledBatch(insts, config=conf)
+    t.launch()
+    torch.cuda.synchronize()
+    bto.timing_reset()
+    bto.timing_enable(True)
+    for _ in range(steps):
+        t.launch()
+    torch.cuda.synchronize()
+    bto.timing_enable(False)
+    times = bto.timing_read()
+    bto.timing_reset()
+    t.close()
+    return {k: round(ms / c, 4) for k, (c, ms) in sorted(times.items())
+            if c and k.startswith("bt_")}
+
+
+ROW_LENGTHS = (256, 512, 1000, 1500, 2000)
+
+
+def row_length_probe(torch, bto, budget: float = 2.5e9) -> int:
+    """The first sweeps at one row length at a time: tiled batches of
+    GEMVER-only and of BiCGK-only n x n instances (about `budget` matrix
+    bytes each, rows 64-byte aligned as in the mixed batch), next to the
+    single-instance sweeps of one tall m x n matrix with the same row length
+    and stride.  GB/s count matrix bytes only (GEMVER's first sweep reads A
+    and writes B; BiCGK's reads A)."""
+    from paper_1205_1098_amd import batch
+
+    dev = torch.device("cuda:0")
+    cfg = bto.TiledConfig.default(use_graph=0)
+    out = {}
+    for n in ROW_LENGTHS:
+        ent = {}
+        for kind, per in (("gemver", 16 * n * n), ("bicgk", 8 * n * n)):
+            count = max(1, int(budget // per))
+            insts, _ = batch.make_instances(torch, bto, count, 64, 2048, {kind: 1.0}, config=4,
+                                            shapes=[(n, n)] * count)
+            ms = tiled_group_ms(torch, bto, insts, cfg)
+            ent[f"batch_{kind}"] = {"instances": count, "first_sweep_ms": ms["bt_first"],
+                                    "gbs": round(count * per / ms["bt_first"] / 1e6, 1)}
+            del insts
+            torch.cuda.empty_cache()
+        m = int(budget // (16 * n))
+        lda = batch._lda(n)
+        A = torch.empty((m, lda), dtype=torch.float64, device=dev)[:, :n]
+        B = torch.empty((m, lda), dtype=torch.float64, device=dev)[:, :n]
+        bto.synth_fill(A, 1)
+        vm = [torch.rand(m, dtype=torch.float64, device=dev) for _ in range(3)]
+        vn = [torch.rand(n, dtype=torch.float64, device=dev) for _ in range(3)]
+        x = torch.empty(n, dtype=torch.float64, device=dev)
+        w = torch.empty(m, dtype=torch.float64, device=dev)
+        q = torch.empty(m, dtype=torch.float64, device=dev)
+        run_g = lambda: bto.gemver(A, vm[0], vn[0], vm[1], vn[1], vm[2], vn[2], 1.5, 0.7, B=B,
+                                   x=x, w=w)
+        run_b = lambda: bto.bicgk(A, vn[0], vm[0], q=q, s=x)
+        for name, fn, per in (("single_gemver_p1", run_g, 16 * m * n),
+                              ("single_bicgk", run_b, 8 * m * n)):
+            fn()
+            torch.cuda.synchronize()
+            bto.timing_reset()
+            bto.timing_enable(True)
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize()
+            bto.timing_enable(False)
+            times = bto.timing_read()
+            bto.timing_reset()
+            key = "gemver_p1" if name == "single_gemver_p1" else max(
+                (k for k in times if k.startswith("bicgk")), key=lambda k: times[k][1])
+            c, tot = times[key]
+            ent[name] = {"rows": m, "kernel": key, "ms": round(tot / c, 4),
+                         "gbs": round(per / (tot / c) / 1e6, 1)}
+        del A, B, vm, vn, x, w, q
+        torch.cuda.empty_cache()
+        out[str(n)] = ent
+        print(f"row length {n}: {json.dumps(ent)}", file=sys.stderr, flush=True)
+    print(json.dumps({"probe": "row_lengths", "budget_bytes": budget, "results": out}),
+          flush=True)
     return 0
 
 
@@ -516,7 +606,14 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
     insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
                                         {"gemver": 0.5, "bicgk": 0.5}, config=4)
     total = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in specs)
-    outs = lambda: [t.clone() for inst in insts for t in inst["out"]]
+    out_list = [t for inst in insts for t in inst["out"]]
+    # every output array flattened into one buffer, and each element's array
+    # index: the comparison below is a handful of launches, not one per array
+    outs = lambda: torch.cat([t.reshape(-1) for t in out_list])
+    seg = torch.repeat_interleave(
+        torch.arange(len(out_list), device=out_list[0].device),
+        torch.tensor([t.numel() for t in out_list], device=out_list[0].device))
+    print(f"batched: {count} instances built", file=sys.stderr, flush=True)
     plan = bto.BatchPlan(insts, use_graph=graph)
     sec, sec_min = time_stats(torch, plan.launch, 10, 2)
     # the last timed launch completed every bounded wait (raises otherwise),
@@ -529,27 +626,32 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         checked = False
     persistent = outs()
     plan.close()
+    print("batched: persistent plan timed", file=sys.stderr, flush=True)
     # the same instances as short-lived workgroup tiles (GEMVER's first
     # sweeps and BiCGK's in one launch, then the finishes and GEMVER's second
-    # sweeps), under the tuned configuration
-    for inst in insts:
-        for t in inst["out"]:
-            t.fill_(float("nan"))
+    # sweeps), under the tuned configuration; outputs start as NaN
+    torch._foreach_zero_(out_list)
+    torch._foreach_add_(out_list, float("nan"))
     tiled_cfg = bto.TiledConfig.default(use_graph=1 if graph else 0)
     tiled = bto.TiledBatch(insts, config=tiled_cfg)
     sec_tiled, sec_tiled_min = time_stats(torch, tiled.launch, 10, 2)
     torch.cuda.synchronize()
     tiled_outs = outs()
     tiled.close()
+    group_ms = tiled_group_ms(torch, bto, insts, tiled_cfg)
+    print("batched: tiled batch timed", file=sys.stderr, flush=True)
     # the two forms add in different orders: they agree to the parity
-    # tolerance (each is checked against the oracle by the GPU tests)
-    worst = 0.0
-    for a, b in zip(persistent, tiled_outs):
-        den = float(a.abs().max()) if a.numel() else 0.0
-        num = float((a - b).abs().max()) if a.numel() else 0.0
-        err = num / den if den > 0 else num
-        worst = max(worst, err if err == err else float("inf"))
-    del persistent, tiled_outs
+    # tolerance (each is checked against the oracle by the GPU tests);
+    # per array, max |difference| over max |persistent|
+    k = len(out_list)
+    amax = lambda v: torch.zeros(k, dtype=v.dtype, device=v.device).scatter_reduce(
+        0, seg, v, "amax", include_self=True)
+    den = amax(persistent.abs())
+    num = amax((persistent - tiled_outs).abs())
+    rel = torch.where(den > 0, num / torch.where(den > 0, den, 1.0), num)
+    nan = bool(torch.isnan(tiled_outs).any() or torch.isnan(persistent).any())
+    worst = float("inf") if nan else float(rel.max())
+    del persistent, tiled_outs, seg
     # the same instances launched one entry-point call at a time
     def loop():
         for inst in insts:
@@ -582,6 +684,9 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
             "pct_peak": round(100 * total / sec_tiled / 1e9 / PEAK_GBS, 1),
             "speedup_vs_persistent": round(sec / sec_tiled, 3),
             "config": tiled_cfg.as_dict(),
+            "launch_ms": group_ms,
+            "launch_ms_how": "mean per launch of each group, HIP events around each launch, "
+                             "plan run without its graph in a separate loop",
             "traffic": counter_traffic("tiled_batch_mixed4096_counters.txt")
             if count == 4096 else None,
         },
@@ -682,6 +787,8 @@ def main() -> int:
 
     if args.copy_probe:
         return copy_probe(torch, bto)
+    if args.row_lengths:
+        return row_length_probe(torch, bto)
     dev = torch.device("cuda:0")
     props = torch.cuda.get_device_properties(0)
     shared = {}

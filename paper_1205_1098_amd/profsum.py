@@ -6,7 +6,9 @@
       --copy-write DB --kernel SUBSTR --label L --alg-bytes B --command CMD --out FILE
       HBM bytes per dispatch of one kernel from two --pmc runs (FETCH_SIZE, then
       WRITE_SIZE), each scaled by what the same counter reads for the 2 GiB copy
-      probe, whose bytes are known
+      probe, whose bytes are known; with --unit SUBSTR, the bytes of every
+      dispatch matching --kernel per dispatch matching SUBSTR (the launches of
+      a plan made of several kernels)
 
 The counter summary records the digest of the kernel sources; the benchmark
 only reports its traffic while the sources still match.
@@ -76,20 +78,42 @@ def trace_summary(db: str, label: str, command: str) -> str:
 
 
 def counters_summary(fetch: str, write: str, cfetch: str, cwrite: str, kernel: str,
-                     label: str, alg_bytes: float, command: str, sources: str = "matrix") -> str:
-    def per_dispatch(rows, sub):
+                     label: str, alg_bytes: float, command: str, sources: str = "matrix",
+                     unit: str | None = None) -> str:
+    """Without `unit`: the median per dispatch of the kernels matching
+    `kernel`.  With it: every dispatch matching `kernel` summed and divided
+    by the number of dispatches matching `unit` (one per launch of a
+    multi-kernel plan), with a per-kernel breakdown."""
+    def per_dispatch(rows, sub, unit=None):
         vals = [v for name, v in rows if sub in name]
         if not vals:
             raise SystemExit(f"no dispatch of a kernel matching {sub!r}")
-        return statistics.median(vals), len(vals)
+        if unit is None:
+            return statistics.median(vals), len(vals)
+        units = sum(1 for name, _ in rows if unit in name)
+        if not units:
+            raise SystemExit(f"no dispatch of a kernel matching {unit!r}")
+        return sum(vals) / units, units
 
     cf, _ = per_dispatch(_pmc(cfetch, "FETCH_SIZE"), "k_copy")
     cw, _ = per_dispatch(_pmc(cwrite, "WRITE_SIZE"), "k_copy")
     f_factor = COPY_BYTES / (cf * 1024.0)
     w_factor = COPY_BYTES / (cw * 1024.0)
-    kf, nf = per_dispatch(_pmc(fetch, "FETCH_SIZE"), kernel)
-    kw, nw = per_dispatch(_pmc(write, "WRITE_SIZE"), kernel)
+    kf, nf = per_dispatch(_pmc(fetch, "FETCH_SIZE"), kernel, unit)
+    kw, nw = per_dispatch(_pmc(write, "WRITE_SIZE"), kernel, unit)
     fb, wb = kf * 1024.0 * f_factor, kw * 1024.0 * w_factor
+    breakdown = []
+    if unit is not None:
+        fr, wr = _pmc(fetch, "FETCH_SIZE"), _pmc(write, "WRITE_SIZE")
+        names = sorted({name for name, _ in fr if kernel in name})
+        breakdown = ["", f"per launch (dispatches matching {kernel!r} per dispatch of {unit!r}):", ""]
+        for nm in names:
+            f1 = sum(v for n_, v in fr if n_ == nm) / nf * 1024.0 * f_factor
+            w1 = sum(v for n_, v in wr if n_ == nm) / nw * 1024.0 * w_factor
+            short = nm.replace("bto::(anonymous namespace)::", "").replace("void ", "")
+            short = short.split("(")[0]
+            breakdown.append(f"    {short}: {f1 / 1e9:.3f} GB fetched + {w1 / 1e9:.3f} GB written")
+        breakdown.append("")
     lines = [
         f"# HBM traffic per dispatch: {label}",
         "",
@@ -97,8 +121,11 @@ def counters_summary(fetch: str, write: str, cfetch: str, cwrite: str, kernel: s
         "",
         *("    " + c for c in command.split(" ;; ")),
         "",
+        *breakdown,
         f"kernel: {kernel}",
-        f"dispatches_measured: {nf} (FETCH_SIZE), {nw} (WRITE_SIZE)",
+        *([f"per_launch_of: {unit}"] if unit is not None else []),
+        f"{'launches' if unit is not None else 'dispatches'}_measured: {nf} (FETCH_SIZE), "
+        f"{nw} (WRITE_SIZE)",
         f"copy_probe_bytes: {COPY_BYTES}",
         f"copy_fetch_kib: {cf:.3f}",
         f"copy_write_kib: {cw:.3f}",
@@ -126,6 +153,9 @@ def main(argv=None) -> int:
     for a in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel"):
         c.add_argument(a, required=True)
     c.add_argument("--alg-bytes", type=float, required=True)
+    c.add_argument("--unit", default=None,
+                   help="sum the --kernel dispatches per dispatch of this kernel (one per "
+                        "launch of a multi-kernel plan)")
     c.add_argument("--sources", choices=sorted(SOURCE_SETS), default="matrix",
                    help="the source set whose digest the summary records")
     for p in (t, c):
@@ -138,7 +168,7 @@ def main(argv=None) -> int:
     else:
         text = counters_summary(args.fetch, args.write, args.copy_fetch, args.copy_write,
                                 args.kernel, args.label, args.alg_bytes, args.command,
-                                args.sources)
+                                args.sources, args.unit)
     with open(args.out, "w") as f:
         f.write(text)
     print(text)

@@ -391,3 +391,13 @@ def test_cache_is_keyed_by_environment(tmp_path):
     other = tune.Tuner(sp, Counter(), cache_path=path, env_key="gfx950|rocm 7|def")
     assert not other.cache
     assert "|" in tune.environment_key(digest="x") and tune.library_digest(None)
+
+
+def test_tiled_knobs_start_at_the_library_defaults():
+    """The first value of each tiled knob is the library's default, so the
+    search starts from the configuration the library runs without tuning."""
+    from paper_1205_1098_amd import bto
+
+    lib = bto.TiledConfig.default().as_dict()
+    assert {k: tune.BATCH_SPACE[k][0] for k in tune.TILED_KNOBS} == \
+        {k: lib[k[2:]] for k in tune.TILED_KNOBS}
