@@ -127,6 +127,19 @@ out: z1 : vector(column), z2 : vector(column), z3 : vector(column)
   z2 = A * x2 - y
   z3 = beta * alpha * A * x3
 }""",
+    "multimv5": """MULTIMV5
+in:  A : matrix(row), x1 : vector(column), x2 : vector(column), x3 : vector(column),
+     x4 : vector(column), x5 : vector(column), r : vector(column), alpha : scalar
+out: z1 : vector(column), z2 : vector(column), z3 : vector(column), z4 : vector(column),
+     z5 : vector(column), s : vector(column)
+{
+  z1 = A * x1
+  z2 = alpha * A * x2
+  z3 = A * x3
+  z4 = A * x4
+  z5 = A * x5
+  s = A' * r
+}""",
     "bicgk2c": """BICGK2C
 in:  A : matrix(column), p1 : vector(column), p2 : vector(column), r1 : vector(column),
      r2 : vector(column)

@@ -280,17 +280,34 @@ def _emit_pass(k: int, p: Pass, scalars: list) -> str:
         w("#pragma unroll")
         w("            for (int k = 0; k < KV; ++k)")
         w(f"                acc[{q}][k] += b[k] * sy{q};")
-    for q in range(P):
+    if P == 1:
         w("            {")
         w("                double s = 0.0;")
         w("#pragma unroll")
         w("                for (int k = 0; k < KV; ++k) {")
-        w(f"                    s += b[k].x * x{q}[k].x;")
-        w(f"                    s += b[k].y * x{q}[k].y;")
+        w("                    s += b[k].x * x0[k].x;")
+        w("                    s += b[k].y * x0[k].y;")
         w("                }")
         w("                s = wave_sum(s);")
         w("                if (lane == (int)(i - r0))")
-        w(f"                    mine[{q}] = s;")
+        w("                    mine[0] = s;")
+        w("            }")
+    elif P > 1:
+        # the row's dots reduced across the wave together
+        w("            {")
+        w(f"                double s[{P}], t[{P}];")
+        for q in range(P):
+            w(f"                s[{q}] = 0.0;")
+            w("#pragma unroll")
+            w("                for (int k = 0; k < KV; ++k) {")
+            w(f"                    s[{q}] += b[k].x * x{q}[k].x;")
+            w(f"                    s[{q}] += b[k].y * x{q}[k].y;")
+            w("                }")
+        w(f"                wave_sums<{P}>(s, t);")
+        w("                if (lane == (int)(i - r0)) {")
+        for q in range(P):
+            w(f"                    mine[{q}] = t[{q}];")
+        w("                }")
         w("            }")
     w("        }")
     w("    }")

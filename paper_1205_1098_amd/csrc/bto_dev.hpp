@@ -56,6 +56,77 @@ __device__ __forceinline__ double wave_sum(double v)
     return readlane_f64(v, 0) + readlane_f64(v, 32);
 }
 
+// The lane permutes of gfx950 that trade half-waves and rows between two
+// registers (each 32-bit half of a double separately).  swap32: x keeps its
+// lanes 0-31 and takes y's lanes 0-31 as its lanes 32-63; y takes x's lanes
+// 32-63 as its lanes 0-31 and keeps its own lanes 32-63.  swap16: the same
+// within each half-wave, with 16-lane rows.
+__device__ __forceinline__ void swap32_f64(double &x, double &y)
+{
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x), yb = __builtin_bit_cast(uint64_t, y);
+    const auto lo = __builtin_amdgcn_permlane32_swap(static_cast<uint32_t>(xb),
+                                                     static_cast<uint32_t>(yb), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(static_cast<uint32_t>(xb >> 32),
+                                                     static_cast<uint32_t>(yb >> 32), false, false);
+    x = __builtin_bit_cast(double, (static_cast<uint64_t>(hi[0]) << 32) | lo[0]);
+    y = __builtin_bit_cast(double, (static_cast<uint64_t>(hi[1]) << 32) | lo[1]);
+}
+
+__device__ __forceinline__ void swap16_f64(double &x, double &y)
+{
+    const uint64_t xb = __builtin_bit_cast(uint64_t, x), yb = __builtin_bit_cast(uint64_t, y);
+    const auto lo = __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(xb),
+                                                     static_cast<uint32_t>(yb), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(static_cast<uint32_t>(xb >> 32),
+                                                     static_cast<uint32_t>(yb >> 32), false, false);
+    x = __builtin_bit_cast(double, (static_cast<uint64_t>(hi[0]) << 32) | lo[0]);
+    y = __builtin_bit_cast(double, (static_cast<uint64_t>(hi[1]) << 32) | lo[1]);
+}
+
+// Sum over each 16-lane row: quad swaps, then the half-row and row mirrors;
+// every lane of a row ends with the same row sum.
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += dpp_f64<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return v;
+}
+
+// The sums over the 64 lanes of P values at once (2 <= P <= 8), cheaper
+// than P wave_sums: values are paired and each half-wave keeps one of a
+// pair (lanes l and l + 32 added), then each row of a half-wave keeps one
+// of a pair of those (lanes l and l + 16 added), so that one set of row
+// reductions serves four values.  Row r of the k-th register then holds
+// value 4k + (0, 2, 1, 3)[r]; a missing partner is a zero.  The order of
+// the additions is fixed, so the results depend only on the inputs (they
+// round differently from wave_sum's).  Needs all 64 lanes active.
+template <int P>
+__device__ __forceinline__ void wave_sums(const double (&v)[P], double (&out)[P])
+{
+    static_assert(P >= 2 && P <= 8, "two to eight values");
+    constexpr int NW = (P + 1) / 2, NU = (NW + 1) / 2;
+    double w[NW];
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+        double x = v[2 * j], y = 2 * j + 1 < P ? v[2 * j + 1] : 0.0;
+        swap32_f64(x, y);
+        w[j] = x + y;
+    }
+    double u[NU];
+#pragma unroll
+    for (int k = 0; k < NU; ++k) {
+        double x = w[2 * k], y = 2 * k + 1 < NW ? w[2 * k + 1] : 0.0;
+        swap16_f64(x, y);
+        u[k] = row_sum16(x + y);
+    }
+    constexpr int kRowLane[4] = {0, 32, 16, 48};
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        out[q] = readlane_f64(u[q / 4], kRowLane[q % 4]);
+}
+
 // Workgroup barrier that orders LDS accesses only.  Global loads in flight
 // (prefetches) are not waited for, unlike __syncthreads().
 __device__ __forceinline__ void lds_barrier()

@@ -20,6 +20,7 @@ SCHEDULES = {
     "bicgk2": ["pass 0: A ROWDOTx2|COLSUMx2"],
     "bicgk2c": ["pass 0: A ROWDOTx2|COLSUMx2"],
     "multimv": ["pass 0: A ROWDOTx3"],
+    "multimv5": ["pass 0: A ROWDOTx5|COLSUM"],
 }
 LAYOUTS = {   # per pass: update terms, stored, row dots, column sums
     "gemver3": [(3, 1, 0, 1), (0, 0, 1, 0)],
@@ -27,6 +28,7 @@ LAYOUTS = {   # per pass: update terms, stored, row dots, column sums
     "bicgk2": [(0, 0, 2, 2)],
     "bicgk2c": [(0, 0, 2, 2)],
     "multimv": [(0, 0, 3, 0)],
+    "multimv5": [(0, 0, 5, 1)],
 }
 
 

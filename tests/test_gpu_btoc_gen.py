@@ -25,6 +25,7 @@ PROGRAMS = {
     "bicgk2": BICGK2_IN,
     "bicgk2c": BICGK2_IN,
     "multimv": dict(A="A", x1="n", x2="n", x3="n", y="m", alpha=1.5, beta=0.7),
+    "multimv5": dict(A="A", x1="n", x2="n", x3="n", x4="n", x5="n", r="m", alpha=1.5),
 }
 SHAPES = [(1, 1), (2, 3), (65, 127), (300, 517), (513, 1000), (1000, 2049), (2048, 2048)]
 
