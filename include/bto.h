@@ -425,13 +425,13 @@ bto_status bto_batch_plan_destroy(bto_batch_plan *plan);
  * the unfused form are refused with BTO_ERR_UNSUPPORTED) cut into
  * short-lived workgroup tiles instead of one workgroup per instance: a tile
  * is one sweep of one instance over a band of rows and a block of columns.
- * Tiles of one kind form a group launched by a kernel specialised for the
- * group's tile shape: GEMVER's first sweeps (B = A + u1 v1^T + u2 v2^T
- * stored, partial column sums of B^T y), BiCGK's sweeps (row dots and
- * column sums in one pass) of narrow and of wide matrices, a launch that
- * adds each instance's partial sums in a fixed order (BiCGK's q and s,
- * GEMVER's x = beta B^T y + z), GEMVER's second sweeps (w = alpha B x) of
- * narrow and of wide matrices, and the sums of w.  The kernel boundaries
+ * The tiles form five launches, each of a kernel specialised for its tile
+ * shape: the first sweeps (GEMVER's B = A + u1 v1^T + u2 v2^T stored with
+ * partial column sums of B^T y, and BiCGK's row dots and column sums in one
+ * pass, each tile taking its instance's operations and band height), a
+ * launch that adds each instance's partial sums in a fixed order (BiCGK's q
+ * and s, GEMVER's x = beta B^T y + z), GEMVER's second sweeps (w = alpha B
+ * x) of narrow and of wide matrices, and the sums of w.  The kernel boundaries
  * order the phases, so no tile waits for another.  Each result depends only
  * on its own instance and the plan's configuration (a fixed tile and
  * summation order), not on the other instances or the launch; it rounds
@@ -445,6 +445,8 @@ typedef struct {
     int wide_shape;    /* of the read-only sweeps of wider matrices */
     int narrow_n;      /* column count up to which narrow_shape is used (>= 0) */
     int store_rb;      /* rows per band of GEMVER's first sweeps */
+    int bicgk_rb;      /* rows per band of BiCGK's sweeps (in the first launch, with
+                          store_shape; at most 64 rows per wave) */
     int read_rb;       /* rows per band of the read-only sweeps (at most 64 rows per
                           wave: read_rb / waves_down <= 64) */
     int wgs_per_cu;    /* 0: one workgroup per tile; 1..16: that many persistent
@@ -466,8 +468,9 @@ bto_status bto_tiled_shape(int shape, int *kv, int *depth, int *waves_across, in
 
 /* bto_tiled_batch_create validates the instances as bto_batch_plan_create
  * does, then allocates and fills the plan's device tables and partial-sum
- * scratch (for the defaults about 1/32 of each matrix for the column sums
- * and 1/128 for the row dots), which the plan owns until it is destroyed.
+ * scratch (for the defaults: column sums 1/32 of each GEMVER matrix and
+ * 1/256 of each BiCGK matrix, row dots 1/256 of each matrix), which the plan
+ * owns until it is destroyed.
  * With use_graph set the launches are captured once in a HIP graph.
  * bto_tiled_batch_create_config does the same under `config` (NULL: the
  * defaults; an invalid configuration gives BTO_ERR_INVALID_ARG).

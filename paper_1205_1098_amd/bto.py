@@ -838,7 +838,8 @@ class TiledConfig(ctypes.Structure):
     """bto_tiled_config: the tiled batch's partition parameters."""
     _fields_ = [("store_shape", ctypes.c_int), ("narrow_shape", ctypes.c_int),
                 ("wide_shape", ctypes.c_int), ("narrow_n", ctypes.c_int),
-                ("store_rb", ctypes.c_int), ("read_rb", ctypes.c_int),
+                ("store_rb", ctypes.c_int), ("bicgk_rb", ctypes.c_int),
+                ("read_rb", ctypes.c_int),
                 ("wgs_per_cu", ctypes.c_int), ("use_graph", ctypes.c_int)]
 
     @classmethod

@@ -1965,15 +1965,15 @@ namespace {
 
 // Defaults from the tiled-batch search (tune.py --batch: 4096 mixed
 // GEMVER/BiCGK instances, n log-uniform on [64, 2048], MI355X): the first
-// sweeps (GEMVER's with BiCGK's) in tiles of 128 rows by 256 columns (8
-// waves down, two 16-byte pairs per lane, two rows in flight per wave);
-// GEMVER's second sweeps in 64-row tiles of 256 columns for matrices up to
-// 512 columns wide and of 512 columns (2 waves, each sweeping the whole
-// band) above; one workgroup per tile.  The best dozen configurations were
-// within 1.5% of each other.
+// sweeps in tiles of 256 columns (8 waves down, two 16-byte pairs per lane,
+// two rows in flight per wave), of 32 rows for GEMVER and 256 rows for
+// BiCGK; GEMVER's second sweeps in 64-row tiles of 256 columns for matrices
+// up to 512 columns wide and of 512 columns (2 waves, each sweeping the
+// whole band) above; one workgroup per tile.  The best dozen configurations
+// were within 1.5% of each other.
 constexpr bto_tiled_config kTiledDefaults = {
     /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 7, /*narrow_n*/ 512,
-    /*store_rb*/ 128, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
+    /*store_rb*/ 32, /*bicgk_rb*/ 256, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
 constexpr int kTiledFinishWgsPerCu = 8;
 constexpr int kTiledRefillWgsPerCu = 2;   // refillable plans made with the defaults
 
@@ -1983,6 +1983,9 @@ bto_status tiled_check_config(const bto_tiled_config &c)
     if (!btile_shape_ok(c.store_shape, kBtFirstOps, c.store_rb))
         return fail(BTO_ERR_INVALID_ARG, "store_shape / store_rb: not an instantiated tile shape "
                                          "for the first sweeps with that band height");
+    if (!btile_shape_ok(c.store_shape, kBtFirstOps, c.bicgk_rb))
+        return fail(BTO_ERR_INVALID_ARG, "store_shape / bicgk_rb: not an instantiated tile shape "
+                                         "for BiCGK's sweeps with that band height");
     for (int sh : {c.narrow_shape, c.wide_shape})
         if (!btile_shape_ok(sh, OP_ROWDOT, c.read_rb))
             return fail(BTO_ERR_INVALID_ARG, "narrow_shape / wide_shape / read_rb: not an "
@@ -2013,8 +2016,10 @@ TiledNeeds tiled_needs(const bto_tiled_config &c, int kind, int64_t m, int64_t n
 {
     TiledNeeds t;
     const bool some = m > 0 && n > 0;
-    // the first sweeps (GEMVER's and BiCGK's) in store_shape tiles of store_rb rows
-    const int64_t fbands = some ? ceil_div(m, (int64_t)c.store_rb) : 0;
+    // the first sweeps (GEMVER's and BiCGK's) in store_shape tiles, of store_rb
+    // rows for GEMVER and bicgk_rb rows for BiCGK
+    const int64_t frb = kind == BTO_K_BICGK ? c.bicgk_rb : c.store_rb;
+    const int64_t fbands = some ? ceil_div(m, frb) : 0;
     const int64_t ftiles = fbands * (some ? ceil_div(n, btile_cols(c.store_shape)) : 0);
     t.jobs = 2;
     t.funits = ceil_div(m, (int64_t)64) + ceil_div(n, (int64_t)64);
@@ -2106,11 +2111,14 @@ bto_status tiled_image(const bto_tiled_config &c, const bto_batch_desc *descs, i
         const BatchItem &it = items[i];
         const int64_t m = it.m, n = it.n;
         const bool some = m > 0 && n > 0;
-        // the first sweeps: store_shape tiles of store_rb rows
-        const int64_t fbands = some ? ceil_div(m, (int64_t)c.store_rb) : 0;
+        // the first sweeps: store_shape tiles, of store_rb rows (GEMVER) or
+        // bicgk_rb rows (BiCGK)
+        const int frb = it.kind == BTO_K_BICGK ? c.bicgk_rb : c.store_rb;
+        const int64_t fbands = some ? ceil_div(m, (int64_t)frb) : 0;
         const int64_t fcols = some ? ceil_div(n, btile_cols(c.store_shape)) : 0;
         const bool rows16 = it.lda % 2 == 0 || m <= 1;
         BTileEntry e{};
+        e.rb = frb;
         e.a.m = m;
         e.a.n = n;
         e.a.lda = it.lda;
@@ -2150,6 +2158,7 @@ bto_status tiled_image(const bto_tiled_config &c, const bto_batch_desc *descs, i
             e.vec = aligned16(it.A) && aligned16(it.B) && rows16 && (it.ldb % 2 == 0 || m <= 1);
             e.ops = OP_UPD1 | OP_UPD2 | OP_COLSUM;
             BTileEntry e2{};
+            e2.rb = c.read_rb;
             e2.a.m = m;
             e2.a.n = n;
             e2.a.lda = it.ldb;
@@ -2248,13 +2257,13 @@ void tiled_group(const bto_tiled_batch *p, int g, hipStream_t st)
     const bto_tiled_config &c = p->cfg;
     switch (g) {
     case BG_FIRST:
-        launch_btile(c.store_shape, kBtFirstOps, c.store_rb, p->d_entries, p->d_units, p->d_hdr,
-                     g, p->grid[g], st);
+        launch_btile(c.store_shape, kBtFirstOps, p->d_entries, p->d_units, p->d_hdr, g,
+                     p->grid[g], st);
         break;
     case BG_ROW_NARROW:
     case BG_ROW_WIDE:
-        launch_btile(g == BG_ROW_NARROW ? c.narrow_shape : c.wide_shape, OP_ROWDOT, c.read_rb,
-                     p->d_entries, p->d_units, p->d_hdr, g, p->grid[g], st);
+        launch_btile(g == BG_ROW_NARROW ? c.narrow_shape : c.wide_shape, OP_ROWDOT, p->d_entries,
+                     p->d_units, p->d_hdr, g, p->grid[g], st);
         break;
     default:
         launch_btile_finish(p->d_jobs, p->d_funits, p->d_hdr, g, p->grid[g], st);

@@ -42,12 +42,12 @@ constexpr int kStoreOps = OP_UPD1 | OP_UPD2 | OP_COLSUM;
 constexpr int kBicgkOps = OP_ROWDOT | OP_COLSUM;
 constexpr int kRowOps = OP_ROWDOT;
 
-// The sweep of one tile.  OPS = kBtFirstOps: the entry's ops, a store sweep
-// (GEMVER's first) or a BiCGK sweep.
+// The sweep of one tile, in bands of the entry's height.  OPS = kBtFirstOps:
+// the entry's ops, a store sweep (GEMVER's first) or a BiCGK sweep.
 template <int KV, int D, int WC, int WR, int OPS>
-__device__ __forceinline__ void bt_tile(const BTileEntry &e, const BTileUnit &u, int rb,
-                                        double *lds)
+__device__ __forceinline__ void bt_tile(const BTileEntry &e, const BTileUnit &u, double *lds)
 {
+    const int rb = e.rb;
     TileArgs a = e.a;
     globalize(a);
     if constexpr (OPS == kBtFirstOps) {
@@ -73,8 +73,7 @@ __device__ __forceinline__ void bt_tile(const BTileEntry &e, const BTileUnit &u,
 template <int KV, int D, int WC, int WR, int OPS>
 __global__ __launch_bounds__(kWave *WC *WR) void k_bt(const BTileEntry *__restrict__ entries,
                                                       const BTileUnit *__restrict__ units,
-                                                      const int *__restrict__ hdr, int group,
-                                                      int rb)
+                                                      const int *__restrict__ hdr, int group)
 {
     constexpr bool COLSUM = OPS == kBtFirstOps || (OPS & OP_COLSUM);
     __shared__ double lds[COLSUM ? tile_lds_doubles<KV, WC, WR>() : 1];
@@ -93,7 +92,7 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_bt(const BTileEntry *__restri
         BTileUnit nxt = cur;
         if (more)
             nxt = units[first + u + step];
-        bt_tile<KV, D, WC, WR, OPS>(entries[cur.entry], cur, rb, lds);
+        bt_tile<KV, D, WC, WR, OPS>(entries[cur.entry], cur, lds);
         if (!more)
             break;
         // the column sums of this tile leave LDS before the next tile's
@@ -128,20 +127,20 @@ const char *const kGroupNames[BG_COUNT] = {"bt_first", "bt_finish1", "bt_row_nar
 
 template <int S, int OPS>
 void launch_shape_ops(const BTileEntry *entries, const BTileUnit *units, const int *hdr,
-                      int group, int rb, int grid, hipStream_t st)
+                      int group, int grid, hipStream_t st)
 {
     constexpr BtShapeDef d = kBtShapes[S];
     launch(kGroupNames[group], k_bt<d.kv, d.d, d.wc, d.wr, OPS>, dim3((unsigned)grid),
-           dim3(kWave * d.wc * d.wr), st, entries, units, hdr, group, rb);
+           dim3(kWave * d.wc * d.wr), st, entries, units, hdr, group);
 }
 
 template <int S>
 void launch_shape(int ops, const BTileEntry *entries, const BTileUnit *units, const int *hdr,
-                  int group, int rb, int grid, hipStream_t st)
+                  int group, int grid, hipStream_t st)
 {
     switch (ops) {
-    case kBtFirstOps: launch_shape_ops<S, kBtFirstOps>(entries, units, hdr, group, rb, grid, st); break;
-    case kRowOps: launch_shape_ops<S, kRowOps>(entries, units, hdr, group, rb, grid, st); break;
+    case kBtFirstOps: launch_shape_ops<S, kBtFirstOps>(entries, units, hdr, group, grid, st); break;
+    case kRowOps: launch_shape_ops<S, kRowOps>(entries, units, hdr, group, grid, st); break;
     default: break;
     }
 }
@@ -177,24 +176,24 @@ void btile_shape_info(int shape, int out[4])
     out[3] = d.wr;
 }
 
-void launch_btile(int shape, int ops, int rb, const BTileEntry *entries, const BTileUnit *units,
+void launch_btile(int shape, int ops, const BTileEntry *entries, const BTileUnit *units,
                   const int *hdr, int group, int grid, hipStream_t st)
 {
     if (grid <= 0)
         return;
     switch (shape) {
-    case 0: launch_shape<0>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 1: launch_shape<1>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 2: launch_shape<2>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 3: launch_shape<3>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 4: launch_shape<4>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 5: launch_shape<5>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 6: launch_shape<6>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 7: launch_shape<7>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 8: launch_shape<8>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 9: launch_shape<9>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 10: launch_shape<10>(ops, entries, units, hdr, group, rb, grid, st); break;
-    case 11: launch_shape<11>(ops, entries, units, hdr, group, rb, grid, st); break;
+    case 0: launch_shape<0>(ops, entries, units, hdr, group, grid, st); break;
+    case 1: launch_shape<1>(ops, entries, units, hdr, group, grid, st); break;
+    case 2: launch_shape<2>(ops, entries, units, hdr, group, grid, st); break;
+    case 3: launch_shape<3>(ops, entries, units, hdr, group, grid, st); break;
+    case 4: launch_shape<4>(ops, entries, units, hdr, group, grid, st); break;
+    case 5: launch_shape<5>(ops, entries, units, hdr, group, grid, st); break;
+    case 6: launch_shape<6>(ops, entries, units, hdr, group, grid, st); break;
+    case 7: launch_shape<7>(ops, entries, units, hdr, group, grid, st); break;
+    case 8: launch_shape<8>(ops, entries, units, hdr, group, grid, st); break;
+    case 9: launch_shape<9>(ops, entries, units, hdr, group, grid, st); break;
+    case 10: launch_shape<10>(ops, entries, units, hdr, group, grid, st); break;
+    case 11: launch_shape<11>(ops, entries, units, hdr, group, grid, st); break;
     default: break;
     }
 }

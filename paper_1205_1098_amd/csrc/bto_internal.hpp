@@ -152,6 +152,8 @@ struct BTileEntry {     // one sweep of one instance
     TileArgs a;
     int32_t vec;        // A (and B) 16-byte aligned with even leading dimensions
     int32_t ops;        // the sweep's operations (OP_* flags)
+    int32_t rb;         // rows per band of its tiles
+    int32_t pad;
 };
 struct BTileUnit {      // one tile
     int32_t entry, band, cblk, pad;
@@ -186,7 +188,7 @@ void btile_shape_info(int shape, int out[4]);   // kv, depth, waves across, wave
 // ops is OP_ROWDOT for GEMVER's second sweeps, or kBtFirstOps for the first
 // launch, whose tiles take their operations from their entries.
 constexpr int kBtFirstOps = -1;
-void launch_btile(int shape, int ops, int rb, const BTileEntry *entries, const BTileUnit *units,
+void launch_btile(int shape, int ops, const BTileEntry *entries, const BTileUnit *units,
                   const int *hdr, int group, int grid, hipStream_t st);
 void launch_btile_finish(const FinishJob *jobs, const BFinishUnit *units, const int *hdr,
                          int group, int grid, hipStream_t st);

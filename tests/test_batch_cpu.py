@@ -179,8 +179,9 @@ def test_tiled_batch_refuses_more_tiles_than_a_launch_indexes(bto):
 
 def test_tiled_config_validation(bto):
     """Configurations are checked before any device work: shapes, band
-    heights against the shapes' row groups (and at most 64 rows per wave in
-    the read-only sweeps), workgroups per compute unit, the graph flag."""
+    heights (GEMVER's first sweeps, BiCGK's, the second sweeps) against the
+    shapes' row groups (and at most 64 rows per wave where rows are dotted),
+    workgroups per compute unit, the graph flag."""
     shapes = bto.tiled_shapes()
     assert len(shapes) == bto._lib.bto_tiled_shape_count() >= 4
     d = bto.TiledConfig.default()
@@ -188,13 +189,16 @@ def test_tiled_config_validation(bto):
     arr = (bto.Desc * 1)()
     plan = ctypes.c_void_p()
     bad = [dict(store_shape=len(shapes)), dict(wide_shape=-1), dict(narrow_shape=99),
-           dict(store_rb=0), dict(read_rb=-4), dict(narrow_n=-1), dict(wgs_per_cu=17),
+           dict(store_rb=0), dict(bicgk_rb=0), dict(read_rb=-4), dict(narrow_n=-1),
+           dict(wgs_per_cu=17),
            dict(wgs_per_cu=-1), dict(use_graph=2)]
     for s, sh in enumerate(shapes):
         wr = sh["waves_down"]
         if wr > 1:
             bad.append(dict(store_shape=s, store_rb=wr + 1))
+            bad.append(dict(store_shape=s, store_rb=wr, bicgk_rb=wr + 1))
         bad.append(dict(wide_shape=s, read_rb=65 * wr))       # 65 rows per wave
+        bad.append(dict(store_shape=s, store_rb=wr, bicgk_rb=65 * wr))
     for ch in bad:
         c = bto.TiledConfig.default(**ch)
         assert bto._lib.bto_tiled_batch_create_config(ctypes.byref(arr), 0, ctypes.byref(c),

@@ -393,21 +393,28 @@ def test_tiled_batch_refuses_other_work(env):
 TILED_CONFIGS = [
     dict(),
     dict(wgs_per_cu=1),
-    dict(store_shape=1, narrow_shape=2, wide_shape=8, store_rb=64, read_rb=64, wgs_per_cu=2),
-    dict(store_shape=2, narrow_shape=3, wide_shape=9, store_rb=8, read_rb=64, wgs_per_cu=3,
-         use_graph=0),
-    dict(store_shape=3, narrow_shape=4, wide_shape=6, store_rb=128, read_rb=8, narrow_n=0,
-         wgs_per_cu=0, use_graph=0),
-    dict(store_shape=4, narrow_shape=5, wide_shape=7, store_rb=8, read_rb=64, wgs_per_cu=16),
-    dict(store_shape=5, narrow_shape=6, wide_shape=1, store_rb=36, read_rb=8, narrow_n=2048,
-         wgs_per_cu=4),
-    dict(store_shape=6, narrow_shape=7, wide_shape=0, store_rb=4, read_rb=16, narrow_n=1000),
-    dict(store_shape=7, narrow_shape=8, wide_shape=2, store_rb=32, read_rb=32, wgs_per_cu=1),
-    dict(store_shape=8, narrow_shape=9, wide_shape=3, store_rb=12, read_rb=12, wgs_per_cu=2),
-    dict(store_shape=9, narrow_shape=1, wide_shape=5, store_rb=1, read_rb=40, wgs_per_cu=8),
-    dict(store_shape=10, narrow_shape=10, wide_shape=11, store_rb=64, read_rb=48, wgs_per_cu=2),
-    dict(store_shape=11, narrow_shape=11, wide_shape=10, store_rb=7, read_rb=5),
-    dict(store_shape=0, store_rb=16, wgs_per_cu=2),
+    dict(store_shape=1, narrow_shape=2, wide_shape=8, store_rb=64, bicgk_rb=256, read_rb=64,
+         wgs_per_cu=2),
+    dict(store_shape=2, narrow_shape=3, wide_shape=9, store_rb=8, bicgk_rb=512, read_rb=64,
+         wgs_per_cu=3, use_graph=0),
+    dict(store_shape=3, narrow_shape=4, wide_shape=6, store_rb=128, bicgk_rb=4, read_rb=8,
+         narrow_n=0, wgs_per_cu=0, use_graph=0),
+    dict(store_shape=4, narrow_shape=5, wide_shape=7, store_rb=8, bicgk_rb=100, read_rb=64,
+         wgs_per_cu=16),
+    dict(store_shape=5, narrow_shape=6, wide_shape=1, store_rb=36, bicgk_rb=64, read_rb=8,
+         narrow_n=2048, wgs_per_cu=4),
+    dict(store_shape=6, narrow_shape=7, wide_shape=0, store_rb=4, bicgk_rb=1, read_rb=16,
+         narrow_n=1000),
+    dict(store_shape=7, narrow_shape=8, wide_shape=2, store_rb=32, bicgk_rb=33, read_rb=32,
+         wgs_per_cu=1),
+    dict(store_shape=8, narrow_shape=9, wide_shape=3, store_rb=12, bicgk_rb=50, read_rb=12,
+         wgs_per_cu=2),
+    dict(store_shape=9, narrow_shape=1, wide_shape=5, store_rb=1, bicgk_rb=64, read_rb=40,
+         wgs_per_cu=8),
+    dict(store_shape=10, narrow_shape=10, wide_shape=11, store_rb=64, bicgk_rb=5, read_rb=48,
+         wgs_per_cu=2),
+    dict(store_shape=11, narrow_shape=11, wide_shape=10, store_rb=7, bicgk_rb=64, read_rb=5),
+    dict(store_shape=0, store_rb=16, bicgk_rb=1024, wgs_per_cu=2),
 ]
 
 
