@@ -701,7 +701,9 @@ def bench_serving(torch, bto, count: int, warmup: int) -> dict:
     (saturated throughput), then Poisson arrivals at 0.7 of what the entry
     points alone sustain, served with continuous batching by three routes
     (tiled batches for small GEMVER/BiCGK, the default; entry points only;
-    persistent batch plans) and by a one-at-a-time FIFO server."""
+    persistent batch plans) and by a one-at-a-time FIFO server.  The default
+    and entry-point routes serve the same arrivals three times each,
+    alternating, and report medians (run-to-run spread of p50 is ~25%)."""
     from paper_1205_1098_amd import serve
 
     GiB = 1 << 30
@@ -731,8 +733,6 @@ def bench_serving(torch, bto, count: int, warmup: int) -> dict:
     # one offered load for every route: 0.7 of what the entry points alone sustain
     lam = 0.7 * direct_sat["req_per_s"]
     print(f"serving: Poisson runs at {lam:.0f} req/s", file=sys.stderr, flush=True)
-    direct_poisson = once(ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
-    ex.close()
     # the default: GEMVER and BiCGK requests of n <= 2048 in refillable tiled
     # batches (one graph launch per step), the rest through the entry points
     tiled_ex = serve.GpuExecutor(torch, bto, pool)
@@ -740,7 +740,22 @@ def bench_serving(torch, bto, count: int, warmup: int) -> dict:
     once(tiled_ex, serve.make_requests(min(total, 2000), sizes, rate=None, first_rid=800000),
          64, 2)
     sat = once(tiled_ex, serve.make_requests(total, sizes, rate=None), 64, 2)
-    poisson = once(tiled_ex, serve.make_requests(total, sizes, rate=lam, first_rid=total), 64, 2)
+    # the same arrivals through both routes, alternating, three times each:
+    # each route reports the run of median p50 and the medians of p50 and p99
+    runs = {"direct": [], "tiled": []}
+    for _ in range(3):
+        for name, e in (("direct", ex), ("tiled", tiled_ex)):
+            runs[name].append(once(e, serve.make_requests(total, sizes, rate=lam,
+                                                          first_rid=total), 64, 2))
+
+    def median_run(rs):
+        pick = sorted(rs, key=lambda r: r["p50_ms"])[len(rs) // 2]
+        return dict(pick, p50_ms_median=float(np.median([r["p50_ms"] for r in rs])),
+                    p99_ms_median=float(np.median([r["p99_ms"] for r in rs])),
+                    p50_ms_runs=[r["p50_ms"] for r in rs], p99_ms_runs=[r["p99_ms"] for r in rs])
+
+    direct_poisson, poisson = median_run(runs["direct"]), median_run(runs["tiled"])
+    ex.close()
     lam_own = 0.7 * sat["req_per_s"]
     poisson_own = once(tiled_ex, serve.make_requests(total, sizes, rate=lam_own,
                                                      first_rid=2 * total), 64, 2)
