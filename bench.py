@@ -600,7 +600,8 @@ def bench_generated_passes(torch, bto, n: int = N) -> dict:
 def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
     fair seeded coin) in one graph-captured persistent launch, then as tiled
-    batches."""
+    batches; then 4096 instances of one kind at a time (all GEMVER, all
+    BiCGK) in both forms."""
     from paper_1205_1098_amd import batch
 
     insts, specs = batch.make_instances(torch, bto, count, 64, 2048,
@@ -661,6 +662,32 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
             else:
                 bto.bicgk(inst["A"], *inst["in"], q=inst["out"][0], s=inst["out"][1])
     sec_loop = time_steps(torch, loop, 2, 1) if with_loop else None
+    del insts, out_list, outs
+    torch.cuda.empty_cache()
+    # the same sizes with every instance of one kind
+    one_kind = {}
+    for kind in ("gemver", "bicgk"):
+        ki, ks = batch.make_instances(torch, bto, count, 64, 2048, {kind: 1.0}, config=4)
+        kb = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in ks)
+        kp = bto.BatchPlan(ki, use_graph=graph)
+        ksec, _ = time_stats(torch, kp.launch, 5, 2)
+        kp.check()
+        kp.close()
+        kt = bto.TiledBatch(ki, config=bto.TiledConfig.default(use_graph=1 if graph else 0))
+        ktsec, _ = time_stats(torch, kt.launch, 5, 2)
+        kt.close()
+        one_kind[kind] = {
+            "alg_gb": round(kb / 1e9, 3),
+            "persistent": {"ms_per_batch": round(ksec * 1e3, 3),
+                           "inst_per_s": round(count / ksec, 1),
+                           "gbs": round(kb / ksec / 1e9, 1)},
+            "tiled": {"ms_per_batch": round(ktsec * 1e3, 3),
+                      "inst_per_s": round(count / ktsec, 1),
+                      "gbs": round(kb / ktsec / 1e9, 1)},
+        }
+        print(f"batched: {count} {kind} instances timed", file=sys.stderr, flush=True)
+        del ki, kp, kt
+        torch.cuda.empty_cache()
     return {
         "instances": count,
         "gemver": sum(1 for s in specs if s.kind == "gemver"),
@@ -692,6 +719,7 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         },
         "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
         "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,
+        "one_kind": one_kind,
     }
 
 
@@ -961,6 +989,20 @@ def main() -> int:
         st["triad_gbs"] = round(3 * n * 8 / s / 1e9, 1)
         result["stream"] = st
         del a, b, c
+        # each kernel against the probe of its own traffic: read-only sweeps
+        # against the read probe, sweeps that also write against the copy
+        # probe, three-input vector kernels against the triad
+        def ceiling(k):
+            if k in ("gemver",):
+                return "copy"
+            if k in ("axpydot", "vadd", "waxpby"):
+                return "triad"
+            return "read"
+        result["pct_of_copy_probe"] = round(100 * result["value"] / st["copy_gbs"], 1)
+        for k, ent in result.get("suite", {}).items():
+            probe = ceiling(k)
+            ent["ceiling"] = {"probe": probe,
+                              "pct": round(100 * ent["fused_gbs"] / st[probe + "_gbs"], 1)}
 
     shared.clear()
     del main_wl
