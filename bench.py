@@ -971,6 +971,26 @@ def main() -> int:
                 del wl
         alt.clear()
         result["suite"] = suite
+        # BiCGK at 512 x 512 (2 MiB: resident in the caches, so not an HBM
+        # figure): the entry point's fused and unfused forms, which cost
+        # their launches
+        ns = 512
+        A5 = torch.from_numpy(synth.matrix(synth.SEED, synth.stream_id(1, 0), ns, ns)).to(dev)
+        p5 = torch.from_numpy(synth.uniform(synth.SEED, synth.stream_id(1, 1), ns)).to(dev)
+        r5 = torch.from_numpy(synth.uniform(synth.SEED, synth.stream_id(1, 2), ns)).to(dev)
+        q5, s5 = torch.empty_like(r5), torch.empty_like(p5)
+        ws5 = torch.empty(max(bto.workspace_bytes("bicgk", ns, ns, "fused"),
+                              bto.workspace_bytes("bicgk", ns, ns, "unfused")),
+                          dtype=torch.uint8, device=dev)
+        small = {"workload": "bicgk 512x512 (cache-resident)"}
+        for form in ("fused", "unfused"):
+            sec5 = time_steps(torch, lambda: bto.bicgk(A5, p5, r5, form=form, q=q5, s=s5,
+                                                       ws=ws5), 200, 20)
+            small[form + "_us"] = round(sec5 * 1e6, 2)
+            small[form + "_gbs"] = round(alg_bytes("bicgk", form, ns) / sec5 / 1e9, 1)
+        small["speedup"] = round(small["unfused_us"] / small["fused_us"], 3)
+        result["small_bicgk"] = small
+        del A5, p5, r5, q5, s5, ws5
         result["generated"] = bench_generated(torch, bto, synth, shared, suite)
 
     if not args.no_stream:
