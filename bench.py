@@ -425,8 +425,21 @@ def cpu_baseline(kernel: str, target_s: float):
 
     full = leg(threads, target_s, 200)
     one = leg(1, 0.0, 3)
-    oracle.set_threads(1)
     del A
+    # a vector kernel at N = 2^26 beside it: AXPYDOT, whose unfused loops
+    # move 5 vectors (axpy: w, v in, z out; dot: z, u in); the oracle's
+    # vector loops run on one thread (its pairwise dot is one recursion)
+    oracle.set_threads(1)
+    xs = [synth.uniform(seed, sid(10 + k), NV) for k in range(3)]
+    times = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.axpydot(*xs, ALPHA)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    vector = {"kernel": f"axpydot N={NV}", "threads": 1, "calls": 3,
+              "median_ms": round(med * 1e3, 2), "gbs": round(5 * NV * 8 / med / 1e9, 3)}
+    del xs
     cpu = host_cpu()
     return {
         "value": full["gbs"],
@@ -442,6 +455,7 @@ def cpu_baseline(kernel: str, target_s: float):
         "all_threads": full,
         "one_thread": one,
         "bytes_per_call": oracle_bytes(kernel),
+        "vector": vector,
     }
 
 
