@@ -1942,6 +1942,7 @@ struct bto_tiled_batch {
     bool refillable = false;
     int capacity = 0;                   // instances per refill
     int64_t cap_entries = 0, cap_units = 0, cap_jobs = 0, cap_funits = 0, cap_scratch = 0;
+    char *d_tables = nullptr;           // one allocation holding the tables below
     BTileEntry *d_entries = nullptr;
     BTileUnit *d_units = nullptr;       // tile groups, in group order
     FinishJob *d_jobs = nullptr;        // jobs after the first sweeps, then after the second
@@ -2241,11 +2242,7 @@ void tiled_free(bto_tiled_batch *p)
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
-    if (p->d_entries) (void)hipFree(p->d_entries);
-    if (p->d_units) (void)hipFree(p->d_units);
-    if (p->d_jobs) (void)hipFree(p->d_jobs);
-    if (p->d_funits) (void)hipFree(p->d_funits);
-    if (p->d_hdr) (void)hipFree(p->d_hdr);
+    if (p->d_tables) (void)hipFree(p->d_tables);
     if (p->d_scratch) (void)hipFree(p->d_scratch);
     if (p->h_stage) (void)hipHostFree(p->h_stage);
     if (p->staged) (void)hipEventDestroy(p->staged);
@@ -2288,20 +2285,28 @@ size_t tiled_stage_layout(const bto_tiled_batch *p, size_t off[5])
     return o;
 }
 
+// Point the plan's tables at their offsets in its one allocation.
+void tiled_point(bto_tiled_batch *p, const size_t off[5])
+{
+    p->d_entries = reinterpret_cast<BTileEntry *>(p->d_tables + off[0]);
+    p->d_units = reinterpret_cast<BTileUnit *>(p->d_tables + off[1]);
+    p->d_jobs = reinterpret_cast<FinishJob *>(p->d_tables + off[2]);
+    p->d_funits = reinterpret_cast<BFinishUnit *>(p->d_tables + off[3]);
+    p->d_hdr = reinterpret_cast<int *>(p->d_tables + off[4]);
+}
+
 // Allocate a plan's device tables (capacities set), its staging and event.
 bto_status tiled_alloc(bto_tiled_batch *p)
 {
     auto bytes = [](size_t each, int64_t n) { return each * (size_t)(n > 0 ? n : 1); };
-    if (hipMalloc(&p->d_entries, bytes(sizeof(BTileEntry), p->cap_entries)) != hipSuccess ||
-        hipMalloc(&p->d_units, bytes(sizeof(BTileUnit), p->cap_units)) != hipSuccess ||
-        hipMalloc(&p->d_jobs, bytes(sizeof(FinishJob), p->cap_jobs)) != hipSuccess ||
-        hipMalloc(&p->d_funits, bytes(sizeof(BFinishUnit), p->cap_funits)) != hipSuccess ||
-        hipMalloc(&p->d_hdr, sizeof(int) * kBtHdrInts) != hipSuccess ||
-        hipMemset(p->d_hdr, 0, sizeof(int) * kBtHdrInts) != hipSuccess ||
-        hipMalloc(&p->d_scratch, bytes(sizeof(double), p->cap_scratch)) != hipSuccess)
-        return fail(BTO_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(hipGetLastError()));
     size_t off[5];
     p->stage_bytes = tiled_stage_layout(p, off);
+    if (hipMalloc(&p->d_tables, p->stage_bytes) != hipSuccess ||
+        hipMalloc(&p->d_scratch, bytes(sizeof(double), p->cap_scratch)) != hipSuccess)
+        return fail(BTO_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(hipGetLastError()));
+    tiled_point(p, off);
+    if (hipMemset(p->d_hdr, 0, sizeof(int) * kBtHdrInts) != hipSuccess)
+        return fail(BTO_ERR_HIP, "hipMemset");
     if (hipHostMalloc((void **)&p->h_stage, p->stage_bytes, hipHostMallocDefault) != hipSuccess)
         return fail(BTO_ERR_HIP, "hipHostMalloc");
     if (hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess)
@@ -2310,32 +2315,47 @@ bto_status tiled_alloc(bto_tiled_batch *p)
 }
 
 // Copy validated tables into the plan on `stream` (asynchronously, through
-// the pinned staging, after the previous refill has been read).
+// the pinned staging, after the previous refill has been read).  A plan
+// launched without a graph gives its kernels the tables' addresses at each
+// launch, so its tables are packed one after another and sent in one copy;
+// a captured graph keeps the fixed layout its launches were recorded with,
+// and each table is sent on its own.
 bto_status tiled_store(bto_tiled_batch *p, const TiledTables &t, hipStream_t stream)
 {
     if (hipEventSynchronize(p->staged) != hipSuccess)
         return fail(BTO_ERR_HIP, "hipEventSynchronize");
+    const size_t bytes[5] = {sizeof(BTileEntry) * t.entries.size(),
+                             sizeof(BTileUnit) * t.units.size(), sizeof(FinishJob) * t.jobs.size(),
+                             sizeof(BFinishUnit) * t.funits.size(), sizeof(int) * kBtHdrInts};
+    const void *src[5] = {t.entries.data(), t.units.data(), t.jobs.data(), t.funits.data(), t.hdr};
+    const bool packed = !p->cfg.use_graph;
     size_t off[5];
-    tiled_stage_layout(p, off);
+    size_t end = 0;
+    if (packed) {
+        for (int k = 0; k < 5; ++k) {
+            off[k] = end;
+            end += round256(bytes[k]);
+        }
+    } else {
+        tiled_stage_layout(p, off);
+    }
     char *st = p->h_stage;
-    struct Part {
-        void *dst;
-        const void *src;
-        size_t bytes;
-        size_t off;
-    } parts[5] = {
-        {p->d_entries, t.entries.data(), sizeof(BTileEntry) * t.entries.size(), off[0]},
-        {p->d_units, t.units.data(), sizeof(BTileUnit) * t.units.size(), off[1]},
-        {p->d_jobs, t.jobs.data(), sizeof(FinishJob) * t.jobs.size(), off[2]},
-        {p->d_funits, t.funits.data(), sizeof(BFinishUnit) * t.funits.size(), off[3]},
-        {p->d_hdr, t.hdr, sizeof(int) * kBtHdrInts, off[4]},
-    };
-    for (const Part &q : parts) {
-        if (q.bytes == 0)
-            continue;
-        std::memcpy(st + q.off, q.src, q.bytes);
-        if (hipMemcpyAsync(q.dst, st + q.off, q.bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+    for (int k = 0; k < 5; ++k)
+        if (bytes[k])
+            std::memcpy(st + off[k], src[k], bytes[k]);
+    if (packed) {
+        tiled_point(p, off);
+        if (hipMemcpyAsync(p->d_tables, st, end, hipMemcpyHostToDevice, stream) != hipSuccess)
             return fail(BTO_ERR_HIP, std::string("refill: ") + hipGetErrorString(hipGetLastError()));
+    } else {
+        for (int k = 0; k < 5; ++k) {
+            if (bytes[k] == 0)
+                continue;
+            if (hipMemcpyAsync(p->d_tables + off[k], st + off[k], bytes[k],
+                               hipMemcpyHostToDevice, stream) != hipSuccess)
+                return fail(BTO_ERR_HIP,
+                            std::string("refill: ") + hipGetErrorString(hipGetLastError()));
+        }
     }
     if (hipEventRecord(p->staged, stream) != hipSuccess)
         return fail(BTO_ERR_HIP, "hipEventRecord");
