@@ -232,6 +232,10 @@ def _check_mat(t: torch.Tensor, name: str) -> int:
     if t.device.type != "cuda":
         raise ValueError(f"{name}: must live on a ROCm device")
     m, n = t.shape
+    if m == 0 or n == 0:
+        # no element is read: the smallest valid leading dimension (torch
+        # gives empty tensors strides of 0)
+        return max(n, 1)
     if n > 1 and t.stride(1) != 1:
         raise ValueError(f"{name}: needs unit column stride (row-major)")
     if m > 1 and t.stride(0) < max(n, 1):

@@ -268,7 +268,7 @@ def _stored(name, t, prog):
     if t.dim() != 2 or name not in prog.colmajor:
         return t
     m, n = t.shape
-    if m > 1 and t.stride(0) != 1:
+    if t.numel() > 0 and m > 1 and t.stride(0) != 1:
         raise SpecError(f"{name}: declared matrix(column) but not stored by columns")
     return t.t()
 

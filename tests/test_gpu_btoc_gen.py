@@ -125,6 +125,22 @@ def test_every_shape_and_band(env, name):
             _check(torch, prog, got, host, text, True, f"{name} genome {genome}")
 
 
+@pytest.mark.parametrize("name", sorted(PROGRAMS))
+def test_empty_extents(env, name):
+    """No rows or no columns: no sweep runs, and every output is its
+    statement over empty sums (the added vectors, scaled)."""
+    torch, btoc, gen, dev = env
+    text = bto_specs.GENERATED[name]
+    prog = btoc.compile_spec(text, target="generated")
+    for case, (m, n) in enumerate(((0, 7), (5, 0), (0, 0))):
+        host = _inputs(PROGRAMS[name], m, n, "uniform", 40 + case)
+        bound = _device(torch, dev, host, prog.colmajor)
+        print(f"{name} empty {m}x{n}", flush=True)
+        got = gen.run(prog, bound)
+        torch.cuda.synchronize()
+        _check(torch, prog, got, host, text, False, f"{name} {m}x{n}")
+
+
 def test_in_place_update(env):
     """GEMVER3 with B bound to A itself (ldb == lda): the rank-3 update in
     place."""
