@@ -733,6 +733,11 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
         },
         "per_instance_loop_ms": round(sec_loop * 1e3, 2) if sec_loop else None,
         "speedup_vs_loop": round(sec_loop / sec, 2) if sec_loop else None,
+        "best": {"form": "tiled" if sec_tiled < sec else "persistent",
+                 "ms_per_batch": round(min(sec, sec_tiled) * 1e3, 3),
+                 "inst_per_s": round(count / min(sec, sec_tiled), 1),
+                 "gbs": round(total / min(sec, sec_tiled) / 1e9, 1),
+                 "pct_peak": round(100 * total / min(sec, sec_tiled) / 1e9 / PEAK_GBS, 1)},
         "one_kind": one_kind,
     }
 
