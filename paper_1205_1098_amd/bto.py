@@ -233,9 +233,12 @@ def _check_mat(t: torch.Tensor, name: str) -> int:
         raise ValueError(f"{name}: must live on a ROCm device")
     m, n = t.shape
     if m == 0 or n == 0:
-        # no element is read: the smallest valid leading dimension (torch
-        # gives empty tensors strides of 0)
-        return max(n, 1)
+        # no element is read, and torch may give empty tensors any strides
+        # (0 among them): every empty matrix gets the smallest even leading
+        # dimension, which every entry point and batch accepts and which is
+        # the same for an empty output and the empty input it may alias
+        k = max(n, 1)
+        return k + (k & 1)
     if n > 1 and t.stride(1) != 1:
         raise ValueError(f"{name}: needs unit column stride (row-major)")
     if m > 1 and t.stride(0) < max(n, 1):
