@@ -409,9 +409,18 @@ def _emit_pass(k: int, p: Pass, scalars: list) -> str:
     # workspace and run
     w(f"size_t p{k}_ws(int64_t m, int64_t n, int shape, int rb)")
     w("{")
-    w("    const int64_t ncols = n > 0 ? cdiv(n, wave_cols(shape)) : 0;")
-    w("    const int64_t nbands = m > 0 ? cdiv(m, rb) : 0;")
-    w(f"    return {P} * r256((size_t)(ncols * m) * 8) + {Q} * r256((size_t)(nbands * n) * 8);")
+    terms = []
+    if P:
+        w("    const int64_t ncols = n > 0 ? cdiv(n, wave_cols(shape)) : 0;")
+        terms.append(f"{P} * r256((size_t)(ncols * m) * 8)")
+    else:
+        w("    (void)shape;")
+    if Q:
+        w("    const int64_t nbands = m > 0 ? cdiv(m, rb) : 0;")
+        terms.append(f"{Q} * r256((size_t)(nbands * n) * 8)")
+    else:
+        w("    (void)rb;")
+    w(f"    return {' + '.join(terms) if terms else '0'};")
     w("}")
     w("")
     w(f"bto_status p{k}_run(const btog_pass_args *g, int shape, int rb, void *ws, "
@@ -425,8 +434,9 @@ def _emit_pass(k: int, p: Pass, scalars: list) -> str:
     w(f"    if (!shape_ok(shape, rb, {'true' if P else 'false'}))")
     w("        return gfail(BTO_ERR_INVALID_ARG, \"tile shape / band height not supported\");")
     nsc = len(scalars)
-    w(f"    if ({nsc} > 0 && (g->scalars == nullptr || g->nscalars < {nsc}))")
-    w("        return gfail(BTO_ERR_INVALID_ARG, \"too few scalars\");")
+    if nsc > 0:
+        w(f"    if (g->scalars == nullptr || g->nscalars < {nsc})")
+        w("        return gfail(BTO_ERR_INVALID_ARG, \"too few scalars\");")
     w("    const bool some = m > 0 && n > 0;")
     w("    if (some && g->A == nullptr)")
     w("        return gfail(BTO_ERR_INVALID_ARG, \"A is NULL\");")
