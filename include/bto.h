@@ -468,8 +468,8 @@ bto_status bto_tiled_shape(int shape, int *kv, int *depth, int *waves_across, in
 
 /* bto_tiled_batch_create validates the instances as bto_batch_plan_create
  * does, then allocates and fills the plan's device tables and partial-sum
- * scratch (for the defaults: column sums 1/32 of each GEMVER matrix and
- * 1/256 of each BiCGK matrix, row dots 1/256 of each matrix), which the plan
+ * scratch (for the defaults: column sums 1/16 of each GEMVER matrix and
+ * 1/64 of each BiCGK matrix, row dots 1/256 of each matrix), which the plan
  * owns until it is destroyed.
  * With use_graph set the launches are captured once in a HIP graph.
  * bto_tiled_batch_create_config does the same under `config` (NULL: the

@@ -8,7 +8,8 @@
 // operations from its instance's entry), then GEMVER's second sweeps of
 // narrow and of wide matrices.  A launch has either one workgroup per tile or a fixed number
 // of persistent workgroups that step through the group's tiles (tile k,
-// k + grid, k + 2 grid, ...).  The groups' first tile and tile count are
+// k + grid, k + 2 grid, ..., where the first sweeps first deal the tiles out
+// in runs per XCD).  The groups' first tile and tile count are
 // read from a small device header, so a plan can be refilled with other
 // instances without changing the launches (a captured graph stays valid).
 // A persistent workgroup fetches the record of its next tile before it
@@ -70,6 +71,24 @@ __device__ __forceinline__ void bt_tile(const BTileEntry &e, const BTileUnit &u,
     }
 }
 
+// Workgroups of a launch are handed to the chip's eight XCDs in turn
+// (workgroup k to XCD k mod 8), and each XCD has an L2 cache of its own.  The
+// first sweeps give XCD x a contiguous run of the group's tiles rather than
+// every eighth tile, so neighbouring tiles of one instance -- which share the
+// cache lines at their edges when a row is not a whole number of lines --
+// meet in one L2.  The runs are as even as possible (the first total mod 8
+// XCDs take one tile more), so the map is a permutation of [0, total) for any
+// total and any grid; persistent workgroups keep their XCD when the grid is a
+// multiple of eight, as it is (a multiple of the CU count).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_run_tile(int v, int total)
+{
+    const int per = total / kXcds, extra = total % kXcds;
+    const int x = v % kXcds;
+    return x * per + (x < extra ? x : extra) + v / kXcds;
+}
+
 template <int KV, int D, int WC, int WR, int OPS>
 __global__ __launch_bounds__(kWave *WC *WR) void k_bt(const BTileEntry *__restrict__ entries,
                                                       const BTileUnit *__restrict__ units,
@@ -78,11 +97,12 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_bt(const BTileEntry *__restri
     constexpr bool COLSUM = OPS == kBtFirstOps || (OPS & OP_COLSUM);
     __shared__ double lds[COLSUM ? tile_lds_doubles<KV, WC, WR>() : 1];
     const int first = hdr[2 * group], total = hdr[2 * group + 1];
+    constexpr bool XCD_RUNS = OPS == kBtFirstOps;
     const int step = (int)gridDim.x;
     int u = (int)blockIdx.x;
     if (u >= total)
         return;
-    BTileUnit cur = units[first + u];
+    BTileUnit cur = units[first + (XCD_RUNS ? xcd_run_tile(u, total) : u)];
     for (;;) {
         // the next tile's record is requested before this tile's rows, so it
         // is at hand when the tile ends; the instance record it points to is
@@ -91,7 +111,7 @@ __global__ __launch_bounds__(kWave *WC *WR) void k_bt(const BTileEntry *__restri
         const bool more = u + step < total;
         BTileUnit nxt = cur;
         if (more)
-            nxt = units[first + u + step];
+            nxt = units[first + (XCD_RUNS ? xcd_run_tile(u + step, total) : u + step)];
         bt_tile<KV, D, WC, WR, OPS>(entries[cur.entry], cur, lds);
         if (!more)
             break;

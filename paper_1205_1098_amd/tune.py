@@ -410,8 +410,8 @@ BATCH_SPACE = {
     # the per-partition parallelism), band heights (how many partitions) and
     # persistent workgroups (0: one per tile)
     "t_store_shape": [2, 3, 11, 7, 1, 0, 4, 5, 6, 8, 9, 10],
-    "t_store_rb": [32, 128, 64, 16, 256, 512],
-    "t_bicgk_rb": [256, 128, 64, 32, 512],
+    "t_store_rb": [16, 32, 64, 8, 128, 256, 512],
+    "t_bicgk_rb": [64, 32, 128, 256, 512],
     "t_wide_shape": [7, 1, 2, 3, 8, 11, 0],
     "t_narrow_shape": [2, 3, 5, 1, 0],
     "t_read_rb": [64, 32, 128],

@@ -327,13 +327,13 @@ def test_batch_knobs_search_the_winning_forms_knobs():
         seen.append(cfg)
         if cfg["form"] != "tiled":
             return 2.0
-        if cfg["t_store_rb"] == 16:
+        if cfg["t_store_rb"] == 128:
             return float("inf")            # e.g. refused by the library
         return 1.0 - 0.01 * (cfg["t_store_shape"] == 3) - 0.02 * (cfg["t_read_rb"] == 32)
 
     best, sec, evals = tune.tune_batch(ev)
     assert best["form"] == "tiled"
-    assert best["t_store_shape"] == 3 and best["t_read_rb"] == 32 and best["t_store_rb"] != 16
+    assert best["t_store_shape"] == 3 and best["t_read_rb"] == 32 and best["t_store_rb"] != 128
     assert sec == pytest.approx(0.97)
     assert all(c["threads"] == tune.BATCH_SPACE["threads"][0] for c in seen)
     assert tune.tiled_config_of(best)["store_shape"] == 3
