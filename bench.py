@@ -77,6 +77,9 @@ def parse():
     ap.add_argument("--batch-direct", action="store_true",
                     help="launch the batch plan without its HIP graph (hardware counters "
                          "are read per direct dispatch only)")
+    ap.add_argument("--no-one-kind", action="store_true",
+                    help="skip the batches of one kind at a time (so that a profile of the "
+                         "batch sees the mixed batch only)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-warmup", type=int, default=1000)
@@ -611,7 +614,8 @@ def bench_generated_passes(torch, bto, n: int = N) -> dict:
     return out
 
 
-def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True) -> dict:
+def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = True,
+                  with_one_kind: bool = True) -> dict:
     """4096 GEMVER / BiCGK instances (n log-uniform on [64, 2048], kinds by a
     fair seeded coin) in one graph-captured persistent launch, then as tiled
     batches; then 4096 instances of one kind at a time (all GEMVER, all
@@ -680,7 +684,7 @@ def bench_batched(torch, bto, count: int, with_loop: bool = True, graph: bool = 
     torch.cuda.empty_cache()
     # the same sizes with every instance of one kind
     one_kind = {}
-    for kind in ("gemver", "bicgk"):
+    for kind in ("gemver", "bicgk") if with_one_kind else ():
         ki, ks = batch.make_instances(torch, bto, count, 64, 2048, {kind: 1.0}, config=4)
         kb = sum(batch.alg_bytes(s.kind, s.m, s.n) for s in ks)
         kp = bto.BatchPlan(ki, use_graph=graph)
@@ -1051,7 +1055,7 @@ def main() -> int:
         torch.cuda.empty_cache()
     if not args.no_batch:
         result["batched"] = bench_batched(torch, bto, args.batch_count, not args.no_batch_loop,
-                                          not args.batch_direct)
+                                          not args.batch_direct, not args.no_one_kind)
         torch.cuda.empty_cache()
     if not args.no_serve:
         result["serving"] = bench_serving(torch, bto, args.serve_requests, args.serve_warmup)
