@@ -1973,8 +1973,8 @@ namespace {
 // whole band) above; one workgroup per tile.  The best dozen configurations
 // were within 1.5% of each other.
 constexpr bto_tiled_config kTiledDefaults = {
-    /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 2, /*narrow_n*/ 512,
-    /*store_rb*/ 16, /*bicgk_rb*/ 64, /*read_rb*/ 32, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
+    /*store_shape*/ 2, /*narrow_shape*/ 2, /*wide_shape*/ 7, /*narrow_n*/ 512,
+    /*store_rb*/ 16, /*bicgk_rb*/ 64, /*read_rb*/ 64, /*wgs_per_cu*/ 0, /*use_graph*/ 1};
 constexpr int kTiledFinishWgsPerCu = 8;
 constexpr int kTiledRefillWgsPerCu = 2;   // refillable plans made with the defaults
 

@@ -412,9 +412,9 @@ BATCH_SPACE = {
     "t_store_shape": [2, 3, 11, 7, 1, 0, 4, 5, 6, 8, 9, 10],
     "t_store_rb": [16, 32, 64, 8, 128, 256, 512],
     "t_bicgk_rb": [64, 32, 128, 256, 512],
-    "t_wide_shape": [2, 7, 1, 3, 8, 11, 0],
+    "t_wide_shape": [7, 2, 1, 3, 8, 11, 0],
     "t_narrow_shape": [2, 3, 5, 1, 0],
-    "t_read_rb": [32, 64, 128],
+    "t_read_rb": [64, 32, 128],
     "t_wgs_per_cu": [0, 1, 2, 4],
 }
 PLAN_KNOBS = ("threads", "wgs_per_cu", "split_bytes")
