@@ -48,7 +48,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wal
 #: the tile shapes every generated pass is compiled for: (kv, depth, waves
 #: across, waves down); a block is 128 * kv * waves_across columns
 SHAPES = [(1, 2, 1, 16), (2, 2, 1, 8), (2, 4, 1, 4), (2, 2, 4, 4), (4, 4, 4, 1),
-          (4, 2, 4, 2), (4, 2, 4, 4), (1, 4, 4, 1), (2, 2, 2, 8), (4, 2, 2, 4)]
+          (4, 2, 4, 2), (4, 2, 4, 4), (1, 4, 4, 1), (2, 2, 2, 8), (4, 2, 2, 4), (4, 2, 2, 8)]
 #: band heights the search tries
 RB_CHOICES = (4, 8, 16, 32, 64, 128, 256, 512)
 MAX_TERMS, MAX_RED = 8, 8
